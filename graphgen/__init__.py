@@ -1,0 +1,275 @@
+"""Seeded synthetic graph generators (edge lists only).
+
+This module produces raw, uncanonicalised undirected edge lists: pairs
+(src, dst) of int32 vertex ids that may contain duplicates, both
+directions and self-loops.  It holds none of the graphlet-transform
+arithmetic and no CSR construction; every consumer canonicalises the
+lists itself (the HIP library with ``fglt_build_csr``, the oracle with
+its own plain CPU routine).
+
+Every generator draws from ``numpy.random.Generator(PCG64)`` keyed by a
+(seed, stream) pair through ``SeedSequence``, so a (seed, stream) pair
+always gives the same graph on the same numpy build.
+
+Workload recipes (the paper measures on LiveJournal and Friendster, which
+are not available here; these synthetic families stand in for them):
+
+* Erdos-Renyi G(n, p): every pair i < j independently with probability p.
+* Chung-Lu: Pareto weights of shape ``exponent - 1`` capped at ``cap``,
+  scale calibrated so that the mean weight equals ``mean_degree``;
+  round(sum(w) / 2) endpoint pairs drawn with probability proportional to w.
+* R-MAT: ``edge_factor * 2**scale`` pairs, one quadrant draw per bit with
+  probabilities (a, b, c, d) and no noise, then a random relabelling.
+* Barabasi-Albert: grown from a star K_{1,m}; each new vertex links to m
+  distinct existing vertices chosen with probability proportional to degree.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "rng_for", "EdgeList", "erdos_renyi", "chung_lu", "rmat", "barabasi_albert",
+    "batch_graphs", "serving_requests", "star", "clique", "cycle", "path",
+]
+
+
+def rng_for(seed: int, stream: int = 0) -> np.random.Generator:
+    """Generator for the (seed, stream) pair."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(stream)])))
+
+
+@dataclass
+class EdgeList:
+    """An undirected multigraph given as raw endpoint arrays."""
+    n: int
+    src: np.ndarray  # int32
+    dst: np.ndarray  # int32
+    name: str = ""
+
+    @property
+    def num_pairs(self) -> int:
+        return int(self.src.shape[0])
+
+
+def _el(n, src, dst, name=""):
+    return EdgeList(int(n), np.ascontiguousarray(src, dtype=np.int32),
+                    np.ascontiguousarray(dst, dtype=np.int32), name)
+
+
+def erdos_renyi(n: int, p: float, seed: int, stream: int = 0) -> EdgeList:
+    """G(n, p): each of the n(n-1)/2 pairs i < j present with probability p."""
+    rng = rng_for(seed, stream)
+    if n < 2:
+        return _el(n, np.zeros(0), np.zeros(0), f"er({n},{p})")
+    # Row-by-row over the strict upper triangle keeps memory at O(n) per step
+    # for large n and is exact G(n, p).
+    src_parts, dst_parts = [], []
+    block = max(1, int(2_000_000 // max(n, 1)))
+    for i0 in range(0, n - 1, block):
+        i1 = min(n - 1, i0 + block)
+        rows = np.arange(i0, i1, dtype=np.int64)
+        lens = n - 1 - rows
+        tot = int(lens.sum())
+        u = rng.random(tot)
+        hit = np.nonzero(u < p)[0]
+        starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+        r = np.searchsorted(starts, hit, side="right") - 1
+        c = rows[r] + 1 + (hit - starts[r])
+        src_parts.append(rows[r])
+        dst_parts.append(c)
+    src = np.concatenate(src_parts) if src_parts else np.zeros(0)
+    dst = np.concatenate(dst_parts) if dst_parts else np.zeros(0)
+    return _el(n, src, dst, f"er({n},{p})")
+
+
+def _pareto_weights(rng, n, shape, mean, cap):
+    """Capped Pareto weights w = min(x_m * U^(-1/shape), cap) with mean(w) == mean.
+
+    x_m is found by bisection on the realised sample so that the sample mean
+    of the capped weights equals ``mean``.
+    """
+    u = rng.random(n)
+    base = np.power(1.0 - u, -1.0 / shape)  # Pareto(1, shape) >= 1
+
+    def mean_for(xm):
+        return float(np.minimum(xm * base, cap).mean())
+
+    lo, hi = 1e-6, float(mean)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mean_for(mid) < mean:
+            lo = mid
+        else:
+            hi = mid
+    return np.minimum(hi * base, cap)
+
+
+def chung_lu(n: int, exponent: float, mean_degree: float, cap: float, seed: int,
+             stream: int = 0) -> EdgeList:
+    """Edge-sampling Chung-Lu graph with degree exponent ``exponent``.
+
+    Weights follow a Pareto law of shape ``exponent - 1`` (so the degree
+    distribution has tail exponent ``exponent``), capped at ``cap`` and scaled
+    to mean ``mean_degree``.  round(sum(w)/2) pairs are drawn with both
+    endpoints proportional to w; duplicates and self-loops are left in.
+    """
+    rng = rng_for(seed, stream)
+    if n < 2:
+        return _el(n, np.zeros(0), np.zeros(0), f"cl({n})")
+    w = _pareto_weights(rng, n, exponent - 1.0, mean_degree, cap)
+    m_pairs = int(round(w.sum() / 2.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    src = np.empty(m_pairs, dtype=np.int32)
+    dst = np.empty(m_pairs, dtype=np.int32)
+    chunk = 1 << 22
+    for s in range(0, m_pairs, chunk):
+        e = min(m_pairs, s + chunk)
+        src[s:e] = np.minimum(np.searchsorted(cdf, rng.random(e - s), side="right"), n - 1)
+        dst[s:e] = np.minimum(np.searchsorted(cdf, rng.random(e - s), side="right"), n - 1)
+    return _el(n, src, dst, f"cl({n},{exponent},{mean_degree},{cap})")
+
+
+def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+         stream: int = 0, permute: bool = True) -> EdgeList:
+    """R-MAT pairs: ``edge_factor * 2**scale`` draws of ``scale`` quadrant bits.
+
+    Quadrant probabilities are (a, b, c, 1-a-b-c) for (top-left, top-right,
+    bottom-left, bottom-right); no noise is added.  With ``permute`` the
+    vertex ids are relabelled by a uniform random permutation.
+    """
+    rng = rng_for(seed, stream)
+    n = 1 << scale
+    m_pairs = edge_factor * n
+    t_ab = a + b
+    t_abc = a + b + c
+    src = np.zeros(m_pairs, dtype=np.int32)
+    dst = np.zeros(m_pairs, dtype=np.int32)
+    chunk = 1 << 22
+    for s in range(0, m_pairs, chunk):
+        e = min(m_pairs, s + chunk)
+        ss = np.zeros(e - s, dtype=np.int32)
+        dd = np.zeros(e - s, dtype=np.int32)
+        for bit in range(scale):
+            u = rng.random(e - s, dtype=np.float32)
+            # quadrant: [0,a) TL, [a,a+b) TR, [a+b,a+b+c) BL, rest BR
+            row_bit = (u >= t_ab).astype(np.int32)
+            col_bit = (((u >= a) & (u < t_ab)) | (u >= t_abc)).astype(np.int32)
+            ss |= row_bit << bit
+            dd |= col_bit << bit
+        src[s:e] = ss
+        dst[s:e] = dd
+    if permute:
+        perm = rng.permutation(n).astype(np.int32)
+        src = perm[src]
+        dst = perm[dst]
+    return _el(n, src, dst, f"rmat({scale},{edge_factor})")
+
+
+def barabasi_albert(n: int, m: int, seed: int, stream: int = 0) -> EdgeList:
+    """Barabasi-Albert graph grown from the star K_{1,m} (vertices 0..m).
+
+    Each later vertex v links to m distinct earlier vertices drawn with
+    probability proportional to their current degree (repeated-endpoint list).
+    """
+    rng = rng_for(seed, stream)
+    m = int(m)
+    if n <= m:
+        # the seed star itself, truncated
+        k = max(0, n - 1)
+        return _el(n, np.zeros(k), np.arange(1, k + 1), f"ba({n},{m})")
+    total = m + (n - m - 1) * m
+    src = np.empty(total, dtype=np.int64)
+    dst = np.empty(total, dtype=np.int64)
+    ends = np.empty(2 * total, dtype=np.int64)
+    src[:m] = 0
+    dst[:m] = np.arange(1, m + 1)
+    ends[0:2 * m:2] = 0
+    ends[1:2 * m:2] = np.arange(1, m + 1)
+    ne = 2 * m
+    e = m
+    u_block = rng.random(8 * m * (n - m) + 64)
+    ui = 0
+    for v in range(m + 1, n):
+        chosen = []
+        while len(chosen) < m:
+            if ui >= u_block.shape[0]:
+                u_block = rng.random(8 * m * (n - m) + 64)
+                ui = 0
+            t = int(ends[int(u_block[ui] * ne)])
+            ui += 1
+            if t not in chosen:
+                chosen.append(t)
+        for t in chosen:
+            src[e] = v
+            dst[e] = t
+            ends[ne] = v
+            ends[ne + 1] = t
+            ne += 2
+            e += 1
+    return _el(n, src, dst, f"ba({n},{m})")
+
+
+def batch_graphs(num_graphs: int, seed: int, n_lo: int = 16, n_hi: int = 512):
+    """The mixed small-graph batch: even g Erdos-Renyi, odd g Barabasi-Albert.
+
+    n_g ~ U{n_lo..n_hi}; ER graphs take mean degree k ~ U[2, 12] and
+    p = k / (n - 1); BA graphs take m ~ U{1..5}.  Graph g draws from stream g.
+    """
+    out = []
+    for g in range(num_graphs):
+        rng = rng_for(seed, 1_000_000 + g)
+        n = int(rng.integers(n_lo, n_hi + 1))
+        if g % 2 == 0:
+            k = float(rng.uniform(2.0, 12.0))
+            out.append(erdos_renyi(n, min(1.0, k / max(1, n - 1)), seed, g))
+        else:
+            mm = int(rng.integers(1, 6))
+            out.append(barabasi_albert(n, mm, seed, g))
+    return out
+
+
+def serving_requests(num: int, seed: int, n_lo_exp: float = 3.0, n_hi_exp: float = 6.0,
+                     cap: int = 50_000):
+    """Request graphs for the serving workload.
+
+    n = round(10^U[n_lo_exp, n_hi_exp]); Chung-Lu with exponent ~ U[2, 3] and
+    mean degree ~ U[8, 32]; weight cap min(n - 1, cap).
+    """
+    out = []
+    for r in range(num):
+        rng = rng_for(seed, 2_000_000 + r)
+        n = int(round(10.0 ** rng.uniform(n_lo_exp, n_hi_exp)))
+        expo = float(rng.uniform(2.0, 3.0))
+        mean = float(rng.uniform(8.0, 32.0))
+        out.append(chung_lu(n, expo, mean, float(min(n - 1, cap)), seed, r))
+    return out
+
+
+def poisson_arrivals(num: int, qps: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of rate ``qps``."""
+    rng = rng_for(seed, 3_000_000)
+    return np.cumsum(rng.exponential(1.0 / qps, size=num))
+
+
+# Small structured graphs used by closed-form checks.
+def star(k: int) -> EdgeList:
+    return _el(k + 1, np.zeros(k), np.arange(1, k + 1), f"star({k})")
+
+
+def clique(n: int) -> EdgeList:
+    i, j = np.triu_indices(n, 1)
+    return _el(n, i, j, f"K{n}")
+
+
+def cycle(n: int) -> EdgeList:
+    i = np.arange(n)
+    return _el(n, i, (i + 1) % n, f"C{n}")
+
+
+def path(n: int) -> EdgeList:
+    i = np.arange(max(0, n - 1))
+    return _el(n, i, i + 1, f"P{n}")

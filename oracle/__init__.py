@@ -1,0 +1,142 @@
+"""CPU oracle for the fast graphlet transform -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  The HIP library and its Python
+binding never import, link or call it, and it shares no code with them.
+
+Contents
+--------
+* ``canonical_csr`` -- the plain definition of a simple undirected graph's
+  adjacency (symmetrise, drop self-loops, drop duplicates, sort rows), in numpy.
+* ``raw`` / ``net`` / ``raw_to_net`` -- ctypes front end of ``fglt_oracle.c``,
+  the per-vertex evaluation of Table I and the back-substitution with Table II.
+* ``bruteforce`` (module) -- enumeration of every vertex subset of size <= 4,
+  the definition of raw and net frequencies, for tiny graphs.
+* ``U16`` -- Table II as a dense integer matrix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fglt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+NORB = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile fglt_oracle.c with gcc -O2 -fopenmp into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall",
+               "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = build()
+            lib = ctypes.CDLL(path)
+            p64 = ctypes.POINTER(ctypes.c_int64)
+            p32 = ctypes.POINTER(ctypes.c_int32)
+            lib.oracle_raw.argtypes = [ctypes.c_int64, p64, p32, ctypes.c_int64, p64, p64, ctypes.c_int]
+            lib.oracle_raw.restype = ctypes.c_int
+            lib.oracle_raw_to_net.argtypes = [ctypes.c_int64, p64, p64]
+            lib.oracle_raw_to_net.restype = None
+            lib.oracle_u16.argtypes = [p64]
+            lib.oracle_u16.restype = None
+            lib.oracle_max_threads.argtypes = []
+            lib.oracle_max_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _p64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _p32(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def canonical_csr(n: int, src, dst):
+    """Adjacency of the simple undirected graph on n vertices spanned by the
+    pairs (src[t], dst[t]): both directions, self-loops and duplicates
+    removed, rows sorted.  Returns (offsets int64[n+1], indices int32[nnz])."""
+    n = int(n)
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    if src.size and (src.min() < 0 or dst.min() < 0 or src.max() >= n or dst.max() >= n):
+        raise ValueError("vertex id out of range")
+    s = np.concatenate([src, dst])
+    d = np.concatenate([dst, src])
+    keep = s != d
+    key = np.unique(s[keep] * max(n, 1) + d[keep])
+    rows = key // max(n, 1)
+    cols = key % max(n, 1)
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    if n:
+        np.cumsum(np.bincount(rows, minlength=n), out=offsets[1:])
+    return offsets, cols.astype(np.int32)
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def raw(offsets, indices, vertices=None, threads: int = 0) -> np.ndarray:
+    """Raw frequencies (Table I) of the selected vertices (all if None)."""
+    lib = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    n = off.shape[0] - 1
+    if vertices is None:
+        nsel = n
+        sel_ptr = ctypes.POINTER(ctypes.c_int64)()
+    else:
+        sel = np.ascontiguousarray(vertices, dtype=np.int64)
+        if sel.size and (sel.min() < 0 or sel.max() >= n):
+            raise ValueError("vertex out of range")
+        nsel = sel.shape[0]
+        sel_ptr = _p64(sel)
+    out = np.zeros((max(nsel, 0), NORB), dtype=np.int64)
+    if idx.size == 0:
+        idx = np.zeros(1, dtype=np.int32)
+    st = lib.oracle_raw(n, _p64(off), _p32(idx), nsel, sel_ptr, _p64(out), int(threads))
+    if st != 0:
+        raise RuntimeError(f"oracle_raw failed with status {st}")
+    return out
+
+
+def raw_to_net(raw_counts) -> np.ndarray:
+    """Back-substitution with U16 (Table II), row by row."""
+    lib = _load()
+    r = np.ascontiguousarray(raw_counts, dtype=np.int64).reshape(-1, NORB)
+    out = np.zeros_like(r)
+    lib.oracle_raw_to_net(r.shape[0], _p64(r), _p64(out))
+    return out
+
+
+def net(offsets, indices, vertices=None, threads: int = 0) -> np.ndarray:
+    """Net frequencies: Table I followed by Table II."""
+    return raw_to_net(raw(offsets, indices, vertices, threads))
+
+
+def U16() -> np.ndarray:
+    """Table II, U16 f = raw, as a dense 16x16 int64 matrix."""
+    u = np.zeros((NORB, NORB), dtype=np.int64)
+    _load().oracle_u16(_p64(u))
+    return u

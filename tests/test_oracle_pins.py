@@ -1,0 +1,293 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these compare the oracle with itself: they use the paper's printed
+worked example (Fig. 2), Table II as printed, brute-force enumeration (the
+definition), closed forms, walk identities on dense matrix powers, orbit-sum
+invariants and networkx's triangle and clique routines.
+"""
+import math
+from itertools import combinations
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import bruteforce
+
+C = math.comb
+
+
+def csr_of(n, edges):
+    edges = list(edges)
+    src = np.array([a for a, b in edges], dtype=np.int64)
+    dst = np.array([b for a, b in edges], dtype=np.int64)
+    return oracle.canonical_csr(n, src, dst)
+
+
+def random_graph(rng, n, p):
+    return [(i, j) for i, j in combinations(range(n), 2) if rng.random() < p]
+
+
+# ---------------------------------------------------------------- Fig. 2 / Table II
+
+def test_fig2_oracle(fig2):
+    off, idx = csr_of(fig2["n"], fig2["edges"])
+    r = oracle.raw(off, idx)
+    np.testing.assert_array_equal(r, fig2["raw"])
+    np.testing.assert_array_equal(oracle.raw_to_net(r), fig2["net"])
+
+
+def test_fig2_bruteforce(fig2):
+    r, f = bruteforce.frequencies(fig2["n"], fig2["edges"])
+    np.testing.assert_array_equal(r, fig2["raw"])
+    np.testing.assert_array_equal(f, fig2["net"])
+
+
+def test_fig2_observations(fig2):
+    """The observations printed under Fig. 2: orbit invariance f(v2) = f(v5),
+    5 triangles, no induced 4-cycles, claw-free."""
+    f = fig2["net"]
+    np.testing.assert_array_equal(f[1], f[4])
+    assert f[:, 4].sum() // 3 == 5
+    assert (f[:, 12] == 0).all()
+    assert (f[:, 7] == 0).all() and (f[:, 8] == 0).all()
+
+
+def test_u16_matches_table2(table2):
+    np.testing.assert_array_equal(oracle.U16(), table2)
+    # 50 non-zeros (the text's "< 3|Sigma|" bound is not met; the pattern claim is)
+    assert np.count_nonzero(table2) == 50
+
+
+def test_raw_to_net_inverts_table2(table2):
+    rng = np.random.default_rng(7)
+    f = rng.integers(0, 1000, size=(200, 16)).astype(np.int64)
+    rawv = f @ table2.T
+    np.testing.assert_array_equal(oracle.raw_to_net(rawv), f)
+    # U^{-1} has the same sparsity pattern as U (Section V)
+    inv = oracle.raw_to_net(np.eye(16, dtype=np.int64)).T
+    np.testing.assert_array_equal(inv @ table2, np.eye(16, dtype=np.int64))
+    assert ((inv != 0) == (table2 != 0)).all()
+
+
+# ---------------------------------------------------------------- brute force
+
+def _edge_cases():
+    yield 0, []
+    yield 1, []
+    yield 2, []
+    yield 2, [(0, 1)]
+    yield 5, []
+    yield 6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)]  # two triangles
+    # star K_{1,4} glued to a K4 through the centre
+    yield 8, [(0, 1), (0, 2), (0, 3), (0, 4)] + list(combinations([0, 5, 6, 7], 2))
+    yield 7, [(0, k) for k in range(1, 7)]  # hub
+    yield 6, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2)] + [(4, 5)]
+
+
+@pytest.mark.parametrize("case", list(range(9)))
+def test_oracle_vs_bruteforce_edge_cases(case):
+    n, edges = list(_edge_cases())[case]
+    off, idx = csr_of(n, edges)
+    br, bn = bruteforce.frequencies(n, edges)
+    r = oracle.raw(off, idx)
+    np.testing.assert_array_equal(r, br)
+    np.testing.assert_array_equal(oracle.raw_to_net(r), bn)
+
+
+@pytest.mark.parametrize("seed", list(range(40)))
+def test_oracle_vs_bruteforce_random(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 10))
+    p = float(rng.choice([0.2, 0.35, 0.5, 0.7, 0.9]))
+    edges = random_graph(rng, n, p)
+    off, idx = csr_of(n, edges)
+    br, bn = bruteforce.frequencies(n, edges)
+    r = oracle.raw(off, idx)
+    np.testing.assert_array_equal(r, br)
+    np.testing.assert_array_equal(oracle.raw_to_net(r), bn)
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", list(range(1, 10)))
+def test_clique_closed_form(n):
+    g = graphgen.clique(n)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    r = oracle.raw(off, idx)
+    f = oracle.raw_to_net(r)
+    exp_net = np.zeros(16, dtype=np.int64)
+    exp_net[0] = 1
+    exp_net[1] = n - 1
+    exp_net[4] = C(n - 1, 2)
+    exp_net[15] = C(n - 1, 3)
+    np.testing.assert_array_equal(f, np.tile(exp_net, (n, 1)))
+    a = n - 1
+    b = max(n - 2, 0)
+    c = max(n - 3, 0)
+    exp_raw = [1, a, a * b, C(a, 2), C(a, 2), a * b * c, a * b * c, a * C(b, 2), C(a, 3),
+               c * C(a, 2), a * b * c, c * C(a, 2), a * C(b, 2), c * C(a, 2), a * C(b, 2), C(a, 3)]
+    np.testing.assert_array_equal(r, np.tile(np.array(exp_raw, dtype=np.int64), (n, 1)))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 9])
+def test_star_closed_form(k):
+    g = graphgen.star(k)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.net(off, idx)
+    centre = np.zeros(16, dtype=np.int64)
+    centre[[0, 1, 3, 8]] = [1, k, C(k, 2), C(k, 3)]
+    leaf = np.zeros(16, dtype=np.int64)
+    leaf[[0, 1, 2, 7]] = [1, 1, k - 1, C(k - 1, 2)]
+    np.testing.assert_array_equal(f[0], centre)
+    for v in range(1, k + 1):
+        np.testing.assert_array_equal(f[v], leaf)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 9])
+def test_cycle_closed_form(n):
+    g = graphgen.cycle(n)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.net(off, idx)
+    exp = np.zeros(16, dtype=np.int64)
+    exp[0] = 1
+    if n == 3:
+        exp[[1, 4]] = [2, 1]
+    elif n == 4:
+        exp[[1, 2, 3, 12]] = [2, 2, 1, 1]
+    else:
+        exp[[1, 2, 3, 5, 6]] = [2, 2, 1, 2, 2]
+    np.testing.assert_array_equal(f, np.tile(exp, (n, 1)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8])
+def test_path_closed_form(n):
+    g = graphgen.path(n)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.net(off, idx)
+    for v in range(n):
+        a, b = v, n - 1 - v
+        exp = np.zeros(16, dtype=np.int64)
+        exp[0] = 1
+        exp[1] = (a >= 1) + (b >= 1)
+        exp[2] = (a >= 2) + (b >= 2)
+        exp[3] = (a >= 1) * (b >= 1)
+        exp[5] = (a >= 3) + (b >= 3)
+        exp[6] = (a >= 1) * (b >= 2) + (a >= 2) * (b >= 1)
+        np.testing.assert_array_equal(f[v], exp)
+
+
+# ---------------------------------------------------------------- walk identities
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_walk_identities(seed):
+    rng = np.random.default_rng(seed)
+    n = 80
+    edges = random_graph(rng, n, 0.12)
+    off, idx = csr_of(n, edges)
+    r = oracle.raw(off, idx)
+    A = np.zeros((n, n), dtype=np.int64)
+    for a, b in edges:
+        A[a, b] = A[b, a] = 1
+    A2 = A @ A
+    A3 = A2 @ A
+    A4 = A3 @ A
+    d = A.sum(1)
+    np.testing.assert_array_equal(np.diag(A3), 2 * r[:, 4])
+    np.testing.assert_array_equal(np.diag(A4), 2 * r[:, 12] + d * d + r[:, 2])
+    # 2-paths from i: walks of length 2 that do not return to i
+    np.testing.assert_array_equal(r[:, 2], A2.sum(1) - d)
+
+
+# ---------------------------------------------------------------- invariants
+
+def _nx_graph(off, idx):
+    g = nx.Graph()
+    n = off.shape[0] - 1
+    g.add_nodes_from(range(n))
+    rows = np.repeat(np.arange(n), np.diff(off))
+    g.add_edges_from(zip(rows.tolist(), idx.tolist()))
+    return g
+
+
+@pytest.mark.parametrize("which", ["er", "cl", "ba"])
+def test_invariants_medium(which):
+    if which == "er":
+        g = graphgen.erdos_renyi(400, 0.05, seed=11)
+    elif which == "cl":
+        g = graphgen.chung_lu(1500, 2.1, 12.0, 300.0, seed=12)
+    else:
+        g = graphgen.barabasi_albert(600, 4, seed=13)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    r = oracle.raw(off, idx)
+    f = oracle.raw_to_net(r)
+    G = _nx_graph(off, idx)
+    tri = nx.triangles(G)
+    np.testing.assert_array_equal(r[:, 4], [tri[v] for v in range(g.n)])
+    ntri = sum(tri.values()) // 3
+    assert f[:, 4].sum() == 3 * ntri
+    n_k4 = sum(1 for c in nx.enumerate_all_cliques(G) if len(c) == 4)
+    assert f[:, 15].sum() == 4 * n_k4
+    S = f.sum(0)
+    assert S[2] == 2 * S[3]
+    assert S[5] == S[6]
+    assert S[7] == 3 * S[8]
+    assert 2 * S[9] == S[10] and S[9] == S[11]
+    assert S[13] == S[14]
+    assert S[12] % 4 == 0 and S[15] % 4 == 0
+    assert (f >= 0).all() and (r >= f).all()
+    np.testing.assert_array_equal(f @ oracle.U16().T, r)
+
+
+def test_degrees_and_library_counts():
+    g = graphgen.chung_lu(800, 2.3, 10.0, 200.0, seed=21)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    r = oracle.raw(off, idx)
+    G = _nx_graph(off, idx)
+    np.testing.assert_array_equal(r[:, 1], [G.degree(v) for v in range(g.n)])
+    np.testing.assert_array_equal(r[:, 0], 1)
+
+
+def test_permutation_equivariance():
+    g = graphgen.chung_lu(700, 2.2, 10.0, 150.0, seed=31)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.net(off, idx)
+    perm = np.random.default_rng(3).permutation(g.n)
+    off2, idx2 = oracle.canonical_csr(g.n, perm[g.src], perm[g.dst])
+    f2 = oracle.net(off2, idx2)
+    np.testing.assert_array_equal(f2[perm], f)
+
+
+def test_vertex_subset_matches_full():
+    g = graphgen.chung_lu(900, 2.1, 12.0, 200.0, seed=41)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    full = oracle.raw(off, idx)
+    sel = np.random.default_rng(0).choice(g.n, 50, replace=False)
+    np.testing.assert_array_equal(oracle.raw(off, idx, sel), full[sel])
+
+
+def test_disjoint_union_is_concatenation():
+    gs = [graphgen.erdos_renyi(30, 0.3, seed=5, stream=s) for s in range(3)]
+    n = sum(g.n for g in gs)
+    src, dst, base = [], [], 0
+    parts = []
+    for g in gs:
+        off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+        parts.append(oracle.net(off, idx))
+        src.append(g.src.astype(np.int64) + base)
+        dst.append(g.dst.astype(np.int64) + base)
+        base += g.n
+    off, idx = oracle.canonical_csr(n, np.concatenate(src), np.concatenate(dst))
+    np.testing.assert_array_equal(oracle.net(off, idx), np.concatenate(parts))
+
+
+def test_canonical_csr_definition():
+    src = np.array([0, 1, 1, 2, 2, 3, 3, 0, 4])
+    dst = np.array([1, 0, 1, 3, 3, 2, 0, 3, 4])
+    off, idx = oracle.canonical_csr(5, src, dst)
+    np.testing.assert_array_equal(off, [0, 2, 3, 4, 6, 6])
+    np.testing.assert_array_equal(idx, [1, 3, 0, 3, 0, 2])
+    with pytest.raises(ValueError):
+        oracle.canonical_csr(3, np.array([0]), np.array([3]))
