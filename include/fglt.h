@@ -1,0 +1,174 @@
+/*
+ * fglt.h -- C ABI of the MI355X (gfx950) fast graphlet transform library.
+ *
+ * The library computes, for every vertex v of a simple undirected graph, the
+ * frequencies of the 16 graphlet orbits sigma_0 .. sigma_15 on up to four
+ * vertices (the dictionary Sigma_16 of Floros, Pitsianis and Sun, "Fast
+ * Graphlet Transform of Sparse Graphs", Fig. 1 and Table I):
+ *   - raw frequencies  \hat f(v) by the sparse matrix-vector formulas of
+ *     Table I (Sections III and IV), and
+ *   - net frequencies  f(v) = U16^{-1} \hat f(v) with the conversion matrix
+ *     U16 of Table II (Section V), i.e. induced-subgraph orbit counts.
+ *
+ * Conventions for every entry point
+ *   - Vertices are 0-based (the paper numbers them from 1).
+ *   - Output arrays are n x 16 int64, row-major: row v, column k = sigma_k in
+ *     the order of Table I.
+ *   - All array arguments are DEVICE pointers unless marked (host); the caller
+ *     allocates and frees every buffer (inputs, outputs, workspace). The
+ *     library keeps no device allocation between calls, except cached HIP
+ *     graphs of fglt_batch, released by fglt_batch_release().
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is enqueued
+ *     on it; where an entry point synchronizes with that stream it says so.
+ *   - Return value: FGLT_OK or a negative fglt_status; nothing throws across
+ *     the ABI.  Argument checks happen on the host before any launch; errors
+ *     reported by the HIP runtime map to FGLT_EHIP.
+ *   - Calls on distinct streams with distinct workspaces may run concurrently.
+ *
+ * Integer ranges: n < 2^31 (int32 vertex ids); the largest degree must be
+ * below 2^21 so that every count (at most d_max^3) fits in int64.
+ */
+#ifndef FGLT_H
+#define FGLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FGLT_OK = 0,
+    FGLT_EINVAL = -1,        /* bad argument (NULL pointer, negative size, n >= 2^31, ...) */
+    FGLT_ENOTCANON = -2,     /* the CSR is not canonical (see fglt_raw)                    */
+    FGLT_EWORKSPACE = -3,    /* ws_bytes below the size the workspace query returns        */
+    FGLT_EOVERFLOW = -4,     /* a degree >= 2^21: counts could overflow int64              */
+    FGLT_EHIP = -5,          /* the HIP runtime reported an error                          */
+    FGLT_EUNSUPPORTED = -6   /* a graph outside what the chosen path supports              */
+} fglt_status;
+
+#define FGLT_NORBITS 16
+#define FGLT_MAX_DEGREE ((int64_t)1 << 21)
+
+/* fglt_raw flags */
+#define FGLT_NET 1u          /* write net frequencies (Table II applied) instead of raw */
+
+/*
+ * Canonical adjacency from an edge list (the simple undirected graph of
+ * Section I: symmetric 0/1 A, no self-loops, no multiple edges).
+ *   n            number of vertices
+ *   num_edges    number of input pairs
+ *   src, dst     [num_edges] int32 endpoints, any order, may repeat, may be self-loops
+ *   offsets      out [n+1] int64 row offsets
+ *   indices      out, capacity 2*num_edges int32, rows strictly increasing
+ *   nnz          out, device int64 scalar: the number of directed entries (2m);
+ *                set to -1 if an endpoint lies outside [0, n) (offsets and
+ *                indices are then undefined)
+ *   ws, ws_bytes device workspace of at least fglt_build_csr_workspace(n, num_edges) bytes
+ * Asynchronous; never synchronizes.
+ */
+size_t fglt_build_csr_workspace(int64_t n, int64_t num_edges);
+int fglt_build_csr(int64_t n, int64_t num_edges, const int32_t* src, const int32_t* dst,
+                   int64_t* offsets, int32_t* indices, int64_t* nnz,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Statistics of the last fglt_raw call, filled when a host pointer is passed. */
+typedef struct {
+    int64_t n, nnz;              /* vertices, directed entries (2m)                       */
+    int64_t d_max;               /* largest degree                                        */
+    int64_t dplus_max;           /* largest out-degree under the degree ordering          */
+    int64_t tri_items;           /* sum over oriented edges u->v of d+(v): merge work    */
+    int64_t wedge_items;         /* rank-ordered wedges visited by the 4-cycle pass      */
+    int64_t n_light_tri, n_mid_tri, n_heavy_tri;  /* vertices per clique-pass tier        */
+    int64_t n_light_c4, n_mid_c4, n_heavy_c4;     /* vertices per 4-cycle-pass tier       */
+} fglt_stats;
+
+/* Tier thresholds of fglt_raw (host struct); 0 selects a default.  A vertex u
+ * with out-degree D (under the degree ordering) is counted by one wavefront if
+ * D <= tri_wave_max (<= 64), by a workgroup with LDS bitmaps if
+ * D <= tri_lds_max (<= 512), else by a workgroup with bitmaps in the
+ * workspace; the 4-cycle pass likewise by its wedge count W against
+ * c4_wave_max (<= 128) and c4_block_max (<= 2048).  Any setting gives the
+ * same result; only the speed changes. */
+typedef struct {
+    int32_t tri_wave_max;   /* default 64   */
+    int32_t tri_lds_max;    /* default 512  */
+    int32_t c4_wave_max;    /* default 128; -1 disables the tier */
+    int32_t c4_block_max;   /* default 2048; -1 disables the tier */
+} fglt_raw_plan;
+
+/*
+ * Raw frequencies \hat f (Table I) of every vertex, or net frequencies
+ * (Table I then Table II) with flags & FGLT_NET.
+ *   n, nnz       vertices and directed entries of the CSR
+ *   offsets      [n+1] int64, offsets[0] == 0, non-decreasing, offsets[n] == nnz
+ *   indices      [nnz] int32; the CSR must be canonical: symmetric, no
+ *                self-loops, no repeated entry in a row (rows need not be sorted)
+ *   out          out [n][16] int64
+ *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
+ *   flags        FGLT_NET or 0
+ *   plan         (host) optional tier thresholds, NULL for the defaults
+ *   stats        (host) optional, filled on success
+ * Returns FGLT_ENOTCANON for a CSR that breaks the contract (checked on the
+ * device), FGLT_EOVERFLOW for a degree >= 2^21.
+ * Synchronizes with `stream` twice: after the input checks and after the
+ * degree relabelling, to size the counting launches.
+ */
+size_t fglt_raw_workspace(int64_t n, int64_t nnz);
+int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices,
+             int64_t* out, void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan,
+             fglt_stats* stats, void* stream);
+
+/*
+ * Net from raw frequencies: f = U16^{-1} \hat f per vertex (Section V,
+ * Table II), by exact integer back-substitution.  `net` may equal `raw`.
+ * Asynchronous; never synchronizes.
+ */
+int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream);
+
+/* Execution plan of fglt_batch (host struct); NULL selects the defaults. */
+typedef struct {
+    int32_t threads;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (default 256) */
+    int32_t small_n;        /* graphs with n <= small_n are packed several per workgroup (0 = off) */
+    int32_t lpt_order;      /* 1: largest graphs first through a device work queue (default 1) */
+    int32_t use_graph;      /* 1: replay a captured hipGraph for this stream and shape (default 0) */
+} fglt_batch_plan;
+
+#define FGLT_BATCH_MAX_N 512
+
+/*
+ * Net frequencies of G independent graphs in one fused launch.
+ *   num_graphs   G
+ *   vtx_offsets  [G+1] int64: graph g owns vertices vtx_offsets[g] .. vtx_offsets[g+1]-1
+ *   n_total      vtx_offsets[G]
+ *   nnz_total    offsets[n_total]
+ *   offsets      [n_total+1] int64 block-diagonal CSR (global vertex ids)
+ *   indices      [nnz_total] int32, canonical as for fglt_raw; every entry of a
+ *                row of graph g must lie in graph g's vertex range
+ *   net          out [n_total][16] int64
+ *   plan         (host) optional execution plan
+ *   ws, ws_bytes device workspace of at least fglt_batch_workspace(...) bytes
+ * Every graph must have at most FGLT_BATCH_MAX_N vertices (FGLT_EUNSUPPORTED
+ * otherwise, checked on the host from the (host) copy `vtx_offsets_host`).
+ * Entries that break the contract are skipped on the device and recorded in
+ * a device status word, read by fglt_batch_status().  Asynchronous; never
+ * synchronizes, so it can be captured into a HIP graph.
+ */
+size_t fglt_batch_workspace(int32_t num_graphs, int64_t n_total, int64_t nnz_total);
+int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const int64_t* vtx_offsets_host,
+               int64_t n_total, int64_t nnz_total, const int64_t* offsets, const int32_t* indices,
+               int64_t* net, const fglt_batch_plan* plan, void* ws, size_t ws_bytes, void* stream);
+/* Reads the status word of the last fglt_batch on this workspace (synchronizes
+ * with `stream`): FGLT_OK or FGLT_ENOTCANON. */
+int fglt_batch_status(const void* ws, void* stream);
+/* Frees the HIP graphs cached for `stream` (NULL: all). */
+int fglt_batch_release(void* stream);
+
+const char* fglt_status_string(int status);
+int fglt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGLT_H */

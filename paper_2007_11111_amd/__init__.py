@@ -1,0 +1,166 @@
+"""Fast graphlet transform on MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libfglt.so`` (include/fglt.h): it only
+allocates device buffers with torch, picks the current HIP stream and passes
+raw pointers.  Every step of the transform runs in the library's HIP kernels.
+
+    offsets, indices = build_csr(n, src, dst)          # canonical CSR on the GPU
+    f = transform(offsets, indices)                    # n x 16 int64 net frequencies
+    r = raw(offsets, indices); f = net(r)              # the two stages separately
+    outs = batch([...])                                # many small graphs, one launch
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import FGLT_NET, NORBITS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+
+__all__ = [
+    "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "FgltError", "Stats",
+    "BatchPlan", "batch_pack", "batch", "NORBITS",
+]
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(device=None):
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Canonical CSR (symmetric, no self-loops, no duplicates, sorted rows) of
+    the undirected graph spanned by the pairs (src, dst) -- ``fglt_build_csr``.
+
+    src, dst: int32 device tensors.  Returns (offsets int64[n+1], indices
+    int32[nnz]) on the same device."""
+    L = lib()
+    assert src.dtype == torch.int32 and dst.dtype == torch.int32 and src.is_cuda and dst.is_cuda
+    src = src.contiguous()
+    dst = dst.contiguous()
+    E = int(src.numel())
+    dev = src.device
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    indices = torch.empty(max(2 * E, 1), dtype=torch.int32, device=dev)
+    nnz = torch.empty(1, dtype=torch.int64, device=dev)
+    ws_bytes = int(L.fglt_build_csr_workspace(n, E))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    check(L.fglt_build_csr(n, E, _ptr(src), _ptr(dst), _ptr(offsets), _ptr(indices), _ptr(nnz),
+                           _ptr(ws), ws_bytes, _stream(stream)), "fglt_build_csr")
+    m = int(nnz.item())
+    if m < 0:
+        raise FgltError(-1, "fglt_build_csr", "an endpoint is outside [0, n)")
+    return offsets, indices[:m]
+
+
+def raw_workspace_bytes(n: int, nnz: int) -> int:
+    return int(lib().fglt_raw_workspace(int(n), int(nnz)))
+
+
+def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
+        workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None, stream=None):
+    """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
+    net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
+    (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
+    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max."""
+    L = lib()
+    assert offsets.dtype == torch.int64 and indices.dtype == torch.int32
+    assert offsets.is_cuda and indices.is_cuda
+    offsets = offsets.contiguous()
+    indices = indices.contiguous()
+    n = int(offsets.numel()) - 1
+    nnz = int(indices.numel())
+    dev = offsets.device
+    if out is None:
+        out = torch.empty((max(n, 0), NORBITS), dtype=torch.int64, device=dev)
+    ws_bytes = int(L.fglt_raw_workspace(n, nnz))
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    st = Stats()
+    rp = None
+    if plan:
+        rp = RawPlan(int(plan.get("tri_wave_max", 0)), int(plan.get("tri_lds_max", 0)),
+                     int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)))
+    check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
+                     int(workspace.numel()), FGLT_NET if net else 0, ctypes.byref(rp) if rp is not None else None,
+                     ctypes.byref(st), _stream(stream)),
+          "fglt_raw")
+    return (out, st.as_dict()) if stats else out
+
+
+def net(raw_counts: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Net from raw frequencies, f = U16^{-1} raw per vertex -- ``fglt_net``."""
+    L = lib()
+    assert raw_counts.dtype == torch.int64 and raw_counts.is_cuda
+    raw_counts = raw_counts.contiguous()
+    n = int(raw_counts.shape[0])
+    if out is None:
+        out = torch.empty_like(raw_counts)
+    check(L.fglt_net(n, _ptr(raw_counts), _ptr(out), _stream(stream)), "fglt_net")
+    return out
+
+
+def transform(offsets: torch.Tensor, indices: torch.Tensor, **kw):
+    """Net frequencies of every vertex (the graphlet transform over Sigma_16)."""
+    return raw(offsets, indices, net=True, **kw)
+
+
+def batch_pack(csrs):
+    """Block-diagonal packing of host CSRs [(offsets, indices), ...] (numpy or
+    torch CPU) into (vtx_offsets, offsets, indices) int64/int64/int32 CPU tensors."""
+    import numpy as np
+    vtx = [0]
+    offs = []
+    idxs = []
+    base_v = 0
+    base_e = 0
+    for off, idx in csrs:
+        off = np.asarray(off, dtype=np.int64)
+        idx = np.asarray(idx, dtype=np.int32)
+        n = off.shape[0] - 1
+        offs.append(off[:-1] + base_e)
+        idxs.append(idx.astype(np.int64) + base_v)
+        base_v += n
+        base_e += int(off[-1])
+        vtx.append(base_v)
+    offs.append(np.array([base_e], dtype=np.int64))
+    return (torch.from_numpy(np.array(vtx, dtype=np.int64)),
+            torch.from_numpy(np.concatenate(offs)),
+            torch.from_numpy(np.concatenate(idxs).astype(np.int32) if idxs else np.zeros(0, np.int32)))
+
+
+def batch(vtx_offsets: torch.Tensor, offsets: torch.Tensor, indices: torch.Tensor, *, plan: dict | None = None,
+          out: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """Net frequencies of many independent graphs in one fused launch --
+    ``fglt_batch``.  vtx_offsets is a CPU int64 tensor [G+1]; offsets and
+    indices are the block-diagonal CSR on the device."""
+    L = lib()
+    if not hasattr(L, "fglt_batch"):
+        raise RuntimeError("libfglt.so was built without fglt_batch")
+    vtx_host = vtx_offsets.to("cpu", torch.int64).contiguous()
+    dev = offsets.device
+    vtx_dev = vtx_host.to(dev)
+    G = int(vtx_host.numel()) - 1
+    n_total = int(vtx_host[-1])
+    nnz = int(indices.numel())
+    if out is None:
+        out = torch.empty((n_total, NORBITS), dtype=torch.int64, device=dev)
+    ws_bytes = int(L.fglt_batch_workspace(G, n_total, nnz))
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    bp = None
+    if plan is not None:
+        bp = BatchPlan(int(plan.get("threads", 256)), int(plan.get("small_n", 0)),
+                       int(plan.get("lpt_order", 1)), int(plan.get("use_graph", 0)))
+    check(L.fglt_batch(G, _ptr(vtx_dev), ctypes.c_void_p(vtx_host.data_ptr()), n_total, nnz, _ptr(offsets),
+                       _ptr(indices if nnz else None), _ptr(out), ctypes.byref(bp) if bp is not None else None,
+                       _ptr(workspace), int(workspace.numel()), _stream(stream)), "fglt_batch")
+    return out

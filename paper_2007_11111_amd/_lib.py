@@ -1,0 +1,101 @@
+"""ctypes loader for libfglt.so (the HIP library built by build.py).
+
+There is no fallback: if the shared library is missing or fails to load, every
+entry point raises.  Build it with ``python -m paper_2007_11111_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfglt.so")
+
+NORBITS = 16
+FGLT_NET = 1
+
+STATUS = {
+    0: "FGLT_OK",
+    -1: "FGLT_EINVAL",
+    -2: "FGLT_ENOTCANON",
+    -3: "FGLT_EWORKSPACE",
+    -4: "FGLT_EOVERFLOW",
+    -5: "FGLT_EHIP",
+    -6: "FGLT_EUNSUPPORTED",
+}
+
+
+class FgltError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({message})")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "nnz", "d_max", "dplus_max", "tri_items", "wedge_items",
+        "n_light_tri", "n_mid_tri", "n_heavy_tri", "n_light_c4", "n_mid_c4", "n_heavy_c4")]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class RawPlan(ctypes.Structure):
+    _fields_ = [("tri_wave_max", ctypes.c_int32), ("tri_lds_max", ctypes.c_int32),
+                ("c4_wave_max", ctypes.c_int32), ("c4_block_max", ctypes.c_int32)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("small_n", ctypes.c_int32),
+                ("lpt_order", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is missing: the HIP library must be built "
+                    "(python -m paper_2007_11111_amd.build); there is no CPU fallback")
+            L = ctypes.CDLL(LIB_PATH)
+            i64, i32, vp, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+            L.fglt_build_csr_workspace.argtypes = [i64, i64]
+            L.fglt_build_csr_workspace.restype = sz
+            L.fglt_build_csr.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+            L.fglt_build_csr.restype = ctypes.c_int
+            L.fglt_raw_workspace.argtypes = [i64, i64]
+            L.fglt_raw_workspace.restype = sz
+            L.fglt_raw.argtypes = [i64, i64, vp, vp, vp, vp, sz, ctypes.c_uint, ctypes.POINTER(RawPlan),
+                                   ctypes.POINTER(Stats), vp]
+            L.fglt_raw.restype = ctypes.c_int
+            L.fglt_net.argtypes = [i64, vp, vp, vp]
+            L.fglt_net.restype = ctypes.c_int
+            if hasattr(L, "fglt_batch"):
+                L.fglt_batch_workspace.argtypes = [i32, i64, i64]
+                L.fglt_batch_workspace.restype = sz
+                L.fglt_batch.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp, ctypes.POINTER(BatchPlan), vp, sz, vp]
+                L.fglt_batch.restype = ctypes.c_int
+                L.fglt_batch_status.argtypes = [vp, vp]
+                L.fglt_batch_status.restype = ctypes.c_int
+                L.fglt_batch_release.argtypes = [vp]
+                L.fglt_batch_release.restype = ctypes.c_int
+            L.fglt_status_string.argtypes = [ctypes.c_int]
+            L.fglt_status_string.restype = ctypes.c_char_p
+            L.fglt_version.argtypes = []
+            L.fglt_version.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def check(status: int, where: str):
+    if status != 0:
+        msg = lib().fglt_status_string(status).decode()
+        raise FgltError(status, where, msg)

@@ -1,0 +1,114 @@
+// api.hip -- C ABI entry points of the single-graph transform (fglt_raw,
+// fglt_net) and the status helpers.  See include/fglt.h.
+#include <algorithm>
+
+#include "raw.h"
+
+using namespace fglt;
+
+namespace {
+
+int status_from_err(u32 err) {
+    if (err & ERR_DEGREE) return FGLT_EOVERFLOW;
+    if (err) return FGLT_ENOTCANON;
+    return FGLT_OK;
+}
+
+int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
+    if (hipMemcpyAsync(&hp, w.plan, sizeof(DevPlan), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FGLT_EHIP;
+    return FGLT_OK;
+}
+
+}  // namespace
+
+extern "C" size_t fglt_raw_workspace(int64_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    Carver c(nullptr, 0);
+    carve_raw(c, n, nnz);
+    return c.used;
+}
+
+extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out,
+                        void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats,
+                        void* stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
+    if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
+    if (nnz > 0 && !indices) return FGLT_EINVAL;
+    if (flags & ~FGLT_NET) return FGLT_EINVAL;
+    if (stats) {
+        *stats = fglt_stats{};
+        stats->n = n;
+        stats->nnz = nnz;
+    }
+    if (n == 0) return nnz == 0 ? FGLT_OK : FGLT_ENOTCANON;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws, ws_bytes);
+    RawWs w = carve_raw(c, n, nnz);
+    if (!c.ok()) return FGLT_EWORKSPACE;
+
+    // 1. input checks (memory safety of everything below), degrees
+    FGLT_HIP_TRY(launch_check_input(n, nnz, offsets, indices, w, s));
+    DevPlan hp{};
+    int st = read_plan(w, hp, s);
+    if (st) return st;
+    if ((st = status_from_err(hp.err))) return st;
+
+    // 2. degree ranking, relabelled CSR, work counts, tiers
+    FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
+    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan), s));
+    i64 g_total = 0;
+    if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
+    if ((st = read_plan(w, hp, s))) return st;
+    if ((st = status_from_err(hp.err))) return st;
+    if (2 * hp.sum_lo != nnz) return FGLT_ENOTCANON;  // every entry below the diagonal has its mirror
+    hp.tri_items = g_total - hp.wedge_items;
+
+    // 3. counting
+    FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
+    if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
+    FGLT_HIP_TRY(launch_l1(n, nnz, w, s));
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, s));
+    FGLT_HIP_TRY(launch_fill_c3(nnz, w, s));
+    FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, s));
+    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s));
+    FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
+
+    if (stats) {
+        stats->d_max = hp.d_max;
+        stats->dplus_max = hp.dplus_max;
+        stats->tri_items = hp.tri_items;
+        stats->wedge_items = hp.wedge_items;
+        stats->n_light_tri = hp.n_tri[0];
+        stats->n_mid_tri = hp.n_tri[1];
+        stats->n_heavy_tri = hp.n_tri[2];
+        stats->n_light_c4 = hp.n_c4[0];
+        stats->n_mid_c4 = hp.n_c4[1];
+        stats->n_heavy_c4 = hp.n_c4[2];
+    }
+    return FGLT_OK;
+}
+
+extern "C" int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return FGLT_EINVAL;
+    if (n == 0) return FGLT_OK;
+    if (!raw || !net) return FGLT_EINVAL;
+    FGLT_HIP_TRY(launch_net(n, raw, net, (hipStream_t)stream));
+    return FGLT_OK;
+}
+
+extern "C" const char* fglt_status_string(int status) {
+    switch (status) {
+        case FGLT_OK: return "ok";
+        case FGLT_EINVAL: return "invalid argument";
+        case FGLT_ENOTCANON: return "CSR is not canonical (symmetric, no self-loops, no repeated entries)";
+        case FGLT_EWORKSPACE: return "workspace too small";
+        case FGLT_EOVERFLOW: return "a degree is >= 2^21; counts could overflow int64";
+        case FGLT_EHIP: return "HIP runtime error";
+        case FGLT_EUNSUPPORTED: return "unsupported input for this path";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int fglt_version(void) { return 1; }

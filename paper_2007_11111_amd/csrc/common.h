@@ -1,0 +1,153 @@
+// common.h -- internal helpers shared by the HIP sources of libfglt.
+// Written for gfx950 (CDNA4): 64-lane wavefronts, 160 KiB LDS per workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fglt.h"
+
+typedef int64_t i64;
+typedef int32_t i32;
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+#define WAVE 64
+
+#define FGLT_HIP_TRY(expr)                          \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return FGLT_EHIP;     \
+    } while (0)
+
+#define FGLT_LAUNCH_CHECK()                                   \
+    do {                                                      \
+        if (hipGetLastError() != hipSuccess) return FGLT_EHIP; \
+    } while (0)
+
+// Error bits written by device-side checks into a status word.
+enum : u32 {
+    ERR_RANGE = 1u,      // an index or offset out of range
+    ERR_SELFLOOP = 2u,   // a self-loop
+    ERR_DUP = 4u,        // a repeated entry in a row
+    ERR_ASYM = 8u,       // an entry (i, j) without (j, i)
+    ERR_DEGREE = 16u,    // a degree >= 2^21
+};
+
+static inline i64 ceil_div(i64 a, i64 b) { return (a + b - 1) / b; }
+static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Linear allocator over a caller-provided workspace (256-byte aligned pieces).
+struct Carver {
+    char* base;
+    size_t cap, used;
+    explicit Carver(void* b, size_t c) : base((char*)b), cap(c), used(0) {}
+    template <class T>
+    T* take(i64 count) {
+        size_t bytes = align_up(sizeof(T) * (size_t)(count > 0 ? count : 1), 256);
+        if (base == nullptr) {  // size query
+            used += bytes;
+            return nullptr;
+        }
+        if (used + bytes > cap) {
+            used += bytes;
+            return nullptr;
+        }
+        T* p = (T*)(base + used);
+        used += bytes;
+        return p;
+    }
+    bool ok() const { return base != nullptr && used <= cap; }
+};
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+__device__ __forceinline__ u64 lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ i64 wave_sum(i64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ i64 wave_max(i64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        i64 w = __shfl_xor(v, o, WAVE);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// First index q in [lo, hi) with a[q] >= key (hi if none).
+template <class T, class K>
+__device__ __forceinline__ i64 lower_bound_dev(const T* a, i64 lo, i64 hi, K key) {
+    while (lo < hi) {
+        i64 mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Last index r in [lo, hi] with a[r] <= key (lo - 1 if none).
+template <class T, class K>
+__device__ __forceinline__ i64 last_le_dev(const T* a, i64 lo, i64 hi, K key) {
+    i64 l = lo, h = hi + 1;  // search first index with a[idx] > key in [lo, hi+1)
+    while (l < h) {
+        i64 mid = l + ((h - l) >> 1);
+        if (a[mid] <= key) l = mid + 1;
+        else h = mid;
+    }
+    return l - 1;
+}
+
+// Row r of a CSR entry p: roff[r] <= p < roff[r+1], searched in [rlo, rhi].
+__device__ __forceinline__ i64 row_of(const i64* roff, i64 rlo, i64 rhi, i64 p) {
+    return last_le_dev(roff, rlo, rhi, p);
+}
+
+// Inclusive segmented sum across a wave: lanes with equal `key` that are
+// contiguous form one segment; returns the running sum within the segment.
+__device__ __forceinline__ i64 wave_seg_scan(i64 v, i64 key) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        i64 u = __shfl_up(v, o, WAVE);
+        i64 k = __shfl_up(key, o, WAVE);
+        if (l >= o && k == key) v += u;
+    }
+    return v;
+}
+
+// True on the last lane of each contiguous run of equal keys.
+__device__ __forceinline__ bool wave_seg_tail(i64 key, bool active) {
+    const int l = lane_id();
+    i64 next = __shfl_down(key, 1, WAVE);
+    int next_active = __shfl_down((int)active, 1, WAVE);
+    return active && (l == WAVE - 1 || !next_active || next != key);
+}
+
+// ---------------------------------------------------------------- host launch helpers
+
+namespace fglt {
+
+hipError_t scan_exclusive_i64(const i64* in, i64* out, i64 count, i64* partials, hipStream_t s);
+hipError_t scan_exclusive_i32_to_i64(const i32* in, i64* out, i64 count, i64* partials, hipStream_t s);
+i64 scan_partials_size(i64 count);
+
+struct SegSortWs {
+    i32* tmp;       // [max total keys]
+    i32* lists;     // [3 * max segments]
+    u32* counters;  // [4]
+};
+hipError_t seg_sort(i32* keys, const i64* seg_off, i64 nseg, int key_bits, SegSortWs ws,
+                    i64 max_seg_grid, hipStream_t s);
+
+}  // namespace fglt

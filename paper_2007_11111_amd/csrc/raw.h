@@ -1,0 +1,104 @@
+// raw.h -- internal interface of the single-graph transform pipeline.
+//
+// All counting runs in "rank space": vertices relabelled by non-decreasing
+// degree (ties by original id), rows re-sorted.  In rank space the degree
+// orientation u -> v (v > u) of the triangle and clique passes is "later in
+// the row", every row splits into N-(u) (entries < u) followed by N+(u)
+// (entries > u), and the 4-cycle pass can stop each wedge scan at u.
+#pragma once
+
+#include "common.h"
+
+namespace fglt {
+
+// Tier thresholds.
+constexpr int TRI_WAVE_MAX = 64;     // out-degree handled by one wavefront (one bitmap word)
+constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup's LDS
+constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
+constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
+constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
+constexpr int NUM_C4_SLOTS = 128;    // dense counter arrays of the heavy 4-cycle tier
+
+// Device statistics / plan words (one small block of device memory).
+struct DevPlan {
+    u32 err;
+    u32 pad0;
+    i64 d_max;
+    i64 dplus_max;
+    i64 sum_lo;
+    i64 tri_items;
+    i64 wedge_items;
+    u32 n_tri[3];  // wave, lds, global tiers
+    u32 n_c4[3];   // wave, block, heavy tiers
+};
+
+struct RawWs {
+    // rank space structure
+    i32* deg;     // [n] degrees, original order
+    i32* perm;    // [n] rank -> original id
+    i32* rank;    // [n] original id -> rank
+    i32* rdeg;    // [n] degree by rank
+    i32* lo;      // [n] |N-(u)|
+    i64* cntd;    // [n+2] degree histogram, then bucket starts
+    i32* cursor;  // [n+2]
+    i64* roff;    // [n+1]
+    i32* ridx;    // [nnz]
+    i32* rpos;    // [nnz] position of u in row v for N- entries, -1 for N+
+    i64* G;       // [nnz+1] exclusive scan of per-entry work counts
+    i32* C3;      // [nnz] triangle count per directed entry
+    // per-vertex accumulators (rank space), contiguous block of 10*n
+    i64* acc;
+    i64 *sumd, *s7, *c3v, *ap2, *ac3, *d10, *d14, *d13, *c4v, *k4v;
+    // work lists
+    i32* tri_list;  // [3][n]
+    i32* c4_list;   // [3][n]
+    // heavy-tier scratch
+    u64* tri_slots;     // NUM_TRI_SLOTS * tri_slot_words
+    i64 tri_slot_words;
+    i32* c4_cnt;        // NUM_C4_SLOTS * n
+    i32* c4_touched;    // NUM_C4_SLOTS * n
+    // scratch
+    i64* partials;
+    SegSortWs sort;
+    DevPlan* plan;
+};
+
+RawWs carve_raw(Carver& c, i64 n, i64 nnz);
+
+// prep (raw_prep.hip)
+hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s);
+hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
+                                   hipStream_t s);
+struct Tiers {
+    i64 tri_wave, tri_lds, c4_wave, c4_block;
+};
+Tiers tiers_from_plan(const fglt_raw_plan* plan);
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, hipStream_t s);
+
+// counting (raw_count.hip)
+hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s);
+hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s);
+hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
+hipError_t launch_net(i64 n, const i64* raw, i64* net, hipStream_t s);
+
+// Conversion raw -> net (Table II): back-substitution with U16.
+__device__ __forceinline__ void raw_to_net16(i64* f) {
+    // f arrives holding raw counts; solve U16 f = raw from the last row up.
+    f[14] -= 3 * f[15];
+    f[13] -= 3 * f[15];
+    f[12] -= f[13] + f[14] + 3 * f[15];
+    f[11] -= 2 * f[14] + 3 * f[15];
+    f[10] -= 2 * f[13] + 2 * f[14] + 6 * f[15];
+    f[9] -= 2 * f[13] + 3 * f[15];
+    f[8] -= f[11] + f[14] + f[15];
+    f[7] -= f[9] + f[10] + 2 * f[13] + f[14] + 3 * f[15];
+    f[6] -= f[10] + 2 * f[11] + 2 * f[12] + 2 * f[13] + 4 * f[14] + 6 * f[15];
+    f[5] -= 2 * f[9] + f[10] + 2 * f[12] + 4 * f[13] + 2 * f[14] + 6 * f[15];
+    f[3] -= f[4];
+    f[2] -= 2 * f[4];
+}
+
+}  // namespace fglt

@@ -1,0 +1,362 @@
+// raw_prep.hip -- input checks, degree ranking, relabelled CSR and the
+// per-entry work counts that drive the counting passes.
+#include <algorithm>
+
+#include "raw.h"
+
+namespace fglt {
+
+static constexpr int PT = 256;  // threads per block for the simple kernels
+
+static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
+    return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(work, 1), per_block), cap));
+}
+
+static int bits_for(i64 maxval) {
+    int b = 0;
+    while (b < 31 && (((i64)1 << b) <= maxval)) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------ input checks
+
+__global__ void k_check_offsets(const i64* __restrict__ off, i64 n, i64 nnz, i32* __restrict__ deg,
+                                DevPlan* plan) {
+    i64 dmax = 0;
+    u32 err = 0;
+    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
+        const i64 a = off[r], b = off[r + 1];
+        i64 d = b - a;
+        if (d < 0 || a < 0 || b > nnz) {
+            err |= ERR_RANGE;
+            d = 0;
+        }
+        if (d >= FGLT_MAX_DEGREE) {
+            err |= ERR_DEGREE;
+            d = 0;
+        }
+        deg[r] = (i32)d;
+        dmax = d > dmax ? d : dmax;
+    }
+    if ((i64)blockIdx.x * blockDim.x + threadIdx.x == 0) {
+        if (off[0] != 0 || off[n] != nnz) err |= ERR_RANGE;
+    }
+    dmax = wave_max(dmax);
+    if (lane_id() == 0 && dmax > 0) atomicMax((unsigned long long*)&plan->d_max, (unsigned long long)dmax);
+    if (err) atomicOr(&plan->err, err);
+}
+
+__global__ void k_check_indices(const i32* __restrict__ idx, i64 nnz, i64 n, DevPlan* plan) {
+    u32 err = 0;
+    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
+        const i32 v = idx[p];
+        if (v < 0 || (i64)v >= n) err |= ERR_RANGE;
+    }
+    if (err) atomicOr(&plan->err, err);
+}
+
+hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(w.plan, 0, sizeof(DevPlan), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n, PT, 4096)), dim3(PT), 0, s, off, n, nnz, w.deg, w.plan);
+    if (nnz > 0) hipLaunchKernelGGL(k_check_indices, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, idx, nnz, n, w.plan);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ degree ranking
+
+static constexpr int PRIV = 1024;  // degrees below this use block-private counters
+
+__global__ void __launch_bounds__(PT) k_deg_hist(const i32* __restrict__ deg, i64 n, i64* __restrict__ cntd) {
+    __shared__ u32 lc[PRIV];
+    for (int t = threadIdx.x; t < PRIV; t += blockDim.x) lc[t] = 0;
+    __syncthreads();
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const i32 d = deg[i];
+        if (d < PRIV) atomicAdd(&lc[d], 1u);
+        else atomicAdd((unsigned long long*)&cntd[d], 1ull);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < PRIV; t += blockDim.x)
+        if (lc[t]) atomicAdd((unsigned long long*)&cntd[t], (unsigned long long)lc[t]);
+}
+
+// perm[bstart[d] + k] = vertex, k unique within bucket d (order fixed later by a sort)
+static constexpr int SCAT_ITEMS = 8;
+__global__ void __launch_bounds__(PT) k_deg_scatter(const i32* __restrict__ deg, i64 n,
+                                                    const i64* __restrict__ bstart, i32* __restrict__ cursor,
+                                                    i32* __restrict__ perm) {
+    __shared__ u32 lc[PRIV];
+    __shared__ u32 lbase[PRIV];
+    for (int t = threadIdx.x; t < PRIV; t += blockDim.x) lc[t] = 0;
+    __syncthreads();
+    const i64 base = (i64)blockIdx.x * PT * SCAT_ITEMS;
+    u32 li[SCAT_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SCAT_ITEMS; ++k) {
+        const i64 i = base + (i64)k * PT + threadIdx.x;
+        li[k] = 0;
+        if (i < n) {
+            const i32 d = deg[i];
+            if (d < PRIV) li[k] = atomicAdd(&lc[d], 1u);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < PRIV; t += blockDim.x)
+        if (lc[t]) lbase[t] = (u32)atomicAdd(&cursor[t], (i32)lc[t]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAT_ITEMS; ++k) {
+        const i64 i = base + (i64)k * PT + threadIdx.x;
+        if (i < n) {
+            const i32 d = deg[i];
+            i64 pos;
+            if (d < PRIV) pos = bstart[d] + lbase[d] + li[k];
+            else pos = bstart[d] + atomicAdd(&cursor[d], 1);
+            perm[pos] = (i32)i;
+        }
+    }
+}
+
+__global__ void k_rank(const i32* __restrict__ perm, const i32* __restrict__ deg, i64 n, i32* __restrict__ rank,
+                       i32* __restrict__ rdeg) {
+    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
+        const i32 i = perm[r];
+        rank[i] = (i32)r;
+        rdeg[r] = deg[i];
+    }
+}
+
+// ridx[q] = rank[idx[off[perm[r]] + (q - roff[r])]] for q in row r of rank space.
+__global__ void k_relabel_copy(const i64* __restrict__ off, const i32* __restrict__ idx,
+                               const i32* __restrict__ perm, const i32* __restrict__ rank,
+                               const i64* __restrict__ roff, i64 n, i64 nnz, i32* __restrict__ ridx) {
+    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
+        const i64 p0 = wv * WAVE;
+        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
+        const i64 r0 = row_of(roff, 0, n - 1, p0);
+        const i64 r1 = row_of(roff, r0, n - 1, pl);
+        const i64 q = p0 + lane_id();
+        if (q < nnz) {
+            const i64 r = row_of(roff, r0, r1, q);
+            const i64 src = off[perm[r]] + (q - roff[r]);
+            ridx[q] = rank[idx[src]];
+        }
+    }
+}
+
+hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
+                                   hipStream_t s) {
+    hipError_t e;
+    const i64 nb = d_max + 1;  // degree buckets 0..d_max
+    if ((e = hipMemsetAsync(w.cntd, 0, sizeof(i64) * (size_t)(nb + 1), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(w.cursor, 0, sizeof(i32) * (size_t)(nb + 1), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_deg_hist, dim3(grid_for(n, PT, 2048)), dim3(PT), 0, s, w.deg, n, w.cntd);
+    if ((e = scan_exclusive_i64(w.cntd, w.cntd, nb, w.partials, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_deg_scatter, dim3(grid_for(n, PT * SCAT_ITEMS, 1 << 30)), dim3(PT), 0, s, w.deg, n,
+                       w.cntd, w.cursor, w.perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // deterministic order inside each degree bucket: ascending original id
+    if ((e = seg_sort(w.perm, w.cntd, nb, bits_for(n - 1), w.sort, 65536, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.perm, w.deg, n, w.rank, w.rdeg);
+    if ((e = scan_exclusive_i32_to_i64(w.rdeg, w.roff, n, w.partials, s)) != hipSuccess) return e;
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_relabel_copy, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, off, idx, w.perm, w.rank,
+                           w.roff, n, nnz, w.ridx);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = seg_sort(w.ridx, w.roff, n, bits_for(n - 1), w.sort, 65536, s)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ structure
+
+// lo[u] = |N-(u)| (entries < u); self-loop check; sum of lo.
+__global__ void k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i32* __restrict__ lo,
+                     DevPlan* plan) {
+    i64 sum = 0;
+    u32 err = 0;
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
+        const i64 b = roff[u], e = roff[u + 1];
+        const i64 q = lower_bound_dev(ridx, b, e, (i32)u);
+        if (q < e && ridx[q] == (i32)u) err |= ERR_SELFLOOP;
+        lo[u] = (i32)(q - b);
+        sum += q - b;
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)&plan->sum_lo, (unsigned long long)sum);
+    if (err) atomicOr(&plan->err, err);
+}
+
+// rpos / work count per entry; duplicate and symmetry checks.
+//   N- entry (u, v), v < u: rpos = position of u in row v (= number of
+//     neighbours of v below u, the wedge count of the 4-cycle pass);
+//   N+ entry (u, v), v > u: rpos = -1, work = d+(v) (the triangle pass).
+__global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ lo,
+                       const i32* __restrict__ rdeg, i64 n, i64 nnz, i32* __restrict__ rpos, i64* __restrict__ G,
+                       DevPlan* plan) {
+    u32 err = 0;
+    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
+        const i64 p0 = wv * WAVE;
+        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
+        const i64 r0 = row_of(roff, 0, n - 1, p0);
+        const i64 r1 = row_of(roff, r0, n - 1, pl);
+        const i64 p = p0 + lane_id();
+        if (p < nnz) {
+            const i64 u = row_of(roff, r0, r1, p);
+            const i32 v = ridx[p];
+            if (p > roff[u] && ridx[p - 1] == v) err |= ERR_DUP;
+            i32 rp = -1;
+            i64 work = 0;
+            if ((i64)v < u) {
+                const i64 b = roff[v] + lo[v], e = roff[v + 1];
+                const i64 q = lower_bound_dev(ridx, b, e, (i32)u);
+                if (q < e && ridx[q] == (i32)u) {
+                    rp = (i32)(q - roff[v]);
+                    work = rp;
+                } else {
+                    err |= ERR_ASYM;
+                    rp = 0;  // harmless: no wedges, no C3 read
+                    work = 0;
+                }
+            } else if ((i64)v > u) {
+                work = rdeg[v] - lo[v];
+            }
+            rpos[p] = rp;
+            G[p] = work;
+        }
+    }
+    if (err) atomicOr(&plan->err, err);
+}
+
+// Tier lists and statistics from the work counts (G holds the exclusive scan).
+__global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo, const i32* __restrict__ rdeg,
+                        const i64* __restrict__ G, i64 n, Tiers th, i32* __restrict__ tri_list,
+                        i32* __restrict__ c4_list, DevPlan* plan) {
+    i64 dpmax = 0;
+    for (i64 u0 = (i64)blockIdx.x * blockDim.x; u0 < n; u0 += (i64)gridDim.x * blockDim.x) {
+        const i64 u = u0 + threadIdx.x;
+        int tcls = -1, ccls = -1;
+        if (u < n) {
+            const i64 b = roff[u], m = roff[u] + lo[u], e = roff[u + 1];
+            const i64 D = e - m;
+            const i64 W = G[m] - G[b];
+            dpmax = D > dpmax ? D : dpmax;
+            if (D >= 2) tcls = D <= th.tri_wave ? 0 : (D <= th.tri_lds ? 1 : 2);
+            if (W > 0) ccls = W <= th.c4_wave ? 0 : (W <= th.c4_block ? 1 : 2);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u64 m = __ballot(tcls == c);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                u32 base = 0;
+                if (lane_id() == leader) base = atomicAdd(&plan->n_tri[c], (u32)__popcll(m));
+                base = __shfl(base, leader, WAVE);
+                if (tcls == c) tri_list[(i64)c * n + base + __popcll(m & lanemask_lt())] = (i32)u;
+            }
+            m = __ballot(ccls == c);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                u32 base = 0;
+                if (lane_id() == leader) base = atomicAdd(&plan->n_c4[c], (u32)__popcll(m));
+                base = __shfl(base, leader, WAVE);
+                if (ccls == c) c4_list[(i64)c * n + base + __popcll(m & lanemask_lt())] = (i32)u;
+            }
+        }
+    }
+    dpmax = wave_max(dpmax);
+    if (lane_id() == 0 && dpmax > 0)
+        atomicMax((unsigned long long*)&plan->dplus_max, (unsigned long long)dpmax);
+}
+
+__global__ void k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo, const i64* __restrict__ G,
+                         i64 n, i64 nnz, DevPlan* plan) {
+    i64 wedges = 0;
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x)
+        wedges += G[roff[u] + lo[u]] - G[roff[u]];
+    wedges = wave_sum(wedges);
+    if (lane_id() == 0 && wedges) atomicAdd((unsigned long long*)&plan->wedge_items, (unsigned long long)wedges);
+}
+
+Tiers tiers_from_plan(const fglt_raw_plan* plan) {
+    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX};
+    if (plan) {
+        if (plan->tri_wave_max > 0) t.tri_wave = std::min<i64>(plan->tri_wave_max, TRI_WAVE_MAX);
+        if (plan->tri_lds_max > 0) t.tri_lds = std::min<i64>(plan->tri_lds_max, TRI_LDS_MAX);
+        if (plan->c4_wave_max > 0) t.c4_wave = std::min<i64>(plan->c4_wave_max, C4_WAVE_MAX);
+        if (plan->c4_wave_max < 0) t.c4_wave = 0;
+        if (plan->c4_block_max > 0) t.c4_block = std::min<i64>(plan->c4_block_max, C4_BLOCK_MAX);
+        if (plan->c4_block_max < 0) t.c4_block = 0;
+    }
+    t.tri_lds = std::max(t.tri_lds, t.tri_wave);
+    t.c4_block = std::max(t.c4_block, t.c4_wave);
+    return t;
+}
+
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream_t s) {
+    hipError_t e;
+    hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 8192)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.plan);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, n,
+                           nnz, w.rpos, w.G, w.plan);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_exclusive_i64(w.G, w.G, nnz, w.partials, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, PT, 8192)), dim3(PT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
+                       w.tri_list, w.c4_list, w.plan);
+    hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 4096)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ workspace layout
+
+RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
+    RawWs w{};
+    const i64 nn = std::max<i64>(n, 1);
+    w.plan = c.take<DevPlan>(1);
+    w.deg = c.take<i32>(nn);
+    w.perm = c.take<i32>(nn);
+    w.rank = c.take<i32>(nn);
+    w.rdeg = c.take<i32>(nn);
+    w.lo = c.take<i32>(nn);
+    w.cntd = c.take<i64>(nn + 2);
+    w.cursor = c.take<i32>(nn + 2);
+    w.roff = c.take<i64>(nn + 1);
+    w.ridx = c.take<i32>(nnz);
+    w.rpos = c.take<i32>(nnz);
+    w.G = c.take<i64>(nnz + 1);
+    w.C3 = c.take<i32>(nnz);
+    w.acc = c.take<i64>(10 * nn);
+    if (w.acc) {
+        w.sumd = w.acc + 0 * nn;
+        w.s7 = w.acc + 1 * nn;
+        w.c3v = w.acc + 2 * nn;
+        w.ap2 = w.acc + 3 * nn;
+        w.ac3 = w.acc + 4 * nn;
+        w.d10 = w.acc + 5 * nn;
+        w.d14 = w.acc + 6 * nn;
+        w.d13 = w.acc + 7 * nn;
+        w.c4v = w.acc + 8 * nn;
+        w.k4v = w.acc + 9 * nn;
+    }
+    w.tri_list = c.take<i32>(3 * nn);
+    w.c4_list = c.take<i32>(3 * nn);
+    // out-degree under the degree ordering is at most sqrt(nnz): two bitmaps
+    // of D x ceil(D/64) words plus per-row lists fit in tri_slot_words.
+    i64 dmax_plus = 1;
+    while (dmax_plus * dmax_plus <= nnz) ++dmax_plus;
+    const i64 words_per_row = ceil_div(dmax_plus, 64);
+    w.tri_slot_words = 2 * dmax_plus * words_per_row + 4 * dmax_plus + 64;
+    w.tri_slots = c.take<u64>(NUM_TRI_SLOTS * w.tri_slot_words);
+    w.c4_cnt = c.take<i32>((i64)NUM_C4_SLOTS * nn);
+    w.c4_touched = c.take<i32>((i64)NUM_C4_SLOTS * nn);
+    w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
+    w.sort.tmp = c.take<i32>(std::max(nnz, nn));
+    w.sort.lists = c.take<i32>(3 * (nn + 2));
+    w.sort.counters = c.take<u32>(4);
+    return w;
+}
+
+}  // namespace fglt

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Every comparison is exact int64 equality.  Tier plans force every vertex
+through each kernel tier on small graphs, so each tier is checked against the
+oracle, not only the tiers a graph would pick by itself.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from tests._util import csr_arrays, say
+
+pytestmark = pytest.mark.gpu
+
+C = math.comb
+
+# Tier plans: default; everything in the wave tiers where allowed; everything
+# in the LDS/workgroup tiers; everything in the global-memory / heavy tiers.
+PLANS = {
+    "default": None,
+    "wave": {"tri_wave_max": 64, "tri_lds_max": 64, "c4_wave_max": 128, "c4_block_max": 128},
+    "block": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": 2048},
+    "global": {"tri_wave_max": 1, "tri_lds_max": 1, "c4_wave_max": -1, "c4_block_max": -1},
+}
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import paper_2007_11111_amd as fg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fg._lib.lib()
+    return fg
+
+
+def to_dev(off, idx):
+    return (torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda())
+
+
+def gpu_raw(fg, off, idx, plan=None, net=False):
+    o, i = to_dev(off, idx)
+    out = fg.raw(o, i, net=net, plan=plan)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------ CSR build
+
+@pytest.mark.parametrize("case", ["empty", "one", "loops_dups", "er", "cl"])
+def test_build_csr_matches_oracle(fg, case):
+    rng = np.random.default_rng(5)
+    if case == "empty":
+        n, src, dst = 0, np.zeros(0, np.int32), np.zeros(0, np.int32)
+    elif case == "one":
+        n, src, dst = 1, np.zeros(3, np.int32), np.zeros(3, np.int32)
+    elif case == "loops_dups":
+        n = 50
+        src = rng.integers(0, n, 3000).astype(np.int32)
+        dst = rng.integers(0, n, 3000).astype(np.int32)
+    elif case == "er":
+        g = graphgen.erdos_renyi(2000, 0.005, seed=1)
+        n, src, dst = g.n, g.src, g.dst
+    else:
+        g = graphgen.chung_lu(60_000, 2.1, 20.0, 3000.0, seed=2)
+        n, src, dst = g.n, g.src, g.dst
+    say(f"build_csr case={case} n={n} pairs={src.size}")
+    off_e, idx_e = oracle.canonical_csr(n, src, dst)
+    o, i = fg.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o.cpu().numpy(), off_e)
+    np.testing.assert_array_equal(i.cpu().numpy(), idx_e)
+
+
+def test_build_csr_rejects_out_of_range(fg):
+    src = torch.tensor([0, 1, 7], dtype=torch.int32).cuda()
+    dst = torch.tensor([1, 2, 0], dtype=torch.int32).cuda()
+    with pytest.raises(fg.FgltError):
+        fg.build_csr(5, src, dst)
+
+
+# ------------------------------------------------------------------ worked example
+
+@pytest.mark.parametrize("plan", list(PLANS))
+def test_fig2(fg, fig2, plan):
+    say(f"fig2 plan={plan}")
+    off, idx = csr_arrays(fig2["n"], fig2["edges"])
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan]), fig2["raw"])
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), fig2["net"])
+
+
+# ------------------------------------------------------------------ small random graphs, every tier
+
+def _small_graphs():
+    rng = np.random.default_rng(2024)
+    out = [(1, []), (2, [(0, 1)]), (7, []), (6, [(0, 1), (1, 2), (0, 2), (3, 4), (4, 5), (3, 5)])]
+    for _ in range(30):
+        n = int(rng.integers(3, 60))
+        p = float(rng.choice([0.05, 0.1, 0.3, 0.6, 0.9]))
+        out.append((n, [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]))
+    return out
+
+
+@pytest.mark.parametrize("plan", list(PLANS))
+def test_small_random_all_tiers(fg, plan):
+    for gi, (n, edges) in enumerate(_small_graphs()):
+        say(f"small graph {gi} n={n} m={len(edges)} plan={plan}")
+        off, idx = csr_arrays(n, edges)
+        exp = oracle.raw(off, idx)
+        got = gpu_raw(fg, off, idx, PLANS[plan])
+        np.testing.assert_array_equal(got, exp, err_msg=f"graph {gi}")
+        np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), oracle.raw_to_net(exp))
+
+
+# ------------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600])
+def test_clique(fg, n):
+    """K_n: out-degree n-1 of the lowest vertex (600 reaches the global-bitmap
+    tier, and the top vertex's (n-1)(n-2) wedges the heavy 4-cycle tier)."""
+    g = graphgen.clique(n)
+    say(f"clique n={n}")
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = gpu_raw(fg, off, idx, net=True)
+    exp = np.zeros(16, dtype=np.int64)
+    exp[0], exp[1], exp[4], exp[15] = 1, n - 1, C(n - 1, 2), C(n - 1, 3)
+    np.testing.assert_array_equal(f, np.tile(exp, (n, 1)))
+    r = gpu_raw(fg, off, idx)
+    a, b, c = n - 1, max(n - 2, 0), max(n - 3, 0)
+    exp_raw = [1, a, a * b, C(a, 2), C(a, 2), a * b * c, a * b * c, a * C(b, 2), C(a, 3),
+               c * C(a, 2), a * b * c, c * C(a, 2), a * C(b, 2), c * C(a, 2), a * C(b, 2), C(a, 3)]
+    np.testing.assert_array_equal(r, np.tile(np.array(exp_raw, dtype=np.int64), (n, 1)))
+
+
+@pytest.mark.parametrize("k", [1, 5, 3000])
+def test_star(fg, k):
+    g = graphgen.star(k)
+    say(f"star k={k}")
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = gpu_raw(fg, off, idx, net=True)
+    centre = np.zeros(16, dtype=np.int64)
+    centre[[0, 1, 3, 8]] = [1, k, C(k, 2), C(k, 3)]
+    leaf = np.zeros(16, dtype=np.int64)
+    leaf[[0, 1, 2, 7]] = [1, 1, k - 1, C(k - 1, 2)]
+    np.testing.assert_array_equal(f[0], centre)
+    np.testing.assert_array_equal(f[1:], np.tile(leaf, (k, 1)))
+
+
+@pytest.mark.parametrize("n", [4, 5, 1000])
+def test_cycle_and_path(fg, n):
+    say(f"cycle/path n={n}")
+    g = graphgen.cycle(n)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, net=True), oracle.net(off, idx))
+    g = graphgen.path(n)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, net=True), oracle.net(off, idx))
+
+
+# ------------------------------------------------------------------ the small config and medium graphs
+
+def test_er_config(fg):
+    """Erdos-Renyi G(2000, 0.005), seed 1: every vertex, raw and net."""
+    g = graphgen.erdos_renyi(2000, 0.005, seed=1)
+    say("er config")
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    exp = oracle.raw(off, idx)
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx), exp)
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, net=True), oracle.raw_to_net(exp))
+
+
+@pytest.mark.parametrize("plan", list(PLANS))
+def test_chung_lu_medium(fg, plan):
+    """A 20k-vertex power-law graph (hubs, ragged rows, many tiles)."""
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say(f"chung-lu medium plan={plan} nnz={idx.size}")
+    exp = oracle.net(off, idx)
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), exp)
+
+
+def test_barabasi_albert_and_rmat_small(fg):
+    for name, g in [("ba", graphgen.barabasi_albert(5000, 4, seed=8)),
+                    ("rmat12", graphgen.rmat(12, 16, 0.57, 0.19, 0.19, seed=9))]:
+        off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+        say(f"{name} n={g.n} nnz={idx.size}")
+        np.testing.assert_array_equal(gpu_raw(fg, off, idx, net=True), oracle.net(off, idx))
+
+
+# ------------------------------------------------------------------ properties
+
+def test_net_entry_point(fg):
+    g = graphgen.chung_lu(5000, 2.3, 12.0, 500.0, seed=10)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say("fglt_net separate vs fused")
+    o, i = to_dev(off, idx)
+    r = fg.raw(o, i)
+    f_sep = fg.net(r)
+    f_fused = fg.raw(o, i, net=True)
+    inplace = r.clone()
+    fg.net(inplace, out=inplace)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(f_sep.cpu().numpy(), f_fused.cpu().numpy())
+    np.testing.assert_array_equal(inplace.cpu().numpy(), f_fused.cpu().numpy())
+    exp_raw = oracle.raw(off, idx)
+    np.testing.assert_array_equal(fg.net(torch.from_numpy(exp_raw).cuda()).cpu().numpy(), oracle.raw_to_net(exp_raw))
+
+
+def test_permutation_and_determinism(fg):
+    g = graphgen.chung_lu(8000, 2.1, 14.0, 800.0, seed=11)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say("permutation equivariance and reruns")
+    f = gpu_raw(fg, off, idx, net=True)
+    for _ in range(3):
+        np.testing.assert_array_equal(gpu_raw(fg, off, idx, net=True), f)
+    perm = np.random.default_rng(1).permutation(g.n)
+    off2, idx2 = oracle.canonical_csr(g.n, perm[g.src], perm[g.dst])
+    np.testing.assert_array_equal(gpu_raw(fg, off2, idx2, net=True)[perm], f)
+
+
+# ------------------------------------------------------------------ contract violations
+
+def _status(fg, off, idx):
+    o, i = to_dev(off, idx)
+    n = off.size - 1
+    out = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+    try:
+        fg.raw(o, i, out=out)
+        return 0
+    except fg.FgltError as e:
+        return e.status
+
+
+def test_errors(fg):
+    say("contract violations")
+    off, idx = csr_arrays(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    assert _status(fg, off, idx) == 0
+    # asymmetric: drop the entry (1 -> 0)
+    o2 = off.copy()
+    keep = [k for k in range(idx.size) if not (off[1] <= k < off[2] and idx[k] == 0)]
+    bad_idx = idx[keep]
+    o2[2:] -= 1
+    assert _status(fg, o2, bad_idx) == -2
+    # self-loop added symmetrically on vertex 4 (appended to its row)
+    sl_idx = np.concatenate([idx, [4]]).astype(np.int32)
+    sl_off = off.copy()
+    sl_off[5] += 1
+    assert _status(fg, sl_off, sl_idx) == -2
+    # a repeated entry on both sides: (0,1) twice
+    d_idx = np.insert(idx, off[1], 1).astype(np.int32)
+    d_off = off.copy()
+    d_off[1:] += 1
+    d_idx = np.insert(d_idx, d_off[1], 0).astype(np.int32)
+    d_off[2:] += 1
+    assert _status(fg, d_off, d_idx) == -2
+    # an index out of range
+    r_idx = idx.copy()
+    r_idx[0] = 99
+    assert _status(fg, off, r_idx) == -2
+    # offsets not monotone
+    m_off = off.copy()
+    m_off[2] = m_off[3] + 1
+    assert _status(fg, m_off, idx) == -2
+    # workspace too small, straight through the C ABI (the binding would grow it)
+    import ctypes
+    o, i = to_dev(off, idx)
+    out = torch.empty((5, 16), dtype=torch.int64, device="cuda")
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    L = fg._lib.lib()
+    st = L.fglt_raw(5, int(i.numel()), ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(i.data_ptr()),
+                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), 64, 0, None, None,
+                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == -3
+    # all isolated
+    assert _status(fg, np.zeros(11, np.int64), np.zeros(0, np.int32)) == 0
+    f = gpu_raw(fg, np.zeros(11, np.int64), np.zeros(0, np.int32), net=True)
+    exp = np.zeros((10, 16), np.int64)
+    exp[:, 0] = 1
+    np.testing.assert_array_equal(f, exp)
