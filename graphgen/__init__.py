@@ -273,3 +273,30 @@ def cycle(n: int) -> EdgeList:
 def path(n: int) -> EdgeList:
     i = np.arange(max(0, n - 1))
     return _el(n, i, i + 1, f"P{n}")
+
+
+# Named workloads (generator parameters only).  Seeds: ER 1, Chung-Lu 2,
+# R-MAT 3, batch 4, serving 5.
+def make(name: str):
+    """The synthetic stand-in for a named workload.
+
+    er       G(n=2000, p=0.005)
+    cl       Chung-Lu, n = 1,000,000, degree exponent 2.1, mean degree 20, cap 50,000
+    rmat22   R-MAT scale 22, edge factor 16, (0.57, 0.19, 0.19, 0.05), ids permuted
+    rmat18   the same recipe at scale 18 (a size the oracle finishes in minutes)
+    cl_small Chung-Lu, n = 100,000, exponent 2.1, mean 20, cap 5,000
+    batch    4096 graphs, n ~ U{16..512}, half ER (mean degree U[2,12]), half BA (m U{1..5})
+    """
+    if name == "er":
+        return erdos_renyi(2000, 0.005, seed=1)
+    if name == "cl":
+        return chung_lu(1_000_000, 2.1, 20.0, 50_000.0, seed=2)
+    if name == "cl_small":
+        return chung_lu(100_000, 2.1, 20.0, 5_000.0, seed=2, stream=1)
+    if name == "rmat22":
+        return rmat(22, 16, 0.57, 0.19, 0.19, seed=3)
+    if name == "rmat18":
+        return rmat(18, 16, 0.57, 0.19, 0.19, seed=3, stream=1)
+    if name == "batch":
+        return batch_graphs(4096, seed=4)
+    raise KeyError(name)

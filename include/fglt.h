@@ -53,6 +53,29 @@ typedef enum {
 
 /* fglt_raw flags */
 #define FGLT_NET 1u          /* write net frequencies (Table II applied) instead of raw */
+#define FGLT_TIMING 2u       /* time each launch segment with HIP events on `stream` (fills
+                                fglt_stats.seg_ms; adds a final synchronization)         */
+
+/* Launch segments of fglt_raw, in execution order (indices into seg_ms). */
+enum {
+    FGLT_SEG_CHECK = 0,      /* input checks and the first synchronization      */
+    FGLT_SEG_RELABEL,        /* degree ranking, relabelled and re-sorted rows    */
+    FGLT_SEG_STRUCTURE,      /* N-/N+ split, mirror positions, work counts, tiers */
+    FGLT_SEG_L1,             /* row pass 1: A p1, A (p1-1)(p1-2)/2               */
+    FGLT_SEG_TRI1_WAVE,      /* triangle pass (C3, c3), wavefront tier            */
+    FGLT_SEG_TRI1_LDS,       /* triangle pass, workgroup/LDS tier                 */
+    FGLT_SEG_TRI1_GLOBAL,    /* triangle pass, workgroup/global-bitmap tier       */
+    FGLT_SEG_FILL,           /* C3 mirrored to the lower entries                  */
+    FGLT_SEG_L2,             /* row pass 2: A p2, A c3, C3 (p1-2), C(C3, 2)       */
+    FGLT_SEG_TRI2_WAVE,      /* clique/diamond pass, wavefront tier               */
+    FGLT_SEG_TRI2_LDS,       /* clique/diamond pass, LDS-bitmap tier              */
+    FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
+    FGLT_SEG_C4_WAVE,        /* 4-cycle pass, wavefront tier                      */
+    FGLT_SEG_C4_BLOCK,       /* 4-cycle pass, workgroup tier                      */
+    FGLT_SEG_C4_HEAVY,       /* 4-cycle pass, dense-counter tier                  */
+    FGLT_SEG_FINALIZE,       /* Table I assembly, Table II, scatter to caller order */
+    FGLT_NSEG
+};
 
 /*
  * Canonical adjacency from an edge list (the simple undirected graph of
@@ -82,6 +105,10 @@ typedef struct {
     int64_t wedge_items;         /* rank-ordered wedges visited by the 4-cycle pass      */
     int64_t n_light_tri, n_mid_tri, n_heavy_tri;  /* vertices per clique-pass tier        */
     int64_t n_light_c4, n_mid_c4, n_heavy_c4;     /* vertices per 4-cycle-pass tier       */
+    int64_t tri_items_tier[3];   /* merge items per clique-pass tier                      */
+    int64_t wedge_items_tier[3]; /* wedges per 4-cycle-pass tier                          */
+    int64_t triangles;           /* triangles in the graph                                */
+    float seg_ms[FGLT_NSEG];     /* with FGLT_TIMING: milliseconds per launch segment     */
 } fglt_stats;
 
 /* Tier thresholds of fglt_raw (host struct); 0 selects a default.  A vertex u
@@ -107,7 +134,7 @@ typedef struct {
  *                self-loops, no repeated entry in a row (rows need not be sorted)
  *   out          out [n][16] int64
  *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
- *   flags        FGLT_NET or 0
+ *   flags        FGLT_NET, FGLT_TIMING or 0
  *   plan         (host) optional tier thresholds, NULL for the defaults
  *   stats        (host) optional, filled on success
  * Returns FGLT_ENOTCANON for a CSR that breaks the contract (checked on the

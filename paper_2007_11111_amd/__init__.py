@@ -15,7 +15,7 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, NORBITS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_TIMING, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
     "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "FgltError", "Stats",
@@ -66,11 +66,13 @@ def raw_workspace_bytes(n: int, nnz: int) -> int:
 
 
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
-        workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None, stream=None):
+        workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
+        timing: bool = False, stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
     (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
-    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max."""
+    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max; with
+    timing=True the statistics carry per-segment milliseconds (HIP events)."""
     L = lib()
     assert offsets.dtype == torch.int64 and indices.dtype == torch.int32
     assert offsets.is_cuda and indices.is_cuda
@@ -90,7 +92,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
         rp = RawPlan(int(plan.get("tri_wave_max", 0)), int(plan.get("tri_lds_max", 0)),
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
-                     int(workspace.numel()), FGLT_NET if net else 0, ctypes.byref(rp) if rp is not None else None,
+                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0), ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st), _stream(stream)),
           "fglt_raw")
     return (out, st.as_dict()) if stats else out

@@ -32,13 +32,29 @@ class FgltError(RuntimeError):
         super().__init__(f"{where}: {STATUS.get(status, status)} ({message})")
 
 
+FGLT_TIMING = 2
+SEGMENTS = ["check", "relabel", "structure", "l1", "tri1_wave", "tri1_lds", "tri1_global", "fill", "l2",
+            "tri2_wave", "tri2_lds", "tri2_global", "c4_wave", "c4_block", "c4_heavy", "finalize"]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "nnz", "d_max", "dplus_max", "tri_items", "wedge_items",
-        "n_light_tri", "n_mid_tri", "n_heavy_tri", "n_light_c4", "n_mid_c4", "n_heavy_c4")]
+        "n_light_tri", "n_mid_tri", "n_heavy_tri", "n_light_c4", "n_mid_c4", "n_heavy_c4")] + [
+        ("tri_items_tier", ctypes.c_int64 * 3), ("wedge_items_tier", ctypes.c_int64 * 3),
+        ("triangles", ctypes.c_int64), ("seg_ms", ctypes.c_float * len(SEGMENTS))]
 
     def as_dict(self):
-        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if name == "seg_ms":
+                d[name] = {SEGMENTS[k]: float(v[k]) for k in range(len(SEGMENTS))}
+            elif name.endswith("_tier"):
+                d[name] = [int(x) for x in v]
+            else:
+                d[name] = int(v)
+        return d
 
 
 class RawPlan(ctypes.Structure):

@@ -35,7 +35,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~FGLT_NET) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING)) return FGLT_EINVAL;
     if (stats) {
         *stats = fglt_stats{};
         stats->n = n;
@@ -47,7 +47,21 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     RawWs w = carve_raw(c, n, nnz);
     if (!c.ok()) return FGLT_EWORKSPACE;
 
+    SegTimer tm;
+    struct EvGuard {
+        SegTimer& t;
+        ~EvGuard() {
+            for (auto& e : t.ev)
+                if (e) hipEventDestroy(e);
+        }
+    } guard{tm};
+    if (flags & FGLT_TIMING) {
+        for (auto& e : tm.ev) FGLT_HIP_TRY(hipEventCreate(&e));
+        tm.on = true;
+    }
+
     // 1. input checks (memory safety of everything below), degrees
+    tm.mark(FGLT_SEG_CHECK, s);
     FGLT_HIP_TRY(launch_check_input(n, nnz, offsets, indices, w, s));
     DevPlan hp{};
     int st = read_plan(w, hp, s);
@@ -55,7 +69,9 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     if ((st = status_from_err(hp.err))) return st;
 
     // 2. degree ranking, relabelled CSR, work counts, tiers
+    tm.mark(FGLT_SEG_RELABEL, s);
     FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
+    tm.mark(FGLT_SEG_STRUCTURE, s);
     FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan), s));
     i64 g_total = 0;
     if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
@@ -67,13 +83,24 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     // 3. counting
     FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
+    tm.mark(FGLT_SEG_L1, s);
     FGLT_HIP_TRY(launch_l1(n, nnz, w, s));
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, s));
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, s, tm));
+    tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, s));
+    tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, s));
-    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s));
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, s, tm));
+    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s, tm));
+    tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
+    i64 triangles = -1;
+    if (tm.on) {
+        FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
+        DevPlan fin{};
+        if ((st = read_plan(w, fin, s))) return st;
+        triangles = fin.triangles;
+    }
 
     if (stats) {
         stats->d_max = hp.d_max;
@@ -86,6 +113,18 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
         stats->n_light_c4 = hp.n_c4[0];
         stats->n_mid_c4 = hp.n_c4[1];
         stats->n_heavy_c4 = hp.n_c4[2];
+        for (int k = 0; k < 3; ++k) {
+            stats->tri_items_tier[k] = hp.tri_items_tier[k];
+            stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
+        }
+        stats->triangles = triangles;
+        if (tm.on) {
+            for (int k = 0; k < FGLT_NSEG; ++k) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) return FGLT_EHIP;
+                stats->seg_ms[k] = ms;
+            }
+        }
     }
     return FGLT_OK;
 }

@@ -30,6 +30,9 @@ struct DevPlan {
     i64 wedge_items;
     u32 n_tri[3];  // wave, lds, global tiers
     u32 n_c4[3];   // wave, block, heavy tiers
+    i64 tri_items_tier[3];
+    i64 wedge_items_tier[3];
+    i64 triangles;
 };
 
 struct RawWs {
@@ -76,11 +79,24 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan);
 hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, hipStream_t s);
 
 // counting (raw_count.hip)
+// Optional event marks between launches (FGLT_TIMING).
+struct SegTimer {
+    hipEvent_t ev[FGLT_NSEG + 1] = {};
+    bool on = false;
+    int last = -1;
+    // records the start of segment `seg` (and thereby the end of the previous one)
+    void mark(int seg, hipStream_t s) {
+        if (!on) return;
+        hipEventRecord(ev[seg], s);
+        last = seg;
+    }
+};
+
 hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s);
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s);
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s, SegTimer& tm);
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s);
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_net(i64 n, const i64* raw, i64* net, hipStream_t s);
 

@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                  const i64* __restrict__ G, const i32* __restrict__ list, u32 count,
                                                  i32* __restrict__ C3, i64* __restrict__ c3v, i64* __restrict__ k4v,
-                                                 i64* __restrict__ d13) {
+                                                 i64* __restrict__ d13, DevPlan* plan) {
     constexpr int NW = PT / WAVE;
     __shared__ i32 sL[NW][WAVE];
     __shared__ i32 sPre[NW][WAVE + 1];
@@ -192,7 +192,10 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
                     }
                 }
                 c = wave_sum(c);
-                if (lane == 0 && c) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
+                if (lane == 0 && c) {
+                    atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
+                    atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(c / 2));
+                }
             } else {
                 i64 R = 0, kv = 0, dv = 0;
                 if (lane < D) {
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
                                                   const i64* __restrict__ G, const i32* __restrict__ list,
                                                   u32 count, i32* __restrict__ C3, i64* __restrict__ c3v,
                                                   i64* __restrict__ k4v, i64* __restrict__ d13,
-                                                  u64* __restrict__ slots, i64 slot_words) {
+                                                  u64* __restrict__ slots, i64 slot_words, DevPlan* plan) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     constexpr bool BITS = MODE == 2;
@@ -379,7 +382,10 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         __syncthreads();
         if (threadIdx.x == 0) {
             if (MODE == 1) {
-                if (red[0]) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red[0] / 2));
+                if (red[0]) {
+                    atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red[0] / 2));
+                    atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(red[0] / 2));
+                }
             } else {
                 if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
                 if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
@@ -653,41 +659,51 @@ hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s) {
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s, SegTimer& tm) {
     (void)nnz;
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
+    const int seg0 = mode == 1 ? FGLT_SEG_TRI1_WAVE : FGLT_SEG_TRI2_WAVE;
     if (mode == 1) {
+        tm.mark(seg0, s);
         if (c0) hipLaunchKernelGGL((k_tri_wave<1>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13);
+                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
+        tm.mark(seg0 + 1, s);
         if (c1) hipLaunchKernelGGL((k_tri_block<1, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
                                    w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words);
+                                   w.tri_slot_words, w.plan);
+        tm.mark(seg0 + 2, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<1, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words);
+                                   w.tri_slot_words, w.plan);
     } else {
+        tm.mark(seg0, s);
         if (c0) hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13);
+                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
+        tm.mark(seg0 + 1, s);
         if (c1) hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
                                    w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words);
+                                   w.tri_slot_words, w.plan);
+        tm.mark(seg0 + 2, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words);
+                                   w.tri_slot_words, w.plan);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s) {
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm) {
     (void)nnz;
     const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2];
+    tm.mark(FGLT_SEG_C4_WAVE, s);
     if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
                                w.G, w.c4_list, c0, w.c4v);
+    tm.mark(FGLT_SEG_C4_BLOCK, s);
     if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
                                w.lo, w.G, w.c4_list + n, c1, w.c4v);
+    tm.mark(FGLT_SEG_C4_HEAVY, s);
     if (c2) {
         const u32 slots = std::min<u32>(c2, NUM_C4_SLOTS);
         hipError_t e = hipMemsetAsync(w.c4_cnt, 0, sizeof(i32) * (size_t)slots * (size_t)n, s);

@@ -236,6 +236,7 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
                         const i64* __restrict__ G, i64 n, Tiers th, i32* __restrict__ tri_list,
                         i32* __restrict__ c4_list, DevPlan* plan) {
     i64 dpmax = 0;
+    i64 titems[3] = {0, 0, 0}, witems[3] = {0, 0, 0};
     for (i64 u0 = (i64)blockIdx.x * blockDim.x; u0 < n; u0 += (i64)gridDim.x * blockDim.x) {
         const i64 u = u0 + threadIdx.x;
         int tcls = -1, ccls = -1;
@@ -243,9 +244,12 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
             const i64 b = roff[u], m = roff[u] + lo[u], e = roff[u + 1];
             const i64 D = e - m;
             const i64 W = G[m] - G[b];
+            const i64 T = G[e] - G[m];
             dpmax = D > dpmax ? D : dpmax;
             if (D >= 2) tcls = D <= th.tri_wave ? 0 : (D <= th.tri_lds ? 1 : 2);
             if (W > 0) ccls = W <= th.c4_wave ? 0 : (W <= th.c4_block ? 1 : 2);
+            if (tcls >= 0) titems[tcls] += T;
+            if (ccls >= 0) witems[ccls] += W;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -270,6 +274,15 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
     dpmax = wave_max(dpmax);
     if (lane_id() == 0 && dpmax > 0)
         atomicMax((unsigned long long*)&plan->dplus_max, (unsigned long long)dpmax);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const i64 ti = wave_sum(titems[c]);
+        const i64 wi = wave_sum(witems[c]);
+        if (lane_id() == 0) {
+            if (ti) atomicAdd((unsigned long long*)&plan->tri_items_tier[c], (unsigned long long)ti);
+            if (wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
+        }
+    }
 }
 
 __global__ void k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo, const i64* __restrict__ G,

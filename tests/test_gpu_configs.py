@@ -1,0 +1,91 @@
+"""Full-size workloads on the GPU against the oracle's stored digests.
+
+tests/golden/digests.json holds, for each named workload, the sha256 of the
+oracle's canonical CSR and of its n x 16 net array over every vertex, written
+by tests/golden/make_digests.py (which calls only the oracle and the
+generators).  The GPU path builds the CSR with fglt_build_csr and runs the
+transform exactly as bench.py times it; both digests must match bit for bit.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from tests._util import ROOT, say, stratified_sample
+
+pytestmark = pytest.mark.gpu
+
+DIGESTS = os.path.join(ROOT, "tests", "golden", "digests.json")
+
+
+def _digests():
+    return json.load(open(DIGESTS)) if os.path.exists(DIGESTS) else {}
+
+
+def sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).astype(a.dtype.newbyteorder("<"), copy=False).tobytes())
+    return h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def fg():
+    import paper_2007_11111_amd as fg
+    assert torch.cuda.is_available()
+    return fg
+
+
+def _edges(name):
+    g = graphgen.make(name)
+    if isinstance(g, list):
+        src, dst, base = [], [], 0
+        for x in g:
+            src.append(x.src.astype(np.int64) + base)
+            dst.append(x.dst.astype(np.int64) + base)
+            base += x.n
+        return base, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+    return g.n, g.src, g.dst
+
+
+def _invariants(f, raw):
+    S = f.sum(0)
+    assert (f[:, 0] == 1).all()
+    assert (f >= 0).all() and (raw >= f).all()
+    assert S[2] == 2 * S[3] and S[5] == S[6] and S[7] == 3 * S[8]
+    assert 2 * S[9] == S[10] and S[9] == S[11] and S[13] == S[14]
+    assert S[4] % 3 == 0 and S[12] % 4 == 0 and S[15] % 4 == 0
+    np.testing.assert_array_equal(f @ oracle.U16().T, raw)
+
+
+@pytest.mark.parametrize("name", ["er", "batch", "rmat18", "cl", "rmat22"])
+def test_workload_digest(fg, name):
+    d = _digests().get(name)
+    if d is None:
+        pytest.skip(f"no stored oracle digest for {name}")
+    n, src, dst = _edges(name)
+    say(f"workload {name}: n={n} pairs={src.size}")
+    off, idx = fg.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    torch.cuda.synchronize()
+    off_h, idx_h = off.cpu().numpy(), idx.cpu().numpy()
+    assert sha(off_h, idx_h) == d["csr_sha256"], "fglt_build_csr differs from the oracle's canonical CSR"
+    say(f"workload {name}: transform nnz={idx.numel()}")
+    raw = fg.raw(off, idx)
+    f = fg.net(raw)
+    torch.cuda.synchronize()
+    f_h = f.cpu().numpy()
+    if sha(f_h) != d["net_sha256"]:
+        colsum = f_h.sum(0).tolist()
+        raise AssertionError(f"net digest mismatch; column sums {colsum} vs oracle {d['net_colsum']}")
+    _invariants(f_h, raw.cpu().numpy())
+    # a stratified vertex sample recomputed live by the oracle (small degrees only:
+    # the oracle's per-vertex cost grows with the square of the neighbourhood)
+    deg = np.diff(off_h)
+    sel = stratified_sample(deg, per_bin=40, top=0, seed=7, max_degree=64)
+    say(f"workload {name}: live oracle sample of {sel.size}")
+    np.testing.assert_array_equal(f_h[sel], oracle.net(off_h, idx_h, sel))
