@@ -17,7 +17,6 @@ constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
-constexpr int NUM_C4_SLOTS = 128;    // dense counter arrays of the heavy 4-cycle tier
 
 // Device statistics / plan words (one small block of device memory).
 struct DevPlan {
@@ -58,8 +57,10 @@ struct RawWs {
     // heavy-tier scratch
     u64* tri_slots;     // NUM_TRI_SLOTS * tri_slot_words
     i64 tri_slot_words;
-    i32* c4_cnt;        // NUM_C4_SLOTS * n
-    i32* c4_touched;    // NUM_C4_SLOTS * n
+    i64* c4_segoff;     // [2] one segment over the heavy list
+    i64* c4_jobcnt;     // [n] windows per heavy vertex
+    i64* c4_jobpre;     // [n+1] their exclusive scan
+    u32* c4_jobctr;     // job queue head
     // scratch
     i64* partials;
     SegSortWs sort;
@@ -87,7 +88,7 @@ struct SegTimer {
     // records the start of segment `seg` (and thereby the end of the previous one)
     void mark(int seg, hipStream_t s) {
         if (!on) return;
-        hipEventRecord(ev[seg], s);
+        (void)hipEventRecord(ev[seg], s);
         last = seg;
     }
 };

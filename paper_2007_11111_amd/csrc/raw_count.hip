@@ -25,6 +25,12 @@ static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
     return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(work, 1), per_block), cap));
 }
 
+static int bits_for_n(i64 n) {
+    int b = 0;
+    while (b < 31 && (((i64)1 << b) <= n - 1)) ++b;
+    return b;
+}
+
 __device__ __forceinline__ void fence_agent() { __threadfence(); }
 
 __device__ __forceinline__ i32 load_relaxed(const i32* p) {
@@ -506,74 +512,212 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
     }
 }
 
-// Heavy tier: one 1024-thread block per vertex with a dense counter array of
-// n entries (block-private slot) and a list of touched ends.
-static constexpr int C4H_THREADS = 1024;
-__global__ void __launch_bounds__(C4H_THREADS) k_c4_heavy(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                          const i32* __restrict__ lo, const i64* __restrict__ G,
-                                                          const i32* __restrict__ list, u32 count, i64 n,
-                                                          i32* __restrict__ cnt_slots, i32* __restrict__ touched_slots,
-                                                          i64* __restrict__ c4v) {
-    __shared__ u32 tcount;
+// Heavy tier: jobs (u, window) with u a vertex of large wedge count and the
+// window a range of WS consecutive ranks for the wedge end w.  One 1024-thread
+// workgroup per job counts the ends of u's wedges inside the window in dense
+// LDS counters (16-bit halves of 32-bit words when every count fits 16 bits),
+// so no global atomics touch the counts.  For every middle vertex v in N-(u)
+// the wedge ends inside the window are one contiguous run of row v, found by
+// two binary searches; the runs of 1024 middles at a time are flattened by a
+// block scan and walked in contiguous per-thread chunks.  Pass A counts, pass
+// B turns each count c into C(c, 2) for u and for w, pass C gives every middle
+// v the sum of (c - 1) over its wedges.  Jobs are pulled from a device queue,
+// largest vertices and highest windows first.
+static constexpr int C4W_THREADS = 1024;
+static constexpr int C4W_CHUNK = 16;
+static constexpr int C4W_WORDS = 32768;  // 128 KiB of counters
+
+template <bool PACK16>
+__device__ __forceinline__ void c4w_inc(u32* cnt, i32 x) {
+    if (PACK16) atomicAdd(&cnt[x >> 1], 1u << ((x & 1) << 4));
+    else atomicAdd(&cnt[x], 1u);
+}
+
+template <bool PACK16>
+__device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
+    if (PACK16) return (cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu;
+    return cnt[x];
+}
+
+// Exclusive block scan of one value per thread (1024 threads); returns the
+// prefix and writes the total to *total.
+__device__ __forceinline__ i32 block_scan_1024(i32 v, i32* wsum, i32* total) {
+    const int l = lane_id(), wv = threadIdx.x / WAVE;
+    i32 x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const i32 y = __shfl_up(x, o, WAVE);
+        if (l >= o) x += y;
+    }
+    if (l == WAVE - 1) wsum[wv] = x;
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        i32 y = threadIdx.x < C4W_THREADS / WAVE ? wsum[threadIdx.x] : 0;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const i32 z = __shfl_up(y, o, WAVE);
+            if ((int)threadIdx.x >= o) y += z;
+        }
+        if (threadIdx.x < C4W_THREADS / WAVE) wsum[threadIdx.x] = y;
+        if (threadIdx.x == C4W_THREADS / WAVE - 1) *total = y;
+    }
+    __syncthreads();
+    return (wv > 0 ? wsum[wv - 1] : 0) + x - v;
+}
+
+// Computes the runs of middles c0 .. c0+1023 of u inside [W0, W1), keeps the
+// non-empty ones in LDS (ridx base such that item t of run r sits at
+// base[r] + t, middle vertex, first item), and returns the item count; the run
+// count goes to *nruns.  rstart[nruns] = item count.
+__device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                        const i32* __restrict__ rpos, i64 b, i32 L, i32 c0, i32 W0, i32 W1,
+                                        i64* rbase, i32* rmid, i32* rstart, i32* wsum, i32* stotal, i32* nruns) {
+    const i32 k = c0 + (i32)threadIdx.x;
+    i32 len = 0;
+    i64 s0 = 0;
+    i32 v = 0;
+    if (k < L) {
+        v = ridx[b + k];
+        const i64 rs = roff[v];
+        const i64 re = rs + rpos[b + k];  // neighbours of v below u
+        s0 = lower_bound_dev(ridx, rs, re, W0);
+        const i64 e0 = lower_bound_dev(ridx, s0, re, W1);
+        len = (i32)(e0 - s0);
+    }
+    const i32 pre = block_scan_1024(len, wsum, stotal);
+    const i32 T = *stotal;
+    __syncthreads();
+    const i32 cidx = block_scan_1024(len > 0 ? 1 : 0, wsum, stotal);
+    if (len > 0) {
+        rbase[cidx] = s0 - pre;
+        rmid[cidx] = v;
+        rstart[cidx] = pre;
+    }
+    if (threadIdx.x == 0) {
+        *nruns = *stotal;
+        rstart[*stotal] = T;
+    }
+    __syncthreads();
+    return T;
+}
+
+__device__ __forceinline__ u64 wave_or(u64 x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, WAVE);
+    return x;
+}
+
+// Walks items [ta, tb) of the compacted runs, 64 consecutive items per step,
+// calling f(active, item, run, ridx index) on every lane.
+template <class F>
+__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, F&& f) {
+    if (ta >= tb) return;
+    const int l = lane_id();
+    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
+    i32 r0 = (i32)last_le_dev(rstart, 0, R - 1, ta);
+    for (i32 t0 = ta; t0 < tb; t0 += WAVE) {
+        const i32 j = r0 + 1 + l;
+        const i32 st = j < R ? rstart[j] : 0x7fffffff;
+        const u64 bit = st < t0 + WAVE ? (1ull << (st - t0)) : 0ull;
+        const u64 mask = wave_or(bit);
+        const i32 r = r0 + __popcll(mask & le);
+        const i32 t = t0 + l;
+        f(t < tb, t, r, rbase[r] + t);
+        r0 = __shfl(r, WAVE - 1, WAVE);
+    }
+}
+
+template <bool PACK16>
+__global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                           const i32* __restrict__ heavy_sorted, u32 nheavy,
+                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
+                                                           i64* __restrict__ c4v) {
+    constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
+    constexpr int NWV = C4W_THREADS / WAVE;
+    __shared__ u32 cnt[C4W_WORDS];
+    __shared__ i64 rbase[C4W_THREADS + 1];
+    __shared__ i32 rmid[C4W_THREADS + 1];
+    __shared__ i32 rstart[C4W_THREADS + 1];
+    __shared__ i32 wsum[C4W_THREADS / WAVE];
+    __shared__ i32 stotal, nruns;
+    __shared__ i64 sjob;
     __shared__ i64 red;
-    i32* cnt = cnt_slots + (i64)blockIdx.x * n;
-    i32* touched = touched_slots + (i64)blockIdx.x * n;
-    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
-        const i64 u = list[it];
-        const i64 b = roff[u], m = b + lo[u];
-        const i64 gb = G[b];
-        const i64 W = G[m] - gb;
+    const i64 njobs = jobpre[nheavy];
+    const int wv = threadIdx.x / WAVE;
+    while (true) {
         if (threadIdx.x == 0) {
-            tcount = 0;
+            sjob = (i64)atomicAdd(job_ctr, 1u);
             red = 0;
         }
         __syncthreads();
-        for (i64 t = threadIdx.x; t < W; t += blockDim.x) {
-            i64 q;
-            i32 w;
-            wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-            const i32 old = atomicAdd(&cnt[w], 1);
-            if (old == 0) touched[atomicAdd(&tcount, 1u)] = w;
-        }
-        fence_agent();
+        const i64 j = sjob;
+        if (j >= njobs) break;
+        // job j -> (heavy vertex, window), heaviest vertices first, top windows first
+        const i64 h = last_le_dev(jobpre, 0, (i64)nheavy - 1, j);
+        const i64 u = heavy_sorted[nheavy - 1 - h];
+        const i64 nwin = jobpre[h + 1] - jobpre[h];
+        const i32 win = (i32)(nwin - 1 - (j - jobpre[h]));
+        const i32 W0 = win * WS;
+        const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
+        const i64 b = roff[u];
+        const i32 L = lo[u];
+        for (int q = threadIdx.x; q < C4W_WORDS; q += C4W_THREADS) cnt[q] = 0;
         __syncthreads();
-        fence_agent();
-        const u32 nt = tcount;
+        // pass A: count the wedge ends in the window
+        i32 T = 0;
+        for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
+            T = c4w_runs(roff, ridx, rpos, b, L, c0, W0, W1, rbase, rmid, rstart, wsum, &stotal, &nruns);
+            const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns,
+                     [&](bool act, i32, i32, i64 e) {
+                         if (act) c4w_inc<PACK16>(cnt, ridx[e] - W0);
+                     });
+            __syncthreads();
+        }
+        // pass B: C(c, 2) to u and to w
         i64 accu = 0;
-        for (u32 i = threadIdx.x; i < nt; i += blockDim.x) {
-            const i32 w = load_relaxed(&touched[i]);
-            const i64 c = load_relaxed(&cnt[w]);
+        for (i32 x = threadIdx.x; x < W1 - W0; x += C4W_THREADS) {
+            const i64 c = c4w_get<PACK16>(cnt, x);
             if (c >= 2) {
                 const i64 pr = c * (c - 1) / 2;
                 accu += pr;
-                atomicAdd((unsigned long long*)&c4v[w], (unsigned long long)pr);
+                atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
             }
-        }
-        for (i64 t0 = 0; t0 < W; t0 += blockDim.x) {
-            const i64 t = t0 + threadIdx.x;
-            const bool act = t < W;
-            i64 q = -1, val = 0;
-            if (act) {
-                i32 w;
-                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-                val = (i64)load_relaxed(&cnt[w]) - 1;
-            }
-            val = wave_seg_scan(val, q);
-            if (wave_seg_tail(q, act) && val) atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)val);
         }
         accu = wave_sum(accu);
         if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
-        fence_agent();
-        __syncthreads();
-        fence_agent();
-        for (u32 i = threadIdx.x; i < nt; i += blockDim.x) {
-            const i32 w = load_relaxed(&touched[i]);
-            __hip_atomic_store(&cnt[w], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // pass C: (c - 1) to the middle of every wedge (runs of the last chunk
+        // are still in LDS when all middles fit in one chunk)
+        for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
+            if (L > C4W_THREADS)
+                T = c4w_runs(roff, ridx, rpos, b, L, c0, W0, W1, rbase, rmid, rstart, wsum, &stotal, &nruns);
+            const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns,
+                     [&](bool act, i32, i32 r, i64 e) {
+                         i64 val = act ? (i64)c4w_get<PACK16>(cnt, ridx[e] - W0) - 1 : 0;
+                         const i64 key = act ? r : -1;
+                         val = wave_seg_scan(val, key);
+                         if (wave_seg_tail(key, act) && val)
+                             atomicAdd((unsigned long long*)&c4v[rmid[r]], (unsigned long long)val);
+                     });
+            __syncthreads();
         }
         if (threadIdx.x == 0 && red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
-        fence_agent();
         __syncthreads();
-        fence_agent();
+    }
+}
+
+__global__ void k_set_pair(i64* p, i64 a, i64 b) {
+    p[0] = a;
+    p[1] = b;
+}
+
+// Windows per heavy vertex, in descending vertex order.
+__global__ void k_c4_jobs(const i32* __restrict__ heavy_sorted, u32 nheavy, i64 WS, i64* __restrict__ jobcnt) {
+    for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += (i64)gridDim.x * blockDim.x) {
+        const i64 u = heavy_sorted[nheavy - 1 - h];
+        jobcnt[h] = (u + WS - 1) / WS;
     }
 }
 
@@ -705,11 +849,23 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
                                w.lo, w.G, w.c4_list + n, c1, w.c4v);
     tm.mark(FGLT_SEG_C4_HEAVY, s);
     if (c2) {
-        const u32 slots = std::min<u32>(c2, NUM_C4_SLOTS);
-        hipError_t e = hipMemsetAsync(w.c4_cnt, 0, sizeof(i32) * (size_t)slots * (size_t)n, s);
+        // heavy vertices in ascending order, then (vertex, window) jobs
+        i32* hs = w.c4_list + 2 * n;
+        hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c2);
+        hipError_t e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), w.sort, 1, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_c4_heavy, dim3(slots), dim3(C4H_THREADS), 0, s, w.roff, w.ridx, w.lo, w.G,
-                           w.c4_list + 2 * n, c2, n, w.c4_cnt, w.c4_touched, w.c4v);
+        const bool pack16 = hp.d_max < 65536;
+        const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
+        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c2, PT, 4096)), dim3(PT), 0, s, hs, c2, WS, w.c4_jobcnt);
+        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c2, w.partials, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(w.c4_jobctr, 0, sizeof(u32), s)) != hipSuccess) return e;
+        const unsigned grid = 2048;
+        if (pack16)
+            hipLaunchKernelGGL((k_c4_window<true>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos,
+                               hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v);
+        else
+            hipLaunchKernelGGL((k_c4_window<false>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos,
+                               hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v);
     }
     return hipGetLastError();
 }

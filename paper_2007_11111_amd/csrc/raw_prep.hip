@@ -363,8 +363,10 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     const i64 words_per_row = ceil_div(dmax_plus, 64);
     w.tri_slot_words = 2 * dmax_plus * words_per_row + 4 * dmax_plus + 64;
     w.tri_slots = c.take<u64>(NUM_TRI_SLOTS * w.tri_slot_words);
-    w.c4_cnt = c.take<i32>((i64)NUM_C4_SLOTS * nn);
-    w.c4_touched = c.take<i32>((i64)NUM_C4_SLOTS * nn);
+    w.c4_segoff = c.take<i64>(2);
+    w.c4_jobcnt = c.take<i64>(nn);
+    w.c4_jobpre = c.take<i64>(nn + 1);
+    w.c4_jobctr = c.take<u32>(4);
     w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
     w.sort.tmp = c.take<i32>(std::max(nnz, nn));
     w.sort.lists = c.take<i32>(3 * (nn + 2));

@@ -148,12 +148,12 @@ class Server:
         req = Request(next(self._ids), off, idx, time.perf_counter())
         small = req.n <= self.small_n
         req.bytes_resident, req.bytes_work = self.ex.bytes_for(req.n, req.nnz, small)
+        req.future.rid = req.rid
+        req.future.cancel_request = lambda r=req: self._cancel(r)
         if req.bytes_resident + req.bytes_work > self.budget:
             req.future.set_exception(Rejected(f"request {req.rid} needs "
                                               f"{req.bytes_resident + req.bytes_work} bytes > budget {self.budget}"))
             return req.future
-        req.future.rid = req.rid
-        req.future.cancel_request = lambda r=req: self._cancel(r)
         with self._cv:
             self._queue.append(req)
             self._cv.notify_all()

@@ -111,9 +111,9 @@ def test_budget_blocks_until_release_and_skip_ahead():
     time.sleep(0.2)
     assert not f1.done(), "request 1 ran without budget"
     r0.release()
+    r2.release()
     r1 = f1.result(timeout=30)
-    for r in (r1, r2):
-        r.release()
+    r1.release()
     srv.close()
     assert srv.free == budget
 
@@ -129,9 +129,11 @@ def test_oversize_is_rejected():
 
 def test_cancel_queued_request():
     csrs = _graphs(2, seed=4)
-    size0 = 8 * csrs[0][0].size + 4 * csrs[0][1].size + 128 * (csrs[0][0].size - 1)
+    size = [8 * o.size + 4 * i.size + 128 * (o.size - 1) for o, i in csrs]
     ex = FakeExecutor()
-    srv = Server(ex, budget_bytes=size0 + 10, streams=1, small_n=0)
+    budget = max(size) + 10
+    assert sum(size) > budget
+    srv = Server(ex, budget_bytes=budget, streams=1, small_n=0)
     r0 = srv.submit(*csrs[0]).result(timeout=30)
     f1 = srv.submit(*csrs[1])  # cannot be admitted while r0 is resident
     assert f1.cancel_request()
