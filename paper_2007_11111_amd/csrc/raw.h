@@ -61,6 +61,8 @@ struct RawWs {
     i64* c4_jobcnt;     // [n] windows per heavy vertex
     i64* c4_jobpre;     // [n+1] their exclusive scan
     u32* c4_jobctr;     // job queue head
+    i32* c4_tab;        // window table of the heavy 4-cycle tier (optional)
+    i64 c4_tab_cap;     // its capacity in entries
     // scratch
     i64* partials;
     SegSortWs sort;

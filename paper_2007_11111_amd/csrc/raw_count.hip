@@ -567,11 +567,15 @@ __device__ __forceinline__ i32 block_scan_1024(i32 v, i32* wsum, i32* total) {
 
 // Computes the runs of middles c0 .. c0+1023 of u inside [W0, W1), keeps the
 // non-empty ones in LDS (ridx base such that item t of run r sits at
-// base[r] + t, middle vertex, first item), and returns the item count; the run
-// count goes to *nruns.  rstart[nruns] = item count.
+// base[r] + t, middle vertex, first item) and the smallest and largest wedge
+// end seen; returns the item count (run count in *nruns, rstart[nruns] = count).
+// With a window table the run bounds are two table reads; otherwise two binary
+// searches in the row.
+template <bool TAB>
 __device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                        const i32* __restrict__ rpos, i64 b, i32 L, i32 c0, i32 W0, i32 W1,
-                                        i64* rbase, i32* rmid, i32* rstart, i32* wsum, i32* stotal, i32* nruns) {
+                                        const i32* __restrict__ rpos, const i32* __restrict__ tab, i64 K1,
+                                        i32 win, i64 b, i32 L, i32 c0, i32 W0, i32 W1, i64* rbase, i32* rmid,
+                                        i32* rstart, i32* wsum, i32* stotal, i32* nruns, i32* wlo, i32* whi) {
     const i32 k = c0 + (i32)threadIdx.x;
     i32 len = 0;
     i64 s0 = 0;
@@ -579,10 +583,21 @@ __device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32*
     if (k < L) {
         v = ridx[b + k];
         const i64 rs = roff[v];
-        const i64 re = rs + rpos[b + k];  // neighbours of v below u
-        s0 = lower_bound_dev(ridx, rs, re, W0);
-        const i64 e0 = lower_bound_dev(ridx, s0, re, W1);
-        len = (i32)(e0 - s0);
+        const i32 cut = rpos[b + k];  // neighbours of v below u
+        if (TAB) {
+            const i32 a0 = tab[(i64)v * K1 + win];
+            const i32 a1 = min(tab[(i64)v * K1 + win + 1], cut);
+            s0 = rs + a0;
+            len = a1 > a0 ? a1 - a0 : 0;
+        } else {
+            const i64 re = rs + cut;
+            s0 = lower_bound_dev(ridx, rs, re, W0);
+            len = (i32)(lower_bound_dev(ridx, s0, re, W1) - s0);
+        }
+    }
+    if (len > 0) {
+        atomicMin(wlo, ridx[s0]);
+        atomicMax(whi, ridx[s0 + len - 1]);
     }
     const i32 pre = block_scan_1024(len, wsum, stotal);
     const i32 T = *stotal;
@@ -601,16 +616,12 @@ __device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32*
     return T;
 }
 
-__device__ __forceinline__ u64 wave_or(u64 x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o, WAVE);
-    return x;
-}
-
-// Walks items [ta, tb) of the compacted runs, 64 consecutive items per step,
-// calling f(active, item, run, ridx index) on every lane.
+// Walks items [ta, tb) of the compacted runs, 64 consecutive items per step.
+// The lanes where a run starts are found through a per-wave LDS flag row and a
+// ballot; f(active, item, run, ridx index, run-start mask) runs on every lane.
 template <class F>
-__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, F&& f) {
+__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R,
+                                         volatile i32* flags, F&& f) {
     if (ta >= tb) return;
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
@@ -618,18 +629,28 @@ __device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const
     for (i32 t0 = ta; t0 < tb; t0 += WAVE) {
         const i32 j = r0 + 1 + l;
         const i32 st = j < R ? rstart[j] : 0x7fffffff;
-        const u64 bit = st < t0 + WAVE ? (1ull << (st - t0)) : 0ull;
-        const u64 mask = wave_or(bit);
+        // lanes talk through LDS here: volatile accesses in program order, and
+        // wavefront barriers so that no store or load moves across the exchange
+        flags[l] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (st < t0 + WAVE) flags[st - t0] = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const u64 mask = __ballot(flags[l] != 0);
+        __builtin_amdgcn_wave_barrier();
         const i32 r = r0 + __popcll(mask & le);
         const i32 t = t0 + l;
-        f(t < tb, t, r, rbase[r] + t);
+        f(t < tb, t, r, rbase[r] + t, mask);
         r0 = __shfl(r, WAVE - 1, WAVE);
     }
 }
 
-template <bool PACK16>
+template <bool PACK16, bool TAB>
 __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                            const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                           const i32* __restrict__ tab, i64 K1,
                                                            const i32* __restrict__ heavy_sorted, u32 nheavy,
                                                            const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
                                                            i64* __restrict__ c4v) {
@@ -639,16 +660,20 @@ __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict
     __shared__ i64 rbase[C4W_THREADS + 1];
     __shared__ i32 rmid[C4W_THREADS + 1];
     __shared__ i32 rstart[C4W_THREADS + 1];
+    __shared__ i32 flags[NWV][WAVE];
     __shared__ i32 wsum[C4W_THREADS / WAVE];
-    __shared__ i32 stotal, nruns;
+    __shared__ i32 stotal, nruns, wlo, whi;
     __shared__ i64 sjob;
     __shared__ i64 red;
     const i64 njobs = jobpre[nheavy];
     const int wv = threadIdx.x / WAVE;
+    const int l = lane_id();
     while (true) {
         if (threadIdx.x == 0) {
             sjob = (i64)atomicAdd(job_ctr, 1u);
             red = 0;
+            wlo = 0x7fffffff;
+            whi = -1;
         }
         __syncthreads();
         const i64 j = sjob;
@@ -662,22 +687,38 @@ __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict
         const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
         const i64 b = roff[u];
         const i32 L = lo[u];
-        for (int q = threadIdx.x; q < C4W_WORDS; q += C4W_THREADS) cnt[q] = 0;
+        const bool one_chunk = L <= C4W_THREADS;
+        i32 T = 0;
+        if (one_chunk) {
+            // all middles fit one chunk: runs first, then clear only the touched range
+            T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, 0, W0, W1, rbase, rmid, rstart, wsum, &stotal,
+                              &nruns, &wlo, &whi);
+            if (T == 0) continue;  // T is block-uniform (LDS)
+            const i32 q0 = PACK16 ? (wlo - W0) >> 1 : wlo - W0;
+            const i32 q1 = PACK16 ? (whi - W0) >> 1 : whi - W0;
+            for (i32 q = q0 + threadIdx.x; q <= q1; q += C4W_THREADS) cnt[q] = 0;
+        } else {
+            for (int q = threadIdx.x; q < C4W_WORDS; q += C4W_THREADS) cnt[q] = 0;
+        }
         __syncthreads();
         // pass A: count the wedge ends in the window
-        i32 T = 0;
         for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
-            T = c4w_runs(roff, ridx, rpos, b, L, c0, W0, W1, rbase, rmid, rstart, wsum, &stotal, &nruns);
+            if (!one_chunk)
+                T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, c0, W0, W1, rbase, rmid, rstart, wsum,
+                                  &stotal, &nruns, &wlo, &whi);
             const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
-            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns,
-                     [&](bool act, i32, i32, i64 e) {
+            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns, flags[wv],
+                     [&](bool act, i32, i32, i64 e, u64) {
                          if (act) c4w_inc<PACK16>(cnt, ridx[e] - W0);
                      });
             __syncthreads();
         }
-        // pass B: C(c, 2) to u and to w
+        // pass B: C(c, 2) to u and to w, over the touched range only (empty when
+        // no middle has a wedge end in the window: then whi < wlo)
         i64 accu = 0;
-        for (i32 x = threadIdx.x; x < W1 - W0; x += C4W_THREADS) {
+        const i32 xa = whi >= wlo ? wlo - W0 : 0;
+        const i32 xb = whi >= wlo ? whi - W0 : -1;
+        for (i32 x = xa + (i32)threadIdx.x; x <= xb; x += C4W_THREADS) {
             const i64 c = c4w_get<PACK16>(cnt, x);
             if (c >= 2) {
                 const i64 pr = c * (c - 1) / 2;
@@ -686,25 +727,48 @@ __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict
             }
         }
         accu = wave_sum(accu);
-        if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
-        // pass C: (c - 1) to the middle of every wedge (runs of the last chunk
-        // are still in LDS when all middles fit in one chunk)
+        if (l == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
+        // pass C: (c - 1) to the middle of every wedge; per-run sums from a wave
+        // prefix sum and the run-start mask
         for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
-            if (L > C4W_THREADS)
-                T = c4w_runs(roff, ridx, rpos, b, L, c0, W0, W1, rbase, rmid, rstart, wsum, &stotal, &nruns);
+            if (!one_chunk)
+                T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, c0, W0, W1, rbase, rmid, rstart, wsum,
+                                  &stotal, &nruns, &wlo, &whi);
             const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
-            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns,
-                     [&](bool act, i32, i32 r, i64 e) {
+            const i32 tb = std::min(T, (wv + 1) * per);
+            c4w_walk(std::min(T, wv * per), tb, rbase, rstart, nruns, flags[wv],
+                     [&](bool act, i32 t, i32 r, i64 e, u64 mask) {
                          i64 val = act ? (i64)c4w_get<PACK16>(cnt, ridx[e] - W0) - 1 : 0;
-                         const i64 key = act ? r : -1;
-                         val = wave_seg_scan(val, key);
-                         if (wave_seg_tail(key, act) && val)
-                             atomicAdd((unsigned long long*)&c4v[rmid[r]], (unsigned long long)val);
+                         // inclusive prefix over the wave
+                         i64 P = val;
+#pragma unroll
+                         for (int o = 1; o < WAVE; o <<= 1) {
+                             const i64 y = __shfl_up(P, o, WAVE);
+                             if (l >= o) P += y;
+                         }
+                         const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
+                         const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of my run
+                         const i64 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+                         const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tb);
+                         const i64 sum = P - (sl > 0 ? before : 0);
+                         if (tail && sum) atomicAdd((unsigned long long*)&c4v[rmid[r]], (unsigned long long)sum);
                      });
             __syncthreads();
         }
         if (threadIdx.x == 0 && red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
         __syncthreads();
+    }
+}
+
+// Window table: tab[v * K1 + k] = number of neighbours of v with rank below k * WS.
+__global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 WS,
+                           i32* __restrict__ tab) {
+    const i64 total = n * K1;
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
+        const i64 v = q / K1, k = q - v * K1;
+        const i64 b = roff[v], e = roff[v + 1];
+        const i64 key = k * WS;
+        tab[q] = (i32)(key >= n ? e - b : lower_bound_dev(ridx, b, e, key) - b);
     }
 }
 
@@ -856,16 +920,23 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
         if (e != hipSuccess) return e;
         const bool pack16 = hp.d_max < 65536;
         const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
+        const i64 K1 = (n + WS - 1) / WS + 1;
+        const bool use_tab = w.c4_tab != nullptr && n * K1 <= w.c4_tab_cap;
+        if (use_tab)
+            hipLaunchKernelGGL(k_c4_table, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n, K1,
+                               WS, w.c4_tab);
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c2, PT, 4096)), dim3(PT), 0, s, hs, c2, WS, w.c4_jobcnt);
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c2, w.partials, s)) != hipSuccess) return e;
         if ((e = hipMemsetAsync(w.c4_jobctr, 0, sizeof(u32), s)) != hipSuccess) return e;
         const unsigned grid = 2048;
-        if (pack16)
-            hipLaunchKernelGGL((k_c4_window<true>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos,
-                               hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v);
-        else
-            hipLaunchKernelGGL((k_c4_window<false>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos,
-                               hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v);
+#define C4W_LAUNCH(P16, TB)                                                                                    \
+    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
+                       w.c4_tab, K1, hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v)
+        if (pack16 && use_tab) C4W_LAUNCH(true, true);
+        else if (pack16) C4W_LAUNCH(true, false);
+        else if (use_tab) C4W_LAUNCH(false, true);
+        else C4W_LAUNCH(false, false);
+#undef C4W_LAUNCH
     }
     return hipGetLastError();
 }

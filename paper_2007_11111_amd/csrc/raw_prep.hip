@@ -367,6 +367,14 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.c4_jobcnt = c.take<i64>(nn);
     w.c4_jobpre = c.take<i64>(nn + 1);
     w.c4_jobctr = c.take<u32>(4);
+    // window table: n x (ceil(n / 32768) + 1) entries when that stays within 1 GiB
+    {
+        const i64 k1 = (nn + 32767) / 32768 + 1;
+        const i64 entries = nn * k1;
+        w.c4_tab_cap = entries * 4 <= ((i64)1 << 30) ? entries : 0;
+        w.c4_tab = w.c4_tab_cap ? c.take<i32>(w.c4_tab_cap) : nullptr;
+        if (!c.base) w.c4_tab = nullptr;
+    }
     w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
     w.sort.tmp = c.take<i32>(std::max(nnz, nn));
     w.sort.lists = c.take<i32>(3 * (nn + 2));
