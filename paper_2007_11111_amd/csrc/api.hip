@@ -73,8 +73,10 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
     tm.mark(FGLT_SEG_STRUCTURE, s);
     FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan), s));
-    i64 g_total = 0;
+    i64 g_total = 0, bitmap_words = 0;
     if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
+    if (hipMemcpyAsync(&bitmap_words, w.boff + n, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return FGLT_EHIP;
     if ((st = read_plan(w, hp, s))) return st;
     if ((st = status_from_err(hp.err))) return st;
     if (2 * hp.sum_lo != nnz) return FGLT_ENOTCANON;  // every entry below the diagonal has its mirror
@@ -85,12 +87,14 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
     tm.mark(FGLT_SEG_L1, s);
     FGLT_HIP_TRY(launch_l1(n, nnz, w, s));
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, s, tm));
+    // the clique pass reuses the triangle pass's bitmaps when the workspace holds them
+    const bool stored = bitmap_words <= w.bstore_cap;
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
     tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, s));
     tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, s, tm));
+    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
     FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));

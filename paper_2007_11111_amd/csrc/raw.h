@@ -61,6 +61,10 @@ struct RawWs {
     i64* c4_jobcnt;     // [n] windows per heavy vertex
     i64* c4_jobpre;     // [n+1] their exclusive scan
     u32* c4_jobctr;     // job queue head
+    i64* bcnt;          // [n] bitmap words per vertex (clique pass store)
+    i64* boff;          // [n+1] their exclusive scan
+    u64* bstore;        // stored N+ bitmaps of the wave and LDS tiers
+    i64 bstore_cap;     // its capacity in words
     i32* c4_tab;        // window table of the heavy 4-cycle tier (optional)
     i64 c4_tab_cap;     // its capacity in entries
     // scratch
@@ -96,7 +100,12 @@ struct SegTimer {
 };
 
 hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s);
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s, SegTimer& tm);
+// tri.hip
+hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s);
+hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier);
+hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier);
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
+                      SegTimer& tm);
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm);

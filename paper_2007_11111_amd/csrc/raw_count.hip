@@ -15,7 +15,7 @@
 //                   rows scattered back to the caller's vertex order
 #include <algorithm>
 
-#include "raw.h"
+#include "walk.h"
 
 namespace fglt {
 
@@ -113,16 +113,6 @@ __global__ void k_fill_c3(const i64* __restrict__ roff, const i32* __restrict__ 
 
 // ------------------------------------------------------------ triangle / clique passes
 
-// Iterates the set bits of a 64-bit word.
-#define FOR_BITS(word, var, body)                 \
-    do {                                          \
-        u64 fb_w_ = (word);                       \
-        while (fb_w_) {                           \
-            const int var = __ffsll((long long)fb_w_) - 1; \
-            fb_w_ &= fb_w_ - 1;                   \
-            body;                                 \
-        }                                         \
-    } while (0)
 
 // Wave tier: out-degree D in [2, 64]; one wavefront per vertex, 4 per block.
 template <int MODE>
@@ -404,30 +394,6 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
 
 // ------------------------------------------------------------ 4-cycle pass
 
-__device__ __forceinline__ u32 hslot(i32 w, u32 mask) { return ((u32)w * 2654435761u) & mask; }
-
-__device__ __forceinline__ void hash_add(i32* keys, i32* cnts, u32 mask, i32 w) {
-    u32 h = hslot(w, mask);
-    while (true) {
-        const i32 old = atomicCAS(&keys[h], -1, w);
-        if (old == -1 || old == w) {
-            atomicAdd(&cnts[h], 1);
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ i32 hash_get(const i32* keys, const i32* cnts, u32 mask, i32 w) {
-    u32 h = hslot(w, mask);
-    while (true) {
-        const i32 k = keys[h];
-        if (k == w) return cnts[h];
-        if (k == -1) return 0;
-        h = (h + 1) & mask;
-    }
-}
-
 // Wedge item t of vertex u (N- entries in [b, m)): the entry q = (u, v) and the
 // wedge end w = the o-th neighbour of v.
 __device__ __forceinline__ void wedge_item(const i64* __restrict__ G, const i64* __restrict__ roff,
@@ -539,32 +505,6 @@ __device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
     return cnt[x];
 }
 
-// Exclusive block scan of one value per thread (1024 threads); returns the
-// prefix and writes the total to *total.
-__device__ __forceinline__ i32 block_scan_1024(i32 v, i32* wsum, i32* total) {
-    const int l = lane_id(), wv = threadIdx.x / WAVE;
-    i32 x = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const i32 y = __shfl_up(x, o, WAVE);
-        if (l >= o) x += y;
-    }
-    if (l == WAVE - 1) wsum[wv] = x;
-    __syncthreads();
-    if (threadIdx.x < WAVE) {
-        i32 y = threadIdx.x < C4W_THREADS / WAVE ? wsum[threadIdx.x] : 0;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const i32 z = __shfl_up(y, o, WAVE);
-            if ((int)threadIdx.x >= o) y += z;
-        }
-        if (threadIdx.x < C4W_THREADS / WAVE) wsum[threadIdx.x] = y;
-        if (threadIdx.x == C4W_THREADS / WAVE - 1) *total = y;
-    }
-    __syncthreads();
-    return (wv > 0 ? wsum[wv - 1] : 0) + x - v;
-}
-
 // Computes the runs of middles c0 .. c0+1023 of u inside [W0, W1), keeps the
 // non-empty ones in LDS (ridx base such that item t of run r sits at
 // base[r] + t, middle vertex, first item) and the smallest and largest wedge
@@ -614,37 +554,6 @@ __device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32*
     }
     __syncthreads();
     return T;
-}
-
-// Walks items [ta, tb) of the compacted runs, 64 consecutive items per step.
-// The lanes where a run starts are found through a per-wave LDS flag row and a
-// ballot; f(active, item, run, ridx index, run-start mask) runs on every lane.
-template <class F>
-__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R,
-                                         volatile i32* flags, F&& f) {
-    if (ta >= tb) return;
-    const int l = lane_id();
-    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
-    i32 r0 = (i32)last_le_dev(rstart, 0, R - 1, ta);
-    for (i32 t0 = ta; t0 < tb; t0 += WAVE) {
-        const i32 j = r0 + 1 + l;
-        const i32 st = j < R ? rstart[j] : 0x7fffffff;
-        // lanes talk through LDS here: volatile accesses in program order, and
-        // wavefront barriers so that no store or load moves across the exchange
-        flags[l] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (st < t0 + WAVE) flags[st - t0] = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const u64 mask = __ballot(flags[l] != 0);
-        __builtin_amdgcn_wave_barrier();
-        const i32 r = r0 + __popcll(mask & le);
-        const i32 t = t0 + l;
-        f(t < tb, t, r, rbase[r] + t, mask);
-        r0 = __shfl(r, WAVE - 1, WAVE);
-    }
 }
 
 template <bool PACK16, bool TAB>
@@ -707,10 +616,10 @@ __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict
                 T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, c0, W0, W1, rbase, rmid, rstart, wsum,
                                   &stotal, &nruns, &wlo, &whi);
             const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
-            c4w_walk(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns, flags[wv],
-                     [&](bool act, i32, i32, i64 e, u64) {
-                         if (act) c4w_inc<PACK16>(cnt, ridx[e] - W0);
-                     });
+            run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns, flags[wv], ridx,
+                        [&](bool act, i32, i32, i32 w, i64, u64) {
+                            if (act) c4w_inc<PACK16>(cnt, w - W0);
+                        });
             __syncthreads();
         }
         // pass B: C(c, 2) to u and to w, over the touched range only (empty when
@@ -736,9 +645,9 @@ __global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict
                                   &stotal, &nruns, &wlo, &whi);
             const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
             const i32 tb = std::min(T, (wv + 1) * per);
-            c4w_walk(std::min(T, wv * per), tb, rbase, rstart, nruns, flags[wv],
-                     [&](bool act, i32 t, i32 r, i64 e, u64 mask) {
-                         i64 val = act ? (i64)c4w_get<PACK16>(cnt, ridx[e] - W0) - 1 : 0;
+            run_walk<4>(std::min(T, wv * per), tb, rbase, rstart, nruns, flags[wv], ridx,
+                     [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask) {
+                         i64 val = act ? (i64)c4w_get<PACK16>(cnt, w - W0) - 1 : 0;
                          // inclusive prefix over the wave
                          i64 P = val;
 #pragma unroll
@@ -867,34 +776,42 @@ hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, hipStream_t s, SegTimer& tm) {
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
+                      SegTimer& tm) {
     (void)nnz;
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
-    const int seg0 = mode == 1 ? FGLT_SEG_TRI1_WAVE : FGLT_SEG_TRI2_WAVE;
+    hipError_t e;
     if (mode == 1) {
-        tm.mark(seg0, s);
-        if (c0) hipLaunchKernelGGL((k_tri_wave<1>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
-        tm.mark(seg0 + 1, s);
-        if (c1) hipLaunchKernelGGL((k_tri_block<1, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
-                                   w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words, w.plan);
-        tm.mark(seg0 + 2, s);
+        // triangle pass; the wave and LDS tiers also store their N+ bitmaps
+        tm.mark(FGLT_SEG_TRI1_WAVE, s);
+        if ((e = launch_tri1_stored(n, w, hp, stored, s, 0)) != hipSuccess) return e;
+        tm.mark(FGLT_SEG_TRI1_LDS, s);
+        if ((e = launch_tri1_stored(n, w, hp, stored, s, 1)) != hipSuccess) return e;
+        tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<1, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
     } else {
-        tm.mark(seg0, s);
-        if (c0) hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                                   w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
-        tm.mark(seg0 + 1, s);
-        if (c1) hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
-                                   w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words, w.plan);
-        tm.mark(seg0 + 2, s);
+        // clique and diamond pass: from the stored bitmaps, or by scanning again
+        tm.mark(FGLT_SEG_TRI2_WAVE, s);
+        if (stored) {
+            if ((e = launch_tri2_stored(n, w, hp, s, 0)) != hipSuccess) return e;
+        } else if (c0) {
+            hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
+                               w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
+        }
+        tm.mark(FGLT_SEG_TRI2_LDS, s);
+        if (stored) {
+            if ((e = launch_tri2_stored(n, w, hp, s, 1)) != hipSuccess) return e;
+        } else if (c1) {
+            hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
+                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
+                               w.tri_slot_words, w.plan);
+        }
+        tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);

@@ -320,7 +320,8 @@ hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream
     hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, PT, 8192)), dim3(PT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
                        w.tri_list, w.c4_list, w.plan);
     hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 4096)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_bitmap_offsets(n, w, th.tri_lds, s);
 }
 
 // ------------------------------------------------------------ workspace layout
@@ -363,6 +364,10 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     const i64 words_per_row = ceil_div(dmax_plus, 64);
     w.tri_slot_words = 2 * dmax_plus * words_per_row + 4 * dmax_plus + 64;
     w.tri_slots = c.take<u64>(NUM_TRI_SLOTS * w.tri_slot_words);
+    w.bcnt = c.take<i64>(nn);
+    w.boff = c.take<i64>(nn + 1);
+    w.bstore_cap = std::max<i64>(2 * nnz, 64);
+    w.bstore = c.take<u64>(w.bstore_cap);
     w.c4_segoff = c.take<i64>(2);
     w.c4_jobcnt = c.take<i64>(nn);
     w.c4_jobpre = c.take<i64>(nn + 1);

@@ -1,0 +1,422 @@
+// tri.hip -- triangle pass with stored neighbourhood bitmaps, and the clique /
+// diamond pass that reuses them.
+//
+// Triangle pass (per vertex u with out-degree D = |N+(u)|, N+(u) in LDS):
+//   the out-lists N+(v) of every v in N+(u) are walked as one flattened item
+//   stream (coalesced, 64 consecutive items per wavefront step); each item y
+//   is looked up in an LDS position map of N+(u).  A hit at position l is a
+//   triangle (u, v_k, v_l): C3 of the edges (u, v_k), (u, v_l) is counted in
+//   LDS, C3 of (v_k, v_l) by one global atomic, and bit l of row k of the
+//   bitmap B (the induced subgraph on N+(u)) is set.  B is stored for the
+//   clique pass when the workspace holds it.
+// Clique / diamond pass from stored bitmaps: B is reloaded, its transpose C
+//   built in LDS, and every 4-clique {u < a < b < c} and every off-cord
+//   diamond of a triangle with lowest vertex u is attributed to its vertices
+//   (Section IV-C: T e / 6 and D4,c e / 2 without forming T or D4,c).  The
+//   diamond term of u needs C3 of the edge (v_k, v_l), found by a binary
+//   search of v_l in N+(v_k).
+#include <algorithm>
+
+#include "walk.h"
+
+namespace fglt {
+
+static constexpr int WT = 256;  // wave-tier block: 4 wavefronts, one vertex each
+static constexpr int LT = 512;  // LDS-tier block: 8 wavefronts on one vertex
+
+// ------------------------------------------------------------------ triangle pass
+
+__global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                  const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
+                                                  i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
+                                                  const i64* __restrict__ boff, int store) {
+    constexpr int NW = WT / WAVE;
+    constexpr u32 HM = 2 * WAVE - 1;
+    __shared__ i32 sL[NW][WAVE];
+    __shared__ i64 rbase[NW][WAVE + 1];
+    __shared__ i32 rstart[NW][WAVE + 1];
+    __shared__ i32 rk[NW][WAVE + 1];
+    __shared__ i32 hk[NW][2 * WAVE];
+    __shared__ i32 hv[NW][2 * WAVE];
+    __shared__ i32 flags[NW][WAVE];
+    __shared__ i32 sCnt[NW][WAVE];
+    __shared__ u64 sB[NW][WAVE];
+    __shared__ i32 sR[NW];
+    const int wid = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
+        const i64 it = base + wid;
+        const bool valid = it < (i64)count;
+        hk[wid][lane] = -1;
+        hk[wid][lane + WAVE] = -1;
+        sCnt[wid][lane] = 0;
+        sB[wid][lane] = 0;
+        __syncthreads();
+        i64 u = 0, bu = 0;
+        int D = 0, T = 0;
+        if (valid) {
+            u = list[it];
+            bu = roff[u] + lo[u];
+            D = (int)(roff[u + 1] - bu);
+            const i64 gb = G[bu];
+            T = (int)(G[bu + D] - gb);
+            i32 len = 0, pre = 0;
+            i64 bv = 0;
+            if (lane < D) {
+                const i32 v = ridx[bu + lane];
+                sL[wid][lane] = v;
+                pos_insert(hk[wid], hv[wid], HM, v, lane);
+                pre = (i32)(G[bu + lane] - gb);
+                len = (i32)(G[bu + lane + 1] - G[bu + lane]);
+                bv = roff[v] + lo[v];
+            }
+            const u64 m = __ballot(lane < D && len > 0);
+            if (lane < D && len > 0) {
+                const int c = __popcll(m & lanemask_lt());
+                rbase[wid][c] = bv - pre;
+                rstart[wid][c] = pre;
+                rk[wid][c] = lane;
+            }
+            if (lane == 0) {
+                const int R = __popcll(m);
+                sR[wid] = R;
+                rstart[wid][R] = T;
+            }
+        }
+        __syncthreads();
+        if (valid && T > 0) {
+            run_walk<4>(0, T, rbase[wid], rstart[wid], sR[wid], flags[wid], ridx,
+                        [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
+                if (!act) return;
+                const i32 l = pos_find(hk[wid], hv[wid], HM, y);
+                if (l >= 0) {
+                    const i32 k = rk[wid][r];
+                    atomicAdd(&sCnt[wid][k], 1);
+                    atomicAdd(&sCnt[wid][l], 1);
+                    atomicAdd(&C3[e], 1);
+                    atomicOr((unsigned long long*)&sB[wid][k], 1ull << l);
+                }
+            });
+        }
+        __syncthreads();
+        if (valid) {
+            i64 c = 0;
+            if (lane < D) {
+                c = sCnt[wid][lane];
+                if (c) {
+                    atomicAdd(&C3[bu + lane], (i32)c);
+                    atomicAdd((unsigned long long*)&c3v[sL[wid][lane]], (unsigned long long)c);
+                }
+                if (store) bstore[boff[u] + lane] = sB[wid][lane];
+            }
+            c = wave_sum(c);
+            if (lane == 0 && c) {
+                atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
+                atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(c / 2));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                 const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                 const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
+                                                 i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
+                                                 const i64* __restrict__ boff, int store) {
+    constexpr int DM = TRI_LDS_MAX;
+    constexpr int WM = DM / 64;
+    constexpr int HS = 2 * DM;
+    constexpr int NWV = LT / WAVE;
+    __shared__ i32 L[DM];
+    __shared__ i64 rbase[DM + 1];
+    __shared__ i32 rstart[DM + 1];
+    __shared__ i32 rk[DM + 1];
+    __shared__ i32 hk[HS];
+    __shared__ i32 hv[HS];
+    __shared__ i32 flags[NWV][WAVE];
+    __shared__ i32 Cnt[DM];
+    __shared__ u64 B[DM * WM];
+    __shared__ i32 wsum[NWV];
+    __shared__ i32 stot, sR;
+    __shared__ i64 red;
+    const int wv = threadIdx.x / WAVE;
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        const int W = (D + 63) >> 6;
+        const i64 gb = G[bu];
+        const i32 T = (i32)(G[bu + D] - gb);
+        for (int q = threadIdx.x; q < HS; q += LT) hk[q] = -1;
+        for (int q = threadIdx.x; q < D * W; q += LT) B[q] = 0;
+        if (threadIdx.x < D) Cnt[threadIdx.x] = 0;
+        if (threadIdx.x == 0) red = 0;
+        __syncthreads();
+        const int k = threadIdx.x;  // D <= DM == LT: one out-neighbour per thread
+        i32 len = 0, pre = 0;
+        i64 bv = 0;
+        if (k < D) {
+            const i32 v = ridx[bu + k];
+            L[k] = v;
+            pos_insert(hk, hv, HS - 1, v, k);
+            pre = (i32)(G[bu + k] - gb);
+            len = (i32)(G[bu + k + 1] - G[bu + k]);
+            bv = roff[v] + lo[v];
+        }
+        const i32 cidx = block_scan<LT>(len > 0 ? 1 : 0, wsum, &stot);
+        if (k < D && len > 0) {
+            rbase[cidx] = bv - pre;
+            rstart[cidx] = pre;
+            rk[cidx] = k;
+        }
+        if (threadIdx.x == 0) {
+            sR = stot;
+            rstart[stot] = T;
+        }
+        __syncthreads();
+        const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+        run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, sR, flags[wv], ridx,
+                    [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
+                     if (!act) return;
+                     const i32 l = pos_find(hk, hv, HS - 1, y);
+                     if (l >= 0) {
+                         const i32 kk = rk[r];
+                         atomicAdd(&Cnt[kk], 1);
+                         atomicAdd(&Cnt[l], 1);
+                         atomicAdd(&C3[e], 1);
+                         atomicOr((unsigned long long*)&B[kk * W + (l >> 6)], 1ull << (l & 63));
+                     }
+                 });
+        __syncthreads();
+        i64 c = 0;
+        if (k < D) {
+            c = Cnt[k];
+            if (c) {
+                atomicAdd(&C3[bu + k], (i32)c);
+                atomicAdd((unsigned long long*)&c3v[L[k]], (unsigned long long)c);
+            }
+            if (store)
+                for (int z = 0; z < W; ++z) bstore[boff[u] + (i64)k * W + z] = B[k * W + z];
+        }
+        c = wave_sum(c);
+        if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&red, (unsigned long long)c);
+        __syncthreads();
+        if (threadIdx.x == 0 && red) {
+            atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red / 2));
+            atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(red / 2));
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ clique / diamond pass
+
+// C3(v, y) - 1 for y in N+(v): y is searched in N+(v) = ridx[from, end),
+// starting at `from`, which then moves past it (callers visit y in
+// increasing order).  A miss contributes nothing.
+__device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i32* __restrict__ C3, i64& from,
+                                          i64 end, i32 y) {
+    const i64 q = lower_bound_dev(ridx, from, end, y);
+    if (q >= end || ridx[q] != y) return 0;
+    from = q + 1;
+    return (i64)C3[q] - 1;
+}
+
+__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
+                                                   const i32* __restrict__ list, u32 count,
+                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                   i64* __restrict__ d13, const u64* __restrict__ bstore,
+                                                   const i64* __restrict__ boff) {
+    constexpr int NW = WT / WAVE;
+    __shared__ u64 sB[NW][WAVE];
+    __shared__ u64 sC[NW][WAVE];
+    __shared__ i32 sL[NW][WAVE];
+    __shared__ i32 c3u[NW][WAVE];
+    const int wid = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
+        const i64 it = base + wid;
+        const bool valid = it < (i64)count;
+        sC[wid][lane] = 0;
+        i64 u = 0, bu = 0;
+        int D = 0;
+        if (valid) {
+            u = list[it];
+            bu = roff[u] + lo[u];
+            D = (int)(roff[u + 1] - bu);
+            if (lane < D) {
+                sB[wid][lane] = bstore[boff[u] + lane];
+                sL[wid][lane] = ridx[bu + lane];
+                c3u[wid][lane] = C3[bu + lane];
+            }
+        }
+        __syncthreads();
+        if (valid && lane < D) {
+            FOR_BITS(sB[wid][lane], l, atomicOr((unsigned long long*)&sC[wid][l], 1ull << lane));
+        }
+        __syncthreads();
+        if (valid) {
+            i64 R = 0, du = 0;
+            if (lane < D) {
+                const u64 Bk = sB[wid][lane], Ck = sC[wid][lane];
+                const i32 vk = sL[wid][lane];
+                i64 from = roff[vk] + lo[vk];
+                const i64 end = roff[vk] + rdeg[vk];
+                i64 M = 0, X = 0, dv = 0;
+                FOR_BITS(Bk, l, {
+                    R += __popcll(Bk & sB[wid][l]);
+                    dv += c3u[wid][l] - 1;
+                    du += c3_minus_1(ridx, C3, from, end, sL[wid][l]);
+                });
+                FOR_BITS(Ck, j, {
+                    const u64 Bj = sB[wid][j];
+                    M += __popcll(Bj & Bk);
+                    X += __popcll(Bj & Ck);
+                    dv += c3u[wid][j] - 1;
+                });
+                const i64 kv = R + M + X;
+                if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
+                if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+            }
+            R = wave_sum(R);
+            du = wave_sum(du);
+            if (lane == 0) {
+                if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)R);
+                if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
+                                                  const i32* __restrict__ list, u32 count,
+                                                  const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                  i64* __restrict__ d13, const u64* __restrict__ bstore,
+                                                  const i64* __restrict__ boff) {
+    constexpr int DM = TRI_LDS_MAX;
+    constexpr int WM = DM / 64;
+    __shared__ u64 B[DM * WM];
+    __shared__ u64 C[DM * WM];
+    __shared__ i32 L[DM];
+    __shared__ i32 c3u[DM];
+    __shared__ i64 red[2];
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        const int W = (D + 63) >> 6;
+        const u64* src = bstore + boff[u];
+        for (int q = threadIdx.x; q < D * W; q += LT) {
+            B[q] = src[q];
+            C[q] = 0;
+        }
+        if (threadIdx.x < D) {
+            L[threadIdx.x] = ridx[bu + threadIdx.x];
+            c3u[threadIdx.x] = C3[bu + threadIdx.x];
+        }
+        if (threadIdx.x < 2) red[threadIdx.x] = 0;
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < D) {
+            for (int z = 0; z < W; ++z)
+                FOR_BITS(B[k * W + z], b, {
+                    const int l = z * 64 + b;
+                    atomicOr((unsigned long long*)&C[l * W + (k >> 6)], 1ull << (k & 63));
+                });
+        }
+        __syncthreads();
+        i64 R = 0, du = 0;
+        if (k < D) {
+            const u64* Bk = B + k * W;
+            const u64* Ck = C + k * W;
+            const i32 vk = L[k];
+            i64 from = roff[vk] + lo[vk];
+            const i64 end = roff[vk] + rdeg[vk];
+            i64 M = 0, X = 0, dv = 0;
+            for (int wa = 0; wa < W; ++wa) {
+                FOR_BITS(Bk[wa], bb, {
+                    const int l = wa * 64 + bb;
+                    const u64* Bl = B + l * W;
+                    for (int z = 0; z < W; ++z) R += __popcll(Bk[z] & Bl[z]);
+                    dv += c3u[l] - 1;
+                    du += c3_minus_1(ridx, C3, from, end, L[l]);
+                });
+                FOR_BITS(Ck[wa], bb, {
+                    const int j = wa * 64 + bb;
+                    const u64* Bj = B + j * W;
+                    for (int z = 0; z < W; ++z) {
+                        M += __popcll(Bj[z] & Bk[z]);
+                        X += __popcll(Bj[z] & Ck[z]);
+                    }
+                    dv += c3u[j] - 1;
+                });
+            }
+            const i64 kv = R + M + X;
+            if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
+            if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+        }
+        R = wave_sum(R);
+        du = wave_sum(du);
+        if (lane_id() == 0) {
+            if (R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
+            if (du) atomicAdd((unsigned long long*)&red[1], (unsigned long long)du);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
+            if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
+        }
+        __syncthreads();
+    }
+}
+
+// Bitmap words of every vertex of the wave and LDS tiers (D x ceil(D/64)).
+__global__ void k_bitmap_words(const i64* __restrict__ roff, const i32* __restrict__ lo, i64 n, i64 lds_max,
+                               i64* __restrict__ words) {
+    for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
+        const i64 D = roff[u + 1] - roff[u] - lo[u];
+        words[u] = (D >= 2 && D <= lds_max) ? D * ((D + 63) / 64) : 0;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned tgrid(i64 work, i64 per_block) {
+    return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(work, 1), per_block), 65536));
+}
+
+hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_bitmap_words, dim3(tgrid(n, 256)), dim3(256), 0, s, w.roff, w.lo, n, lds_max, w.bcnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_exclusive_i64(w.bcnt, w.boff, n, w.partials, s);
+}
+
+hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier) {
+    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
+    if (tier == 0 && c0)
+        hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.G,
+                           w.tri_list, c0, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0);
+    if (tier == 1 && c1)
+        hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
+                           w.tri_list + n, c1, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier) {
+    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
+    if (tier == 0 && c0)
+        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
+                           w.tri_list, c0, w.C3, w.k4v, w.d13, w.bstore, w.boff);
+    if (tier == 1 && c1)
+        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
+                           w.tri_list + n, c1, w.C3, w.k4v, w.d13, w.bstore, w.boff);
+    return hipGetLastError();
+}
+
+}  // namespace fglt
