@@ -47,7 +47,8 @@ SEG_UNITS = {
     "tri2_global": ("item", 8),
     "c4_wave": ("wedge", 8),     # wedge end read in the count and attribution passes
     "c4_block": ("wedge", 8),
-    "c4_heavy": ("wedge", 8),
+    "c4_hash": ("wedge", 8),
+    "c4_window": ("wedge", 8),
     "fill": ("entry", 12),       # mirror position, index, C3 copy
     "finalize": ("vertex", 232), # 13 accumulators + degree + id in, 128 B row out
 }
@@ -59,7 +60,7 @@ def seg_units(seg, st):
         return st["nnz"]
     if kind == "vertex":
         return st["n"]
-    tier = {"wave": 0, "lds": 1, "global": 2, "block": 1, "heavy": 2}[seg.split("_")[1]]
+    tier = {"wave": 0, "lds": 1, "global": 2, "block": 1, "hash": 2, "window": 3}[seg.split("_")[1]]
     if kind == "item":
         return st["tri_items_tier"][tier]
     return st["wedge_items_tier"][tier]

@@ -72,7 +72,8 @@ enum {
     FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
     FGLT_SEG_C4_WAVE,        /* 4-cycle pass, wavefront tier                      */
     FGLT_SEG_C4_BLOCK,       /* 4-cycle pass, workgroup tier                      */
-    FGLT_SEG_C4_HEAVY,       /* 4-cycle pass, dense-counter tier                  */
+    FGLT_SEG_C4_HASH,        /* 4-cycle pass, packed-hash workgroup tier          */
+    FGLT_SEG_C4_WINDOW,      /* 4-cycle pass, dense-counter window tier           */
     FGLT_SEG_FINALIZE,       /* Table I assembly, Table II, scatter to caller order */
     FGLT_NSEG
 };
@@ -103,10 +104,10 @@ typedef struct {
     int64_t dplus_max;           /* largest out-degree under the degree ordering          */
     int64_t tri_items;           /* sum over oriented edges u->v of d+(v): merge work    */
     int64_t wedge_items;         /* rank-ordered wedges visited by the 4-cycle pass      */
-    int64_t n_light_tri, n_mid_tri, n_heavy_tri;  /* vertices per clique-pass tier        */
-    int64_t n_light_c4, n_mid_c4, n_heavy_c4;     /* vertices per 4-cycle-pass tier       */
-    int64_t tri_items_tier[3];   /* merge items per clique-pass tier                      */
-    int64_t wedge_items_tier[3]; /* wedges per 4-cycle-pass tier                          */
+    int64_t tri_tier_vertices[3]; /* vertices per triangle/clique tier: wave, LDS, global  */
+    int64_t c4_tier_vertices[4];  /* vertices per 4-cycle tier: wave, block, hash, window  */
+    int64_t tri_items_tier[3];    /* merge items per triangle/clique tier                  */
+    int64_t wedge_items_tier[4];  /* wedges per 4-cycle tier                               */
     int64_t triangles;           /* triangles in the graph                                */
     float seg_ms[FGLT_NSEG];     /* with FGLT_TIMING: milliseconds per launch segment     */
 } fglt_stats;
@@ -115,14 +116,18 @@ typedef struct {
  * with out-degree D (under the degree ordering) is counted by one wavefront if
  * D <= tri_wave_max (<= 64), by a workgroup with LDS bitmaps if
  * D <= tri_lds_max (<= 512), else by a workgroup with bitmaps in the
- * workspace; the 4-cycle pass likewise by its wedge count W against
- * c4_wave_max (<= 128) and c4_block_max (<= 2048).  Any setting gives the
- * same result; only the speed changes. */
+ * workspace.  The 4-cycle pass goes by the number W of rank-ordered wedges of
+ * u: one wavefront if W <= c4_wave_max (<= 128), a workgroup with an LDS hash
+ * if W <= c4_block_max (<= 2048), a large workgroup with a packed LDS hash if
+ * W <= c4_hash_max (<= 16384) and the counts fit the packing, else dense LDS
+ * counters over windows of ranks.  Any setting gives the same result; only
+ * the speed changes. */
 typedef struct {
     int32_t tri_wave_max;   /* default 64   */
     int32_t tri_lds_max;    /* default 512  */
     int32_t c4_wave_max;    /* default 128; -1 disables the tier */
     int32_t c4_block_max;   /* default 2048; -1 disables the tier */
+    int32_t c4_hash_max;    /* default 16384; -1 disables the tier */
 } fglt_raw_plan;
 
 /*

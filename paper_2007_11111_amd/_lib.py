@@ -34,14 +34,15 @@ class FgltError(RuntimeError):
 
 FGLT_TIMING = 2
 SEGMENTS = ["check", "relabel", "structure", "l1", "tri1_wave", "tri1_lds", "tri1_global", "fill", "l2",
-            "tri2_wave", "tri2_lds", "tri2_global", "c4_wave", "c4_block", "c4_heavy", "finalize"]
+            "tri2_wave", "tri2_lds", "tri2_global", "c4_wave", "c4_block", "c4_hash", "c4_window",
+            "finalize"]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
-        "n", "nnz", "d_max", "dplus_max", "tri_items", "wedge_items",
-        "n_light_tri", "n_mid_tri", "n_heavy_tri", "n_light_c4", "n_mid_c4", "n_heavy_c4")] + [
-        ("tri_items_tier", ctypes.c_int64 * 3), ("wedge_items_tier", ctypes.c_int64 * 3),
+        "n", "nnz", "d_max", "dplus_max", "tri_items", "wedge_items")] + [
+        ("tri_tier_vertices", ctypes.c_int64 * 3), ("c4_tier_vertices", ctypes.c_int64 * 4),
+        ("tri_items_tier", ctypes.c_int64 * 3), ("wedge_items_tier", ctypes.c_int64 * 4),
         ("triangles", ctypes.c_int64), ("seg_ms", ctypes.c_float * len(SEGMENTS))]
 
     def as_dict(self):
@@ -50,7 +51,7 @@ class Stats(ctypes.Structure):
             v = getattr(self, name)
             if name == "seg_ms":
                 d[name] = {SEGMENTS[k]: float(v[k]) for k in range(len(SEGMENTS))}
-            elif name.endswith("_tier"):
+            elif name.endswith(("_tier", "_vertices")):
                 d[name] = [int(x) for x in v]
             else:
                 d[name] = int(v)
@@ -59,7 +60,8 @@ class Stats(ctypes.Structure):
 
 class RawPlan(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("tri_lds_max", ctypes.c_int32),
-                ("c4_wave_max", ctypes.c_int32), ("c4_block_max", ctypes.c_int32)]
+                ("c4_wave_max", ctypes.c_int32), ("c4_block_max", ctypes.c_int32),
+                ("c4_hash_max", ctypes.c_int32)]
 
 
 class BatchPlan(ctypes.Structure):

@@ -72,7 +72,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     tm.mark(FGLT_SEG_RELABEL, s);
     FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
     tm.mark(FGLT_SEG_STRUCTURE, s);
-    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan), s));
+    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan, n), s));
     i64 g_total = 0, bitmap_words = 0;
     if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
     if (hipMemcpyAsync(&bitmap_words, w.boff + n, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -111,14 +111,12 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
         stats->dplus_max = hp.dplus_max;
         stats->tri_items = hp.tri_items;
         stats->wedge_items = hp.wedge_items;
-        stats->n_light_tri = hp.n_tri[0];
-        stats->n_mid_tri = hp.n_tri[1];
-        stats->n_heavy_tri = hp.n_tri[2];
-        stats->n_light_c4 = hp.n_c4[0];
-        stats->n_mid_c4 = hp.n_c4[1];
-        stats->n_heavy_c4 = hp.n_c4[2];
         for (int k = 0; k < 3; ++k) {
+            stats->tri_tier_vertices[k] = hp.n_tri[k];
             stats->tri_items_tier[k] = hp.tri_items_tier[k];
+        }
+        for (int k = 0; k < 4; ++k) {
+            stats->c4_tier_vertices[k] = hp.n_c4[k];
             stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
         }
         stats->triangles = triangles;

@@ -1,0 +1,576 @@
+// c4.hip -- the 4-cycle pass: per-vertex 4-cycle counts (C4,2 e / 2, Lemma 5)
+// with their attribution to every vertex of the cycle.
+//
+// Every 4-cycle is found once, from its highest-ranked vertex u, as a pair of
+// rank-ordered wedges u - v - w and u - v' - w with v, v', w < u.  With c(w)
+// the number of wedges of u that end in w (the common neighbours of u and w
+// that rank below u), u gains sum_w C(c(w), 2), each end w gains C(c(w), 2),
+// and each middle v gains, over its wedges u - v - w, the sum of c(w) - 1.
+//
+// Tiers by the wedge count W(u) = sum over v in N-(u) of |N(v) below u|:
+//   wave    W <= 128     one wavefront per vertex, 256-slot LDS hash
+//   block   W <= 2048    one 256-thread workgroup per vertex, 4096-slot hash
+//   hash    W <= 16384   one 1024-thread workgroup per vertex, 32768-slot hash
+//                        of packed (end rank, count) words
+//   window  beyond       dense LDS counters over windows of consecutive ranks;
+//                        one workgroup per vertex (all windows in turn) when
+//                        its middles fit one 1024-thread chunk, else one per
+//                        (vertex, window)
+// The two large-workgroup tiers flatten the wedge runs of up to 1024 middles
+// (middle v of u contributes the run of N(v) below u, or its part inside the
+// window) with one block scan and walk them 64 consecutive items per
+// wavefront step, so the reads of each run are coalesced.
+#include <algorithm>
+#include <climits>
+
+#include "walk.h"
+
+namespace fglt {
+
+static constexpr int PT = 256;
+
+// ------------------------------------------------------------ small tiers
+
+// Wedge item t of vertex u (N- entries in [b, m)): the entry q = (u, v) and the
+// wedge end w = the o-th neighbour of v.
+__device__ __forceinline__ void wedge_item(const i64* __restrict__ G, const i64* __restrict__ roff,
+                                           const i32* __restrict__ ridx, i64 b, i64 m, i64 g, i64& q, i32& w) {
+    q = last_le_dev(G, b, m - 1, g);
+    const i32 v = ridx[q];
+    w = ridx[roff[v] + (g - G[q])];
+}
+
+// LDS-hash tiers.  WAVES_PER_U = 1: one wavefront per vertex (4 per block,
+// 256-slot table each); WAVES_PER_U = 4: the whole block on one vertex with a
+// 4096-slot table.
+template <int WAVES_PER_U, int HSLOTS>
+__global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                const i32* __restrict__ list, u32 count, i64* __restrict__ c4v) {
+    constexpr int NW = PT / WAVE;
+    constexpr int GROUPS = NW / WAVES_PER_U;  // vertices per block
+    constexpr int GT = WAVES_PER_U * WAVE;    // threads per vertex
+    __shared__ i32 hk[GROUPS][HSLOTS];
+    __shared__ i32 hc[GROUPS][HSLOTS];
+    __shared__ i64 red[GROUPS];
+    const int grp = threadIdx.x / GT;
+    const int gt = threadIdx.x % GT;
+    const u32 mask = HSLOTS - 1;
+    for (i64 base = (i64)blockIdx.x * GROUPS; base < (i64)count; base += (i64)gridDim.x * GROUPS) {
+        const i64 it = base + grp;
+        const bool valid = it < (i64)count;
+        i64 u = 0, b = 0, m = 0, gb = 0, W = 0;
+        if (valid) {
+            u = list[it];
+            b = roff[u];
+            m = b + lo[u];
+            gb = G[b];
+            W = G[m] - gb;
+        }
+        for (int s = gt; s < HSLOTS; s += GT) {
+            hk[grp][s] = -1;
+            hc[grp][s] = 0;
+        }
+        if (gt == 0) red[grp] = 0;
+        __syncthreads();
+        // pass A: count wedge ends
+        for (i64 t = gt; t < W; t += GT) {
+            i64 q;
+            i32 w;
+            wedge_item(G, roff, ridx, b, m, gb + t, q, w);
+            hash_add(hk[grp], hc[grp], mask, w);
+        }
+        __syncthreads();
+        // pass B: C(cnt, 2) to u and to w
+        i64 accu = 0;
+        for (int s = gt; s < HSLOTS; s += GT) {
+            const i32 w = hk[grp][s];
+            if (w >= 0) {
+                const i64 c = hc[grp][s];
+                if (c >= 2) {
+                    const i64 pr = c * (c - 1) / 2;
+                    accu += pr;
+                    atomicAdd((unsigned long long*)&c4v[w], (unsigned long long)pr);
+                }
+            }
+        }
+        // pass C: cnt(w) - 1 to the middle vertex of every wedge
+        for (i64 t0 = 0; t0 < W; t0 += GT) {
+            const i64 t = t0 + gt;
+            const bool act = t < W;
+            i64 q = -1, val = 0;
+            if (act) {
+                i32 w;
+                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
+                val = hash_get(hk[grp], hc[grp], mask, w) - 1;
+            }
+            val = wave_seg_scan(val, q);
+            if (wave_seg_tail(q, act) && val) atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)val);
+        }
+        accu = wave_sum(accu);
+        if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red[grp], (unsigned long long)accu);
+        __syncthreads();
+        if (valid && gt == 0 && red[grp]) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red[grp]);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ large-workgroup tiers
+
+static constexpr int CB_THREADS = 1024;
+static constexpr int CB_NWV = CB_THREADS / WAVE;
+
+__device__ __forceinline__ i32 wave_min_i32(i32 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ i32 wave_max_i32(i32 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// LDS state of the flattened wedge runs of one chunk of middles.
+struct RunLds {
+    i64 rbase[CB_THREADS + 1];  // item t of run r sits at ridx[rbase[r] + t]
+    i32 rmid[CB_THREADS + 1];   // middle vertex of run r
+    i32 rstart[CB_THREADS + 1]; // first item of run r; rstart[nruns] = item count
+    i32 flags[CB_NWV][WAVE];    // run-start exchange rows of the walk
+    i64 wsum[CB_NWV];
+    i64 total;
+    i32 nruns;
+};
+
+// Compacts the wedge runs of middles c0 .. c0+1023 of the current vertex
+// (middle k < L).  run(k, v, s0, len) gives middle k's vertex and its wedge
+// ends ridx[s0 .. s0+len).  The non-empty runs are kept in middle order; one
+// block scan of (items << 16 | non-empty) gives both prefixes.  Returns the
+// item count.  Every thread of the block calls it.
+template <class RunOf>
+__device__ __forceinline__ i32 flatten_runs(i32 L, i32 c0, RunOf&& run, RunLds& R) {
+    const i32 k = c0 + (i32)threadIdx.x;
+    i32 len = 0, v = 0;
+    i64 s0 = 0;
+    if (k < L) run(k, v, s0, len);
+    const i64 packed = ((i64)len << 16) | (len > 0 ? 1 : 0);
+    const i64 pre = block_scan<CB_THREADS>(packed, R.wsum, &R.total);
+    const i64 tot = R.total;
+    const i32 items_before = (i32)(pre >> 16), runs_before = (i32)(pre & 0xffff);
+    if (len > 0) {
+        R.rbase[runs_before] = s0 - items_before;
+        R.rmid[runs_before] = v;
+        R.rstart[runs_before] = items_before;
+    }
+    const i32 T = (i32)(tot >> 16);
+    if (threadIdx.x == 0) {
+        R.nruns = (i32)(tot & 0xffff);
+        R.rstart[tot & 0xffff] = T;
+    }
+    __syncthreads();
+    return T;
+}
+
+// Items of the chunk handled by wavefront wv: [ta, tb), a multiple of 64 wide.
+__device__ __forceinline__ void wave_share(i32 T, i32& ta, i32& tb) {
+    const i32 per = ((T + CB_THREADS - 1) / CB_THREADS) * WAVE;
+    const i32 wv = (i32)threadIdx.x / WAVE;
+    ta = min(T, wv * per);
+    tb = min(T, (wv + 1) * per);
+}
+
+// Pass C walk: every wedge item gives cnt(w) - 1 to its middle; the sums of
+// each run's piece in a wavefront step come from a wave prefix sum and the
+// run-start mask, one global atomic per piece.
+template <class Get>
+__device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* __restrict__ ridx,
+                                                  i64* __restrict__ c4v, Get&& get) {
+    i32 ta, tb;
+    wave_share(T, ta, tb);
+    const int l = lane_id();
+    const int wv = (int)threadIdx.x / WAVE;
+    run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
+                [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask) {
+                    const i64 val = act ? (i64)get(w) - 1 : 0;
+                    i64 P = val;  // inclusive prefix over the wave
+#pragma unroll
+                    for (int o = 1; o < WAVE; o <<= 1) {
+                        const i64 y = __shfl_up(P, o, WAVE);
+                        if (l >= o) P += y;
+                    }
+                    const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
+                    const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this run piece
+                    const i64 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+                    const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tb);
+                    const i64 sum = P - (sl > 0 ? before : 0);
+                    if (tail && sum) atomicAdd((unsigned long long*)&c4v[R.rmid[r]], (unsigned long long)sum);
+                });
+}
+
+// ---- hash tier: packed words (end rank << cb) | count, 0 when empty.  The
+// count of an end is at most |N-(u)|, which the tier assignment keeps below
+// 2^cb; at most 16384 distinct ends keep the table at most half full.
+
+static constexpr int C4H_BITS = 15;
+static constexpr int C4H_SLOTS = 1 << C4H_BITS;  // 128 KiB
+
+__device__ __forceinline__ u32 c4h_slot(i32 w) { return ((u32)w * 2654435761u) >> (32 - C4H_BITS); }
+
+__device__ __forceinline__ void c4h_add(u32* tab, i32 w, int cb) {
+    u32 h = c4h_slot(w);
+    while (true) {
+        u32 e = tab[h];
+        if (e == 0) {
+            const u32 old = atomicCAS(&tab[h], 0u, ((u32)w << cb) | 1u);
+            if (old == 0) return;
+            e = old;
+        }
+        if ((e >> cb) == (u32)w) {  // the key bits of a word never change once set
+            atomicAdd(&tab[h], 1u);
+            return;
+        }
+        h = (h + 1) & (C4H_SLOTS - 1);
+    }
+}
+
+__device__ __forceinline__ u32 c4h_get(const u32* tab, i32 w, int cb) {
+    u32 h = c4h_slot(w);
+    while (true) {
+        const u32 e = tab[h];
+        if (e == 0) return 0;
+        if ((e >> cb) == (u32)w) return e & ((1u << cb) - 1u);
+        h = (h + 1) & (C4H_SLOTS - 1);
+    }
+}
+
+__global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                           const i32* __restrict__ list, u32 count,
+                                                           u32* __restrict__ job_ctr, int cb, i64* __restrict__ c4v) {
+    __shared__ u32 tab[C4H_SLOTS];
+    __shared__ RunLds R;
+    __shared__ i64 sj, red;
+    const u32 cmask = (1u << cb) - 1u;
+    for (int q = threadIdx.x; q < C4H_SLOTS; q += CB_THREADS) tab[q] = 0;
+    if (threadIdx.x == 0) {
+        sj = atomicAdd(job_ctr, 1u);
+        red = 0;
+    }
+    __syncthreads();
+    while (true) {
+        const i64 j = sj;
+        if (j >= (i64)count) break;
+        u32 nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(job_ctr, 1u);  // consumed at the end of this job
+        const i32 u = list[j];
+        const i64 b = roff[u];
+        const i32 L = lo[u];
+        const i32 nch = (L + CB_THREADS - 1) / CB_THREADS;
+        auto run_of = [&](i32 k, i32& v, i64& s0, i32& len) {
+            v = ridx[b + k];
+            s0 = roff[v];
+            len = rpos[b + k];  // neighbours of v below u: the first rpos entries of row v
+        };
+        // pass A: count the wedge ends
+        i32 T = 0;
+        for (i32 ch = 0; ch < nch; ++ch) {
+            T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+            i32 ta, tb;
+            wave_share(T, ta, tb);
+            run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[threadIdx.x / WAVE], ridx,
+                        [&](bool act, i32, i32, i32 w, i64, u64) {
+                            if (act) c4h_add(tab, w, cb);
+                        });
+            __syncthreads();
+        }
+        // pass B: C(c, 2) to every end w and to u
+        i64 accu = 0;
+        for (int q = threadIdx.x; q < C4H_SLOTS; q += CB_THREADS) {
+            const u32 e = tab[q];
+            const i64 c = e & cmask;
+            if (c >= 2) {
+                const i64 pr = c * (c - 1) / 2;
+                accu += pr;
+                atomicAdd((unsigned long long*)&c4v[e >> cb], (unsigned long long)pr);
+            }
+        }
+        // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
+        for (i32 ch = 0; ch < nch; ++ch) {
+            if (nch > 1) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+            attribute_middles(T, R, ridx, c4v, [&](i32 w) { return c4h_get(tab, w, cb); });
+            if (nch > 1) __syncthreads();
+        }
+        accu = wave_sum(accu);
+        if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
+        __syncthreads();
+        for (int q = threadIdx.x; q < C4H_SLOTS; q += CB_THREADS) tab[q] = 0;
+        if (threadIdx.x == 0) {
+            if (red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
+            red = 0;
+            sj = nxt;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- window tier: dense counters for the ranks [W0, W0 + WS) of one window,
+// 16-bit halves of 32-bit words when every count fits 16 bits (d_max < 65536).
+
+static constexpr int C4W_WORDS = 32768;  // 128 KiB
+
+template <bool PACK16>
+__device__ __forceinline__ void c4w_inc(u32* cnt, i32 x) {
+    if (PACK16) atomicAdd(&cnt[x >> 1], 1u << ((x & 1) << 4));
+    else atomicAdd(&cnt[x], 1u);
+}
+
+template <bool PACK16>
+__device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
+    if (PACK16) return (cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu;
+    return cnt[x];
+}
+
+// Last index h in [0, cnt) with a[h] <= key, for a non-decreasing a with
+// a[0] <= key.  The whole wavefront searches, 64 probes per round, so a list
+// of N entries takes about log64(N) dependent loads.
+__device__ __forceinline__ i64 wave_last_le(const i64* __restrict__ a, i64 cnt, i64 key) {
+    i64 lo_ = 0, hi_ = cnt;  // the answer lies in [lo_, hi_)
+    while (hi_ - lo_ > 1) {
+        const i64 step = (hi_ - lo_ + WAVE - 1) / WAVE;
+        const i64 p = lo_ + (i64)lane_id() * step;
+        const bool ok = p < hi_ && a[p] <= key;
+        const int c = __popcll(__ballot(ok));  // lanes 0 .. c-1 hold probes <= key
+        lo_ += (i64)(c - 1) * step;
+        hi_ = min(hi_, lo_ + step);
+    }
+    return lo_;
+}
+
+// Jobs: window-tier vertices in descending rank order (hs holds them in
+// ascending order); a vertex whose middles fit one chunk is one job over all
+// its windows, top window first; a larger one is one job per window.
+template <bool PACK16, bool TAB>
+__global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                          const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                          const i32* __restrict__ tab, i64 K1,
+                                                          const i32* __restrict__ hs, u32 nh,
+                                                          const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
+                                                          i64* __restrict__ c4v) {
+    constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
+    __shared__ u32 cnt[C4W_WORDS];
+    __shared__ RunLds R;
+    __shared__ i64 sj, sh, red;
+    __shared__ i32 wlo, whi;
+    const int wv = threadIdx.x / WAVE, l = lane_id();
+    const i64 njobs = jobpre[nh];
+    for (int q = threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
+    if (wv == 0) {
+        i64 j = 0;
+        if (l == 0) j = atomicAdd(job_ctr, 1u);
+        j = __shfl(j, 0, WAVE);
+        const i64 h = j < njobs ? wave_last_le(jobpre, nh, j) : 0;
+        if (l == 0) {
+            sj = j;
+            sh = h;
+            red = 0;
+            wlo = INT_MAX;
+            whi = -1;
+        }
+    }
+    __syncthreads();
+    while (true) {
+        const i64 j = sj, h = sh;
+        if (j >= njobs) break;
+        u32 nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(job_ctr, 1u);  // consumed at the end of this job
+        const i32 u = hs[nh - 1 - h];
+        const i64 b = roff[u];
+        const i32 L = lo[u];
+        const i32 nwin = (i32)(((i64)u + WS - 1) / WS);
+        const bool single = L <= CB_THREADS;
+        const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
+        const i32 wtop = single ? nwin - 1 : nwin - 1 - (i32)(j - jobpre[h]);
+        const i32 wbot = single ? 0 : wtop;
+        // one chunk: thread k keeps middle k and the end of its not yet
+        // visited run (windows go top-down, so each run ends where the
+        // previous window's run began)
+        i32 mv = 0, mcut = 0;
+        i64 mrs = 0, mhi = 0;
+        if (single && (i32)threadIdx.x < L) {
+            mv = ridx[b + threadIdx.x];
+            mrs = roff[mv];
+            mcut = rpos[b + threadIdx.x];
+            mhi = mrs + mcut;
+        }
+        i64 accu = 0;
+        for (i32 win = wtop; win >= wbot; --win) {
+            const i32 W0 = win * WS;
+            const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
+            auto run_of = [&](i32 k, i32& v, i64& s0, i32& len) {
+                if (single) {
+                    const i64 a0 = TAB ? mrs + std::min(tab[(i64)mv * K1 + win], mcut)
+                                       : lower_bound_dev(ridx, mrs, mhi, W0);
+                    v = mv;
+                    s0 = a0;
+                    len = (i32)(mhi - a0);
+                    mhi = a0;
+                } else {
+                    v = ridx[b + k];
+                    const i64 rs = roff[v];
+                    const i32 cut = rpos[b + k];
+                    if (TAB) {
+                        const i32 a0 = std::min(tab[(i64)v * K1 + win], cut);
+                        const i32 a1 = std::min(tab[(i64)v * K1 + win + 1], cut);
+                        s0 = rs + a0;
+                        len = a1 - a0;
+                    } else {
+                        const i64 re = rs + cut;
+                        s0 = lower_bound_dev(ridx, rs, re, W0);
+                        len = (i32)(lower_bound_dev(ridx, s0, re, W1) - s0);
+                    }
+                }
+            };
+            // pass A: count the wedge ends inside the window, note the touched range
+            i32 T = 0, lmin = INT_MAX, lmax = -1;
+            for (i32 ch = 0; ch < nch; ++ch) {
+                T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                i32 ta, tb;
+                wave_share(T, ta, tb);
+                run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
+                            [&](bool act, i32, i32, i32 w, i64, u64) {
+                                if (act) {
+                                    c4w_inc<PACK16>(cnt, w - W0);
+                                    lmin = min(lmin, w);
+                                    lmax = max(lmax, w);
+                                }
+                            });
+                if (!single) __syncthreads();  // the next chunk overwrites the runs
+            }
+            lmin = wave_min_i32(lmin);
+            lmax = wave_max_i32(lmax);
+            if (l == 0 && lmax >= 0) {
+                atomicMin(&wlo, lmin);
+                atomicMax(&whi, lmax);
+            }
+            __syncthreads();
+            const i32 xlo = wlo - W0, xhi = whi - W0;
+            if (xhi < xlo) continue;  // no wedge end in this window (block-uniform)
+            // pass B: C(c, 2) to every end w and to u, over the touched range
+            for (i32 x = xlo + (i32)threadIdx.x; x <= xhi; x += CB_THREADS) {
+                const i64 c = c4w_get<PACK16>(cnt, x);
+                if (c >= 2) {
+                    const i64 pr = c * (c - 1) / 2;
+                    accu += pr;
+                    atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+                }
+            }
+            // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
+            for (i32 ch = 0; ch < nch; ++ch) {
+                if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                attribute_middles(T, R, ridx, c4v, [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
+                if (!single) __syncthreads();
+            }
+            __syncthreads();
+            // clear the touched counters for the next window
+            const i32 q0 = PACK16 ? xlo >> 1 : xlo, q1 = PACK16 ? xhi >> 1 : xhi;
+            for (i32 q = q0 + (i32)threadIdx.x; q <= q1; q += CB_THREADS) cnt[q] = 0;
+            if (threadIdx.x == 0) {
+                wlo = INT_MAX;
+                whi = -1;
+            }
+        }
+        accu = wave_sum(accu);
+        if (l == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
+            red = 0;
+        }
+        if (wv == 0) {  // decode the next job
+            const i64 nj = __shfl((i64)nxt, 0, WAVE);
+            const i64 nhh = nj < njobs ? wave_last_le(jobpre, nh, nj) : 0;
+            if (l == 0) {
+                sj = nj;
+                sh = nhh;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Window table: tab[v * K1 + k] = number of neighbours of v with rank below k * WS.
+__global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 WS,
+                           i32* __restrict__ tab) {
+    const i64 total = n * K1;
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
+        const i64 v = q / K1, k = q - v * K1;
+        const i64 b = roff[v], e = roff[v + 1];
+        const i64 key = k * WS;
+        tab[q] = (i32)(key >= n ? e - b : lower_bound_dev(ridx, b, e, key) - b);
+    }
+}
+
+__global__ void k_set_pair(i64* p, i64 a, i64 b) {
+    p[0] = a;
+    p[1] = b;
+}
+
+// Jobs per window-tier vertex, in descending vertex order.
+__global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS,
+                          i64* __restrict__ jobcnt) {
+    for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (i64)gridDim.x * blockDim.x) {
+        const i64 u = hs[nh - 1 - h];
+        jobcnt[h] = lo[u] <= CB_THREADS ? 1 : (u + WS - 1) / WS;
+    }
+}
+
+// ------------------------------------------------------------ launcher
+
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm) {
+    (void)nnz;
+    const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
+    hipError_t e;
+    if (c2 || c3)
+        if ((e = hipMemsetAsync(w.c4_jobctr, 0, 2 * sizeof(u32), s)) != hipSuccess) return e;
+    tm.mark(FGLT_SEG_C4_WAVE, s);
+    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
+                               w.G, w.c4_list, c0, w.c4v);
+    tm.mark(FGLT_SEG_C4_BLOCK, s);
+    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+                               w.lo, w.G, w.c4_list + n, c1, w.c4v);
+    tm.mark(FGLT_SEG_C4_HASH, s);
+    if (c2) {
+        const int cb = 32 - std::max(1, bits_for_n(n));
+        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
+                           w.rpos, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
+    }
+    tm.mark(FGLT_SEG_C4_WINDOW, s);
+    if (c3) {
+        // window-tier vertices in ascending order, then the job counts
+        i32* hs = w.c4_list + 3 * n;
+        hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c3);
+        if ((e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), w.sort, 1, s)) != hipSuccess) return e;
+        const bool pack16 = hp.d_max < 65536;
+        const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
+        const i64 K1 = (n + WS - 1) / WS + 1;
+        const bool use_tab = w.c4_tab != nullptr && n * K1 <= w.c4_tab_cap;
+        if (use_tab)
+            hipLaunchKernelGGL(k_c4_table, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n, K1,
+                               WS, w.c4_tab);
+        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS, w.c4_jobcnt);
+        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
+        const unsigned grid = 512;
+#define C4W_LAUNCH(P16, TB)                                                                                    \
+    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
+                       w.c4_tab, K1, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4v)
+        if (pack16 && use_tab) C4W_LAUNCH(true, true);
+        else if (pack16) C4W_LAUNCH(true, false);
+        else if (use_tab) C4W_LAUNCH(false, true);
+        else C4W_LAUNCH(false, false);
+#undef C4W_LAUNCH
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fglt

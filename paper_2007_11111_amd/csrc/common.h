@@ -36,6 +36,12 @@ enum : u32 {
 };
 
 static inline i64 ceil_div(i64 a, i64 b) { return (a + b - 1) / b; }
+
+// Grid size for `work` items at `per_block` items per workgroup, at least 1, at most cap.
+static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
+    const i64 g = ceil_div(work > 1 ? work : 1, per_block);
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Linear allocator over a caller-provided workspace (256-byte aligned pieces).

@@ -16,6 +16,7 @@ constexpr int TRI_WAVE_MAX = 64;     // out-degree handled by one wavefront (one
 constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup's LDS
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
+constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
 constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
 
 // Device statistics / plan words (one small block of device memory).
@@ -28,9 +29,9 @@ struct DevPlan {
     i64 tri_items;
     i64 wedge_items;
     u32 n_tri[3];  // wave, lds, global tiers
-    u32 n_c4[3];   // wave, block, heavy tiers
+    u32 n_c4[4];   // wave, block, hash, window tiers
     i64 tri_items_tier[3];
-    i64 wedge_items_tier[3];
+    i64 wedge_items_tier[4];
     i64 triangles;
 };
 
@@ -53,14 +54,14 @@ struct RawWs {
     i64 *sumd, *s7, *c3v, *ap2, *ac3, *d10, *d14, *d13, *c4v, *k4v;
     // work lists
     i32* tri_list;  // [3][n]
-    i32* c4_list;   // [3][n]
+    i32* c4_list;   // [4][n]
     // heavy-tier scratch
     u64* tri_slots;     // NUM_TRI_SLOTS * tri_slot_words
     i64 tri_slot_words;
-    i64* c4_segoff;     // [2] one segment over the heavy list
-    i64* c4_jobcnt;     // [n] windows per heavy vertex
+    i64* c4_segoff;     // [2] one segment over the window-tier list
+    i64* c4_jobcnt;     // [n] jobs per window-tier vertex
     i64* c4_jobpre;     // [n+1] their exclusive scan
-    u32* c4_jobctr;     // job queue head
+    u32* c4_jobctr;     // [4] job queue heads: window tier, hash tier
     i64* bcnt;          // [n] bitmap words per vertex (clique pass store)
     i64* boff;          // [n+1] their exclusive scan
     u64* bstore;        // stored N+ bitmaps of the wave and LDS tiers
@@ -80,9 +81,11 @@ hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, Ra
 hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
                                    hipStream_t s);
 struct Tiers {
-    i64 tri_wave, tri_lds, c4_wave, c4_block;
+    i64 tri_wave, tri_lds, c4_wave, c4_block, c4_hash;
+    i64 c4_hash_lmax;  // largest |N-(u)| whose counts fit the packed hash words
 };
-Tiers tiers_from_plan(const fglt_raw_plan* plan);
+Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n);
+int bits_for_n(i64 n);   // bits of the largest rank n - 1 (0 for n <= 1)
 hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, hipStream_t s);
 
 // counting (raw_count.hip)

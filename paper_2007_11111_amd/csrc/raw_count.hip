@@ -8,9 +8,8 @@
 //   TRI mode 2:     the induced subgraph on N+(u) as LDS bitmaps; per vertex
 //                   4-cliques (T e / 6, Section IV-C) and off-cord diamonds
 //                   (D4,c e / 2) attributed to all four / three vertices
-//   C4:             rank-ordered wedges u - v - w with v, w < u, counted in an
-//                   LDS hash (or a dense global array for heavy u); 4-cycles
-//                   (C4,2 e / 2, Lemma 5) attributed to u, w and the middles
+//   C4:             (c4.hip) rank-ordered wedges u - v - w with v, w < u;
+//                   4-cycles (C4,2 e / 2, Lemma 5) attributed to u, w and the middles
 //   FINALIZE:       Table I assembled per vertex, Table II back-substitution,
 //                   rows scattered back to the caller's vertex order
 #include <algorithm>
@@ -21,15 +20,6 @@ namespace fglt {
 
 static constexpr int PT = 256;
 
-static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
-    return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(work, 1), per_block), cap));
-}
-
-static int bits_for_n(i64 n) {
-    int b = 0;
-    while (b < 31 && (((i64)1 << b) <= n - 1)) ++b;
-    return b;
-}
 
 __device__ __forceinline__ void fence_agent() { __threadfence(); }
 
@@ -392,308 +382,6 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
     }
 }
 
-// ------------------------------------------------------------ 4-cycle pass
-
-// Wedge item t of vertex u (N- entries in [b, m)): the entry q = (u, v) and the
-// wedge end w = the o-th neighbour of v.
-__device__ __forceinline__ void wedge_item(const i64* __restrict__ G, const i64* __restrict__ roff,
-                                           const i32* __restrict__ ridx, i64 b, i64 m, i64 g, i64& q, i32& w) {
-    q = last_le_dev(G, b, m - 1, g);
-    const i32 v = ridx[q];
-    w = ridx[roff[v] + (g - G[q])];
-}
-
-// LDS-hash tiers.  WAVES_PER_U = 1: one wavefront per vertex (4 per block,
-// 256-slot table each); WAVES_PER_U = 4: the whole block on one vertex with a
-// 4096-slot table.
-template <int WAVES_PER_U, int HSLOTS>
-__global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                const i32* __restrict__ lo, const i64* __restrict__ G,
-                                                const i32* __restrict__ list, u32 count, i64* __restrict__ c4v) {
-    constexpr int NW = PT / WAVE;
-    constexpr int GROUPS = NW / WAVES_PER_U;  // vertices per block
-    constexpr int GT = WAVES_PER_U * WAVE;    // threads per vertex
-    __shared__ i32 hk[GROUPS][HSLOTS];
-    __shared__ i32 hc[GROUPS][HSLOTS];
-    __shared__ i64 red[GROUPS];
-    const int grp = threadIdx.x / GT;
-    const int gt = threadIdx.x % GT;
-    const u32 mask = HSLOTS - 1;
-    for (i64 base = (i64)blockIdx.x * GROUPS; base < (i64)count; base += (i64)gridDim.x * GROUPS) {
-        const i64 it = base + grp;
-        const bool valid = it < (i64)count;
-        i64 u = 0, b = 0, m = 0, gb = 0, W = 0;
-        if (valid) {
-            u = list[it];
-            b = roff[u];
-            m = b + lo[u];
-            gb = G[b];
-            W = G[m] - gb;
-        }
-        for (int s = gt; s < HSLOTS; s += GT) {
-            hk[grp][s] = -1;
-            hc[grp][s] = 0;
-        }
-        if (gt == 0) red[grp] = 0;
-        __syncthreads();
-        // pass A: count wedge ends
-        for (i64 t = gt; t < W; t += GT) {
-            i64 q;
-            i32 w;
-            wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-            hash_add(hk[grp], hc[grp], mask, w);
-        }
-        __syncthreads();
-        // pass B: C(cnt, 2) to u and to w
-        i64 accu = 0;
-        for (int s = gt; s < HSLOTS; s += GT) {
-            const i32 w = hk[grp][s];
-            if (w >= 0) {
-                const i64 c = hc[grp][s];
-                if (c >= 2) {
-                    const i64 pr = c * (c - 1) / 2;
-                    accu += pr;
-                    atomicAdd((unsigned long long*)&c4v[w], (unsigned long long)pr);
-                }
-            }
-        }
-        // pass C: cnt(w) - 1 to the middle vertex of every wedge
-        for (i64 t0 = 0; t0 < W; t0 += GT) {
-            const i64 t = t0 + gt;
-            const bool act = t < W;
-            i64 q = -1, val = 0;
-            if (act) {
-                i32 w;
-                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-                val = hash_get(hk[grp], hc[grp], mask, w) - 1;
-            }
-            val = wave_seg_scan(val, q);
-            if (wave_seg_tail(q, act) && val) atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)val);
-        }
-        accu = wave_sum(accu);
-        if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red[grp], (unsigned long long)accu);
-        __syncthreads();
-        if (valid && gt == 0 && red[grp]) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red[grp]);
-        __syncthreads();
-    }
-}
-
-// Heavy tier: jobs (u, window) with u a vertex of large wedge count and the
-// window a range of WS consecutive ranks for the wedge end w.  One 1024-thread
-// workgroup per job counts the ends of u's wedges inside the window in dense
-// LDS counters (16-bit halves of 32-bit words when every count fits 16 bits),
-// so no global atomics touch the counts.  For every middle vertex v in N-(u)
-// the wedge ends inside the window are one contiguous run of row v, found by
-// two binary searches; the runs of 1024 middles at a time are flattened by a
-// block scan and walked in contiguous per-thread chunks.  Pass A counts, pass
-// B turns each count c into C(c, 2) for u and for w, pass C gives every middle
-// v the sum of (c - 1) over its wedges.  Jobs are pulled from a device queue,
-// largest vertices and highest windows first.
-static constexpr int C4W_THREADS = 1024;
-static constexpr int C4W_CHUNK = 16;
-static constexpr int C4W_WORDS = 32768;  // 128 KiB of counters
-
-template <bool PACK16>
-__device__ __forceinline__ void c4w_inc(u32* cnt, i32 x) {
-    if (PACK16) atomicAdd(&cnt[x >> 1], 1u << ((x & 1) << 4));
-    else atomicAdd(&cnt[x], 1u);
-}
-
-template <bool PACK16>
-__device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
-    if (PACK16) return (cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu;
-    return cnt[x];
-}
-
-// Computes the runs of middles c0 .. c0+1023 of u inside [W0, W1), keeps the
-// non-empty ones in LDS (ridx base such that item t of run r sits at
-// base[r] + t, middle vertex, first item) and the smallest and largest wedge
-// end seen; returns the item count (run count in *nruns, rstart[nruns] = count).
-// With a window table the run bounds are two table reads; otherwise two binary
-// searches in the row.
-template <bool TAB>
-__device__ __forceinline__ i32 c4w_runs(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                        const i32* __restrict__ rpos, const i32* __restrict__ tab, i64 K1,
-                                        i32 win, i64 b, i32 L, i32 c0, i32 W0, i32 W1, i64* rbase, i32* rmid,
-                                        i32* rstart, i32* wsum, i32* stotal, i32* nruns, i32* wlo, i32* whi) {
-    const i32 k = c0 + (i32)threadIdx.x;
-    i32 len = 0;
-    i64 s0 = 0;
-    i32 v = 0;
-    if (k < L) {
-        v = ridx[b + k];
-        const i64 rs = roff[v];
-        const i32 cut = rpos[b + k];  // neighbours of v below u
-        if (TAB) {
-            const i32 a0 = tab[(i64)v * K1 + win];
-            const i32 a1 = min(tab[(i64)v * K1 + win + 1], cut);
-            s0 = rs + a0;
-            len = a1 > a0 ? a1 - a0 : 0;
-        } else {
-            const i64 re = rs + cut;
-            s0 = lower_bound_dev(ridx, rs, re, W0);
-            len = (i32)(lower_bound_dev(ridx, s0, re, W1) - s0);
-        }
-    }
-    if (len > 0) {
-        atomicMin(wlo, ridx[s0]);
-        atomicMax(whi, ridx[s0 + len - 1]);
-    }
-    const i32 pre = block_scan_1024(len, wsum, stotal);
-    const i32 T = *stotal;
-    __syncthreads();
-    const i32 cidx = block_scan_1024(len > 0 ? 1 : 0, wsum, stotal);
-    if (len > 0) {
-        rbase[cidx] = s0 - pre;
-        rmid[cidx] = v;
-        rstart[cidx] = pre;
-    }
-    if (threadIdx.x == 0) {
-        *nruns = *stotal;
-        rstart[*stotal] = T;
-    }
-    __syncthreads();
-    return T;
-}
-
-template <bool PACK16, bool TAB>
-__global__ void __launch_bounds__(C4W_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
-                                                           const i32* __restrict__ tab, i64 K1,
-                                                           const i32* __restrict__ heavy_sorted, u32 nheavy,
-                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
-                                                           i64* __restrict__ c4v) {
-    constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
-    constexpr int NWV = C4W_THREADS / WAVE;
-    __shared__ u32 cnt[C4W_WORDS];
-    __shared__ i64 rbase[C4W_THREADS + 1];
-    __shared__ i32 rmid[C4W_THREADS + 1];
-    __shared__ i32 rstart[C4W_THREADS + 1];
-    __shared__ i32 flags[NWV][WAVE];
-    __shared__ i32 wsum[C4W_THREADS / WAVE];
-    __shared__ i32 stotal, nruns, wlo, whi;
-    __shared__ i64 sjob;
-    __shared__ i64 red;
-    const i64 njobs = jobpre[nheavy];
-    const int wv = threadIdx.x / WAVE;
-    const int l = lane_id();
-    while (true) {
-        if (threadIdx.x == 0) {
-            sjob = (i64)atomicAdd(job_ctr, 1u);
-            red = 0;
-            wlo = 0x7fffffff;
-            whi = -1;
-        }
-        __syncthreads();
-        const i64 j = sjob;
-        if (j >= njobs) break;
-        // job j -> (heavy vertex, window), heaviest vertices first, top windows first
-        const i64 h = last_le_dev(jobpre, 0, (i64)nheavy - 1, j);
-        const i64 u = heavy_sorted[nheavy - 1 - h];
-        const i64 nwin = jobpre[h + 1] - jobpre[h];
-        const i32 win = (i32)(nwin - 1 - (j - jobpre[h]));
-        const i32 W0 = win * WS;
-        const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
-        const i64 b = roff[u];
-        const i32 L = lo[u];
-        const bool one_chunk = L <= C4W_THREADS;
-        i32 T = 0;
-        if (one_chunk) {
-            // all middles fit one chunk: runs first, then clear only the touched range
-            T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, 0, W0, W1, rbase, rmid, rstart, wsum, &stotal,
-                              &nruns, &wlo, &whi);
-            if (T == 0) continue;  // T is block-uniform (LDS)
-            const i32 q0 = PACK16 ? (wlo - W0) >> 1 : wlo - W0;
-            const i32 q1 = PACK16 ? (whi - W0) >> 1 : whi - W0;
-            for (i32 q = q0 + threadIdx.x; q <= q1; q += C4W_THREADS) cnt[q] = 0;
-        } else {
-            for (int q = threadIdx.x; q < C4W_WORDS; q += C4W_THREADS) cnt[q] = 0;
-        }
-        __syncthreads();
-        // pass A: count the wedge ends in the window
-        for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
-            if (!one_chunk)
-                T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, c0, W0, W1, rbase, rmid, rstart, wsum,
-                                  &stotal, &nruns, &wlo, &whi);
-            const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
-            run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, nruns, flags[wv], ridx,
-                        [&](bool act, i32, i32, i32 w, i64, u64) {
-                            if (act) c4w_inc<PACK16>(cnt, w - W0);
-                        });
-            __syncthreads();
-        }
-        // pass B: C(c, 2) to u and to w, over the touched range only (empty when
-        // no middle has a wedge end in the window: then whi < wlo)
-        i64 accu = 0;
-        const i32 xa = whi >= wlo ? wlo - W0 : 0;
-        const i32 xb = whi >= wlo ? whi - W0 : -1;
-        for (i32 x = xa + (i32)threadIdx.x; x <= xb; x += C4W_THREADS) {
-            const i64 c = c4w_get<PACK16>(cnt, x);
-            if (c >= 2) {
-                const i64 pr = c * (c - 1) / 2;
-                accu += pr;
-                atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
-            }
-        }
-        accu = wave_sum(accu);
-        if (l == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
-        // pass C: (c - 1) to the middle of every wedge; per-run sums from a wave
-        // prefix sum and the run-start mask
-        for (i32 c0 = 0; c0 < L; c0 += C4W_THREADS) {
-            if (!one_chunk)
-                T = c4w_runs<TAB>(roff, ridx, rpos, tab, K1, win, b, L, c0, W0, W1, rbase, rmid, rstart, wsum,
-                                  &stotal, &nruns, &wlo, &whi);
-            const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
-            const i32 tb = std::min(T, (wv + 1) * per);
-            run_walk<4>(std::min(T, wv * per), tb, rbase, rstart, nruns, flags[wv], ridx,
-                     [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask) {
-                         i64 val = act ? (i64)c4w_get<PACK16>(cnt, w - W0) - 1 : 0;
-                         // inclusive prefix over the wave
-                         i64 P = val;
-#pragma unroll
-                         for (int o = 1; o < WAVE; o <<= 1) {
-                             const i64 y = __shfl_up(P, o, WAVE);
-                             if (l >= o) P += y;
-                         }
-                         const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
-                         const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of my run
-                         const i64 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
-                         const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tb);
-                         const i64 sum = P - (sl > 0 ? before : 0);
-                         if (tail && sum) atomicAdd((unsigned long long*)&c4v[rmid[r]], (unsigned long long)sum);
-                     });
-            __syncthreads();
-        }
-        if (threadIdx.x == 0 && red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
-        __syncthreads();
-    }
-}
-
-// Window table: tab[v * K1 + k] = number of neighbours of v with rank below k * WS.
-__global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 WS,
-                           i32* __restrict__ tab) {
-    const i64 total = n * K1;
-    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
-        const i64 v = q / K1, k = q - v * K1;
-        const i64 b = roff[v], e = roff[v + 1];
-        const i64 key = k * WS;
-        tab[q] = (i32)(key >= n ? e - b : lower_bound_dev(ridx, b, e, key) - b);
-    }
-}
-
-__global__ void k_set_pair(i64* p, i64 a, i64 b) {
-    p[0] = a;
-    p[1] = b;
-}
-
-// Windows per heavy vertex, in descending vertex order.
-__global__ void k_c4_jobs(const i32* __restrict__ heavy_sorted, u32 nheavy, i64 WS, i64* __restrict__ jobcnt) {
-    for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < nheavy; h += (i64)gridDim.x * blockDim.x) {
-        const i64 u = heavy_sorted[nheavy - 1 - h];
-        jobcnt[h] = (u + WS - 1) / WS;
-    }
-}
-
 // ------------------------------------------------------------ finalize / net
 
 __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
@@ -815,45 +503,6 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm) {
-    (void)nnz;
-    const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2];
-    tm.mark(FGLT_SEG_C4_WAVE, s);
-    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                               w.G, w.c4_list, c0, w.c4v);
-    tm.mark(FGLT_SEG_C4_BLOCK, s);
-    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               w.lo, w.G, w.c4_list + n, c1, w.c4v);
-    tm.mark(FGLT_SEG_C4_HEAVY, s);
-    if (c2) {
-        // heavy vertices in ascending order, then (vertex, window) jobs
-        i32* hs = w.c4_list + 2 * n;
-        hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c2);
-        hipError_t e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), w.sort, 1, s);
-        if (e != hipSuccess) return e;
-        const bool pack16 = hp.d_max < 65536;
-        const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
-        const i64 K1 = (n + WS - 1) / WS + 1;
-        const bool use_tab = w.c4_tab != nullptr && n * K1 <= w.c4_tab_cap;
-        if (use_tab)
-            hipLaunchKernelGGL(k_c4_table, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n, K1,
-                               WS, w.c4_tab);
-        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c2, PT, 4096)), dim3(PT), 0, s, hs, c2, WS, w.c4_jobcnt);
-        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c2, w.partials, s)) != hipSuccess) return e;
-        if ((e = hipMemsetAsync(w.c4_jobctr, 0, sizeof(u32), s)) != hipSuccess) return e;
-        const unsigned grid = 2048;
-#define C4W_LAUNCH(P16, TB)                                                                                    \
-    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(C4W_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.c4_tab, K1, hs, c2, w.c4_jobpre, w.c4_jobctr, w.c4v)
-        if (pack16 && use_tab) C4W_LAUNCH(true, true);
-        else if (pack16) C4W_LAUNCH(true, false);
-        else if (use_tab) C4W_LAUNCH(false, true);
-        else C4W_LAUNCH(false, false);
-#undef C4W_LAUNCH
     }
     return hipGetLastError();
 }

@@ -8,9 +8,6 @@ namespace fglt {
 
 static constexpr int PT = 256;  // threads per block for the simple kernels
 
-static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
-    return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(work, 1), per_block), cap));
-}
 
 static int bits_for(i64 maxval) {
     int b = 0;
@@ -236,7 +233,7 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
                         const i64* __restrict__ G, i64 n, Tiers th, i32* __restrict__ tri_list,
                         i32* __restrict__ c4_list, DevPlan* plan) {
     i64 dpmax = 0;
-    i64 titems[3] = {0, 0, 0}, witems[3] = {0, 0, 0};
+    i64 titems[3] = {0, 0, 0}, witems[4] = {0, 0, 0, 0};
     for (i64 u0 = (i64)blockIdx.x * blockDim.x; u0 < n; u0 += (i64)gridDim.x * blockDim.x) {
         const i64 u = u0 + threadIdx.x;
         int tcls = -1, ccls = -1;
@@ -247,13 +244,18 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
             const i64 T = G[e] - G[m];
             dpmax = D > dpmax ? D : dpmax;
             if (D >= 2) tcls = D <= th.tri_wave ? 0 : (D <= th.tri_lds ? 1 : 2);
-            if (W > 0) ccls = W <= th.c4_wave ? 0 : (W <= th.c4_block ? 1 : 2);
+            if (W > 0) {
+                const i64 L = m - b;
+                ccls = W <= th.c4_wave ? 0
+                       : W <= th.c4_block ? 1
+                       : (W <= th.c4_hash && L <= th.c4_hash_lmax) ? 2 : 3;
+            }
             if (tcls >= 0) titems[tcls] += T;
             if (ccls >= 0) witems[ccls] += W;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            u64 m = __ballot(tcls == c);
+            const u64 m = __ballot(tcls == c);
             if (m) {
                 const int leader = __ffsll((long long)m) - 1;
                 u32 base = 0;
@@ -261,7 +263,10 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
                 base = __shfl(base, leader, WAVE);
                 if (tcls == c) tri_list[(i64)c * n + base + __popcll(m & lanemask_lt())] = (i32)u;
             }
-            m = __ballot(ccls == c);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const u64 m = __ballot(ccls == c);
             if (m) {
                 const int leader = __ffsll((long long)m) - 1;
                 u32 base = 0;
@@ -277,11 +282,12 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const i64 ti = wave_sum(titems[c]);
+        if (lane_id() == 0 && ti) atomicAdd((unsigned long long*)&plan->tri_items_tier[c], (unsigned long long)ti);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
         const i64 wi = wave_sum(witems[c]);
-        if (lane_id() == 0) {
-            if (ti) atomicAdd((unsigned long long*)&plan->tri_items_tier[c], (unsigned long long)ti);
-            if (wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
-        }
+        if (lane_id() == 0 && wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
     }
 }
 
@@ -294,8 +300,14 @@ __global__ void k_totals(const i64* __restrict__ roff, const i32* __restrict__ l
     if (lane_id() == 0 && wedges) atomicAdd((unsigned long long*)&plan->wedge_items, (unsigned long long)wedges);
 }
 
-Tiers tiers_from_plan(const fglt_raw_plan* plan) {
-    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX};
+int bits_for_n(i64 n) {
+    int b = 0;
+    while (b < 31 && (((i64)1 << b) <= n - 1)) ++b;
+    return b;
+}
+
+Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
+    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0};
     if (plan) {
         if (plan->tri_wave_max > 0) t.tri_wave = std::min<i64>(plan->tri_wave_max, TRI_WAVE_MAX);
         if (plan->tri_lds_max > 0) t.tri_lds = std::min<i64>(plan->tri_lds_max, TRI_LDS_MAX);
@@ -303,9 +315,16 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan) {
         if (plan->c4_wave_max < 0) t.c4_wave = 0;
         if (plan->c4_block_max > 0) t.c4_block = std::min<i64>(plan->c4_block_max, C4_BLOCK_MAX);
         if (plan->c4_block_max < 0) t.c4_block = 0;
+        if (plan->c4_hash_max > 0) t.c4_hash = std::min<i64>(plan->c4_hash_max, C4_HASH_MAX);
+        if (plan->c4_hash_max < 0) t.c4_hash = 0;
     }
     t.tri_lds = std::max(t.tri_lds, t.tri_wave);
     t.c4_block = std::max(t.c4_block, t.c4_wave);
+    t.c4_hash = std::max(t.c4_hash, t.c4_block);
+    // a hash word holds the rank of a wedge end in the high bits and its count
+    // (at most |N-(u)|) in the remaining low bits
+    const int kb = std::max(1, bits_for_n(n));
+    t.c4_hash_lmax = ((i64)1 << (32 - kb)) - 1;
     return t;
 }
 
@@ -356,7 +375,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
         w.k4v = w.acc + 9 * nn;
     }
     w.tri_list = c.take<i32>(3 * nn);
-    w.c4_list = c.take<i32>(3 * nn);
+    w.c4_list = c.take<i32>(4 * nn);
     // out-degree under the degree ordering is at most sqrt(nnz): two bitmaps
     // of D x ceil(D/64) words plus per-row lists fit in tri_slot_words.
     i64 dmax_plus = 1;

@@ -21,23 +21,23 @@ namespace fglt {
 // Exclusive scan of one value per thread over a block of NT threads; returns
 // the thread's prefix and writes the block total to *total.  Every thread of
 // the block must call it.
-template <int NT>
-__device__ __forceinline__ i32 block_scan(i32 v, i32* wsum, i32* total) {
+template <int NT, class T>
+__device__ __forceinline__ T block_scan(T v, T* wsum, T* total) {
     constexpr int NWV = NT / WAVE;
     const int l = lane_id(), wv = threadIdx.x / WAVE;
-    i32 x = v;
+    T x = v;
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
-        const i32 y = __shfl_up(x, o, WAVE);
+        const T y = __shfl_up(x, o, WAVE);
         if (l >= o) x += y;
     }
     if (l == WAVE - 1) wsum[wv] = x;
     __syncthreads();
     if (threadIdx.x < WAVE) {
-        i32 y = threadIdx.x < NWV ? wsum[threadIdx.x] : 0;
+        T y = threadIdx.x < NWV ? wsum[threadIdx.x] : 0;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) {
-            const i32 z = __shfl_up(y, o, WAVE);
+            const T z = __shfl_up(y, o, WAVE);
             if ((int)threadIdx.x >= o) y += z;
         }
         if (threadIdx.x < NWV) wsum[threadIdx.x] = y;

@@ -19,12 +19,14 @@ pytestmark = pytest.mark.gpu
 C = math.comb
 
 # Tier plans: default; everything in the wave tiers where allowed; everything
-# in the LDS/workgroup tiers; everything in the global-memory / heavy tiers.
+# in the LDS/workgroup tiers; the 4-cycle pass in the packed-hash tier where
+# it fits; everything in the global-memory / window tiers.
 PLANS = {
     "default": None,
-    "wave": {"tri_wave_max": 64, "tri_lds_max": 64, "c4_wave_max": 128, "c4_block_max": 128},
-    "block": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": 2048},
-    "global": {"tri_wave_max": 1, "tri_lds_max": 1, "c4_wave_max": -1, "c4_block_max": -1},
+    "wave": {"tri_wave_max": 64, "tri_lds_max": 64, "c4_wave_max": 128, "c4_block_max": 128, "c4_hash_max": 128},
+    "block": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": 2048, "c4_hash_max": -1},
+    "hash": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": 16384},
+    "global": {"tri_wave_max": 1, "tri_lds_max": 1, "c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": -1},
 }
 
 
@@ -180,6 +182,31 @@ def test_chung_lu_medium(fg, plan):
     say(f"chung-lu medium plan={plan} nnz={idx.size}")
     exp = oracle.net(off, idx)
     np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), exp)
+
+
+@pytest.mark.parametrize("plan", ["default", "hash", "global"])
+@pytest.mark.parametrize("a,b", [(2, 1500), (3, 2600), (40, 300)])
+def test_complete_bipartite(fg, plan, a, b):
+    """K_{a,b}: the top hub's middles are all b leaves (more than one
+    1024-middle chunk for b > 1024), each leaf's wedge ends are the other hubs."""
+    edges = [(i, a + j) for i in range(a) for j in range(b)]
+    off, idx = csr_arrays(a + b, edges)
+    say(f"K_{a},{b} plan={plan}")
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), oracle.net(off, idx))
+
+
+@pytest.mark.parametrize("plan", ["default", "hash", "global"])
+def test_window_tier_several_windows(fg, plan):
+    """150k vertices: ranks span three 65536-rank counter windows, hubs have
+    more than 1024 middles (one job per window) and fewer (one job for all
+    windows)."""
+    g = graphgen.chung_lu(150_000, 2.1, 10.0, 6000.0, seed=11)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say(f"chung-lu 150k plan={plan} nnz={idx.size}")
+    st = fg.raw(*to_dev(off, idx), net=True, plan=PLANS[plan], stats=True)
+    got, stats = st[0].cpu().numpy(), st[1]
+    say(f"c4 tiers {stats['c4_tier_vertices']} wedges {stats['wedge_items_tier']}")
+    np.testing.assert_array_equal(got, oracle.net(off, idx))
 
 
 def test_barabasi_albert_and_rmat_small(fg):
