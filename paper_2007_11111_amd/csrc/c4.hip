@@ -50,8 +50,10 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
     constexpr int NW = PT / WAVE;
     constexpr int GROUPS = NW / WAVES_PER_U;  // vertices per block
     constexpr int GT = WAVES_PER_U * WAVE;    // threads per vertex
+    constexpr int LMAX = HSLOTS / 2;  // middles of a vertex: at most its wedge count
     __shared__ i32 hk[GROUPS][HSLOTS];
     __shared__ i32 hc[GROUPS][HSLOTS];
+    __shared__ i32 msum[GROUPS][LMAX];  // per-middle sums of pass C (at most W^2 < 2^31)
     __shared__ i64 red[GROUPS];
     const int grp = threadIdx.x / GT;
     const int gt = threadIdx.x % GT;
@@ -71,6 +73,7 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
             hk[grp][s] = -1;
             hc[grp][s] = 0;
         }
+        for (int s = gt; s < LMAX; s += GT) msum[grp][s] = 0;
         if (gt == 0) red[grp] = 0;
         __syncthreads();
         // pass A: count wedge ends
@@ -81,7 +84,27 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
             hash_add(hk[grp], hc[grp], mask, w);
         }
         __syncthreads();
-        // pass B: C(cnt, 2) to u and to w
+        // pass C: cnt(w) - 1 to the middle vertex of every wedge; the sums go
+        // to LDS per middle when the vertex's middles fit the array (a vertex
+        // may have many middles without wedges), else straight to memory
+        const bool lsum = m - b <= LMAX;
+        for (i64 t0 = 0; t0 < W; t0 += GT) {
+            const i64 t = t0 + gt;
+            const bool act = t < W;
+            i64 q = -1, val = 0;
+            if (act) {
+                i32 w;
+                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
+                val = hash_get(hk[grp], hc[grp], mask, w) - 1;
+            }
+            val = wave_seg_scan(val, q);
+            if (wave_seg_tail(q, act) && val) {
+                if (lsum) atomicAdd(&msum[grp][q - b], (i32)val);
+                else atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)val);
+            }
+        }
+        // pass B: C(cnt, 2) to u and to w (after the gathers, so that these
+        // atomics hold back no load of pass C)
         i64 accu = 0;
         for (int s = gt; s < HSLOTS; s += GT) {
             const i32 w = hk[grp][s];
@@ -94,22 +117,16 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
                 }
             }
         }
-        // pass C: cnt(w) - 1 to the middle vertex of every wedge
-        for (i64 t0 = 0; t0 < W; t0 += GT) {
-            const i64 t = t0 + gt;
-            const bool act = t < W;
-            i64 q = -1, val = 0;
-            if (act) {
-                i32 w;
-                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-                val = hash_get(hk[grp], hc[grp], mask, w) - 1;
-            }
-            val = wave_seg_scan(val, q);
-            if (wave_seg_tail(q, act) && val) atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)val);
-        }
         accu = wave_sum(accu);
         if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red[grp], (unsigned long long)accu);
         __syncthreads();
+        // the middles' sums, one global atomic per middle
+        if (lsum) {
+            for (i64 k = gt; k < m - b; k += GT) {
+                const i32 v = msum[grp][k];
+                if (v) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)v);
+            }
+        }
         if (valid && gt == 0 && red[grp]) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red[grp]);
         __syncthreads();
     }
@@ -135,7 +152,7 @@ __device__ __forceinline__ i32 wave_max_i32(i32 v) {
 // LDS state of the flattened wedge runs of one chunk of middles.
 struct RunLds {
     i64 rbase[CB_THREADS + 1];  // item t of run r sits at ridx[rbase[r] + t]
-    i32 rmid[CB_THREADS + 1];   // middle vertex of run r
+    i32 rk[CB_THREADS + 1];     // middle of run r, as its index within the chunk
     i32 rstart[CB_THREADS + 1]; // first item of run r; rstart[nruns] = item count
     i32 flags[CB_NWV][WAVE];    // run-start exchange rows of the walk
     i64 wsum[CB_NWV];
@@ -144,23 +161,23 @@ struct RunLds {
 };
 
 // Compacts the wedge runs of middles c0 .. c0+1023 of the current vertex
-// (middle k < L).  run(k, v, s0, len) gives middle k's vertex and its wedge
-// ends ridx[s0 .. s0+len).  The non-empty runs are kept in middle order; one
+// (middle k < L).  run(k, s0, len) gives middle k's wedge ends
+// ridx[s0 .. s0+len).  The non-empty runs are kept in middle order; one
 // block scan of (items << 16 | non-empty) gives both prefixes.  Returns the
 // item count.  Every thread of the block calls it.
 template <class RunOf>
 __device__ __forceinline__ i32 flatten_runs(i32 L, i32 c0, RunOf&& run, RunLds& R) {
     const i32 k = c0 + (i32)threadIdx.x;
-    i32 len = 0, v = 0;
+    i32 len = 0;
     i64 s0 = 0;
-    if (k < L) run(k, v, s0, len);
+    if (k < L) run(k, s0, len);
     const i64 packed = ((i64)len << 16) | (len > 0 ? 1 : 0);
     const i64 pre = block_scan<CB_THREADS>(packed, R.wsum, &R.total);
     const i64 tot = R.total;
     const i32 items_before = (i32)(pre >> 16), runs_before = (i32)(pre & 0xffff);
     if (len > 0) {
         R.rbase[runs_before] = s0 - items_before;
-        R.rmid[runs_before] = v;
+        R.rk[runs_before] = (i32)threadIdx.x;
         R.rstart[runs_before] = items_before;
     }
     const i32 T = (i32)(tot >> 16);
@@ -180,31 +197,41 @@ __device__ __forceinline__ void wave_share(i32 T, i32& ta, i32& tb) {
     tb = min(T, (wv + 1) * per);
 }
 
-// Pass C walk: every wedge item gives cnt(w) - 1 to its middle; the sums of
-// each run's piece in a wavefront step come from a wave prefix sum and the
-// run-start mask, one global atomic per piece.
-template <class Get>
-__device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* __restrict__ ridx,
-                                                  i64* __restrict__ c4v, Get&& get) {
+// Pass C walk: every wedge item gives cnt(w) - 1 to its middle.  The sum of
+// each run's piece in a wavefront step comes from a wave prefix sum and the
+// run-start mask and goes to the middle's LDS sum msum[k]; the caller moves
+// the sums to global memory once per chunk (or per vertex), so that no global
+// atomic sits between the gathers of the walk.
+// SMALL: every count is below 2^16, so a wavefront's prefix sums fit 32 bits
+// and the DPP scan applies.
+template <bool SMALL, class Get>
+__device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* __restrict__ ridx, i64* msum,
+                                                  Get&& get) {
     i32 ta, tb;
     wave_share(T, ta, tb);
     const int l = lane_id();
     const int wv = (int)threadIdx.x / WAVE;
     run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
                 [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask) {
-                    const i64 val = act ? (i64)get(w) - 1 : 0;
-                    i64 P = val;  // inclusive prefix over the wave
-#pragma unroll
-                    for (int o = 1; o < WAVE; o <<= 1) {
-                        const i64 y = __shfl_up(P, o, WAVE);
-                        if (l >= o) P += y;
-                    }
+                    i64 P, before;  // inclusive prefix over the wave; the prefix before this run piece
                     const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
                     const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this run piece
-                    const i64 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+                    if (SMALL) {
+                        const i32 p = wave_incl_scan_i32(act ? (i32)get(w) - 1 : 0);
+                        P = p;
+                        before = __shfl(p, sl > 0 ? sl - 1 : 0, WAVE);
+                    } else {
+                        P = act ? (i64)get(w) - 1 : 0;
+#pragma unroll
+                        for (int o = 1; o < WAVE; o <<= 1) {
+                            const i64 y = __shfl_up(P, o, WAVE);
+                            if (l >= o) P += y;
+                        }
+                        before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+                    }
                     const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tb);
                     const i64 sum = P - (sl > 0 ? before : 0);
-                    if (tail && sum) atomicAdd((unsigned long long*)&c4v[R.rmid[r]], (unsigned long long)sum);
+                    if (tail && sum) atomicAdd((unsigned long long*)&msum[R.rk[r]], (unsigned long long)sum);
                 });
 }
 
@@ -250,9 +277,11 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
                                                            u32* __restrict__ job_ctr, int cb, i64* __restrict__ c4v) {
     __shared__ u32 tab[C4H_SLOTS];
     __shared__ RunLds R;
+    __shared__ i64 msum[CB_THREADS];
     __shared__ i64 sj, red;
     const u32 cmask = (1u << cb) - 1u;
     for (int q = threadIdx.x; q < C4H_SLOTS; q += CB_THREADS) tab[q] = 0;
+    msum[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         sj = atomicAdd(job_ctr, 1u);
         red = 0;
@@ -267,10 +296,9 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
         const i64 b = roff[u];
         const i32 L = lo[u];
         const i32 nch = (L + CB_THREADS - 1) / CB_THREADS;
-        auto run_of = [&](i32 k, i32& v, i64& s0, i32& len) {
-            v = ridx[b + k];
-            s0 = roff[v];
-            len = rpos[b + k];  // neighbours of v below u: the first rpos entries of row v
+        auto run_of = [&](i32 k, i64& s0, i32& len) {
+            s0 = roff[ridx[b + k]];
+            len = rpos[b + k];  // neighbours of the middle below u: the first rpos entries of its row
         };
         // pass A: count the wedge ends
         i32 T = 0;
@@ -284,7 +312,20 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
                         });
             __syncthreads();
         }
-        // pass B: C(c, 2) to every end w and to u
+        // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
+        for (i32 ch = 0; ch < nch; ++ch) {
+            if (nch > 1) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+            attribute_middles<true>(T, R, ridx, msum, [&](i32 w) { return c4h_get(tab, w, cb); });
+            __syncthreads();
+            const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
+            if (k < L) {
+                const i64 m = msum[threadIdx.x];
+                if (m) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)m);
+                msum[threadIdx.x] = 0;
+            }
+        }
+        // pass B: C(c, 2) to every end w and to u (after the gathers, so that
+        // these atomics hold back no load of the walks)
         i64 accu = 0;
         for (int q = threadIdx.x; q < C4H_SLOTS; q += CB_THREADS) {
             const u32 e = tab[q];
@@ -294,12 +335,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
                 accu += pr;
                 atomicAdd((unsigned long long*)&c4v[e >> cb], (unsigned long long)pr);
             }
-        }
-        // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
-        for (i32 ch = 0; ch < nch; ++ch) {
-            if (nch > 1) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
-            attribute_middles(T, R, ridx, c4v, [&](i32 w) { return c4h_get(tab, w, cb); });
-            if (nch > 1) __syncthreads();
         }
         accu = wave_sum(accu);
         if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
@@ -360,11 +395,13 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
     __shared__ u32 cnt[C4W_WORDS];
     __shared__ RunLds R;
+    __shared__ i64 msum[CB_THREADS];
     __shared__ i64 sj, sh, red;
     __shared__ i32 wlo, whi;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
     for (int q = threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
+    msum[threadIdx.x] = 0;
     if (wv == 0) {
         i64 j = 0;
         if (l == 0) j = atomicAdd(job_ctr, 1u);
@@ -394,7 +431,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 wbot = single ? 0 : wtop;
         // one chunk: thread k keeps middle k and the end of its not yet
         // visited run (windows go top-down, so each run ends where the
-        // previous window's run began)
+        // previous window's run began); its LDS sum msum[k] collects the
+        // middle's share over all windows
         i32 mv = 0, mcut = 0;
         i64 mrs = 0, mhi = 0;
         if (single && (i32)threadIdx.x < L) {
@@ -407,21 +445,20 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         for (i32 win = wtop; win >= wbot; --win) {
             const i32 W0 = win * WS;
             const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
-            auto run_of = [&](i32 k, i32& v, i64& s0, i32& len) {
+            auto run_of = [&](i32 k, i64& s0, i32& len) {
                 if (single) {
                     const i64 a0 = TAB ? mrs + std::min(tab[(i64)mv * K1 + win], mcut)
                                        : lower_bound_dev(ridx, mrs, mhi, W0);
-                    v = mv;
                     s0 = a0;
                     len = (i32)(mhi - a0);
                     mhi = a0;
                 } else {
-                    v = ridx[b + k];
-                    const i64 rs = roff[v];
+                    const i64 rs = roff[ridx[b + k]];
                     const i32 cut = rpos[b + k];
                     if (TAB) {
-                        const i32 a0 = std::min(tab[(i64)v * K1 + win], cut);
-                        const i32 a1 = std::min(tab[(i64)v * K1 + win + 1], cut);
+                        const i64 vrow = (i64)ridx[b + k] * K1;
+                        const i32 a0 = std::min(tab[vrow + win], cut);
+                        const i32 a1 = std::min(tab[vrow + win + 1], cut);
                         s0 = rs + a0;
                         len = a1 - a0;
                     } else {
@@ -456,7 +493,22 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             __syncthreads();
             const i32 xlo = wlo - W0, xhi = whi - W0;
             if (xhi < xlo) continue;  // no wedge end in this window (block-uniform)
+            // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
+            for (i32 ch = 0; ch < nch; ++ch) {
+                if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                attribute_middles<PACK16>(T, R, ridx, msum, [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
+                if (!single) {
+                    __syncthreads();
+                    const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
+                    if (k < L) {
+                        const i64 m = msum[threadIdx.x];
+                        if (m) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)m);
+                        msum[threadIdx.x] = 0;
+                    }
+                }
+            }
             // pass B: C(c, 2) to every end w and to u, over the touched range
+            // (after the gathers, so that these atomics hold back no load of the walks)
             for (i32 x = xlo + (i32)threadIdx.x; x <= xhi; x += CB_THREADS) {
                 const i64 c = c4w_get<PACK16>(cnt, x);
                 if (c >= 2) {
@@ -464,12 +516,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     accu += pr;
                     atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
                 }
-            }
-            // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
-            for (i32 ch = 0; ch < nch; ++ch) {
-                if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
-                attribute_middles(T, R, ridx, c4v, [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
-                if (!single) __syncthreads();
             }
             __syncthreads();
             // clear the touched counters for the next window
@@ -483,6 +529,11 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         accu = wave_sum(accu);
         if (l == 0 && accu) atomicAdd((unsigned long long*)&red, (unsigned long long)accu);
         __syncthreads();
+        if (single && (i32)threadIdx.x < L) {
+            const i64 m = msum[threadIdx.x];
+            if (m) atomicAdd((unsigned long long*)&c4v[mv], (unsigned long long)m);
+            msum[threadIdx.x] = 0;
+        }
         if (threadIdx.x == 0) {
             if (red) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red);
             red = 0;

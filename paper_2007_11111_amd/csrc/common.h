@@ -12,6 +12,7 @@ typedef int64_t i64;
 typedef int32_t i32;
 typedef uint64_t u64;
 typedef uint32_t u32;
+typedef uint16_t u16;
 
 #define WAVE 64
 

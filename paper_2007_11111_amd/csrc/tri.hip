@@ -26,30 +26,52 @@ static constexpr int LT = 512;  // LDS-tier block: 8 wavefronts on one vertex
 
 // ------------------------------------------------------------------ triangle pass
 
+// C3 of the edge (v_k, v_l) of a triangle is a global counter.  A device-scope
+// atomic issued between the gathers of a walk holds back the next gather
+// (vector memory operations complete in order), so the walk queues the entry
+// indices of its hits in LDS -- one ballot per step, no LDS atomic -- and the
+// wavefront issues the increments after the walk.  A full queue (or entry
+// indices beyond 32 bits: defer == 0) falls back to the direct atomic.
+static constexpr int TRI_QCAP = 512;
+
+__device__ __forceinline__ void defer_c3(bool hit, i64 e, u32* q, u32& nq, i32* __restrict__ C3, int defer) {
+    const u64 hm = __ballot(hit);
+    if (!hm) return;
+    const u32 pos = nq + (u32)__popcll(hm & lanemask_lt());
+    if (hit) {
+        if (defer && pos < TRI_QCAP) q[pos] = (u32)e;
+        else atomicAdd(&C3[e], 1);
+    }
+    nq += (u32)__popcll(hm);
+}
+
+__device__ __forceinline__ void flush_c3(const u32* q, u32 nq, i32* __restrict__ C3, int lane, int width) {
+    const u32 cnt = nq < (u32)TRI_QCAP ? nq : (u32)TRI_QCAP;
+    for (u32 i = lane; i < cnt; i += width) atomicAdd(&C3[q[i]], 1);
+}
+
 __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i64* __restrict__ G,
                                                   const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
                                                   i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
-                                                  const i64* __restrict__ boff, int store) {
+                                                  const i64* __restrict__ boff, int store, int defer) {
     constexpr int NW = WT / WAVE;
-    constexpr u32 HM = 2 * WAVE - 1;
     __shared__ i32 sL[NW][WAVE];
     __shared__ i64 rbase[NW][WAVE + 1];
     __shared__ i32 rstart[NW][WAVE + 1];
     __shared__ i32 rk[NW][WAVE + 1];
-    __shared__ i32 hk[NW][2 * WAVE];
-    __shared__ i32 hv[NW][2 * WAVE];
+    __shared__ BucketMap<6> pm[NW];  // positions of N+(u): 64 buckets of 4
     __shared__ i32 flags[NW][WAVE];
     __shared__ i32 sCnt[NW][WAVE];
     __shared__ u64 sB[NW][WAVE];
     __shared__ i32 sR[NW];
+    __shared__ u32 sQ[NW][TRI_QCAP];  // deferred C3 increments (entry indices)
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
     for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
         const i64 it = base + wid;
         const bool valid = it < (i64)count;
-        hk[wid][lane] = -1;
-        hk[wid][lane + WAVE] = -1;
+        bmap_clear(pm[wid], lane, WAVE);
         sCnt[wid][lane] = 0;
         sB[wid][lane] = 0;
         __syncthreads();
@@ -66,7 +88,7 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
             if (lane < D) {
                 const i32 v = ridx[bu + lane];
                 sL[wid][lane] = v;
-                pos_insert(hk[wid], hv[wid], HM, v, lane);
+                bmap_insert(pm[wid], v, lane);
                 pre = (i32)(G[bu + lane] - gb);
                 len = (i32)(G[bu + lane + 1] - G[bu + lane]);
                 bv = roff[v] + lo[v];
@@ -85,22 +107,24 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
             }
         }
         __syncthreads();
+        u32 nq = 0;  // wave-uniform
         if (valid && T > 0) {
             run_walk<4>(0, T, rbase[wid], rstart[wid], sR[wid], flags[wid], ridx,
                         [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
-                if (!act) return;
-                const i32 l = pos_find(hk[wid], hv[wid], HM, y);
-                if (l >= 0) {
+                const i32 l = act ? bmap_find(pm[wid], y) : -1;
+                const bool hit = l >= 0;
+                if (hit) {
                     const i32 k = rk[wid][r];
                     atomicAdd(&sCnt[wid][k], 1);
                     atomicAdd(&sCnt[wid][l], 1);
-                    atomicAdd(&C3[e], 1);
                     atomicOr((unsigned long long*)&sB[wid][k], 1ull << l);
                 }
+                defer_c3(hit, e, sQ[wid], nq, C3, defer);
             });
         }
         __syncthreads();
         if (valid) {
+            flush_c3(sQ[wid], nq, C3, lane, WAVE);
             i64 c = 0;
             if (lane < D) {
                 c = sCnt[wid][lane];
@@ -124,23 +148,22 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
                                                  const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
                                                  i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
-                                                 const i64* __restrict__ boff, int store) {
+                                                 const i64* __restrict__ boff, int store, int defer) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
-    constexpr int HS = 2 * DM;
     constexpr int NWV = LT / WAVE;
     __shared__ i32 L[DM];
     __shared__ i64 rbase[DM + 1];
     __shared__ i32 rstart[DM + 1];
     __shared__ i32 rk[DM + 1];
-    __shared__ i32 hk[HS];
-    __shared__ i32 hv[HS];
+    __shared__ BucketMap<9> pm;  // positions of N+(u): 512 buckets of 4
     __shared__ i32 flags[NWV][WAVE];
     __shared__ i32 Cnt[DM];
     __shared__ u64 B[DM * WM];
     __shared__ i32 wsum[NWV];
     __shared__ i32 stot, sR;
     __shared__ i64 red;
+    __shared__ u32 sQ[NWV][TRI_QCAP];  // deferred C3 increments per wavefront
     const int wv = threadIdx.x / WAVE;
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
         const i64 u = list[it];
@@ -149,7 +172,7 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         const int W = (D + 63) >> 6;
         const i64 gb = G[bu];
         const i32 T = (i32)(G[bu + D] - gb);
-        for (int q = threadIdx.x; q < HS; q += LT) hk[q] = -1;
+        bmap_clear(pm, threadIdx.x, LT);
         for (int q = threadIdx.x; q < D * W; q += LT) B[q] = 0;
         if (threadIdx.x < D) Cnt[threadIdx.x] = 0;
         if (threadIdx.x == 0) red = 0;
@@ -160,7 +183,7 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         if (k < D) {
             const i32 v = ridx[bu + k];
             L[k] = v;
-            pos_insert(hk, hv, HS - 1, v, k);
+            bmap_insert(pm, v, k);
             pre = (i32)(G[bu + k] - gb);
             len = (i32)(G[bu + k + 1] - G[bu + k]);
             bv = roff[v] + lo[v];
@@ -177,19 +200,21 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         }
         __syncthreads();
         const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+        u32 nq = 0;  // wave-uniform
         run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, sR, flags[wv], ridx,
                     [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
-                     if (!act) return;
-                     const i32 l = pos_find(hk, hv, HS - 1, y);
-                     if (l >= 0) {
-                         const i32 kk = rk[r];
-                         atomicAdd(&Cnt[kk], 1);
-                         atomicAdd(&Cnt[l], 1);
-                         atomicAdd(&C3[e], 1);
-                         atomicOr((unsigned long long*)&B[kk * W + (l >> 6)], 1ull << (l & 63));
-                     }
-                 });
+                        const i32 l = act ? bmap_find(pm, y) : -1;
+                        const bool hit = l >= 0;
+                        if (hit) {
+                            const i32 kk = rk[r];
+                            atomicAdd(&Cnt[kk], 1);
+                            atomicAdd(&Cnt[l], 1);
+                            atomicOr((unsigned long long*)&B[kk * W + (l >> 6)], 1ull << (l & 63));
+                        }
+                        defer_c3(hit, e, sQ[wv], nq, C3, defer);
+                    });
         __syncthreads();
+        flush_c3(sQ[wv], nq, C3, lane_id(), WAVE);
         i64 c = 0;
         if (k < D) {
             c = Cnt[k];
@@ -399,12 +424,13 @@ hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s) {
 
 hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier) {
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
+    const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.G,
-                           w.tri_list, c0, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0);
+                           w.tri_list, c0, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0, defer);
     if (tier == 1 && c1)
         hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
-                           w.tri_list + n, c1, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0);
+                           w.tri_list + n, c1, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0, defer);
     return hipGetLastError();
 }
 

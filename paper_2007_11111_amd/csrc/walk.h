@@ -51,14 +51,46 @@ __device__ __forceinline__ i32 block_scan_1024(i32 v, i32* wsum, i32* total) {
     return block_scan<1024>(v, wsum, total);
 }
 
+// Lanes of one wavefront exchange words through LDS: relaxed atomics at
+// wavefront scope keep the compiler from forwarding a lane's own store to its
+// later load (another lane may have written in between) while still compiling
+// to plain ds_write / ds_read, which a wavefront executes in order.  (A
+// volatile pointer would do the former but loses the LDS address space and
+// turns into system-coherent flat accesses that wait for every outstanding
+// global load.)
+__device__ __forceinline__ void lds_put(i32* p, i32 v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ i32 lds_get(i32* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Run starts among the 64 items ts .. ts+63: bit p set when a run begins at
+// item ts + p.  Lane l holds st, the first item of run r0 + 1 + l (runs are
+// non-empty and ordered, so every such st is >= ts); the lanes mark their
+// starts in a per-wavefront LDS row and read the row back as a ballot.
+__device__ __forceinline__ u64 run_start_mask(i32* flags, i32 st, i32 ts) {
+    const int l = lane_id();
+    lds_put(&flags[l], 0);
+    wave_lds_fence();
+    if (st < ts + WAVE) lds_put(&flags[st - ts], 1);
+    wave_lds_fence();
+    const u64 mask = __ballot(lds_get(&flags[l]) != 0);
+    wave_lds_fence();
+    return mask;
+}
+
 // Walks items [ta, tb) of compacted non-empty runs, 64 consecutive items per
-// step.  Run r holds items rstart[r] .. rstart[r+1]-1 at ridx indices
-// rbase[r] + item.  The lanes where a run starts are found through a per-wave
-// LDS flag row and a ballot.  f(active, item, run, ridx index, run-start mask)
-// runs on every lane of the wave.
+// step (ta, tb wave-uniform).  Run r holds items rstart[r] .. rstart[r+1]-1 at
+// ridx indices rbase[r] + item.  f(active, item, run, ridx index, run-start
+// mask) runs on every lane of the wave.
 template <class F>
-__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R,
-                                         volatile i32* flags, F&& f) {
+__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
+                                         F&& f) {
     if (ta >= tb) return;
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
@@ -66,17 +98,7 @@ __device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const
     for (i32 t0 = ta; t0 < tb; t0 += WAVE) {
         const i32 j = r0 + 1 + l;
         const i32 st = j < R ? rstart[j] : 0x7fffffff;
-        // lanes talk through LDS here: volatile accesses in program order, and
-        // wavefront barriers so that no store or load moves across the exchange
-        flags[l] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (st < t0 + WAVE) flags[st - t0] = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const u64 mask = __ballot(flags[l] != 0);
-        __builtin_amdgcn_wave_barrier();
+        const u64 mask = run_start_mask(flags, st, t0);
         const i32 r = r0 + __popcll(mask & le);
         const i32 t = t0 + l;
         f(t < tb, t, r, rbase[r] + t, mask);
@@ -89,8 +111,8 @@ __device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const
 // f(active, item, run, w, e, run-start mask) runs for each step.  Several loads
 // per wavefront hide the cache-miss latency that a single load per step exposes.
 template <int U, class F>
-__device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R,
-                                         volatile i32* flags, const i32* __restrict__ ridx, F&& f) {
+__device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
+                                         const i32* __restrict__ ridx, F&& f) {
     if (ta >= tb) return;
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
@@ -105,15 +127,7 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
             const i32 ts = t0 + s * WAVE;
             const i32 j = r0 + 1 + l;
             const i32 st = j < R ? rstart[j] : 0x7fffffff;
-            flags[l] = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (st < ts + WAVE) flags[st - ts] = 1;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            mm[s] = __ballot(flags[l] != 0);
-            __builtin_amdgcn_wave_barrier();
+            mm[s] = run_start_mask(flags, st, ts);
             rr[s] = r0 + __popcll(mm[s] & le);
             r0 = __shfl(rr[s], WAVE - 1, WAVE);
         }
@@ -133,6 +147,19 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
             f(t < tb, t, rr[s], ww[s], ee[s], mm[s]);
         }
     }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP: shifts by
+// 1, 2, 4, 8 within each row of 16 lanes, then the row totals broadcast to
+// the rows above (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ __forceinline__ i32 wave_incl_scan_i32(i32 x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
 }
 
 __device__ __forceinline__ u32 hslot(i32 w, u32 mask) { return ((u32)w * 2654435761u) & mask; }
@@ -157,6 +184,57 @@ __device__ __forceinline__ i32 hash_get(const i32* keys, const i32* cnts, u32 ma
         if (k == w) return cnts[h];
         if (k == -1) return 0;
         h = (h + 1) & mask;
+    }
+}
+
+// Position map of up to 2^B distinct vertex ids in 2^B buckets of 4 slots:
+// a bucket's keys are one 16-byte LDS word (-1 when empty), so a lookup reads
+// one bucket and branches only when the bucket is full and the key is not in
+// it (then the next bucket).  Slots of a bucket fill in order, so an empty
+// slot ends the search.  Positions are below 2^16.
+template <int B>
+struct BucketMap {
+    int4 key[1 << B];
+    u16 pos[4 << B];
+};
+
+template <int B>
+__device__ __forceinline__ u32 bucket_of(i32 v) {
+    return ((u32)v * 2654435761u) >> (32 - B);
+}
+
+template <int B>
+__device__ __forceinline__ void bmap_clear(BucketMap<B>& m, int tid, int nthreads) {
+    for (int q = tid; q < (1 << B); q += nthreads) m.key[q] = make_int4(-1, -1, -1, -1);
+}
+
+template <int B>
+__device__ __forceinline__ void bmap_insert(BucketMap<B>& m, i32 v, i32 position) {
+    u32 b = bucket_of<B>(v);
+    i32* keys = reinterpret_cast<i32*>(m.key);
+    while (true) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (atomicCAS(&keys[4 * b + s], -1, v) == -1) {
+                m.pos[4 * b + s] = (u16)position;
+                return;
+            }
+        }
+        b = (b + 1) & ((1u << B) - 1);
+    }
+}
+
+template <int B>
+__device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
+    u32 b = bucket_of<B>(v);
+    while (true) {
+        const int4 q = m.key[b];
+        if (q.x == v) return m.pos[4 * b];
+        if (q.y == v) return m.pos[4 * b + 1];
+        if (q.z == v) return m.pos[4 * b + 2];
+        if (q.w == v) return m.pos[4 * b + 3];
+        if (q.w == -1) return -1;
+        b = (b + 1) & ((1u << B) - 1);
     }
 }
 

@@ -195,6 +195,20 @@ def test_complete_bipartite(fg, plan, a, b):
     np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), oracle.net(off, idx))
 
 
+@pytest.mark.parametrize("plan", list(PLANS))
+@pytest.mark.parametrize("leaves", [100, 600, 3000])
+def test_hub_with_leaves(fg, plan, leaves):
+    """A top-ranked hub whose middles are mostly leaves (no wedges below the
+    hub) plus a few with wedges: few wedges, many middles."""
+    rng = np.random.default_rng(leaves)
+    hub, x, y = 0, [1, 2, 3], [4, 5, 6, 7, 8]
+    edges = [(hub, xi) for xi in x] + [(xi, yj) for xi in x for yj in y if rng.random() < 0.8]
+    edges += [(hub, 9 + k) for k in range(leaves)]
+    off, idx = csr_arrays(9 + leaves, edges)
+    say(f"hub with {leaves} leaves plan={plan}")
+    np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), oracle.net(off, idx))
+
+
 @pytest.mark.parametrize("plan", ["default", "hash", "global"])
 def test_window_tier_several_windows(fg, plan):
     """150k vertices: ranks span three 65536-rank counter windows, hubs have
