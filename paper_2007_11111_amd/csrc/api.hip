@@ -98,12 +98,13 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
+    if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
     i64 triangles = -1;
-    if (tm.on) {
-        FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
+    if (stats) {
+        FGLT_HIP_TRY(launch_count_triangles(n, w, s));
         DevPlan fin{};
         if ((st = read_plan(w, fin, s))) return st;
-        triangles = fin.triangles;
+        triangles = fin.triangles / 3;  // every triangle is counted at its three vertices
     }
 
     if (stats) {

@@ -178,10 +178,7 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
                     }
                 }
                 c = wave_sum(c);
-                if (lane == 0 && c) {
-                    atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
-                    atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(c / 2));
-                }
+                if (lane == 0 && c) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
             } else {
                 i64 R = 0, kv = 0, dv = 0;
                 if (lane < D) {
@@ -368,10 +365,7 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         __syncthreads();
         if (threadIdx.x == 0) {
             if (MODE == 1) {
-                if (red[0]) {
-                    atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red[0] / 2));
-                    atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(red[0] / 2));
-                }
+                if (red[0]) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red[0] / 2));
             } else {
                 if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
                 if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
@@ -504,6 +498,29 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
     }
+    return hipGetLastError();
+}
+
+// Triangles of the graph, sum over vertices of c3 / 3, into plan->triangles
+// (statistics only: one atomic per workgroup).
+__global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __restrict__ c3v, DevPlan* plan) {
+    __shared__ i64 part[PT / WAVE];
+    i64 sum = 0;
+    for (i64 r = (i64)blockIdx.x * PT + threadIdx.x; r < n; r += (i64)gridDim.x * PT) sum += c3v[r];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        i64 t = 0;
+        for (int k = 0; k < PT / WAVE; ++k) t += part[k];
+        if (t) atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)t);
+    }
+}
+
+hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
+    const hipError_t e = hipMemsetAsync(&w.plan->triangles, 0, sizeof(i64), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_triangles, dim3(grid_for(n, PT, 256)), dim3(PT), 0, s, n, w.c3v, w.plan);
     return hipGetLastError();
 }
 

@@ -62,7 +62,6 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
     __shared__ i32 rk[NW][WAVE + 1];
     __shared__ BucketMap<6> pm[NW];  // positions of N+(u): 64 buckets of 4
     __shared__ i32 flags[NW][WAVE];
-    __shared__ i32 sCnt[NW][WAVE];
     __shared__ u64 sB[NW][WAVE];
     __shared__ i32 sR[NW];
     __shared__ u32 sQ[NW][TRI_QCAP];  // deferred C3 increments (entry indices)
@@ -72,7 +71,6 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
         const i64 it = base + wid;
         const bool valid = it < (i64)count;
         bmap_clear(pm[wid], lane, WAVE);
-        sCnt[wid][lane] = 0;
         sB[wid][lane] = 0;
         __syncthreads();
         i64 u = 0, bu = 0;
@@ -113,21 +111,20 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
                         [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
                 const i32 l = act ? bmap_find(pm[wid], y) : -1;
                 const bool hit = l >= 0;
-                if (hit) {
-                    const i32 k = rk[wid][r];
-                    atomicAdd(&sCnt[wid][k], 1);
-                    atomicAdd(&sCnt[wid][l], 1);
-                    atomicOr((unsigned long long*)&sB[wid][k], 1ull << l);
-                }
+                if (hit) atomicOr((unsigned long long*)&sB[wid][rk[wid][r]], 1ull << l);
                 defer_c3(hit, e, sQ[wid], nq, C3, defer);
             });
         }
         __syncthreads();
         if (valid) {
             flush_c3(sQ[wid], nq, C3, lane, WAVE);
+            // triangles on the edge (u, v_k): row k of B (v_l in N+(v_k)) plus
+            // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
+            const u64 row = sB[wid][lane];
+            const u64 col = wave_transpose64(row);
             i64 c = 0;
             if (lane < D) {
-                c = sCnt[wid][lane];
+                c = __popcll(row) + __popcll(col);
                 if (c) {
                     atomicAdd(&C3[bu + lane], (i32)c);
                     atomicAdd((unsigned long long*)&c3v[sL[wid][lane]], (unsigned long long)c);
@@ -135,10 +132,7 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
                 if (store) bstore[boff[u] + lane] = sB[wid][lane];
             }
             c = wave_sum(c);
-            if (lane == 0 && c) {
-                atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
-                atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(c / 2));
-            }
+            if (lane == 0 && c) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
         }
         __syncthreads();
     }
@@ -228,10 +222,7 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         c = wave_sum(c);
         if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&red, (unsigned long long)c);
         __syncthreads();
-        if (threadIdx.x == 0 && red) {
-            atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red / 2));
-            atomicAdd((unsigned long long*)&plan->triangles, (unsigned long long)(red / 2));
-        }
+        if (threadIdx.x == 0 && red) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red / 2));
         __syncthreads();
     }
 }
@@ -265,7 +256,6 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
     for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
         const i64 it = base + wid;
         const bool valid = it < (i64)count;
-        sC[wid][lane] = 0;
         i64 u = 0, bu = 0;
         int D = 0;
         if (valid) {
@@ -279,9 +269,7 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
             }
         }
         __syncthreads();
-        if (valid && lane < D) {
-            FOR_BITS(sB[wid][lane], l, atomicOr((unsigned long long*)&sC[wid][l], 1ull << lane));
-        }
+        if (valid) sC[wid][lane] = wave_transpose64(lane < D ? sB[wid][lane] : 0ull);
         __syncthreads();
         if (valid) {
             i64 R = 0, du = 0;

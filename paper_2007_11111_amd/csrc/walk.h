@@ -162,6 +162,22 @@ __device__ __forceinline__ i32 wave_incl_scan_i32(i32 x) {
     return x;
 }
 
+// Transpose of a 64 x 64 bit matrix held one row per lane (bit j of lane i's
+// word = entry (i, j)): returns column `lane`.  Six butterfly rounds; round s
+// swaps the off-diagonal s x s blocks of every 2s x 2s block.
+__device__ __forceinline__ u64 wave_transpose64(u64 m) {
+    const int l = lane_id();
+    const u64 M0[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                       0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const int s = 32 >> r;
+        const u64 p = __shfl_xor(m, s, WAVE);
+        m = (l & s) ? (((p & ~M0[r]) >> s) | (m & ~M0[r])) : ((m & M0[r]) | ((p & M0[r]) << s));
+    }
+    return m;
+}
+
 __device__ __forceinline__ u32 hslot(i32 w, u32 mask) { return ((u32)w * 2654435761u) & mask; }
 
 // Counting hash (open addressing, linear probing, keys -1 when empty).
@@ -229,10 +245,10 @@ __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
     u32 b = bucket_of<B>(v);
     while (true) {
         const int4 q = m.key[b];
-        if (q.x == v) return m.pos[4 * b];
-        if (q.y == v) return m.pos[4 * b + 1];
-        if (q.z == v) return m.pos[4 * b + 2];
-        if (q.w == v) return m.pos[4 * b + 3];
+        // keys are distinct, so at most one term is non-zero; the sum needs all
+        // four keys, which keeps the bucket a single 16-byte read
+        const int hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
+        if (hit) return m.pos[4 * b + hit - 1];
         if (q.w == -1) return -1;
         b = (b + 1) & ((1u << B) - 1);
     }

@@ -223,6 +223,20 @@ def test_window_tier_several_windows(fg, plan):
     np.testing.assert_array_equal(got, oracle.net(off, idx))
 
 
+def test_stats(fg):
+    """Statistics: the triangle total is the sum of the per-vertex triangle
+    counts (raw orbit 4) over three; the tiers partition the vertices with work."""
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    raw_e = oracle.raw(off, idx)
+    _, st = fg.raw(*to_dev(off, idx), stats=True)
+    assert st["triangles"] == int(raw_e[:, 4].sum()) // 3
+    assert st["n"] == g.n and st["nnz"] == idx.size
+    assert sum(st["wedge_items_tier"]) == st["wedge_items"]
+    assert sum(st["tri_items_tier"]) == st["tri_items"]
+    assert st["d_max"] == int(np.diff(off).max())
+
+
 def test_barabasi_albert_and_rmat_small(fg):
     for name, g in [("ba", graphgen.barabasi_albert(5000, 4, seed=8)),
                     ("rmat12", graphgen.rmat(12, 16, 0.57, 0.19, 0.19, seed=9))]:
