@@ -212,7 +212,7 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
     const int l = lane_id();
     const int wv = (int)threadIdx.x / WAVE;
     run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask) {
+                [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask, i32 tend) {
                     i64 P, before;  // inclusive prefix over the wave; the prefix before this run piece
                     const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
                     const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this run piece
@@ -229,7 +229,7 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
                         }
                         before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
                     }
-                    const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tb);
+                    const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tend);
                     const i64 sum = P - (sl > 0 ? before : 0);
                     if (tail && sum) atomicAdd((unsigned long long*)&msum[R.rk[r]], (unsigned long long)sum);
                 });
@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
             i32 ta, tb;
             wave_share(T, ta, tb);
             run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[threadIdx.x / WAVE], ridx,
-                        [&](bool act, i32, i32, i32 w, i64, u64) {
+                        [&](bool act, i32, i32, i32 w, i64, u64, i32) {
                             if (act) c4h_add(tab, w, cb);
                         });
             __syncthreads();
@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                 i32 ta, tb;
                 wave_share(T, ta, tb);
                 run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                            [&](bool act, i32, i32, i32 w, i64, u64) {
+                            [&](bool act, i32, i32, i32 w, i64, u64, i32) {
                                 if (act) {
                                     c4w_inc<PACK16>(cnt, w - W0);
                                     lmin = min(lmin, w);

@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
         u32 nq = 0;  // wave-uniform
         if (valid && T > 0) {
             run_walk<4>(0, T, rbase[wid], rstart[wid], sR[wid], flags[wid], ridx,
-                        [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
+                        [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
                 const i32 l = act ? bmap_find(pm[wid], y) : -1;
                 const bool hit = l >= 0;
                 if (hit) atomicOr((unsigned long long*)&sB[wid][rk[wid][r]], 1ull << l);
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
         u32 nq = 0;  // wave-uniform
         run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, sR, flags[wv], ridx,
-                    [&](bool act, i32, i32 r, i32 y, i64 e, u64) {
+                    [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
                         const i32 l = act ? bmap_find(pm, y) : -1;
                         const bool hit = l >= 0;
                         if (hit) {

@@ -47,10 +47,6 @@ __device__ __forceinline__ T block_scan(T v, T* wsum, T* total) {
     return (wv > 0 ? wsum[wv - 1] : 0) + x - v;
 }
 
-__device__ __forceinline__ i32 block_scan_1024(i32 v, i32* wsum, i32* total) {
-    return block_scan<1024>(v, wsum, total);
-}
-
 // Lanes of one wavefront exchange words through LDS: relaxed atomics at
 // wavefront scope keep the compiler from forwarding a lane's own store to its
 // later load (another lane may have written in between) while still compiling
@@ -70,54 +66,41 @@ __device__ __forceinline__ void wave_lds_fence() {
 }
 
 // Run starts among the 64 items ts .. ts+63: bit p set when a run begins at
-// item ts + p.  Lane l holds st, the first item of run r0 + 1 + l (runs are
-// non-empty and ordered, so every such st is >= ts); the lanes mark their
-// starts in a per-wavefront LDS row and read the row back as a ballot.
+// item ts + p.  Lane l holds st, the first item of some run (distinct lanes,
+// distinct runs); the lanes whose start falls in the step mark it in a
+// per-wavefront LDS row and the row is read back as a ballot.
 __device__ __forceinline__ u64 run_start_mask(i32* flags, i32 st, i32 ts) {
     const int l = lane_id();
     lds_put(&flags[l], 0);
     wave_lds_fence();
-    if (st < ts + WAVE) lds_put(&flags[st - ts], 1);
+    if ((u32)(st - ts) < (u32)WAVE) lds_put(&flags[st - ts], 1);
     wave_lds_fence();
     const u64 mask = __ballot(lds_get(&flags[l]) != 0);
     wave_lds_fence();
     return mask;
 }
 
-// Walks items [ta, tb) of compacted non-empty runs, 64 consecutive items per
-// step (ta, tb wave-uniform).  Run r holds items rstart[r] .. rstart[r+1]-1 at
-// ridx indices rbase[r] + item.  f(active, item, run, ridx index, run-start
-// mask) runs on every lane of the wave.
-template <class F>
-__device__ __forceinline__ void c4w_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
-                                         F&& f) {
-    if (ta >= tb) return;
-    const int l = lane_id();
-    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
-    i32 r0 = (i32)last_le_dev(rstart, 0, R - 1, ta);
-    for (i32 t0 = ta; t0 < tb; t0 += WAVE) {
-        const i32 j = r0 + 1 + l;
-        const i32 st = j < R ? rstart[j] : 0x7fffffff;
-        const u64 mask = run_start_mask(flags, st, t0);
-        const i32 r = r0 + __popcll(mask & le);
-        const i32 t = t0 + l;
-        f(t < tb, t, r, rbase[r] + t, mask);
-        r0 = __shfl(r, WAVE - 1, WAVE);
-    }
-}
-
-// The run walk with U steps in flight: the run masks of U consecutive steps
-// are found first, then U independent gathers w = ridx[e] are issued, then
-// f(active, item, run, w, e, run-start mask) runs for each step.  Several loads
-// per wavefront hide the cache-miss latency that a single load per step exposes.
+// The run walk, in groups of up to U steps of 64 items.  A group reads the
+// starts of the next 64 runs once (one per lane); it ends before the last of
+// them, so every item in it has a known run.  Per step, the run of item
+// ts + l is r0 + (starts before ts) + (starts in [ts, ts + l]), the latter from
+// the LDS run-start mask.  The U gathers w = ridx[e] of a group are issued
+// together, then f(active, item, run, w, e, run-start mask, group end) runs for
+// each step.  Inactive lanes gather a valid dummy item, so no load is branched.
 template <int U, class F>
 __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
                                          const i32* __restrict__ ridx, F&& f) {
     if (ta >= tb) return;
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
-    i32 r0 = (i32)last_le_dev(rstart, 0, R - 1, ta);
-    for (i32 t0 = ta; t0 < tb; t0 += WAVE * U) {
+    i32 r0 = __builtin_amdgcn_readfirstlane((i32)last_le_dev(rstart, 0, R - 1, ta));  // run holding item ta
+    i32 t0 = ta;
+    while (t0 < tb) {
+        const i32 j = r0 + 1 + l;
+        const i32 sj = rstart[j < R ? j : R];
+        const i32 st = j < R ? sj : 0x7fffffff;  // start of run r0 + 1 + l (> t0)
+        const i32 t1 = min(min(tb, t0 + U * WAVE), __builtin_amdgcn_readlane(st, WAVE - 1));
+        const i64 esafe = rbase[r0] + t0;
         i32 rr[U];
         u64 mm[U];
         i64 ee[U];
@@ -125,27 +108,25 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const i32 ts = t0 + s * WAVE;
-            const i32 j = r0 + 1 + l;
-            const i32 st = j < R ? rstart[j] : 0x7fffffff;
+            const i32 before = __popcll(__ballot(st < ts));
             mm[s] = run_start_mask(flags, st, ts);
-            rr[s] = r0 + __popcll(mm[s] & le);
-            r0 = __shfl(rr[s], WAVE - 1, WAVE);
+            rr[s] = r0 + before + __popcll(mm[s] & le);
         }
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const i32 t = t0 + s * WAVE + l;
-            ee[s] = t < tb ? rbase[rr[s]] + t : 0;
+            const i64 e = rbase[rr[s]] + t;
+            ee[s] = t < t1 ? e : esafe;
         }
+#pragma unroll
+        for (int s = 0; s < U; ++s) ww[s] = ridx[ee[s]];
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const i32 t = t0 + s * WAVE + l;
-            ww[s] = t < tb ? ridx[ee[s]] : 0;
+            f(t < t1, t, rr[s], ww[s], ee[s], mm[s], t1);
         }
-#pragma unroll
-        for (int s = 0; s < U; ++s) {
-            const i32 t = t0 + s * WAVE + l;
-            f(t < tb, t, rr[s], ww[s], ee[s], mm[s]);
-        }
+        r0 += __popcll(__ballot(st <= t1));  // the run holding item t1
+        t0 = t1;
     }
 }
 
@@ -251,29 +232,6 @@ __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
         if (hit) return m.pos[4 * b + hit - 1];
         if (q.w == -1) return -1;
         b = (b + 1) & ((1u << B) - 1);
-    }
-}
-
-// Position map of a set of distinct vertex ids (insert once, then look up).
-__device__ __forceinline__ void pos_insert(i32* keys, i32* vals, u32 mask, i32 v, i32 pos) {
-    u32 h = hslot(v, mask);
-    while (true) {
-        const i32 old = atomicCAS(&keys[h], -1, v);
-        if (old == -1) {
-            vals[h] = pos;
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ i32 pos_find(const i32* keys, const i32* vals, u32 mask, i32 v) {
-    u32 h = hslot(v, mask);
-    while (true) {
-        const i32 k = keys[h];
-        if (k == v) return vals[h];
-        if (k == -1) return -1;
-        h = (h + 1) & mask;
     }
 }
 
