@@ -92,6 +92,31 @@ __device__ __forceinline__ i64 wave_max(i64 v) {
     return v;
 }
 
+// Sum over a workgroup of NT threads, valid on thread 0 (part: NT/64 words of LDS).
+template <int NT>
+__device__ __forceinline__ i64 block_sum(i64 v, i64* part) {
+    v = wave_sum(v);
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    i64 t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / WAVE; ++k) t += part[k];
+    __syncthreads();
+    return t;
+}
+
+template <int NT>
+__device__ __forceinline__ i64 block_max(i64 v, i64* part) {
+    v = wave_max(v);
+    if (lane_id() == 0) part[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    i64 t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / WAVE; ++k) t = part[k] > t ? part[k] : t;
+    __syncthreads();
+    return t;
+}
+
 // First index q in [lo, hi) with a[q] >= key (hi if none).
 template <class T, class K>
 __device__ __forceinline__ i64 lower_bound_dev(const T* a, i64 lo, i64 hi, K key) {

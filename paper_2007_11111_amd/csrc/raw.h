@@ -46,6 +46,7 @@ struct RawWs {
     i32* cursor;  // [n+2]
     i64* roff;    // [n+1]
     i32* ridx;    // [nnz]
+    i32* rrow;    // [nnz] row of each entry (rank space)
     i32* rpos;    // [nnz] position of u in row v for N- entries, -1 for N+
     i64* G;       // [nnz+1] exclusive scan of per-entry work counts
     i32* C3;      // [nnz] triangle count per directed entry

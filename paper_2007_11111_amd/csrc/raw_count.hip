@@ -29,20 +29,16 @@ __device__ __forceinline__ i32 load_relaxed(const i32* p) {
 
 // ------------------------------------------------------------ row passes
 
-__global__ void __launch_bounds__(PT) k_l1(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                           const i32* __restrict__ rdeg, i64 n, i64 nnz, i64* __restrict__ sumd,
+__global__ void __launch_bounds__(PT) k_l1(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
+                                           const i32* __restrict__ rdeg, i64 nnz, i64* __restrict__ sumd,
                                            i64* __restrict__ s7) {
     const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
     for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p0 = wv * WAVE;
-        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
-        const i64 r0 = row_of(roff, 0, n - 1, p0);
-        const i64 r1 = row_of(roff, r0, n - 1, pl);
-        const i64 p = p0 + lane_id();
+        const i64 p = wv * WAVE + lane_id();
         const bool act = p < nnz;
         i64 r = -1, a = 0, b = 0;
         if (act) {
-            r = row_of(roff, r0, r1, p);
+            r = rrow[p];
             const i64 dj = rdeg[ridx[p]];
             a = dj;
             b = (dj - 1) * (dj - 2) / 2;
@@ -56,22 +52,18 @@ __global__ void __launch_bounds__(PT) k_l1(const i64* __restrict__ roff, const i
     }
 }
 
-__global__ void __launch_bounds__(PT) k_l2(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
                                            const i32* __restrict__ rdeg, const i32* __restrict__ C3,
-                                           const i64* __restrict__ sumd, const i64* __restrict__ c3v, i64 n,
+                                           const i64* __restrict__ sumd, const i64* __restrict__ c3v,
                                            i64 nnz, i64* __restrict__ ap2, i64* __restrict__ ac3,
                                            i64* __restrict__ d10, i64* __restrict__ d14) {
     const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
     for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p0 = wv * WAVE;
-        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
-        const i64 r0 = row_of(roff, 0, n - 1, p0);
-        const i64 r1 = row_of(roff, r0, n - 1, pl);
-        const i64 p = p0 + lane_id();
+        const i64 p = wv * WAVE + lane_id();
         const bool act = p < nnz;
         i64 r = -1, a = 0, b = 0, c = 0, d = 0;
         if (act) {
-            r = row_of(roff, r0, r1, p);
+            r = rrow[p];
             const i32 j = ridx[p];
             const i64 dj = rdeg[j];
             const i64 t = C3[p];
@@ -440,15 +432,15 @@ __global__ void k_net(i64 n, const i64* __restrict__ raw, i64* __restrict__ net)
 
 hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l1, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rdeg, n, nnz, w.sumd,
+    hipLaunchKernelGGL(k_l1, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, nnz, w.sumd,
                        w.s7);
     return hipGetLastError();
 }
 
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rdeg, w.C3, w.sumd,
-                       w.c3v, n, nnz, w.ap2, w.ac3, w.d10, w.d14);
+    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, w.C3, w.sumd,
+                       w.c3v, nnz, w.ap2, w.ac3, w.d10, w.d14);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ static int bits_for(i64 maxval) {
 
 // ------------------------------------------------------------ input checks
 
-__global__ void k_check_offsets(const i64* __restrict__ off, i64 n, i64 nnz, i32* __restrict__ deg,
+__global__ void __launch_bounds__(PT) k_check_offsets(const i64* __restrict__ off, i64 n, i64 nnz, i32* __restrict__ deg,
                                 DevPlan* plan) {
     i64 dmax = 0;
     u32 err = 0;
@@ -38,8 +38,9 @@ __global__ void k_check_offsets(const i64* __restrict__ off, i64 n, i64 nnz, i32
     if ((i64)blockIdx.x * blockDim.x + threadIdx.x == 0) {
         if (off[0] != 0 || off[n] != nnz) err |= ERR_RANGE;
     }
-    dmax = wave_max(dmax);
-    if (lane_id() == 0 && dmax > 0) atomicMax((unsigned long long*)&plan->d_max, (unsigned long long)dmax);
+    __shared__ i64 part[PT / WAVE];
+    dmax = block_max<PT>(dmax, part);
+    if (threadIdx.x == 0 && dmax > 0) atomicMax((unsigned long long*)&plan->d_max, (unsigned long long)dmax);
     if (err) atomicOr(&plan->err, err);
 }
 
@@ -55,7 +56,7 @@ __global__ void k_check_indices(const i32* __restrict__ idx, i64 nnz, i64 n, Dev
 hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s) {
     hipError_t e = hipMemsetAsync(w.plan, 0, sizeof(DevPlan), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n, PT, 4096)), dim3(PT), 0, s, off, n, nnz, w.deg, w.plan);
+    hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, off, n, nnz, w.deg, w.plan);
     if (nnz > 0) hipLaunchKernelGGL(k_check_indices, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, idx, nnz, n, w.plan);
     return hipGetLastError();
 }
@@ -124,22 +125,31 @@ __global__ void k_rank(const i32* __restrict__ perm, const i32* __restrict__ deg
     }
 }
 
-// ridx[q] = rank[idx[off[perm[r]] + (q - roff[r])]] for q in row r of rank space.
-__global__ void k_relabel_copy(const i64* __restrict__ off, const i32* __restrict__ idx,
-                               const i32* __restrict__ perm, const i32* __restrict__ rank,
-                               const i64* __restrict__ roff, i64 n, i64 nnz, i32* __restrict__ ridx) {
+// rrow[p] = r for every entry p of row r: a wavefront takes 64 consecutive
+// rows, reads their bounds in one load and fills them one after another.
+__global__ void __launch_bounds__(PT) k_rowfill(const i64* __restrict__ roff, i64 n, i32* __restrict__ rrow) {
     const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p0 = wv * WAVE;
-        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
-        const i64 r0 = row_of(roff, 0, n - 1, p0);
-        const i64 r1 = row_of(roff, r0, n - 1, pl);
-        const i64 q = p0 + lane_id();
-        if (q < nnz) {
-            const i64 r = row_of(roff, r0, r1, q);
-            const i64 src = off[perm[r]] + (q - roff[r]);
-            ridx[q] = rank[idx[src]];
+    const int l = lane_id();
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < n; wv += nw) {
+        const i64 r = wv * WAVE + l;
+        const i64 b = r < n ? roff[r] : 0, e = r < n ? roff[r + 1] : 0;
+        const int cnt = (int)std::min<i64>(WAVE, n - wv * WAVE);
+        for (int k = 0; k < cnt; ++k) {
+            const i64 bk = __shfl(b, k, WAVE), ek = __shfl(e, k, WAVE);
+            for (i64 p = bk + l; p < ek; p += WAVE) rrow[p] = (i32)(wv * WAVE + k);
         }
+    }
+}
+
+// ridx[q] = rank[idx[off[perm[r]] + (q - roff[r])]] for q in row r of rank space.
+__global__ void __launch_bounds__(PT) k_relabel_copy(const i64* __restrict__ off, const i32* __restrict__ idx,
+                                                     const i32* __restrict__ perm, const i32* __restrict__ rank,
+                                                     const i64* __restrict__ roff, const i32* __restrict__ rrow,
+                                                     i64 nnz, i32* __restrict__ ridx) {
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (i64)gridDim.x * blockDim.x) {
+        const i64 r = rrow[q];
+        const i64 src = off[perm[r]] + (q - roff[r]);
+        ridx[q] = rank[idx[src]];
     }
 }
 
@@ -159,8 +169,9 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
     hipLaunchKernelGGL(k_rank, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.perm, w.deg, n, w.rank, w.rdeg);
     if ((e = scan_exclusive_i32_to_i64(w.rdeg, w.roff, n, w.partials, s)) != hipSuccess) return e;
     if (nnz > 0) {
+        hipLaunchKernelGGL(k_rowfill, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.roff, n, w.rrow);
         hipLaunchKernelGGL(k_relabel_copy, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, off, idx, w.perm, w.rank,
-                           w.roff, n, nnz, w.ridx);
+                           w.roff, w.rrow, nnz, w.ridx);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = seg_sort(w.ridx, w.roff, n, bits_for(n - 1), w.sort, 65536, s)) != hipSuccess) return e;
     }
@@ -170,8 +181,9 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
 // ------------------------------------------------------------ structure
 
 // lo[u] = |N-(u)| (entries < u); self-loop check; sum of lo.
-__global__ void k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i32* __restrict__ lo,
-                     DevPlan* plan) {
+__global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n,
+                                           i32* __restrict__ lo, DevPlan* plan) {
+    __shared__ i64 part[PT / WAVE];
     i64 sum = 0;
     u32 err = 0;
     for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
@@ -181,8 +193,8 @@ __global__ void k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx,
         lo[u] = (i32)(q - b);
         sum += q - b;
     }
-    sum = wave_sum(sum);
-    if (lane_id() == 0 && sum) atomicAdd((unsigned long long*)&plan->sum_lo, (unsigned long long)sum);
+    sum = block_sum<PT>(sum, part);
+    if (threadIdx.x == 0 && sum) atomicAdd((unsigned long long*)&plan->sum_lo, (unsigned long long)sum);
     if (err) atomicOr(&plan->err, err);
 }
 
@@ -190,19 +202,13 @@ __global__ void k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx,
 //   N- entry (u, v), v < u: rpos = position of u in row v (= number of
 //     neighbours of v below u, the wedge count of the 4-cycle pass);
 //   N+ entry (u, v), v > u: rpos = -1, work = d+(v) (the triangle pass).
-__global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ lo,
-                       const i32* __restrict__ rdeg, i64 n, i64 nnz, i32* __restrict__ rpos, i64* __restrict__ G,
-                       DevPlan* plan) {
+__global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
+                       const i32* __restrict__ lo, const i32* __restrict__ rdeg, i64 nnz, i32* __restrict__ rpos,
+                       i64* __restrict__ G, DevPlan* plan) {
     u32 err = 0;
-    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p0 = wv * WAVE;
-        const i64 pl = std::min<i64>(p0 + WAVE - 1, nnz - 1);
-        const i64 r0 = row_of(roff, 0, n - 1, p0);
-        const i64 r1 = row_of(roff, r0, n - 1, pl);
-        const i64 p = p0 + lane_id();
-        if (p < nnz) {
-            const i64 u = row_of(roff, r0, r1, p);
+    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
+        {
+            const i64 u = rrow[p];
             const i32 v = ridx[p];
             if (p > roff[u] && ridx[p - 1] == v) err |= ERR_DUP;
             i32 rp = -1;
@@ -228,13 +234,47 @@ __global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ rid
     if (err) atomicOr(&plan->err, err);
 }
 
+// Appends the threads of class cls >= 0 to lists[cls * n + ...]: one ballot
+// per class and wavefront, one global atomic per class and workgroup.
+template <int NT, int K>
+__device__ __forceinline__ void block_append(int cls, i32 value, u32* __restrict__ counters, i32* __restrict__ lists,
+                                             i64 n, u32 (*wcnt)[K], u32* sbase) {
+    const int wv = threadIdx.x / WAVE, l = lane_id();
+    u32 rank = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const u64 m = __ballot(cls == c);
+        if (l == 0) wcnt[wv][c] = (u32)__popcll(m);
+        if (cls == c) rank = (u32)__popcll(m & lanemask_lt());
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        const int c = threadIdx.x;
+        u32 run = 0;
+        for (int w = 0; w < NT / WAVE; ++w) {
+            const u32 x = wcnt[w][c];
+            wcnt[w][c] = run;
+            run += x;
+        }
+        sbase[c] = run ? atomicAdd(&counters[c], run) : 0;
+    }
+    __syncthreads();
+    if (cls >= 0) lists[(i64)cls * n + sbase[cls] + wcnt[wv][cls] + rank] = value;
+    __syncthreads();
+}
+
 // Tier lists and statistics from the work counts (G holds the exclusive scan).
-__global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo, const i32* __restrict__ rdeg,
-                        const i64* __restrict__ G, i64 n, Tiers th, i32* __restrict__ tri_list,
-                        i32* __restrict__ c4_list, DevPlan* plan) {
+static constexpr int TT = 1024;
+__global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo,
+                                              const i32* __restrict__ rdeg, const i64* __restrict__ G, i64 n,
+                                              Tiers th, i32* __restrict__ tri_list, i32* __restrict__ c4_list,
+                                              DevPlan* plan) {
+    __shared__ u32 wt[TT / WAVE][3], wc[TT / WAVE][4];
+    __shared__ u32 bt[3], bc[4];
+    __shared__ i64 part[TT / WAVE];
     i64 dpmax = 0;
     i64 titems[3] = {0, 0, 0}, witems[4] = {0, 0, 0, 0};
-    for (i64 u0 = (i64)blockIdx.x * blockDim.x; u0 < n; u0 += (i64)gridDim.x * blockDim.x) {
+    for (i64 u0 = (i64)blockIdx.x * TT; u0 < n; u0 += (i64)gridDim.x * TT) {
         const i64 u = u0 + threadIdx.x;
         int tcls = -1, ccls = -1;
         if (u < n) {
@@ -253,51 +293,31 @@ __global__ void k_tiers(const i64* __restrict__ roff, const i32* __restrict__ lo
             if (tcls >= 0) titems[tcls] += T;
             if (ccls >= 0) witems[ccls] += W;
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const u64 m = __ballot(tcls == c);
-            if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                u32 base = 0;
-                if (lane_id() == leader) base = atomicAdd(&plan->n_tri[c], (u32)__popcll(m));
-                base = __shfl(base, leader, WAVE);
-                if (tcls == c) tri_list[(i64)c * n + base + __popcll(m & lanemask_lt())] = (i32)u;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const u64 m = __ballot(ccls == c);
-            if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                u32 base = 0;
-                if (lane_id() == leader) base = atomicAdd(&plan->n_c4[c], (u32)__popcll(m));
-                base = __shfl(base, leader, WAVE);
-                if (ccls == c) c4_list[(i64)c * n + base + __popcll(m & lanemask_lt())] = (i32)u;
-            }
-        }
+        block_append<TT, 3>(tcls, (i32)u, plan->n_tri, tri_list, n, wt, bt);
+        block_append<TT, 4>(ccls, (i32)u, plan->n_c4, c4_list, n, wc, bc);
     }
-    dpmax = wave_max(dpmax);
-    if (lane_id() == 0 && dpmax > 0)
-        atomicMax((unsigned long long*)&plan->dplus_max, (unsigned long long)dpmax);
+    dpmax = block_max<TT>(dpmax, part);
+    if (threadIdx.x == 0 && dpmax > 0) atomicMax((unsigned long long*)&plan->dplus_max, (unsigned long long)dpmax);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const i64 ti = wave_sum(titems[c]);
-        if (lane_id() == 0 && ti) atomicAdd((unsigned long long*)&plan->tri_items_tier[c], (unsigned long long)ti);
+        const i64 ti = block_sum<TT>(titems[c], part);
+        if (threadIdx.x == 0 && ti) atomicAdd((unsigned long long*)&plan->tri_items_tier[c], (unsigned long long)ti);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        const i64 wi = wave_sum(witems[c]);
-        if (lane_id() == 0 && wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
+        const i64 wi = block_sum<TT>(witems[c], part);
+        if (threadIdx.x == 0 && wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
     }
 }
 
-__global__ void k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo, const i64* __restrict__ G,
-                         i64 n, i64 nnz, DevPlan* plan) {
+__global__ void __launch_bounds__(PT) k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo,
+                                               const i64* __restrict__ G, i64 n, i64 nnz, DevPlan* plan) {
+    __shared__ i64 part[PT / WAVE];
     i64 wedges = 0;
     for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x)
         wedges += G[roff[u] + lo[u]] - G[roff[u]];
-    wedges = wave_sum(wedges);
-    if (lane_id() == 0 && wedges) atomicAdd((unsigned long long*)&plan->wedge_items, (unsigned long long)wedges);
+    wedges = block_sum<PT>(wedges, part);
+    if (threadIdx.x == 0 && wedges) atomicAdd((unsigned long long*)&plan->wedge_items, (unsigned long long)wedges);
 }
 
 int bits_for_n(i64 n) {
@@ -330,15 +350,15 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
 
 hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream_t s) {
     hipError_t e;
-    hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 8192)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.plan);
+    hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.plan);
     if (nnz > 0)
-        hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, n,
-                           nnz, w.rpos, w.G, w.plan);
+        hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rrow, w.lo,
+                           w.rdeg, nnz, w.rpos, w.G, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive_i64(w.G, w.G, nnz, w.partials, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, PT, 8192)), dim3(PT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
+    hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, TT, 256)), dim3(TT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
                        w.tri_list, w.c4_list, w.plan);
-    hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 4096)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
+    hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_bitmap_offsets(n, w, th.tri_lds, s);
 }
@@ -359,6 +379,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.roff = c.take<i64>(nn + 1);
     w.ridx = c.take<i32>(nnz);
     w.rpos = c.take<i32>(nnz);
+    w.rrow = c.take<i32>(nnz);
     w.G = c.take<i64>(nnz + 1);
     w.C3 = c.take<i32>(nnz);
     w.acc = c.take<i64>(10 * nn);
