@@ -366,6 +366,41 @@ __device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
     return cnt[x];
 }
 
+// Pass C from the scratch copy of a chunk's wedge ends, words
+// (middle << 16) | (end - W0) in middle order at sc[cs .. ce): every end gives
+// cnt - 1 to its middle; per wavefront step the sums of each middle's piece
+// come from a DPP prefix sum and go to msum[middle - k0].  Four words in
+// flight per thread.
+__device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs, i32 ce, i32 k0, const u32* cnt,
+                                             i64* msum) {
+    constexpr int U = 4;
+    const int l = lane_id();
+    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
+    for (i32 b0 = cs; b0 < ce; b0 += U * CB_THREADS) {
+        u32 iv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
+            iv[q] = t < ce ? sc[t] : 0u;
+        }
+        const int nq = min(U, (ce - b0 + CB_THREADS - 1) / CB_THREADS);
+        for (int q = 0; q < nq; ++q) {
+            const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
+            const bool act = t < ce;
+            const i32 k = (i32)(iv[q] >> 16);
+            const u32 x = iv[q] & 0xffffu;
+            const i32 P = wave_incl_scan_i32(act ? (i32)((cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu) - 1 : 0);
+            const i32 kp = __shfl_up(k, 1, WAVE), kn = __shfl_down(k, 1, WAVE);
+            const u64 below = __ballot(act && (l == 0 || kp != k)) & le;
+            const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this middle's piece
+            const i32 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+            const bool tail = act && (l == WAVE - 1 || t + 1 >= ce || kn != k);
+            const i64 sum = (i64)P - (sl > 0 ? before : 0);
+            if (tail && sum) atomicAdd((unsigned long long*)&msum[k - k0], (unsigned long long)sum);
+        }
+    }
+}
+
 // Last index h in [0, cnt) with a[h] <= key, for a non-decreasing a with
 // a[0] <= key.  The whole wavefront searches, 64 probes per round, so a list
 // of N entries takes about log64(N) dependent loads.
@@ -391,11 +426,14 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const i32* __restrict__ tab, i64 K1,
                                                           const i32* __restrict__ hs, u32 nh,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
-                                                          i64* __restrict__ c4v) {
+                                                          u32* __restrict__ scr, i64 scr_cap, i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
+    constexpr int MAXCH = 64;  // chunks of a vertex: |N-(u)| < 65536 when counts are packed
     __shared__ u32 cnt[C4W_WORDS];
     __shared__ RunLds R;
     __shared__ i64 msum[CB_THREADS];
+    __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
+    u32* const sc = scr + (i64)blockIdx.x * scr_cap;
     __shared__ i64 sj, sh, red;
     __shared__ i32 wlo, whi;
     const int wv = threadIdx.x / WAVE, l = lane_id();
@@ -468,20 +506,37 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     }
                 }
             };
-            // pass A: count the wedge ends inside the window, note the touched range
+            // pass A: count the wedge ends inside the window, note the touched
+            // range; with packed counts, also copy the ends with their middles
+            // to the workgroup's scratch (chunk by chunk while they fit), so
+            // that pass C streams them instead of gathering the rows again
             i32 T = 0, lmin = INT_MAX, lmax = -1;
+            i64 toff = 0;     // scratch words used (block-uniform)
+            u64 stored = 0;   // chunks whose ends are in the scratch
             for (i32 ch = 0; ch < nch; ++ch) {
                 T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                const bool keep = PACK16 && ch < MAXCH && toff + T <= scr_cap;
+                if (keep && threadIdx.x == 0) {
+                    cst[ch] = (i32)toff;
+                    cst[ch + 1] = (i32)(toff + T);
+                }
+                const i32 k0 = ch * CB_THREADS;
+                u32* const dst = sc + toff;
                 i32 ta, tb;
                 wave_share(T, ta, tb);
                 run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                            [&](bool act, i32, i32, i32 w, i64, u64, i32) {
+                            [&](bool act, i32 t, i32 r, i32 w, i64, u64, i32) {
                                 if (act) {
                                     c4w_inc<PACK16>(cnt, w - W0);
                                     lmin = min(lmin, w);
                                     lmax = max(lmax, w);
+                                    if (keep) dst[t] = ((u32)(k0 + R.rk[r]) << 16) | (u32)(w - W0);
                                 }
                             });
+                if (keep) {
+                    stored |= 1ull << ch;
+                    toff += T;
+                }
                 if (!single) __syncthreads();  // the next chunk overwrites the runs
             }
             lmin = wave_min_i32(lmin);
@@ -493,10 +548,16 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             __syncthreads();
             const i32 xlo = wlo - W0, xhi = whi - W0;
             if (xhi < xlo) continue;  // no wedge end in this window (block-uniform)
-            // pass C: c - 1 to the middle of every wedge (one chunk: its runs are still in LDS)
+            // pass C: c - 1 to the middle of every wedge, streamed from the
+            // scratch, else gathered again (one chunk: its runs are still in LDS)
             for (i32 ch = 0; ch < nch; ++ch) {
-                if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
-                attribute_middles<PACK16>(T, R, ridx, msum, [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
+                if ((stored >> ch) & 1ull) {
+                    c4w_stream_c(sc, cst[ch], cst[ch + 1], ch * CB_THREADS, cnt, msum);
+                } else {
+                    if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                    attribute_middles<PACK16>(T, R, ridx, msum,
+                                              [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
+                }
                 if (!single) {
                     __syncthreads();
                     const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
@@ -611,10 +672,10 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
                                WS, w.c4_tab);
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS, w.c4_jobcnt);
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
-        const unsigned grid = 512;
+        const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
 #define C4W_LAUNCH(P16, TB)                                                                                    \
     hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.c4_tab, K1, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4v)
+                       w.c4_tab, K1, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
         if (pack16 && use_tab) C4W_LAUNCH(true, true);
         else if (pack16) C4W_LAUNCH(true, false);
         else if (use_tab) C4W_LAUNCH(false, true);

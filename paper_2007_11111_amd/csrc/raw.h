@@ -18,6 +18,7 @@ constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slo
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
 constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
+constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
 
 // Device statistics / plan words (one small block of device memory).
 struct DevPlan {
@@ -69,6 +70,8 @@ struct RawWs {
     i64 bstore_cap;     // its capacity in words
     i32* c4_tab;        // window table of the heavy 4-cycle tier (optional)
     i64 c4_tab_cap;     // its capacity in entries
+    u32* c4_scr;        // [C4W_GRID * c4_scr_cap] per-workgroup copies of a window's wedge ends
+    i64 c4_scr_cap;
     // scratch
     i64* partials;
     SegSortWs sort;

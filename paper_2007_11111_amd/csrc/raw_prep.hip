@@ -420,6 +420,9 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
         w.c4_tab = w.c4_tab_cap ? c.take<i32>(w.c4_tab_cap) : nullptr;
         if (!c.base) w.c4_tab = nullptr;
     }
+    // window-tier scratch: up to 2^20 words per workgroup, at most nnz / 16
+    w.c4_scr_cap = std::max<i64>(std::min<i64>((i64)1 << 20, nnz / 16), 1024);
+    w.c4_scr = c.take<u32>(C4W_GRID * w.c4_scr_cap);
     w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
     w.sort.tmp = c.take<i32>(std::max(nnz, nn));
     w.sort.lists = c.take<i32>(3 * (nn + 2));
