@@ -2,7 +2,7 @@
 // per-entry work counts that drive the counting passes.
 #include <algorithm>
 
-#include "raw.h"
+#include "walk.h"
 
 namespace fglt {
 
@@ -125,18 +125,43 @@ __global__ void k_rank(const i32* __restrict__ perm, const i32* __restrict__ deg
     }
 }
 
-// rrow[p] = r for every entry p of row r: a wavefront takes 64 consecutive
-// rows, reads their bounds in one load and fills them one after another.
-__global__ void __launch_bounds__(PT) k_rowfill(const i64* __restrict__ roff, i64 n, i32* __restrict__ rrow) {
+// rrow[p] = r for every entry p of row r.  A wavefront takes 4096
+// consecutive entries (balanced whatever the row lengths), finds the row of
+// its first entry with a 64-way search, then walks 64 entries per step: the
+// next 64 row starts (one per lane, strictly increasing past the first row
+// with entries) are marked in an LDS row and counted per lane.
+static constexpr i64 RF_CHUNK = 4096;
+__global__ void __launch_bounds__(PT) k_rowfill(const i64* __restrict__ roff, i64 n, i64 nnz,
+                                                i32* __restrict__ rrow) {
+    __shared__ i32 flags[PT / WAVE][WAVE];
+    const int l = lane_id(), wv = threadIdx.x / WAVE;
+    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
     const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    const int l = lane_id();
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < n; wv += nw) {
-        const i64 r = wv * WAVE + l;
-        const i64 b = r < n ? roff[r] : 0, e = r < n ? roff[r + 1] : 0;
-        const int cnt = (int)std::min<i64>(WAVE, n - wv * WAVE);
-        for (int k = 0; k < cnt; ++k) {
-            const i64 bk = __shfl(b, k, WAVE), ek = __shfl(e, k, WAVE);
-            for (i64 p = bk + l; p < ek; p += WAVE) rrow[p] = (i32)(wv * WAVE + k);
+    for (i64 c = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; c * RF_CHUNK < nnz; c += nw) {
+        const i64 p0 = c * RF_CHUNK, p1 = std::min<i64>(p0 + RF_CHUNK, nnz);
+        // last row r with roff[r] <= p0 (that row has entries, as p0 < nnz)
+        i64 lo_ = 0, hi_ = n;
+        while (hi_ - lo_ > 1) {
+            const i64 step = (hi_ - lo_ + WAVE - 1) / WAVE;
+            const i64 q = lo_ + (i64)l * step;
+            const int cnt = __popcll(__ballot(q < hi_ && roff[q] <= p0));
+            lo_ += (i64)(cnt - 1) * step;
+            hi_ = std::min<i64>(hi_, lo_ + step);
+        }
+        i64 r = lo_;
+        for (i64 t0 = p0; t0 < p1; t0 += WAVE) {
+            const i64 j = r + 1 + l;
+            const i64 stl = j < n ? roff[j] : ((i64)1 << 62);
+            const i32 st = stl < t0 + WAVE ? (i32)(stl - t0) : WAVE;  // offset in this step, WAVE when later
+            lds_put(&flags[wv][l], 0);
+            wave_lds_fence();
+            if (st < WAVE) lds_put(&flags[wv][st], 1);
+            wave_lds_fence();
+            const u64 mask = __ballot(lds_get(&flags[wv][l]) != 0);
+            wave_lds_fence();
+            const i64 t = t0 + l;
+            if (t < p1) rrow[t] = (i32)(r + __popcll(mask & le));
+            r += __popcll(mask);
         }
     }
 }
@@ -169,7 +194,8 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
     hipLaunchKernelGGL(k_rank, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.perm, w.deg, n, w.rank, w.rdeg);
     if ((e = scan_exclusive_i32_to_i64(w.rdeg, w.roff, n, w.partials, s)) != hipSuccess) return e;
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_rowfill, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.roff, n, w.rrow);
+        hipLaunchKernelGGL(k_rowfill, dim3(grid_for(nnz, PT / WAVE * RF_CHUNK, 65536)), dim3(PT), 0, s, w.roff, n,
+                           nnz, w.rrow);
         hipLaunchKernelGGL(k_relabel_copy, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, off, idx, w.perm, w.rank,
                            w.roff, w.rrow, nnz, w.ridx);
         if ((e = hipGetLastError()) != hipSuccess) return e;
