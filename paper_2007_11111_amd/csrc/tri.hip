@@ -234,7 +234,14 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
 // increasing order).  A miss contributes nothing.
 __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i32* __restrict__ C3, i64& from,
                                           i64 end, i32 y) {
-    const i64 q = lower_bound_dev(ridx, from, end, y);
+    // galloping from `from`: probes at from, from+1, from+3, ... until past y,
+    // then a binary search in the last gap (successive targets are close)
+    i64 lo_ = from, step = 1;
+    while (lo_ + step - 1 < end && ridx[lo_ + step - 1] < y) {
+        lo_ += step;
+        step <<= 1;
+    }
+    const i64 q = lower_bound_dev(ridx, lo_, std::min(lo_ + step - 1, end), y);
     if (q >= end || ridx[q] != y) return 0;
     from = q + 1;
     return (i64)C3[q] - 1;
@@ -324,25 +331,25 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
         const int D = (int)(roff[u + 1] - bu);
         const int W = (D + 63) >> 6;
         const u64* src = bstore + boff[u];
-        for (int q = threadIdx.x; q < D * W; q += LT) {
-            B[q] = src[q];
-            C[q] = 0;
-        }
+        for (int q = threadIdx.x; q < D * W; q += LT) B[q] = src[q];
         if (threadIdx.x < D) {
             L[threadIdx.x] = ridx[bu + threadIdx.x];
             c3u[threadIdx.x] = C3[bu + threadIdx.x];
         }
         if (threadIdx.x < 2) red[threadIdx.x] = 0;
         __syncthreads();
-        const int k = threadIdx.x;
-        if (k < D) {
-            for (int z = 0; z < W; ++z)
-                FOR_BITS(B[k * W + z], b, {
-                    const int l = z * 64 + b;
-                    atomicOr((unsigned long long*)&C[l * W + (k >> 6)], 1ull << (k & 63));
-                });
+        // C = transpose of B, 64 x 64 blocks: wavefront wv takes the blocks
+        // (bi, bj) with bi * W + bj = wv (mod LT / 64); lane = row in the block
+        for (int blk = threadIdx.x / WAVE; blk < W * W; blk += LT / WAVE) {
+            const int bi = blk / W, bj = blk % W;
+            const int row = bi * 64 + lane_id();
+            const u64 m = row < D ? B[row * W + bj] : 0ull;
+            const u64 t = wave_transpose64(m);  // column bj * 64 + lane of the block
+            const int col = bj * 64 + lane_id();
+            if (col < D) C[col * W + bi] = t;
         }
         __syncthreads();
+        const int k = threadIdx.x;
         i64 R = 0, du = 0;
         if (k < D) {
             const u64* Bk = B + k * W;
