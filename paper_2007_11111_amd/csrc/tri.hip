@@ -350,13 +350,11 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
         }
         __syncthreads();
         const int k = threadIdx.x;
-        i64 R = 0, du = 0;
+        i64 R = 0;  // the diamond term of u comes from k_tri2_du_lds
         if (k < D) {
             const u64* Bk = B + k * W;
             const u64* Ck = C + k * W;
             const i32 vk = L[k];
-            i64 from = roff[vk] + lo[vk];
-            const i64 end = roff[vk] + rdeg[vk];
             i64 M = 0, X = 0, dv = 0;
             for (int wa = 0; wa < W; ++wa) {
                 FOR_BITS(Bk[wa], bb, {
@@ -364,7 +362,6 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
                     const u64* Bl = B + l * W;
                     for (int z = 0; z < W; ++z) R += __popcll(Bk[z] & Bl[z]);
                     dv += c3u[l] - 1;
-                    du += c3_minus_1(ridx, C3, from, end, L[l]);
                 });
                 FOR_BITS(Ck[wa], bb, {
                     const int j = wa * 64 + bb;
@@ -381,17 +378,67 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
             if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
         }
         R = wave_sum(R);
-        du = wave_sum(du);
-        if (lane_id() == 0) {
-            if (R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
-            if (du) atomicAdd((unsigned long long*)&red[1], (unsigned long long)du);
-        }
+        if (lane_id() == 0 && R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
         __syncthreads();
+        if (threadIdx.x == 0 && red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
+        __syncthreads();
+    }
+}
+
+// Diamond term of u for the LDS tier: over the triangles (u, v_k, v_l), the
+// number of other triangles on the opposite edge, C3(v_k, v_l) - 1.  The
+// out-lists N+(v_k) are walked again as in the triangle pass; a hit y = v_l
+// sits at the walked entry e, whose C3 is final now.
+__global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                    const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                    const i32* __restrict__ list, u32 count,
+                                                    const i32* __restrict__ C3, i64* __restrict__ d13) {
+    constexpr int DM = TRI_LDS_MAX;
+    constexpr int NWV = LT / WAVE;
+    __shared__ i64 rbase[DM + 1];
+    __shared__ i32 rstart[DM + 1];
+    __shared__ BucketMap<9> pm;
+    __shared__ i32 flags[NWV][WAVE];
+    __shared__ i32 wsum[NWV];
+    __shared__ i32 stot, sR;
+    __shared__ i64 part[NWV];
+    const int wv = threadIdx.x / WAVE;
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        const i64 gb = G[bu];
+        const i32 T = (i32)(G[bu + D] - gb);
+        bmap_clear(pm, threadIdx.x, LT);
+        __syncthreads();
+        const int k = threadIdx.x;
+        i32 len = 0, pre = 0;
+        i64 bv = 0;
+        if (k < D) {
+            const i32 v = ridx[bu + k];
+            bmap_insert(pm, v, k);
+            pre = (i32)(G[bu + k] - gb);
+            len = (i32)(G[bu + k + 1] - G[bu + k]);
+            bv = roff[v] + lo[v];
+        }
+        const i32 cidx = block_scan<LT>(len > 0 ? 1 : 0, wsum, &stot);
+        if (k < D && len > 0) {
+            rbase[cidx] = bv - pre;
+            rstart[cidx] = pre;
+        }
         if (threadIdx.x == 0) {
-            if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
-            if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
+            sR = stot;
+            rstart[stot] = T;
         }
         __syncthreads();
+        const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+        i64 du = 0;
+        run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, sR, flags[wv], ridx,
+                    [&](bool act, i32, i32, i32 y, i64 e, u64, i32) {
+                        if (act && bmap_find(pm, y) >= 0) du += (i64)C3[e] - 1;
+                    });
+        du = block_sum<LT>(du, part);
+        if (threadIdx.x == 0 && du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
     }
 }
 
@@ -434,9 +481,12 @@ hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s,
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
                            w.tri_list, c0, w.C3, w.k4v, w.d13, w.bstore, w.boff);
-    if (tier == 1 && c1)
+    if (tier == 1 && c1) {
         hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
                            w.tri_list + n, c1, w.C3, w.k4v, w.d13, w.bstore, w.boff);
+        hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
+                           w.tri_list + n, c1, w.C3, w.d13);
+    }
     return hipGetLastError();
 }
 
