@@ -66,6 +66,14 @@ def seg_units(seg, st):
     return st["wedge_items_tier"][tier]
 
 
+# The kernel behind each timed segment whose traffic the counters give.
+SEG_KERNEL = {
+    "c4_window": "k_c4_window", "c4_hash": "k_c4_hashbig", "c4_block": "k_c4_hash<4, 4096>",
+    "c4_wave": "k_c4_hash<1, 256>", "tri1_wave": "k_tri1_wave", "tri1_lds": "k_tri1_lds",
+    "tri2_wave": "k_tri2s_wave", "l1": "k_l1", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
+}
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2007_11111_amd", "csrc")
@@ -76,10 +84,11 @@ def source_hash():
 
 
 def load_traffic(seg):
-    """HBM bytes per launch of `seg` from committed rocprofv3 counters, or None
-    if absent or taken on a different kernel source."""
+    """HBM bytes per launch of the kernel behind `seg` from the committed
+    rocprofv3 counters (profiles/traffic.json), or None if absent or taken on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or seg not in SEG_KERNEL:
         return None
     try:
         t = json.load(open(path))
@@ -87,8 +96,61 @@ def load_traffic(seg):
         return None
     if t.get("source_sha256") != source_hash():
         return None
-    entry = t.get("segments", {}).get(seg)
-    return None if entry is None else entry.get("bytes_per_launch")
+    k = SEG_KERNEL[seg]
+    hits = [v for name, v in t.get("kernels", {}).items() if name == k or name.startswith(k + "<")]
+    return max(v["bytes_per_launch"] for v in hits) if hits else None
+
+
+def _counter_means(db):
+    """Per-kernel mean of each counter (KiB for FETCH_SIZE / WRITE_SIZE) over
+    the dispatches of a rocprofv3 results database."""
+    import collections
+    import sqlite3
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)")]
+    ki, ci, vi = cols.index("kernel_name"), cols.index("counter_name"), cols.index("value")
+    di = cols.index("dispatch_id")
+    tot = collections.defaultdict(float)
+    disp = collections.defaultdict(set)
+    for r in cur.execute("select * from counters_collection"):
+        name = r[ki].split("(")[0].replace("void ", "").replace("fglt::", "")
+        tot[(name, r[ci])] += r[vi]
+        disp[(name, r[ci])].add(r[di])
+    return {k: v / len(disp[k]) for k, v in tot.items()}
+
+
+def write_traffic(prof_dir, command):
+    """profiles/traffic.json from four rocprofv3 --pmc runs under prof_dir
+    (fetch/, write/: the benchmark; cfetch/, cwrite/: --copy-calibration 1024).
+    Each counter is scaled by what it reads for the plain 1 GiB device copy."""
+    import glob
+    def db(sub):
+        return glob.glob(os.path.join(prof_dir, sub, "*_results.db"))[0]
+    copy_bytes = 1024 << 20
+    cf = _counter_means(db("cfetch"))
+    cw = _counter_means(db("cwrite"))
+    fetch_copy = cf[("__amd_rocclr_copyBuffer", "FETCH_SIZE")] * 1024
+    write_copy = cw[("__amd_rocclr_copyBuffer", "WRITE_SIZE")] * 1024
+    fs, ws_ = copy_bytes / fetch_copy, copy_bytes / write_copy
+    f = _counter_means(db("fetch"))
+    w = _counter_means(db("write"))
+    kernels = {}
+    for (name, ctr), v in f.items():
+        if ctr != "FETCH_SIZE" or not name.startswith("k_"):
+            continue
+        wr = w.get((name, "WRITE_SIZE"), 0.0)
+        kernels[name] = {"fetch_kib": round(v, 1), "write_kib": round(wr, 1),
+                         "bytes_per_launch": int(v * 1024 * fs + wr * 1024 * ws_)}
+    out = {"source_sha256": source_hash(), "command": command,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_bytes_read": fetch_copy, "write_bytes_read": write_copy,
+                           "fetch_scale": fs, "write_scale": ws_},
+           "kernels": dict(sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"]))}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
 
 
 def cpu_baseline(off, idx, m, sample, seed=0):
@@ -154,7 +216,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="only write profiles/traffic.json from rocprofv3 counter runs under DIR and exit")
+    ap.add_argument("--traffic-command", default="", help="the command recorded with --traffic-from")
     args = ap.parse_args()
+    if args.traffic_from:
+        out = write_traffic(args.traffic_from, args.traffic_command)
+        print(json.dumps(out["calibration"]))
+        return
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20

@@ -72,8 +72,9 @@ enum {
     FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
     FGLT_SEG_C4_WAVE,        /* 4-cycle pass, wavefront tier                      */
     FGLT_SEG_C4_BLOCK,       /* 4-cycle pass, workgroup tier                      */
-    FGLT_SEG_C4_HASH,        /* 4-cycle pass, packed-hash workgroup tier          */
-    FGLT_SEG_C4_WINDOW,      /* 4-cycle pass, dense-counter window tier           */
+    FGLT_SEG_C4_HASH,        /* 4-cycle pass, packed-hash workgroup tier, then the
+                                window tier's job setup (sort, window table)      */
+    FGLT_SEG_C4_WINDOW,      /* 4-cycle pass, dense-counter window tier (kernel)  */
     FGLT_SEG_FINALIZE,       /* Table I assembly, Table II, scatter to caller order */
     FGLT_NSEG
 };

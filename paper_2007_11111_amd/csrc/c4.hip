@@ -657,7 +657,7 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
         hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
                            w.rpos, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
     }
-    tm.mark(FGLT_SEG_C4_WINDOW, s);
+    if (!c3) tm.mark(FGLT_SEG_C4_WINDOW, s);
     if (c3) {
         // window-tier vertices in ascending order, then the job counts
         i32* hs = w.c4_list + 3 * n;
@@ -672,6 +672,7 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
                                WS, w.c4_tab);
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS, w.c4_jobcnt);
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
+        tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
         const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
 #define C4W_LAUNCH(P16, TB)                                                                                    \
     hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
