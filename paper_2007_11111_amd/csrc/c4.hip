@@ -375,7 +375,6 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
                                              i64* msum) {
     constexpr int U = 4;
     const int l = lane_id();
-    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
     for (i32 b0 = cs; b0 < ce; b0 += U * CB_THREADS) {
         u32 iv[U];
 #pragma unroll
@@ -389,14 +388,17 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
             const bool act = t < ce;
             const i32 k = (i32)(iv[q] >> 16);
             const u32 x = iv[q] & 0xffffu;
-            const i32 P = wave_incl_scan_i32(act ? (i32)((cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu) - 1 : 0);
-            const i32 kp = __shfl_up(k, 1, WAVE), kn = __shfl_down(k, 1, WAVE);
-            const u64 below = __ballot(act && (l == 0 || kp != k)) & le;
-            const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this middle's piece
-            const i32 before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
+            const i32 val = act ? (i32)((cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu) - 1 : 0;
+            const i32 P = wave_incl_scan_i32(val);
+            // neighbours' middles by DPP wavefront shifts (lane 0 and lane 63 are ends anyway)
+            const i32 kp = __builtin_amdgcn_update_dpp(0, k, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const i32 kn = __builtin_amdgcn_update_dpp(0, k, 0x130, 0xf, 0xf, false);  // wave_shl:1
+            const bool head = act && (l == 0 || kp != k);
             const bool tail = act && (l == WAVE - 1 || t + 1 >= ce || kn != k);
-            const i64 sum = (i64)P - (sl > 0 ? before : 0);
-            if (tail && sum) atomicAdd((unsigned long long*)&msum[k - k0], (unsigned long long)sum);
+            // a piece's sum is P(tail) - P(before its head): the tail adds P, the head
+            // takes away its exclusive prefix
+            const i64 add = (tail ? (i64)P : 0) - (head ? (i64)(P - val) : 0);
+            if (add) atomicAdd((unsigned long long*)&msum[k - k0], (unsigned long long)add);
         }
     }
 }
@@ -570,12 +572,28 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             }
             // pass B: C(c, 2) to every end w and to u, over the touched range
             // (after the gathers, so that these atomics hold back no load of the walks)
-            for (i32 x = xlo + (i32)threadIdx.x; x <= xhi; x += CB_THREADS) {
-                const i64 c = c4w_get<PACK16>(cnt, x);
-                if (c >= 2) {
-                    const i64 pr = c * (c - 1) / 2;
-                    accu += pr;
-                    atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+            if (PACK16) {  // word by word: two counts per word, most words zero
+                for (i32 q = (xlo >> 1) + (i32)threadIdx.x; q <= (xhi >> 1); q += CB_THREADS) {
+                    const u32 wd = cnt[q];
+                    if (wd == 0) continue;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const i64 c = (wd >> (16 * h)) & 0xffffu;
+                        if (c >= 2) {
+                            const i64 pr = c * (c - 1) / 2;
+                            accu += pr;
+                            atomicAdd((unsigned long long*)&c4v[W0 + 2 * q + h], (unsigned long long)pr);
+                        }
+                    }
+                }
+            } else {
+                for (i32 x = xlo + (i32)threadIdx.x; x <= xhi; x += CB_THREADS) {
+                    const i64 c = c4w_get<PACK16>(cnt, x);
+                    if (c >= 2) {
+                        const i64 pr = c * (c - 1) / 2;
+                        accu += pr;
+                        atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+                    }
                 }
             }
             __syncthreads();
