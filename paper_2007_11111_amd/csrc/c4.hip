@@ -213,25 +213,26 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
     const int wv = (int)threadIdx.x / WAVE;
     run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
                 [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask, i32 tend) {
-                    i64 P, before;  // inclusive prefix over the wave; the prefix before this run piece
-                    const u64 below = mask & (l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1));
-                    const int sl = below ? 63 - __clzll((long long)below) : 0;  // first lane of this run piece
+                    // a run piece's sum is P(tail) - P(before its head): the tail
+                    // adds the inclusive prefix, the head takes away its exclusive one
+                    i64 P, val;
                     if (SMALL) {
-                        const i32 p = wave_incl_scan_i32(act ? (i32)get(w) - 1 : 0);
-                        P = p;
-                        before = __shfl(p, sl > 0 ? sl - 1 : 0, WAVE);
+                        const i32 v = act ? (i32)get(w) - 1 : 0;
+                        P = wave_incl_scan_i32(v);
+                        val = v;
                     } else {
-                        P = act ? (i64)get(w) - 1 : 0;
+                        val = act ? (i64)get(w) - 1 : 0;
+                        P = val;
 #pragma unroll
                         for (int o = 1; o < WAVE; o <<= 1) {
                             const i64 y = __shfl_up(P, o, WAVE);
                             if (l >= o) P += y;
                         }
-                        before = __shfl(P, sl > 0 ? sl - 1 : 0, WAVE);
                     }
+                    const bool head = act && (l == 0 || ((mask >> l) & 1ull));
                     const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tend);
-                    const i64 sum = P - (sl > 0 ? before : 0);
-                    if (tail && sum) atomicAdd((unsigned long long*)&msum[R.rk[r]], (unsigned long long)sum);
+                    const i64 add = (tail ? P : 0) - (head ? P - val : 0);
+                    if (add) atomicAdd((unsigned long long*)&msum[R.rk[r]], (unsigned long long)add);
                 });
 }
 
