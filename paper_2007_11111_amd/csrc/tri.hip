@@ -253,62 +253,60 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
                                                    const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                    i64* __restrict__ d13, const u64* __restrict__ bstore,
                                                    const i64* __restrict__ boff) {
+    // Each wavefront works alone on its vertices: row k of B and of C = B^T in
+    // lane k's registers, the rows l broadcast one after another (readlane), so
+    // every lane runs the same D iterations with no LDS traffic and no
+    // divergence.  Only the searches of the diamond term of u diverge.
     constexpr int NW = WT / WAVE;
-    __shared__ u64 sB[NW][WAVE];
-    __shared__ u64 sC[NW][WAVE];
     __shared__ i32 sL[NW][WAVE];
-    __shared__ i32 c3u[NW][WAVE];
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
-    for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
-        const i64 it = base + wid;
-        const bool valid = it < (i64)count;
-        i64 u = 0, bu = 0;
-        int D = 0;
-        if (valid) {
-            u = list[it];
-            bu = roff[u] + lo[u];
-            D = (int)(roff[u + 1] - bu);
-            if (lane < D) {
-                sB[wid][lane] = bstore[boff[u] + lane];
-                sL[wid][lane] = ridx[bu + lane];
-                c3u[wid][lane] = C3[bu + lane];
-            }
+    for (i64 it = (i64)blockIdx.x * NW + wid; it < (i64)count; it += (i64)gridDim.x * NW) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        u64 Bk = 0;
+        i32 vk = 0, c3k = 0;
+        if (lane < D) {
+            Bk = bstore[boff[u] + lane];
+            vk = ridx[bu + lane];
+            c3k = C3[bu + lane];
         }
-        __syncthreads();
-        if (valid) sC[wid][lane] = wave_transpose64(lane < D ? sB[wid][lane] : 0ull);
-        __syncthreads();
-        if (valid) {
-            i64 R = 0, du = 0;
-            if (lane < D) {
-                const u64 Bk = sB[wid][lane], Ck = sC[wid][lane];
-                const i32 vk = sL[wid][lane];
-                i64 from = roff[vk] + lo[vk];
-                const i64 end = roff[vk] + rdeg[vk];
-                i64 M = 0, X = 0, dv = 0;
-                FOR_BITS(Bk, l, {
-                    R += __popcll(Bk & sB[wid][l]);
-                    dv += c3u[wid][l] - 1;
-                    du += c3_minus_1(ridx, C3, from, end, sL[wid][l]);
-                });
-                FOR_BITS(Ck, j, {
-                    const u64 Bj = sB[wid][j];
-                    M += __popcll(Bj & Bk);
-                    X += __popcll(Bj & Ck);
-                    dv += c3u[wid][j] - 1;
-                });
-                const i64 kv = R + M + X;
-                if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
-                if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
-            }
-            R = wave_sum(R);
-            du = wave_sum(du);
-            if (lane == 0) {
-                if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)R);
-                if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
-            }
+        const u64 Ck = wave_transpose64(Bk);
+        lds_put(&sL[wid][lane], vk);
+        wave_lds_fence();
+        // K4: R_k = sum over l in B_k of |B_k & B_l|, M_k = sum over j in C_k of
+        // |B_j & B_k|, X_k = sum over j in C_k of |B_j & C_k|.  Diamonds of v_k:
+        // C3(u, v_l) - 1 over the other vertex v_l of each of its triangles.
+        i64 R = 0, M = 0, X = 0, dv = 0;
+        for (int l = 0; l < D; ++l) {
+            const u64 Bl = (u64)(u32)__builtin_amdgcn_readlane((i32)(u32)Bk, l) |
+                           ((u64)(u32)__builtin_amdgcn_readlane((i32)(u32)(Bk >> 32), l) << 32);
+            const i64 cl = __builtin_amdgcn_readlane(c3k, l);
+            const bool inB = (Bk >> l) & 1ull, inC = (Ck >> l) & 1ull;
+            const i64 t = __popcll(Bk & Bl);
+            R += inB ? t : 0;
+            M += inC ? t : 0;
+            X += inC ? (i64)__popcll(Bl & Ck) : 0;
+            dv += (inB || inC) ? cl - 1 : 0;
         }
-        __syncthreads();
+        i64 du = 0;
+        if (lane < D) {
+            // diamonds of u: C3(v_k, v_l) - 1 over the triangles (u, v_k, v_l)
+            i64 from = roff[vk] + lo[vk];
+            const i64 end = roff[vk] + rdeg[vk];
+            FOR_BITS(Bk, l, { du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l])); });
+            const i64 kv = R + M + X;
+            if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
+            if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+        }
+        R = wave_sum(R);
+        du = wave_sum(du);
+        if (lane == 0) {
+            if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)R);
+            if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
+        }
+        wave_lds_fence();  // the next vertex overwrites sL
     }
 }
 
