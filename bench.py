@@ -45,6 +45,7 @@ SEG_UNITS = {
     "tri2_wave": ("item", 8),    # out-list index + its C3 per merge item
     "tri2_lds": ("item", 8),
     "tri2_global": ("item", 8),
+    "tri2_sum": ("entry", 12),   # row id + packed clique/diamond counts per entry
     "c4_wave": ("wedge", 8),     # wedge end read in the count and attribution passes
     "c4_block": ("wedge", 8),
     "c4_hash": ("wedge", 8),

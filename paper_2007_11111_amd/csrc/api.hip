@@ -91,7 +91,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     const bool stored = bitmap_words <= w.bstore_cap;
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
     tm.mark(FGLT_SEG_FILL, s);
-    FGLT_HIP_TRY(launch_fill_c3(nnz, w, s));
+    FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
     tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
@@ -104,7 +104,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
         FGLT_HIP_TRY(launch_count_triangles(n, w, s));
         DevPlan fin{};
         if ((st = read_plan(w, fin, s))) return st;
-        triangles = fin.triangles / 3;  // every triangle is counted at its three vertices
+        triangles = fin.triangles / 6;  // twice at each of its three vertices
     }
 
     if (stats) {

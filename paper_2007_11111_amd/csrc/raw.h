@@ -14,6 +14,11 @@ namespace fglt {
 // Tier thresholds.
 constexpr int TRI_WAVE_MAX = 64;     // out-degree handled by one wavefront (one bitmap word)
 constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup's LDS
+// Clique-pass count of an N+ entry, packed as dv << EK_SHIFT | kv: kv (the
+// 4-cliques) is at most 2 (D - 1)^2 < 2^20 for D <= TRI_LDS_MAX, dv (the
+// diamonds) below D * 2^21 (degrees < 2^21), so the word stays below 2^50.
+constexpr int EK_SHIFT = 20;
+static_assert(2 * (TRI_LDS_MAX - 1) * (TRI_LDS_MAX - 1) < (1 << EK_SHIFT), "kv must fit below EK_SHIFT");
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
@@ -48,12 +53,14 @@ struct RawWs {
     i64* roff;    // [n+1]
     i32* ridx;    // [nnz]
     i32* rrow;    // [nnz] row of each entry (rank space)
-    i32* rpos;    // [nnz] position of u in row v for N- entries, -1 for N+
+    i32* rpos;    // [nnz] N- entry (u, v): position of u in row v; N+ entry (u, v): ~(position of u in row v)
     i64* G;       // [nnz+1] exclusive scan of per-entry work counts
     i32* C3;      // [nnz] triangle count per directed entry
-    // per-vertex accumulators (rank space), contiguous block of 10*n
+    i64* ek;      // [max(nnz, n)] clique pass: packed 4-clique / diamond counts of the N+ entry (u, v)
+                  // stored at its mirror (v, u); shares memory with sort.tmp (relabelling only)
+    // per-vertex accumulators (rank space), contiguous block of 10*n; c3x2 = 2 c3
     i64* acc;
-    i64 *sumd, *s7, *c3v, *ap2, *ac3, *d10, *d14, *d13, *c4v, *k4v;
+    i64 *sumd, *s7, *c3x2, *ap2, *ac3, *d10, *d14, *d13, *c4v, *k4v;
     // work lists
     i32* tri_list;  // [3][n]
     i32* c4_list;   // [4][n]
@@ -113,7 +120,7 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
 hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier);
 hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
                       SegTimer& tm);
-hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);

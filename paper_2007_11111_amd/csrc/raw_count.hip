@@ -2,12 +2,13 @@
 //
 //   L1  row pass:   sum_j d_j (-> p2 = A p1 - p1) and sum_j C(d_j - 1, 2) (-> \hat d_7)
 //   TRI mode 1:     oriented triangle listing per vertex u over N+(u); C3 on
-//                   every oriented edge and c3 per vertex (C3 = A .* A^2, Lemma 2)
-//   FILL:           C3 copied to the mirrored entries
+//                   every oriented edge (C3 = A .* A^2, Lemma 2)
+//   FILL:           C3 copied to the mirrored entries; row sums 2 c3 = C3 e
 //   L2  row pass:   A p2, A c3, C3 (p1 - 2), sum_j C(C3(i,j), 2)   (Table I rows 5, 9, 10, 14)
 //   TRI mode 2:     the induced subgraph on N+(u) as LDS bitmaps; per vertex
 //                   4-cliques (T e / 6, Section IV-C) and off-cord diamonds
-//                   (D4,c e / 2) attributed to all four / three vertices
+//                   (D4,c e / 2) attributed to all four / three vertices; the
+//                   per-entry shares stored at mirrored entries summed by rows
 //   C4:             (c4.hip) rank-ordered wedges u - v - w with v, w < u;
 //                   4-cycles (C4,2 e / 2, Lemma 5) attributed to u, w and the middles
 //   FINALIZE:       Table I assembled per vertex, Table II back-substitution,
@@ -54,7 +55,7 @@ __global__ void __launch_bounds__(PT) k_l1(const i32* __restrict__ rrow, const i
 
 __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
                                            const i32* __restrict__ rdeg, const i32* __restrict__ C3,
-                                           const i64* __restrict__ sumd, const i64* __restrict__ c3v,
+                                           const i64* __restrict__ sumd, const i64* __restrict__ c3x2,
                                            i64 nnz, i64* __restrict__ ap2, i64* __restrict__ ac3,
                                            i64* __restrict__ d10, i64* __restrict__ d14) {
     const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
@@ -68,7 +69,7 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
             const i64 dj = rdeg[j];
             const i64 t = C3[p];
             a = sumd[j] - dj;          // p2(j)
-            b = c3v[j];                // c3(j)
+            b = c3x2[j] >> 1;          // c3(j)
             c = t * (dj - 2);          // C3(i,j) (p1(j) - 2); t == 0 when dj == 1
             d = t * (t - 1) / 2;       // C(C3(i,j), 2)
         }
@@ -85,11 +86,57 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
     }
 }
 
-__global__ void k_fill_c3(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ rpos,
-                          i64 nnz, i32* __restrict__ C3) {
-    for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
-        const i32 rp = rpos[p];
-        if (rp >= 0) C3[p] = C3[roff[ridx[p]] + rp];
+// C3 of each N- entry copied from its mirror, and the row sums C3 e = 2 c3
+// (each triangle at v lies on two of its edges; Lemma 2).  When the clique
+// pass stores per-entry counts, their slots are cleared here.
+__global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                const i32* __restrict__ rpos, const i32* __restrict__ rrow,
+                                                i64 nnz, i32* __restrict__ C3, i64* __restrict__ c3x2,
+                                                i64* __restrict__ ek) {
+    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
+        const i64 p = wv * WAVE + lane_id();
+        const bool act = p < nnz;
+        i64 r = -1, c = 0;
+        if (act) {
+            r = rrow[p];
+            const i32 rp = rpos[p];
+            if (rp >= 0) {
+                c = C3[roff[ridx[p]] + rp];
+                C3[p] = (i32)c;
+            } else {
+                c = C3[p];
+            }
+            if (ek) ek[p] = 0;
+        }
+        c = wave_seg_scan(c, r);
+        if (wave_seg_tail(r, act) && c) atomicAdd((unsigned long long*)&c3x2[r], (unsigned long long)c);
+    }
+}
+
+// The clique pass stores, for each N+ entry (u, v) of its wave and LDS tiers,
+// the 4-cliques and diamonds it attributes to v, packed as dv << EK_SHIFT | kv,
+// at the mirror (v, u).  This pass sums them by rows: one coalesced read per
+// entry instead of two device atomics per N+ entry.
+__global__ void __launch_bounds__(PT) k_sum_ek(const i32* __restrict__ rrow, const i64* __restrict__ ek, i64 nnz,
+                                               i64* __restrict__ k4v, i64* __restrict__ d13) {
+    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
+        const i64 p = wv * WAVE + lane_id();
+        const bool act = p < nnz;
+        i64 r = -1, a = 0, b = 0;
+        if (act) {
+            r = rrow[p];
+            const i64 x = ek[p];
+            a = x & (((i64)1 << EK_SHIFT) - 1);
+            b = x >> EK_SHIFT;
+        }
+        a = wave_seg_scan(a, r);
+        b = wave_seg_scan(b, r);
+        if (wave_seg_tail(r, act)) {
+            if (a) atomicAdd((unsigned long long*)&k4v[r], (unsigned long long)a);
+            if (b) atomicAdd((unsigned long long*)&d13[r], (unsigned long long)b);
+        }
     }
 }
 
@@ -101,7 +148,7 @@ template <int MODE>
 __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                  const i64* __restrict__ G, const i32* __restrict__ list, u32 count,
-                                                 i32* __restrict__ C3, i64* __restrict__ c3v, i64* __restrict__ k4v,
+                                                 i32* __restrict__ C3, i64* __restrict__ k4v,
                                                  i64* __restrict__ d13, DevPlan* plan) {
     constexpr int NW = PT / WAVE;
     __shared__ i32 sL[NW][WAVE];
@@ -161,16 +208,10 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
         __syncthreads();
         if (valid) {
             if (MODE == 1) {
-                i64 c = 0;
                 if (lane < D) {
-                    c = sCnt[wid][lane];
-                    if (c) {
-                        atomicAdd(&C3[bu + lane], (i32)c);
-                        atomicAdd((unsigned long long*)&c3v[sL[wid][lane]], (unsigned long long)c);
-                    }
+                    const i32 c = sCnt[wid][lane];
+                    if (c) atomicAdd(&C3[bu + lane], c);
                 }
-                c = wave_sum(c);
-                if (lane == 0 && c) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
             } else {
                 i64 R = 0, kv = 0, dv = 0;
                 if (lane < D) {
@@ -211,8 +252,7 @@ template <int MODE, bool GLOBAL>
 __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                   const i64* __restrict__ G, const i32* __restrict__ list,
-                                                  u32 count, i32* __restrict__ C3, i64* __restrict__ c3v,
-                                                  i64* __restrict__ k4v, i64* __restrict__ d13,
+                                                  u32 count, i32* __restrict__ C3, i64* __restrict__ k4v, i64* __restrict__ d13,
                                                   u64* __restrict__ slots, i64 slot_words, DevPlan* plan) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
@@ -308,17 +348,10 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         if (GLOBAL) fence_agent();
 
         if (MODE == 1) {
-            i64 c = 0;
             for (int k = threadIdx.x; k < D; k += blockDim.x) {
-                const i64 ck = GLOBAL ? (i64)load_relaxed(&Cnt[k]) : (i64)Cnt[k];
-                if (ck) {
-                    atomicAdd(&C3[bu + k], (i32)ck);
-                    atomicAdd((unsigned long long*)&c3v[L[k]], (unsigned long long)ck);
-                }
-                c += ck;
+                const i32 ck = GLOBAL ? load_relaxed(&Cnt[k]) : Cnt[k];
+                if (ck) atomicAdd(&C3[bu + k], ck);
             }
-            c = wave_sum(c);
-            if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&red[0], (unsigned long long)c);
         } else {
             i64 Rsum = 0;
             for (int k = threadIdx.x; k < D; k += blockDim.x) {
@@ -355,13 +388,9 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (MODE == 1) {
-                if (red[0]) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red[0] / 2));
-            } else {
-                if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
-                if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
-            }
+        if (MODE == 2 && threadIdx.x == 0) {
+            if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
+            if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
         }
         if (GLOBAL) fence_agent();
         __syncthreads();
@@ -371,14 +400,14 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
 // ------------------------------------------------------------ finalize / net
 
 __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
-                           const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3v,
+                           const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3x2,
                            const i64* __restrict__ ap2, const i64* __restrict__ ac3, const i64* __restrict__ d10,
                            const i64* __restrict__ d14, const i64* __restrict__ d13, const i64* __restrict__ c4v,
                            const i64* __restrict__ k4v, i64* __restrict__ out, int net) {
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
         const i64 d = rdeg[r];
         const i64 p2 = sumd[r] - d;
-        const i64 c3 = c3v[r];
+        const i64 c3 = c3x2[r] >> 1;
         i64 f[16];
         f[0] = 1;
         f[1] = d;
@@ -440,19 +469,19 @@ hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, w.C3, w.sumd,
-                       w.c3v, nnz, w.ap2, w.ac3, w.d10, w.d14);
+                       w.c3x2, nnz, w.ap2, w.ac3, w.d10, w.d14);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s) {
+hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rpos, nnz, w.C3);
+    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rpos, w.rrow,
+                       nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
                       SegTimer& tm) {
-    (void)nnz;
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
@@ -466,7 +495,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
         if ((e = launch_tri1_stored(n, w, hp, stored, s, 1)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<1, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
+                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
     } else {
         // clique and diamond pass: from the stored bitmaps, or by scanning again
@@ -475,30 +504,34 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
             if ((e = launch_tri2_stored(n, w, hp, s, 0)) != hipSuccess) return e;
         } else if (c0) {
             hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                               w.rdeg, w.G, l0, c0, w.C3, w.c3v, w.k4v, w.d13, w.plan);
+                               w.rdeg, w.G, l0, c0, w.C3, w.k4v, w.d13, w.plan);
         }
         tm.mark(FGLT_SEG_TRI2_LDS, s);
         if (stored) {
             if ((e = launch_tri2_stored(n, w, hp, s, 1)) != hipSuccess) return e;
         } else if (c1) {
             hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
-                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
+                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.k4v, w.d13, w.tri_slots,
                                w.tri_slot_words, w.plan);
         }
         tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.c3v, w.k4v, w.d13, w.tri_slots,
+                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
+        tm.mark(FGLT_SEG_TRI2_SUM, s);
+        if (stored && nnz > 0)
+            hipLaunchKernelGGL(k_sum_ek, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ek, nnz, w.k4v,
+                               w.d13);
     }
     return hipGetLastError();
 }
 
-// Triangles of the graph, sum over vertices of c3 / 3, into plan->triangles
-// (statistics only: one atomic per workgroup).
-__global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __restrict__ c3v, DevPlan* plan) {
+// Six times the triangles of the graph (the sum over vertices of 2 c3) into
+// plan->triangles (statistics only: one atomic per workgroup).
+__global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __restrict__ c3x2, DevPlan* plan) {
     __shared__ i64 part[PT / WAVE];
     i64 sum = 0;
-    for (i64 r = (i64)blockIdx.x * PT + threadIdx.x; r < n; r += (i64)gridDim.x * PT) sum += c3v[r];
+    for (i64 r = (i64)blockIdx.x * PT + threadIdx.x; r < n; r += (i64)gridDim.x * PT) sum += c3x2[r];
     sum = wave_sum(sum);
     if (lane_id() == 0) part[threadIdx.x / WAVE] = sum;
     __syncthreads();
@@ -512,12 +545,12 @@ __global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __rest
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
     const hipError_t e = hipMemsetAsync(&w.plan->triangles, 0, sizeof(i64), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_count_triangles, dim3(grid_for(n, PT, 256)), dim3(PT), 0, s, n, w.c3v, w.plan);
+    hipLaunchKernelGGL(k_count_triangles, dim3(grid_for(n, PT, 256)), dim3(PT), 0, s, n, w.c3x2, w.plan);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7, w.c3v,
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7, w.c3x2,
                        w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0);
     return hipGetLastError();
 }

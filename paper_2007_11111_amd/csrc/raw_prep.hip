@@ -227,7 +227,10 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
 // rpos / work count per entry; duplicate and symmetry checks.
 //   N- entry (u, v), v < u: rpos = position of u in row v (= number of
 //     neighbours of v below u, the wedge count of the 4-cycle pass);
-//   N+ entry (u, v), v > u: rpos = -1, work = d+(v) (the triangle pass).
+//   N+ entry (v, u), u > v: rpos = ~(position of v in row u), written by the
+//     thread of its mirror (u, v); work = d+(u) (the triangle pass).
+//   A diagonal entry gets rpos = -1 (the input check rejects it).
+//   rpos >= 0 marks the N- entries; ~rpos of an N+ entry locates its mirror.
 __global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
                        const i32* __restrict__ lo, const i32* __restrict__ rdeg, i64 nnz, i32* __restrict__ rpos,
                        i64* __restrict__ G, DevPlan* plan) {
@@ -237,23 +240,24 @@ __global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ rid
             const i64 u = rrow[p];
             const i32 v = ridx[p];
             if (p > roff[u] && ridx[p - 1] == v) err |= ERR_DUP;
-            i32 rp = -1;
             i64 work = 0;
             if ((i64)v < u) {
                 const i64 b = roff[v] + lo[v], e = roff[v + 1];
                 const i64 q = lower_bound_dev(ridx, b, e, (i32)u);
+                i32 rp = 0;  // on an asymmetric input: harmless, no wedges (the run stops there)
                 if (q < e && ridx[q] == (i32)u) {
                     rp = (i32)(q - roff[v]);
-                    work = rp;
+                    rpos[q] = ~(i32)(p - roff[u]);  // the mirror (v, u) learns where (u, v) sits
                 } else {
                     err |= ERR_ASYM;
-                    rp = 0;  // harmless: no wedges, no C3 read
-                    work = 0;
                 }
+                rpos[p] = rp;
+                work = rp;
             } else if ((i64)v > u) {
-                work = rdeg[v] - lo[v];
+                work = rdeg[v] - lo[v];  // rpos[p] comes from the mirror's thread
+            } else {
+                rpos[p] = -1;
             }
-            rpos[p] = rp;
             G[p] = work;
         }
     }
@@ -412,7 +416,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     if (w.acc) {
         w.sumd = w.acc + 0 * nn;
         w.s7 = w.acc + 1 * nn;
-        w.c3v = w.acc + 2 * nn;
+        w.c3x2 = w.acc + 2 * nn;
         w.ap2 = w.acc + 3 * nn;
         w.ac3 = w.acc + 4 * nn;
         w.d10 = w.acc + 5 * nn;
@@ -450,7 +454,8 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.c4_scr_cap = std::max<i64>(std::min<i64>((i64)1 << 20, nnz / 16), 1024);
     w.c4_scr = c.take<u32>(C4W_GRID * w.c4_scr_cap);
     w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
-    w.sort.tmp = c.take<i32>(std::max(nnz, nn));
+    w.ek = c.take<i64>(std::max(nnz, nn));
+    w.sort.tmp = reinterpret_cast<i32*>(w.ek);  // dead once the relabelled rows are built
     w.sort.lists = c.take<i32>(3 * (nn + 2));
     w.sort.counters = c.take<u32>(4);
     return w;

@@ -5,16 +5,17 @@
 //   the out-lists N+(v) of every v in N+(u) are walked as one flattened item
 //   stream (coalesced, 64 consecutive items per wavefront step); each item y
 //   is looked up in an LDS position map of N+(u).  A hit at position l is a
-//   triangle (u, v_k, v_l): C3 of the edges (u, v_k), (u, v_l) is counted in
-//   LDS, C3 of (v_k, v_l) by one global atomic, and bit l of row k of the
-//   bitmap B (the induced subgraph on N+(u)) is set.  B is stored for the
-//   clique pass when the workspace holds it.
+//   triangle (u, v_k, v_l): bit l of row k of the bitmap B (the induced
+//   subgraph on N+(u)) is set, and C3 of (v_k, v_l) counted by one global
+//   atomic; C3 of the edges (u, v_k) follows from B's rows and columns.  B is
+//   stored for the clique pass when the workspace holds it.
 // Clique / diamond pass from stored bitmaps: B is reloaded, its transpose C
 //   built in LDS, and every 4-clique {u < a < b < c} and every off-cord
 //   diamond of a triangle with lowest vertex u is attributed to its vertices
 //   (Section IV-C: T e / 6 and D4,c e / 2 without forming T or D4,c).  The
 //   diamond term of u needs C3 of the edge (v_k, v_l), found by a binary
-//   search of v_l in N+(v_k).
+//   search of v_l in N+(v_k).  The counts of the N+ vertices are stored at the
+//   mirrored entries and summed by rows afterwards (no per-entry atomics).
 #include <algorithm>
 
 #include "walk.h"
@@ -53,10 +54,9 @@ __device__ __forceinline__ void flush_c3(const u32* q, u32 nq, i32* __restrict__
 __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i64* __restrict__ G,
                                                   const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
-                                                  i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
-                                                  const i64* __restrict__ boff, int store, int defer) {
+                                                  u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
+                                                  int defer) {
     constexpr int NW = WT / WAVE;
-    __shared__ i32 sL[NW][WAVE];
     __shared__ i64 rbase[NW][WAVE + 1];
     __shared__ i32 rstart[NW][WAVE + 1];
     __shared__ i32 rk[NW][WAVE + 1];
@@ -85,7 +85,6 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
             i64 bv = 0;
             if (lane < D) {
                 const i32 v = ridx[bu + lane];
-                sL[wid][lane] = v;
                 bmap_insert(pm[wid], v, lane);
                 pre = (i32)(G[bu + lane] - gb);
                 len = (i32)(G[bu + lane + 1] - G[bu + lane]);
@@ -122,17 +121,11 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
             // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
             const u64 row = sB[wid][lane];
             const u64 col = wave_transpose64(row);
-            i64 c = 0;
             if (lane < D) {
-                c = __popcll(row) + __popcll(col);
-                if (c) {
-                    atomicAdd(&C3[bu + lane], (i32)c);
-                    atomicAdd((unsigned long long*)&c3v[sL[wid][lane]], (unsigned long long)c);
-                }
-                if (store) bstore[boff[u] + lane] = sB[wid][lane];
+                const i32 c = __popcll(row) + __popcll(col);
+                if (c) atomicAdd(&C3[bu + lane], c);
+                if (store) bstore[boff[u] + lane] = row;
             }
-            c = wave_sum(c);
-            if (lane == 0 && c) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(c / 2));
         }
         __syncthreads();
     }
@@ -141,12 +134,11 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
 __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
                                                  const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
-                                                 i64* __restrict__ c3v, DevPlan* plan, u64* __restrict__ bstore,
-                                                 const i64* __restrict__ boff, int store, int defer) {
+                                                 u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
+                                                 int defer) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     constexpr int NWV = LT / WAVE;
-    __shared__ i32 L[DM];
     __shared__ i64 rbase[DM + 1];
     __shared__ i32 rstart[DM + 1];
     __shared__ i32 rk[DM + 1];
@@ -156,7 +148,6 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
     __shared__ u64 B[DM * WM];
     __shared__ i32 wsum[NWV];
     __shared__ i32 stot, sR;
-    __shared__ i64 red;
     __shared__ u32 sQ[NWV][TRI_QCAP];  // deferred C3 increments per wavefront
     const int wv = threadIdx.x / WAVE;
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
@@ -169,14 +160,12 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         bmap_clear(pm, threadIdx.x, LT);
         for (int q = threadIdx.x; q < D * W; q += LT) B[q] = 0;
         if (threadIdx.x < D) Cnt[threadIdx.x] = 0;
-        if (threadIdx.x == 0) red = 0;
         __syncthreads();
         const int k = threadIdx.x;  // D <= DM == LT: one out-neighbour per thread
         i32 len = 0, pre = 0;
         i64 bv = 0;
         if (k < D) {
             const i32 v = ridx[bu + k];
-            L[k] = v;
             bmap_insert(pm, v, k);
             pre = (i32)(G[bu + k] - gb);
             len = (i32)(G[bu + k + 1] - G[bu + k]);
@@ -209,20 +198,12 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
                     });
         __syncthreads();
         flush_c3(sQ[wv], nq, C3, lane_id(), WAVE);
-        i64 c = 0;
         if (k < D) {
-            c = Cnt[k];
-            if (c) {
-                atomicAdd(&C3[bu + k], (i32)c);
-                atomicAdd((unsigned long long*)&c3v[L[k]], (unsigned long long)c);
-            }
+            const i32 c = Cnt[k];
+            if (c) atomicAdd(&C3[bu + k], c);
             if (store)
                 for (int z = 0; z < W; ++z) bstore[boff[u] + (i64)k * W + z] = B[k * W + z];
         }
-        c = wave_sum(c);
-        if (lane_id() == 0 && c) atomicAdd((unsigned long long*)&red, (unsigned long long)c);
-        __syncthreads();
-        if (threadIdx.x == 0 && red) atomicAdd((unsigned long long*)&c3v[u], (unsigned long long)(red / 2));
         __syncthreads();
     }
 }
@@ -249,10 +230,10 @@ __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i3
 
 __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                    const i32* __restrict__ lo, const i32* __restrict__ rdeg,
-                                                   const i32* __restrict__ list, u32 count,
-                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
-                                                   i64* __restrict__ d13, const u64* __restrict__ bstore,
-                                                   const i64* __restrict__ boff) {
+                                                   const i32* __restrict__ rpos, const i32* __restrict__ list,
+                                                   u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                   i64* __restrict__ d13, i64* __restrict__ ek,
+                                                   const u64* __restrict__ bstore, const i64* __restrict__ boff) {
     // Each wavefront works alone on its vertices: row k of B and of C = B^T in
     // lane k's registers, the rows l broadcast one after another (readlane), so
     // every lane runs the same D iterations with no LDS traffic and no
@@ -266,11 +247,12 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
         const i64 bu = roff[u] + lo[u];
         const int D = (int)(roff[u + 1] - bu);
         u64 Bk = 0;
-        i32 vk = 0, c3k = 0;
+        i32 vk = 0, c3k = 0, mk = 0;
         if (lane < D) {
             Bk = bstore[boff[u] + lane];
             vk = ridx[bu + lane];
             c3k = C3[bu + lane];
+            mk = ~rpos[bu + lane];  // position of u in row v_k
         }
         const u64 Ck = wave_transpose64(Bk);
         lds_put(&sL[wid][lane], vk);
@@ -293,12 +275,12 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
         i64 du = 0;
         if (lane < D) {
             // diamonds of u: C3(v_k, v_l) - 1 over the triangles (u, v_k, v_l)
-            i64 from = roff[vk] + lo[vk];
-            const i64 end = roff[vk] + rdeg[vk];
+            const i64 rv = roff[vk];
+            i64 from = rv + lo[vk];
+            const i64 end = rv + rdeg[vk];
             FOR_BITS(Bk, l, { du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l])); });
             const i64 kv = R + M + X;
-            if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
-            if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+            if (kv | dv) ek[rv + mk] = (dv << EK_SHIFT) | kv;
         }
         R = wave_sum(R);
         du = wave_sum(du);
@@ -311,10 +293,10 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
 }
 
 __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
+                                                  const i32* __restrict__ lo, const i32* __restrict__ rpos,
                                                   const i32* __restrict__ list, u32 count,
                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
-                                                  i64* __restrict__ d13, const u64* __restrict__ bstore,
+                                                  i64* __restrict__ ek, const u64* __restrict__ bstore,
                                                   const i64* __restrict__ boff) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
@@ -372,8 +354,7 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
                 });
             }
             const i64 kv = R + M + X;
-            if (kv) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)kv);
-            if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+            if (kv | dv) ek[roff[vk] + ~rpos[bu + k]] = (dv << EK_SHIFT) | kv;
         }
         R = wave_sum(R);
         if (lane_id() == 0 && R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
@@ -467,10 +448,10 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
     const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.G,
-                           w.tri_list, c0, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0, defer);
+                           w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
     if (tier == 1 && c1)
         hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
-                           w.tri_list + n, c1, w.C3, w.c3v, w.plan, w.bstore, w.boff, store ? 1 : 0, defer);
+                           w.tri_list + n, c1, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
     return hipGetLastError();
 }
 
@@ -478,10 +459,10 @@ hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s,
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
-                           w.tri_list, c0, w.C3, w.k4v, w.d13, w.bstore, w.boff);
+                           w.rpos, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
     if (tier == 1 && c1) {
-        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
-                           w.tri_list + n, c1, w.C3, w.k4v, w.d13, w.bstore, w.boff);
+        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rpos,
+                           w.tri_list + n, c1, w.C3, w.k4v, w.ek, w.bstore, w.boff);
         hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.d13);
     }
