@@ -182,4 +182,14 @@ struct SegSortWs {
 hipError_t seg_sort(i32* keys, const i64* seg_off, i64 nseg, int key_bits, SegSortWs ws,
                     i64 max_seg_grid, hipStream_t s);
 
+// Stable LSD radix sort of n pairs (in_k, in_v) by the low key_bits bits of
+// the keys (keys below 2^key_bits) into (out_k, out_v).  in_v == nullptr means
+// values 0 .. n-1; out_k == nullptr skips the sorted keys.  Passes alternate
+// through (ta_k, ta_v) and (tb_k, tb_v), n words each; tb may be the memory
+// of in_k / in_v (read only by the first pass), ta may not.  hist holds
+// radix_hist_size(n) words; partials as for scan_exclusive_i64 of that many.
+i64 radix_hist_size(i64 n);
+hipError_t radix_sort_pairs(i64 n, int key_bits, const u32* in_k, const i32* in_v, u32* out_k, i32* out_v,
+                            u32* ta_k, i32* ta_v, u32* tb_k, i32* tb_v, i64* hist, i64* partials, hipStream_t s);
+
 }  // namespace fglt

@@ -48,8 +48,7 @@ struct RawWs {
     i32* rank;    // [n] original id -> rank
     i32* rdeg;    // [n] degree by rank
     i32* lo;      // [n] |N-(u)|
-    i64* cntd;    // [n+2] degree histogram, then bucket starts
-    i32* cursor;  // [n+2]
+    i64* cntd;    // [n+2] scratch of the degree sort
     i64* roff;    // [n+1]
     i32* ridx;    // [nnz]
     i32* rrow;    // [nnz] row of each entry (rank space)
@@ -82,6 +81,7 @@ struct RawWs {
     // scratch
     i64* partials;
     SegSortWs sort;
+    i64* rx_hist;       // radix sort: digit counts per tile, then their offsets
     DevPlan* plan;
 };
 

@@ -63,66 +63,9 @@ hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, Ra
 
 // ------------------------------------------------------------ degree ranking
 
-static constexpr int PRIV = 1024;  // degrees below this use block-private counters
-
-__global__ void __launch_bounds__(PT) k_deg_hist(const i32* __restrict__ deg, i64 n, i64* __restrict__ cntd) {
-    __shared__ u32 lc[PRIV];
-    for (int t = threadIdx.x; t < PRIV; t += blockDim.x) lc[t] = 0;
-    __syncthreads();
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
-        const i32 d = deg[i];
-        if (d < PRIV) atomicAdd(&lc[d], 1u);
-        else atomicAdd((unsigned long long*)&cntd[d], 1ull);
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < PRIV; t += blockDim.x)
-        if (lc[t]) atomicAdd((unsigned long long*)&cntd[t], (unsigned long long)lc[t]);
-}
-
-// perm[bstart[d] + k] = vertex, k unique within bucket d (order fixed later by a sort)
-static constexpr int SCAT_ITEMS = 8;
-__global__ void __launch_bounds__(PT) k_deg_scatter(const i32* __restrict__ deg, i64 n,
-                                                    const i64* __restrict__ bstart, i32* __restrict__ cursor,
-                                                    i32* __restrict__ perm) {
-    __shared__ u32 lc[PRIV];
-    __shared__ u32 lbase[PRIV];
-    for (int t = threadIdx.x; t < PRIV; t += blockDim.x) lc[t] = 0;
-    __syncthreads();
-    const i64 base = (i64)blockIdx.x * PT * SCAT_ITEMS;
-    u32 li[SCAT_ITEMS];
-#pragma unroll
-    for (int k = 0; k < SCAT_ITEMS; ++k) {
-        const i64 i = base + (i64)k * PT + threadIdx.x;
-        li[k] = 0;
-        if (i < n) {
-            const i32 d = deg[i];
-            if (d < PRIV) li[k] = atomicAdd(&lc[d], 1u);
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < PRIV; t += blockDim.x)
-        if (lc[t]) lbase[t] = (u32)atomicAdd(&cursor[t], (i32)lc[t]);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SCAT_ITEMS; ++k) {
-        const i64 i = base + (i64)k * PT + threadIdx.x;
-        if (i < n) {
-            const i32 d = deg[i];
-            i64 pos;
-            if (d < PRIV) pos = bstart[d] + lbase[d] + li[k];
-            else pos = bstart[d] + atomicAdd(&cursor[d], 1);
-            perm[pos] = (i32)i;
-        }
-    }
-}
-
-__global__ void k_rank(const i32* __restrict__ perm, const i32* __restrict__ deg, i64 n, i32* __restrict__ rank,
-                       i32* __restrict__ rdeg) {
-    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
-        const i32 i = perm[r];
-        rank[i] = (i32)r;
-        rdeg[r] = deg[i];
-    }
+__global__ void k_rank(const i32* __restrict__ perm, i64 n, i32* __restrict__ rank) {
+    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x)
+        rank[perm[r]] = (i32)r;
 }
 
 // rrow[p] = r for every entry p of row r.  A wavefront takes 4096
@@ -166,40 +109,49 @@ __global__ void __launch_bounds__(PT) k_rowfill(const i64* __restrict__ roff, i6
     }
 }
 
-// ridx[q] = rank[idx[off[perm[r]] + (q - roff[r])]] for q in row r of rank space.
+// key[q] = rank[idx[off[perm[r]] + (q - roff[r])]] for q in row r of rank
+// space: the rows of rank space, each in the caller's column order.
 __global__ void __launch_bounds__(PT) k_relabel_copy(const i64* __restrict__ off, const i32* __restrict__ idx,
                                                      const i32* __restrict__ perm, const i32* __restrict__ rank,
                                                      const i64* __restrict__ roff, const i32* __restrict__ rrow,
-                                                     i64 nnz, i32* __restrict__ ridx) {
+                                                     i64 nnz, u32* __restrict__ key) {
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (i64)gridDim.x * blockDim.x) {
         const i64 r = rrow[q];
         const i64 src = off[perm[r]] + (q - roff[r]);
-        ridx[q] = rank[idx[src]];
+        key[q] = (u32)rank[idx[src]];
     }
 }
 
+// Ranks: vertices by (degree, id), a stable radix sort of the pairs
+// (degree, id) by degree, which also yields the degrees in rank order.
+// Rows: the entries of rank space (r, t) taken row by row are pairs (t, r);
+// a stable radix sort by t gathers row t with its columns r in ascending
+// order, and the row ids of the sorted pairs are rrow itself.
 hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
                                    hipStream_t s) {
     hipError_t e;
-    const i64 nb = d_max + 1;  // degree buckets 0..d_max
-    if ((e = hipMemsetAsync(w.cntd, 0, sizeof(i64) * (size_t)(nb + 1), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(w.cursor, 0, sizeof(i32) * (size_t)(nb + 1), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_deg_hist, dim3(grid_for(n, PT, 2048)), dim3(PT), 0, s, w.deg, n, w.cntd);
-    if ((e = scan_exclusive_i64(w.cntd, w.cntd, nb, w.partials, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_deg_scatter, dim3(grid_for(n, PT * SCAT_ITEMS, 1 << 30)), dim3(PT), 0, s, w.deg, n,
-                       w.cntd, w.cursor, w.perm);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // deterministic order inside each degree bucket: ascending original id
-    if ((e = seg_sort(w.perm, w.cntd, nb, bits_for(n - 1), w.sort, 65536, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.perm, w.deg, n, w.rank, w.rdeg);
+    const i64 nn = std::max<i64>(n, 1);
+    // pass buffers: ek holds 2 max(nnz, n) and cntd 2 (n + 2) 32-bit words, G 2 (nnz + 1)
+    u32* ek_k = reinterpret_cast<u32*>(w.ek);
+    if ((e = radix_sort_pairs(n, bits_for(d_max), reinterpret_cast<const u32*>(w.deg), nullptr,
+                              reinterpret_cast<u32*>(w.rdeg), w.perm, ek_k, reinterpret_cast<i32*>(ek_k + nn),
+                              reinterpret_cast<u32*>(w.cntd), reinterpret_cast<i32*>(w.cntd) + nn, w.rx_hist,
+                              w.partials, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, w.perm, n, w.rank);
     if ((e = scan_exclusive_i32_to_i64(w.rdeg, w.roff, n, w.partials, s)) != hipSuccess) return e;
     if (nnz > 0) {
         hipLaunchKernelGGL(k_rowfill, dim3(grid_for(nnz, PT / WAVE * RF_CHUNK, 65536)), dim3(PT), 0, s, w.roff, n,
                            nnz, w.rrow);
+        u32* g_k = reinterpret_cast<u32*>(w.G);
         hipLaunchKernelGGL(k_relabel_copy, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, off, idx, w.perm, w.rank,
-                           w.roff, w.rrow, nnz, w.ridx);
+                           w.roff, w.rrow, nnz, g_k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = seg_sort(w.ridx, w.roff, n, bits_for(n - 1), w.sort, 65536, s)) != hipSuccess) return e;
+        // pass 1 reads (G, rrow); later passes alternate between ek and G
+        if ((e = radix_sort_pairs(nnz, bits_for(n - 1), g_k, w.rrow, nullptr, w.ridx, ek_k,
+                                  reinterpret_cast<i32*>(ek_k + nnz), g_k, reinterpret_cast<i32*>(g_k + nnz),
+                                  w.rx_hist, w.partials, s)) != hipSuccess)
+            return e;
     }
     return hipGetLastError();
 }
@@ -405,7 +357,6 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.rdeg = c.take<i32>(nn);
     w.lo = c.take<i32>(nn);
     w.cntd = c.take<i64>(nn + 2);
-    w.cursor = c.take<i32>(nn + 2);
     w.roff = c.take<i64>(nn + 1);
     w.ridx = c.take<i32>(nnz);
     w.rpos = c.take<i32>(nnz);
@@ -458,6 +409,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.sort.tmp = reinterpret_cast<i32*>(w.ek);  // dead once the relabelled rows are built
     w.sort.lists = c.take<i32>(3 * (nn + 2));
     w.sort.counters = c.take<u32>(4);
+    w.rx_hist = c.take<i64>(radix_hist_size(std::max(nnz, nn)));
     return w;
 }
 
