@@ -292,19 +292,30 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
     }
 }
 
+// LDS tier: edge-parallel over the induced subgraph H on N+(u).  With A =
+// B | B^T (full adjacency rows of H), an edge (k, l) of H lies on
+// c = |A_k & A_l| triangles of H, each a 4-clique with u; the triangles of H
+// through k are half the sum of c over its edges, and its 4-clique count of u
+// is the sum over edges divided by three.  Threads take the 64-bit words of
+// B (each at most 64 edges), so the work does not pile up on the rows of
+// popular vertices; per-vertex sums gather in LDS.  The diamond term of u
+// comes from k_tri2_du_lds (a search per edge here costs more than walking
+// the out-lists again).
 __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i32* __restrict__ rpos,
                                                   const i32* __restrict__ list, u32 count,
                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
-                                                  i64* __restrict__ ek, const u64* __restrict__ bstore,
-                                                  const i64* __restrict__ boff) {
+                                                  i64* __restrict__ ek,
+                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     __shared__ u64 B[DM * WM];
-    __shared__ u64 C[DM * WM];
+    __shared__ u64 A[DM * WM];
     __shared__ i32 L[DM];
     __shared__ i32 c3u[DM];
-    __shared__ i64 red[2];
+    __shared__ u32 t2[DM];   // twice the triangles of H through k: below 2 * 511 * 510
+    __shared__ u32 dvs[DM];  // diamonds of v_k: below 511 * 2^21
+    __shared__ i64 red[1];
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
         const i64 u = list[it];
         const i64 bu = roff[u] + lo[u];
@@ -315,51 +326,55 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
         if (threadIdx.x < D) {
             L[threadIdx.x] = ridx[bu + threadIdx.x];
             c3u[threadIdx.x] = C3[bu + threadIdx.x];
+            t2[threadIdx.x] = 0;
+            dvs[threadIdx.x] = 0;
         }
-        if (threadIdx.x < 2) red[threadIdx.x] = 0;
+        if (threadIdx.x == 0) red[0] = 0;
         __syncthreads();
-        // C = transpose of B, 64 x 64 blocks: wavefront wv takes the blocks
-        // (bi, bj) with bi * W + bj = wv (mod LT / 64); lane = row in the block
+        // A = B | B^T, 64 x 64 blocks: wavefront wv takes the blocks (bi, bj)
+        // with bi * W + bj = wv (mod LT / 64); lane = row in the block
         for (int blk = threadIdx.x / WAVE; blk < W * W; blk += LT / WAVE) {
             const int bi = blk / W, bj = blk % W;
             const int row = bi * 64 + lane_id();
             const u64 m = row < D ? B[row * W + bj] : 0ull;
             const u64 t = wave_transpose64(m);  // column bj * 64 + lane of the block
             const int col = bj * 64 + lane_id();
-            if (col < D) C[col * W + bi] = t;
+            if (col < D) A[col * W + bi] = t | B[col * W + bi];
         }
         __syncthreads();
-        const int k = threadIdx.x;
-        i64 R = 0;  // the diamond term of u comes from k_tri2_du_lds
-        if (k < D) {
-            const u64* Bk = B + k * W;
-            const u64* Ck = C + k * W;
-            const i32 vk = L[k];
-            i64 M = 0, X = 0, dv = 0;
-            for (int wa = 0; wa < W; ++wa) {
-                FOR_BITS(Bk[wa], bb, {
-                    const int l = wa * 64 + bb;
-                    const u64* Bl = B + l * W;
-                    for (int z = 0; z < W; ++z) R += __popcll(Bk[z] & Bl[z]);
-                    dv += c3u[l] - 1;
-                });
-                FOR_BITS(Ck[wa], bb, {
-                    const int j = wa * 64 + bb;
-                    const u64* Bj = B + j * W;
-                    for (int z = 0; z < W; ++z) {
-                        M += __popcll(Bj[z] & Bk[z]);
-                        X += __popcll(Bj[z] & Ck[z]);
-                    }
-                    dv += c3u[j] - 1;
-                });
-            }
-            const i64 kv = R + M + X;
-            if (kv | dv) ek[roff[vk] + ~rpos[bu + k]] = (dv << EK_SHIFT) | kv;
+        i64 R = 0;
+        for (int i = threadIdx.x; i < D * W; i += LT) {
+            const int k = i / W, wa = i - k * W;
+            u64 bits = B[i];
+            if (!bits) continue;
+            u64 Ak[WM];
+#pragma unroll
+            for (int z = 0; z < WM; ++z) Ak[z] = z < W ? A[k * W + z] : 0ull;
+            const u32 ck = (u32)(c3u[k] - 1);
+            u32 tk = 0, dk = 0;
+            FOR_BITS(bits, bb, {
+                const int l = wa * 64 + bb;
+                const u64* Al = A + l * W;
+                u32 c = 0;
+                for (int z = 0; z < W; ++z) c += (u32)__popcll(Ak[z] & Al[z]);
+                tk += c;
+                dk += (u32)(c3u[l] - 1);
+                if (c) atomicAdd(&t2[l], c);
+                if (ck) atomicAdd(&dvs[l], ck);
+                R += c;
+            });
+            if (tk) atomicAdd(&t2[k], tk);
+            if (dk) atomicAdd(&dvs[k], dk);
         }
         R = wave_sum(R);
         if (lane_id() == 0 && R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
         __syncthreads();
-        if (threadIdx.x == 0 && red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
+        const int k = threadIdx.x;
+        if (k < D) {
+            const i64 kv = t2[k] >> 1, dv = dvs[k];
+            if (kv | dv) ek[roff[L[k]] + ~rpos[bu + k]] = (dv << EK_SHIFT) | kv;
+        }
+        if (threadIdx.x == 0 && red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(red[0] / 3));
         __syncthreads();
     }
 }
