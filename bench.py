@@ -38,14 +38,13 @@ HBM_PEAK_GBPS = 8000.0
 # notes in the sources): unit, bytes per unit.
 SEG_UNITS = {
     "l1": ("entry", 8),          # index + gathered degree per directed entry
-    "l2": ("entry", 28),         # index, C3, degree, p2 and c3 of the neighbour
+    "l2": ("entry", 36),         # row, index, C3, degree, p2 and c3 of the neighbour, clique counts
     "tri1_wave": ("item", 4),    # one out-list index per merge item
     "tri1_lds": ("item", 4),
     "tri1_global": ("item", 4),
     "tri2_wave": ("item", 8),    # out-list index + its C3 per merge item
     "tri2_lds": ("item", 8),
     "tri2_global": ("item", 8),
-    "tri2_sum": ("entry", 12),   # row id + packed clique/diamond counts per entry
     "c4_wave": ("wedge", 8),     # wedge end read in the count and attribution passes
     "c4_block": ("wedge", 8),
     "c4_hash": ("wedge", 8),

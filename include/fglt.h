@@ -66,11 +66,11 @@ enum {
     FGLT_SEG_TRI1_LDS,       /* triangle pass, workgroup/LDS tier                 */
     FGLT_SEG_TRI1_GLOBAL,    /* triangle pass, workgroup/global-bitmap tier       */
     FGLT_SEG_FILL,           /* C3 mirrored to the lower entries, c3 by row sums  */
-    FGLT_SEG_L2,             /* row pass 2: A p2, A c3, C3 (p1-2), C(C3, 2)       */
     FGLT_SEG_TRI2_WAVE,      /* clique/diamond pass, wavefront tier               */
     FGLT_SEG_TRI2_LDS,       /* clique/diamond pass, LDS-bitmap tier              */
     FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
-    FGLT_SEG_TRI2_SUM,       /* clique/diamond counts stored per entry, row sums  */
+    FGLT_SEG_L2,             /* row pass 2: A p2, A c3, C3 (p1-2), C(C3, 2), and the
+                                clique/diamond counts stored per entry            */
     FGLT_SEG_C4_WAVE,        /* 4-cycle pass, wavefront tier                      */
     FGLT_SEG_C4_BLOCK,       /* 4-cycle pass, workgroup tier                      */
     FGLT_SEG_C4_HASH,        /* 4-cycle pass, packed-hash workgroup tier, then the

@@ -92,9 +92,9 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
     tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
-    tm.mark(FGLT_SEG_L2, s);
-    FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
+    tm.mark(FGLT_SEG_L2, s);
+    FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
     FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));

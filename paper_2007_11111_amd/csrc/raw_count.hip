@@ -4,11 +4,11 @@
 //   TRI mode 1:     oriented triangle listing per vertex u over N+(u); C3 on
 //                   every oriented edge (C3 = A .* A^2, Lemma 2)
 //   FILL:           C3 copied to the mirrored entries; row sums 2 c3 = C3 e
-//   L2  row pass:   A p2, A c3, C3 (p1 - 2), sum_j C(C3(i,j), 2)   (Table I rows 5, 9, 10, 14)
 //   TRI mode 2:     the induced subgraph on N+(u) as LDS bitmaps; per vertex
 //                   4-cliques (T e / 6, Section IV-C) and off-cord diamonds
-//                   (D4,c e / 2) attributed to all four / three vertices; the
-//                   per-entry shares stored at mirrored entries summed by rows
+//                   (D4,c e / 2) attributed to all four / three vertices
+//   L2  row pass:   A p2, A c3, C3 (p1 - 2), sum_j C(C3(i,j), 2)   (Table I rows 5, 9, 10, 14),
+//                   and the clique pass's per-entry shares stored at mirrored entries
 //   C4:             (c4.hip) rank-ordered wedges u - v - w with v, w < u;
 //                   4-cycles (C4,2 e / 2, Lemma 5) attributed to u, w and the middles
 //   FINALIZE:       Table I assembled per vertex, Table II back-substitution,
@@ -29,61 +29,99 @@ __device__ __forceinline__ i32 load_relaxed(const i32* p) {
 }
 
 // ------------------------------------------------------------ row passes
+//
+// Entry-parallel passes that sum per-entry terms into their rows.  A
+// wavefront takes RP_CH chunks of 64 consecutive entries, issues all their
+// loads first, then sums each chunk's runs of equal rows (wave_runs /
+// run_total) and adds the totals with one atomic per run and quantity.
+
+static constexpr int RP_CH = 4;
+
+template <class F>
+__device__ __forceinline__ void row_chunks(i64 nnz, F&& f) {
+    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
+    const int l = lane_id();
+    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE * RP_CH < nnz; wv += nw) {
+        i64 p[RP_CH];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) p[c] = wv * WAVE * RP_CH + c * WAVE + l;
+        f(p);
+    }
+}
+
+__device__ __forceinline__ void add_run(i64* acc, i32 r, i64 v, const WaveRuns& w) {
+    const i64 t = run_total(v, w);
+    if (w.tail && t) atomicAdd((unsigned long long*)&acc[r], (unsigned long long)t);
+}
 
 __global__ void __launch_bounds__(PT) k_l1(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
                                            const i32* __restrict__ rdeg, i64 nnz, i64* __restrict__ sumd,
                                            i64* __restrict__ s7) {
-    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p = wv * WAVE + lane_id();
-        const bool act = p < nnz;
-        i64 r = -1, a = 0, b = 0;
-        if (act) {
-            r = rrow[p];
-            const i64 dj = rdeg[ridx[p]];
-            a = dj;
-            b = (dj - 1) * (dj - 2) / 2;
+    row_chunks(nnz, [&](const i64* p) {
+        i32 r[RP_CH], j[RP_CH], dj[RP_CH];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
+            r[c] = rrow[q];
+            j[c] = ridx[q];
         }
-        a = wave_seg_scan(a, r);
-        b = wave_seg_scan(b, r);
-        if (wave_seg_tail(r, act)) {
-            atomicAdd((unsigned long long*)&sumd[r], (unsigned long long)a);
-            if (b) atomicAdd((unsigned long long*)&s7[r], (unsigned long long)b);
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) dj[c] = rdeg[j[c]];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const bool act = p[c] < nnz;
+            const WaveRuns w = wave_runs(r[c], act);
+            const i64 d = act ? dj[c] : 0;
+            add_run(sumd, r[c], d, w);                          // A p1
+            add_run(s7, r[c], act ? (d - 1) * (d - 2) / 2 : 0, w);  // sum_j C(d_j - 1, 2)
         }
-    }
+    });
 }
 
+// After the clique pass: A p2, A c3, C3 (p1 - 2) and C(C3, 2) by rows
+// (Table I rows 5, 9, 10, 14), and, when the clique pass stored per-entry
+// counts (ek != nullptr), their row sums: it stores, for each N+ entry
+// (u, v) of its wave and LDS tiers, the 4-cliques and diamonds it attributes
+// to v, packed as dv << EK_SHIFT | kv, at the mirror (v, u).
 __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
                                            const i32* __restrict__ rdeg, const i32* __restrict__ C3,
                                            const i64* __restrict__ sumd, const i64* __restrict__ c3x2,
-                                           i64 nnz, i64* __restrict__ ap2, i64* __restrict__ ac3,
-                                           i64* __restrict__ d10, i64* __restrict__ d14) {
-    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p = wv * WAVE + lane_id();
-        const bool act = p < nnz;
-        i64 r = -1, a = 0, b = 0, c = 0, d = 0;
-        if (act) {
-            r = rrow[p];
-            const i32 j = ridx[p];
-            const i64 dj = rdeg[j];
-            const i64 t = C3[p];
-            a = sumd[j] - dj;          // p2(j)
-            b = c3x2[j] >> 1;          // c3(j)
-            c = t * (dj - 2);          // C3(i,j) (p1(j) - 2); t == 0 when dj == 1
-            d = t * (t - 1) / 2;       // C(C3(i,j), 2)
+                                           const i64* __restrict__ ek, i64 nnz, i64* __restrict__ ap2,
+                                           i64* __restrict__ ac3, i64* __restrict__ d10, i64* __restrict__ d14,
+                                           i64* __restrict__ k4v, i64* __restrict__ d13) {
+    row_chunks(nnz, [&](const i64* p) {
+        i32 r[RP_CH], j[RP_CH], t[RP_CH], dj[RP_CH];
+        i64 sj[RP_CH], cj[RP_CH], x[RP_CH];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
+            r[c] = rrow[q];
+            j[c] = ridx[q];
+            t[c] = C3[q];
+            x[c] = ek ? ek[q] : 0;
         }
-        a = wave_seg_scan(a, r);
-        b = wave_seg_scan(b, r);
-        c = wave_seg_scan(c, r);
-        d = wave_seg_scan(d, r);
-        if (wave_seg_tail(r, act)) {
-            if (a) atomicAdd((unsigned long long*)&ap2[r], (unsigned long long)a);
-            if (b) atomicAdd((unsigned long long*)&ac3[r], (unsigned long long)b);
-            if (c) atomicAdd((unsigned long long*)&d10[r], (unsigned long long)c);
-            if (d) atomicAdd((unsigned long long*)&d14[r], (unsigned long long)d);
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            dj[c] = rdeg[j[c]];
+            sj[c] = sumd[j[c]];
+            cj[c] = c3x2[j[c]];
         }
-    }
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const bool act = p[c] < nnz;
+            const WaveRuns w = wave_runs(r[c], act);
+            const i64 d = dj[c], tt = act ? t[c] : 0;
+            add_run(ap2, r[c], act ? sj[c] - d : 0, w);       // p2(j)
+            add_run(ac3, r[c], act ? cj[c] >> 1 : 0, w);      // c3(j)
+            add_run(d10, r[c], tt * (d - 2), w);              // C3(i,j) (p1(j) - 2); C3 = 0 when d_j = 1
+            add_run(d14, r[c], tt * (tt - 1) / 2, w);         // C(C3(i,j), 2)
+            if (ek) {
+                const i64 xx = act ? x[c] : 0;
+                add_run(k4v, r[c], xx & (((i64)1 << EK_SHIFT) - 1), w);
+                add_run(d13, r[c], xx >> EK_SHIFT, w);
+            }
+        }
+    });
 }
 
 // C3 of each N- entry copied from its mirror, and the row sums C3 e = 2 c3
@@ -93,51 +131,31 @@ __global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ roff, co
                                                 const i32* __restrict__ rpos, const i32* __restrict__ rrow,
                                                 i64 nnz, i32* __restrict__ C3, i64* __restrict__ c3x2,
                                                 i64* __restrict__ ek) {
-    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p = wv * WAVE + lane_id();
-        const bool act = p < nnz;
-        i64 r = -1, c = 0;
-        if (act) {
-            r = rrow[p];
-            const i32 rp = rpos[p];
-            if (rp >= 0) {
-                c = C3[roff[ridx[p]] + rp];
-                C3[p] = (i32)c;
-            } else {
-                c = C3[p];
-            }
-            if (ek) ek[p] = 0;
+    row_chunks(nnz, [&](const i64* p) {
+        i32 r[RP_CH], rp[RP_CH], j[RP_CH], cv[RP_CH];
+        i64 rj[RP_CH];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
+            r[c] = rrow[q];
+            rp[c] = rpos[q];
+            j[c] = ridx[q];
         }
-        c = wave_seg_scan(c, r);
-        if (wave_seg_tail(r, act) && c) atomicAdd((unsigned long long*)&c3x2[r], (unsigned long long)c);
-    }
-}
-
-// The clique pass stores, for each N+ entry (u, v) of its wave and LDS tiers,
-// the 4-cliques and diamonds it attributes to v, packed as dv << EK_SHIFT | kv,
-// at the mirror (v, u).  This pass sums them by rows: one coalesced read per
-// entry instead of two device atomics per N+ entry.
-__global__ void __launch_bounds__(PT) k_sum_ek(const i32* __restrict__ rrow, const i64* __restrict__ ek, i64 nnz,
-                                               i64* __restrict__ k4v, i64* __restrict__ d13) {
-    const i64 nw = ((i64)gridDim.x * blockDim.x) / WAVE;
-    for (i64 wv = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE; wv * WAVE < nnz; wv += nw) {
-        const i64 p = wv * WAVE + lane_id();
-        const bool act = p < nnz;
-        i64 r = -1, a = 0, b = 0;
-        if (act) {
-            r = rrow[p];
-            const i64 x = ek[p];
-            a = x & (((i64)1 << EK_SHIFT) - 1);
-            b = x >> EK_SHIFT;
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) rj[c] = roff[j[c]];
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
+            cv[c] = C3[rp[c] >= 0 ? rj[c] + rp[c] : q];  // an N+ entry keeps its own count
         }
-        a = wave_seg_scan(a, r);
-        b = wave_seg_scan(b, r);
-        if (wave_seg_tail(r, act)) {
-            if (a) atomicAdd((unsigned long long*)&k4v[r], (unsigned long long)a);
-            if (b) atomicAdd((unsigned long long*)&d13[r], (unsigned long long)b);
+#pragma unroll
+        for (int c = 0; c < RP_CH; ++c) {
+            const bool act = p[c] < nnz;
+            if (act && rp[c] >= 0) C3[p[c]] = cv[c];
+            if (act && ek) ek[p[c]] = 0;
+            add_run(c3x2, r[c], act ? cv[c] : 0, wave_runs(r[c], act));
         }
-    }
+    });
 }
 
 // ------------------------------------------------------------ triangle / clique passes
@@ -461,27 +479,28 @@ __global__ void k_net(i64 n, const i64* __restrict__ raw, i64* __restrict__ net)
 
 hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l1, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, nnz, w.sumd,
-                       w.s7);
+    hipLaunchKernelGGL(k_l1, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, nnz,
+                       w.sumd, w.s7);
     return hipGetLastError();
 }
 
-hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
+hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, w.C3, w.sumd,
-                       w.c3x2, nnz, w.ap2, w.ac3, w.d10, w.d14);
+    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, w.C3,
+                       w.sumd, w.c3x2, stored ? w.ek : nullptr, nnz, w.ap2, w.ac3, w.d10, w.d14, w.k4v, w.d13);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rpos, w.rrow,
-                       nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
+    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rpos,
+                       w.rrow, nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
                       SegTimer& tm) {
+    (void)nnz;
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
@@ -518,10 +537,6 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
                                    w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.k4v, w.d13, w.tri_slots,
                                    w.tri_slot_words, w.plan);
-        tm.mark(FGLT_SEG_TRI2_SUM, s);
-        if (stored && nnz > 0)
-            hipLaunchKernelGGL(k_sum_ek, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ek, nnz, w.k4v,
-                               w.d13);
     }
     return hipGetLastError();
 }

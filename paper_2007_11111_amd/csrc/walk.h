@@ -143,6 +143,51 @@ __device__ __forceinline__ i32 wave_incl_scan_i32(i32 x) {
     return x;
 }
 
+// The same scan for 64-bit values: both halves move together, the sum carries.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ i64 dpp_add_i64(i64 x) {
+    const u32 lo_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)x, CTRL, ROWS, 0xf, false);
+    const u32 hi_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)((u64)x >> 32), CTRL, ROWS, 0xf, false);
+    return x + (i64)(((u64)hi_ << 32) | lo_);
+}
+__device__ __forceinline__ i64 wave_incl_scan_i64(i64 x) {
+    x = dpp_add_i64<0x111, 0xf>(x);  // row_shr:1
+    x = dpp_add_i64<0x112, 0xf>(x);  // row_shr:2
+    x = dpp_add_i64<0x114, 0xf>(x);  // row_shr:4
+    x = dpp_add_i64<0x118, 0xf>(x);  // row_shr:8
+    x = dpp_add_i64<0x142, 0xa>(x);  // row_bcast:15
+    x = dpp_add_i64<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
+
+// Runs of equal keys among the active lanes of a wavefront (active lanes
+// first, keys non-decreasing): `tail` on the last lane of each run, `h` the
+// first lane of the run holding this lane.  run_total(v) gives every lane the
+// sum of v over its run up to itself -- the run's total on its tail lane --
+// from one prefix sum and one shuffle from the lane before the run's head.
+struct WaveRuns {
+    int h;
+    bool tail;
+};
+__device__ __forceinline__ WaveRuns wave_runs(i32 key, bool act) {
+    const int l = lane_id();
+    const i32 kp = __builtin_amdgcn_update_dpp(0, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    const i32 kn = __builtin_amdgcn_update_dpp(0, key, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    const u64 am = __ballot(act);
+    const u64 hm = __ballot(act && (l == 0 || kp != key));
+    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
+    const u64 below = hm & le;
+    WaveRuns w;
+    w.h = below ? 63 - __clzll((long long)below) : 0;
+    w.tail = act && (l == WAVE - 1 || kn != key || !((am >> (l + 1)) & 1ull));
+    return w;
+}
+__device__ __forceinline__ i64 run_total(i64 v, const WaveRuns& w) {
+    const i64 P = wave_incl_scan_i64(v);
+    const i64 Pb = __shfl(P, w.h > 0 ? w.h - 1 : 0, WAVE);
+    return w.h > 0 ? P - Pb : P;
+}
+
 // Transpose of a 64 x 64 bit matrix held one row per lane (bit j of lane i's
 // word = entry (i, j)): returns column `lane`.  Six butterfly rounds; round s
 // swaps the off-diagonal s x s blocks of every 2s x 2s block.
