@@ -65,34 +65,30 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Run starts among the 64 items ts .. ts+63: bit p set when a run begins at
-// item ts + p.  Lane l holds st, the first item of some run (distinct lanes,
-// distinct runs); the lanes whose start falls in the step mark it in a
-// per-wavefront LDS row and the row is read back as a ballot.
-__device__ __forceinline__ u64 run_start_mask(i32* flags, i32 st, i32 ts) {
-    const int l = lane_id();
-    lds_put(&flags[l], 0);
-    wave_lds_fence();
-    if ((u32)(st - ts) < (u32)WAVE) lds_put(&flags[st - ts], 1);
-    wave_lds_fence();
-    const u64 mask = __ballot(lds_get(&flags[l]) != 0);
-    wave_lds_fence();
-    return mask;
+__device__ __forceinline__ void lds_put8(u8* p, u8 v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ u8 lds_get8(u8* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // The run walk, in groups of up to U steps of 64 items.  A group reads the
 // starts of the next 64 runs once (one per lane); it ends before the last of
-// them, so every item in it has a known run.  Per step, the run of item
-// ts + l is r0 + (starts before ts) + (starts in [ts, ts + l]), the latter from
-// the LDS run-start mask.  The U gathers w = ridx[e] of a group are issued
-// together, then f(active, item, run, w, e, run-start mask, group end) runs for
-// each step.  Inactive lanes gather a valid dummy item, so no load is branched.
+// them, so every item in it has a known run.  The run starts inside the group
+// are marked as bytes in the wavefront's 256-byte flags row (cleared, marked,
+// then read back once per step: three LDS round trips per group); the run of
+// item ts + l is r0 + (starts in earlier steps) + (starts in [ts, ts + l]).
+// The U gathers w = ridx[e] of a group are issued together, then
+// f(active, item, run, w, e, run-start mask, group end) runs for each step.
+// Inactive lanes gather a valid dummy item, so no load is branched.
 template <int U, class F>
 __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
                                          const i32* __restrict__ ridx, F&& f) {
+    static_assert(U * WAVE <= (int)(WAVE * sizeof(i32)), "one flag byte per item of a group");
     if (ta >= tb) return;
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
+    u8* const fb = reinterpret_cast<u8*>(flags);
     i32 r0 = __builtin_amdgcn_readfirstlane((i32)last_le_dev(rstart, 0, R - 1, ta));  // run holding item ta
     i32 t0 = ta;
     while (t0 < tb) {
@@ -101,16 +97,24 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
         const i32 st = j < R ? sj : 0x7fffffff;  // start of run r0 + 1 + l (> t0)
         const i32 t1 = min(min(tb, t0 + U * WAVE), __builtin_amdgcn_readlane(st, WAVE - 1));
         const i64 esafe = rbase[r0] + t0;
+        lds_put(&flags[l], 0);
+        wave_lds_fence();
+        if ((u32)(st - t0) < (u32)(U * WAVE)) lds_put8(&fb[st - t0], 1);
+        wave_lds_fence();
+        u8 fl[U];
+#pragma unroll
+        for (int s = 0; s < U; ++s) fl[s] = lds_get8(&fb[s * WAVE + l]);
+        wave_lds_fence();
         i32 rr[U];
         u64 mm[U];
         i64 ee[U];
         i32 ww[U];
+        i32 before = 0;  // run starts in the group's earlier steps
 #pragma unroll
         for (int s = 0; s < U; ++s) {
-            const i32 ts = t0 + s * WAVE;
-            const i32 before = __popcll(__ballot(st < ts));
-            mm[s] = run_start_mask(flags, st, ts);
+            mm[s] = __ballot(fl[s] != 0);
             rr[s] = r0 + before + __popcll(mm[s] & le);
+            before += __popcll(mm[s]);
         }
 #pragma unroll
         for (int s = 0; s < U; ++s) {
