@@ -9,7 +9,8 @@
 //            consecutive pairs in RX_ITEMS steps of 64; lanes with equal
 //            digits find each other with 8 ballots, and a per-wavefront LDS
 //            counter per digit carries the ranks from step to step -- then
-//            adds the counts of the earlier wavefronts and writes.
+//            places them in LDS in digit order and writes each digit's pairs
+//            as one run of consecutive lanes.
 // Stable passes from the least significant digit up leave the pairs ordered
 // by key, ties in input order.
 #include "walk.h"
@@ -45,17 +46,23 @@ __global__ void __launch_bounds__(RX_THREADS) k_rx_count(const u32* __restrict__
 }
 
 // vals == nullptr: the value of pair i is i.  out_k == nullptr: keys not written.
+// The ranked tile is staged in LDS in digit order, so that the pairs of one
+// digit leave as one contiguous run of consecutive lanes.
 __global__ void __launch_bounds__(RX_THREADS) k_rx_scatter(const u32* __restrict__ keys, const i32* __restrict__ vals,
                                                            i64 n, int shift, i64 ntiles, const i64* __restrict__ off,
                                                            u32* __restrict__ out_k, i32* __restrict__ out_v) {
-    __shared__ i32 wc[RX_NW][RX_DIG];  // per wavefront: pairs of each digit so far, then its first position
-    __shared__ i64 wo[RX_NW][RX_DIG];
+    __shared__ i32 wc[RX_NW][RX_DIG];  // per wavefront: pairs of each digit so far, then its first tile slot
+    __shared__ i64 gofs[RX_DIG];       // output position of digit d minus its first tile slot
+    __shared__ u32 sk[RX_TILE];
+    __shared__ i32 sv[RX_TILE];
+    __shared__ i32 wsum[RX_NW], wtot;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const u64 lt = lanemask_lt();
     for (i64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         for (int w = 0; w < RX_NW; ++w) wc[w][threadIdx.x] = 0;
         __syncthreads();
-        const i64 w0 = tile * RX_TILE + (i64)wv * WAVE * RX_ITEMS;
+        const i64 t0 = tile * RX_TILE;
+        const i64 w0 = t0 + (i64)wv * WAVE * RX_ITEMS;
         u32 kk[RX_ITEMS];
         i32 vv[RX_ITEMS];
 #pragma unroll
@@ -85,21 +92,40 @@ __global__ void __launch_bounds__(RX_THREADS) k_rx_scatter(const u32* __restrict
         }
         __syncthreads();
         {
+            // digit d: its tile slots start after all smaller digits; within
+            // the digit, wavefront w's pairs follow those of wavefronts < w
             const int d = threadIdx.x;
-            i64 run = off[(i64)d * ntiles + tile];
+            i32 c[RX_NW], tot = 0;
+#pragma unroll
             for (int w = 0; w < RX_NW; ++w) {
-                wo[w][d] = run;
-                run += wc[w][d];
+                c[w] = wc[w][d];
+                tot += c[w];
             }
+            const i32 start = block_scan<RX_THREADS>(tot, wsum, &wtot);
+            i32 run = start;
+#pragma unroll
+            for (int w = 0; w < RX_NW; ++w) {
+                wc[w][d] = run;
+                run += c[w];
+            }
+            gofs[d] = off[(i64)d * ntiles + tile] - start;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < RX_ITEMS; ++j) {
             if (w0 + (i64)j * WAVE + l < n) {
-                const i64 pos = wo[wv][(kk[j] >> shift) & (RX_DIG - 1)] + rk[j];
-                out_v[pos] = vv[j];
-                if (out_k) out_k[pos] = kk[j];
+                const i32 slot = wc[wv][(kk[j] >> shift) & (RX_DIG - 1)] + rk[j];
+                sk[slot] = kk[j];
+                sv[slot] = vv[j];
             }
+        }
+        __syncthreads();
+        const i32 cnt = (i32)std::min<i64>(RX_TILE, n - t0);
+        for (i32 i = threadIdx.x; i < cnt; i += RX_THREADS) {
+            const u32 k = sk[i];
+            const i64 pos = gofs[(k >> shift) & (RX_DIG - 1)] + i;
+            out_v[pos] = sv[i];
+            if (out_k) out_k[pos] = k;
         }
         __syncthreads();
     }
