@@ -571,9 +571,29 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     }
                 }
             }
-            // pass B: C(c, 2) to every end w and to u, over the touched range
-            // (after the gathers, so that these atomics hold back no load of the walks)
-            if (PACK16) {  // word by word: two counts per word, most words zero
+            // pass B: C(c, 2) to every end w and to u (after the gathers, so
+            // that these atomics hold back no load of the walks).  A window
+            // with few wedges for its touched range goes over the scratch copy
+            // of its wedges: the first wedge of each end takes the end's count
+            // and clears it, which also leaves the counters zero for the next
+            // window.  Otherwise the touched range is read word by word, then
+            // cleared.
+            const bool all_kept = nch <= MAXCH && stored == (nch == 64 ? ~0ull : ((1ull << nch) - 1));
+            const bool sparse = PACK16 && all_kept && toff < 2 * (i64)((xhi >> 1) - (xlo >> 1) + 1);
+            if (sparse) {
+                __syncthreads();  // every count has been read by pass C
+                for (i32 t = (i32)threadIdx.x; t < (i32)toff; t += CB_THREADS) {
+                    const u32 x = sc[t] & 0xffffu;
+                    const u32 sh = (x & 1u) << 4;
+                    const u32 old = atomicAnd(&cnt[x >> 1], ~(0xffffu << sh));
+                    const i64 c = (old >> sh) & 0xffffu;
+                    if (c >= 2) {
+                        const i64 pr = c * (c - 1) / 2;
+                        accu += pr;
+                        atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+                    }
+                }
+            } else if (PACK16) {  // word by word: two counts per word, most words zero
                 for (i32 q = (xlo >> 1) + (i32)threadIdx.x; q <= (xhi >> 1); q += CB_THREADS) {
                     const u32 wd = cnt[q];
                     if (wd == 0) continue;
@@ -598,9 +618,10 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                 }
             }
             __syncthreads();
-            // clear the touched counters for the next window
-            const i32 q0 = PACK16 ? xlo >> 1 : xlo, q1 = PACK16 ? xhi >> 1 : xhi;
-            for (i32 q = q0 + (i32)threadIdx.x; q <= q1; q += CB_THREADS) cnt[q] = 0;
+            if (!sparse) {  // clear the touched counters for the next window
+                const i32 q0 = PACK16 ? xlo >> 1 : xlo, q1 = PACK16 ? xhi >> 1 : xhi;
+                for (i32 q = q0 + (i32)threadIdx.x; q <= q1; q += CB_THREADS) cnt[q] = 0;
+            }
             if (threadIdx.x == 0) {
                 wlo = INT_MAX;
                 whi = -1;
