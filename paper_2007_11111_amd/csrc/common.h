@@ -46,11 +46,15 @@ static inline unsigned grid_for(i64 work, i64 per_block, i64 cap = 1 << 20) {
 }
 static inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Linear allocator over a caller-provided workspace (256-byte aligned pieces).
+// Linear allocator over a caller-provided workspace (256-byte aligned pieces;
+// up to 255 leading bytes are skipped when the workspace itself is not
+// aligned, and the size query reserves them).
 struct Carver {
     char* base;
     size_t cap, used;
-    explicit Carver(void* b, size_t c) : base((char*)b), cap(c), used(0) {}
+    explicit Carver(void* b, size_t c) : base((char*)b), cap(c), used(0) {
+        used = base ? (size_t)(align_up((size_t)(uintptr_t)base, 256) - (size_t)(uintptr_t)base) : 256;
+    }
     template <class T>
     T* take(i64 count) {
         size_t bytes = align_up(sizeof(T) * (size_t)(count > 0 ? count : 1), 256);

@@ -41,6 +41,21 @@ struct DevPlan {
     i64 triangles;
 };
 
+// Per-vertex record of rank space, read with one 16-byte load where a kernel
+// needs a neighbour's row: its start, |N-(v)| and degree.
+struct __align__(16) VRec {
+    i64 off;
+    i32 lo;
+    i32 deg;
+};
+
+// What row pass 2 gathers of a neighbour j, in one 16-byte load: p2(j), and
+// c3(j) << 21 | d(j) (degrees are below 2^21, so c3 < 2^41 and the word < 2^62).
+struct __align__(16) L2Rec {
+    i64 p2;
+    i64 c3d;
+};
+
 struct RawWs {
     // rank space structure
     i32* deg;     // [n] degrees, original order
@@ -50,6 +65,8 @@ struct RawWs {
     i32* lo;      // [n] |N-(u)|
     i64* cntd;    // [n+2] scratch of the degree sort
     i64* roff;    // [n+1]
+    VRec* vrec;   // [n] roff, lo and degree of each vertex
+    L2Rec* l2rec; // [n] p2, c3 and degree of each vertex, for row pass 2
     i32* ridx;    // [nnz]
     i32* rrow;    // [nnz] row of each entry (rank space)
     i32* rpos;    // [nnz] N- entry (u, v): position of u in row v; N+ entry (u, v): ~(position of u in row v)

@@ -83,15 +83,23 @@ __global__ void __launch_bounds__(PT) k_l1(const i32* __restrict__ rrow, const i
 // counts (ek != nullptr), their row sums: it stores, for each N+ entry
 // (u, v) of its wave and LDS tiers, the 4-cliques and diamonds it attributes
 // to v, packed as dv << EK_SHIFT | kv, at the mirror (v, u).
+__global__ void k_l2_rec(i64 n, const i32* __restrict__ rdeg, const i64* __restrict__ sumd,
+                         const i64* __restrict__ c3x2, L2Rec* __restrict__ rec) {
+    for (i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (i64)gridDim.x * blockDim.x) {
+        const i64 d = rdeg[v];
+        rec[v] = L2Rec{sumd[v] - d, ((c3x2[v] >> 1) << 21) | d};
+    }
+}
+
 __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
-                                           const i32* __restrict__ rdeg, const i32* __restrict__ C3,
-                                           const i64* __restrict__ sumd, const i64* __restrict__ c3x2,
+                                           const L2Rec* __restrict__ rec, const i32* __restrict__ C3,
                                            const i64* __restrict__ ek, i64 nnz, i64* __restrict__ ap2,
                                            i64* __restrict__ ac3, i64* __restrict__ d10, i64* __restrict__ d14,
                                            i64* __restrict__ k4v, i64* __restrict__ d13) {
     row_chunks(nnz, [&](const i64* p) {
-        i32 r[RP_CH], j[RP_CH], t[RP_CH], dj[RP_CH];
-        i64 sj[RP_CH], cj[RP_CH], x[RP_CH];
+        i32 r[RP_CH], j[RP_CH], t[RP_CH];
+        L2Rec g[RP_CH];
+        i64 x[RP_CH];
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const i64 q = p[c] < nnz ? p[c] : nnz - 1;
@@ -101,18 +109,14 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
             x[c] = ek ? ek[q] : 0;
         }
 #pragma unroll
-        for (int c = 0; c < RP_CH; ++c) {
-            dj[c] = rdeg[j[c]];
-            sj[c] = sumd[j[c]];
-            cj[c] = c3x2[j[c]];
-        }
+        for (int c = 0; c < RP_CH; ++c) g[c] = rec[j[c]];
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const bool act = p[c] < nnz;
             const WaveRuns w = wave_runs(r[c], act);
-            const i64 d = dj[c], tt = act ? t[c] : 0;
-            add_run(ap2, r[c], act ? sj[c] - d : 0, w);       // p2(j)
-            add_run(ac3, r[c], act ? cj[c] >> 1 : 0, w);      // c3(j)
+            const i64 d = g[c].c3d & ((1 << 21) - 1), tt = act ? t[c] : 0;
+            add_run(ap2, r[c], act ? g[c].p2 : 0, w);          // p2(j)
+            add_run(ac3, r[c], act ? g[c].c3d >> 21 : 0, w);   // c3(j)
             add_run(d10, r[c], tt * (d - 2), w);              // C3(i,j) (p1(j) - 2); C3 = 0 when d_j = 1
             add_run(d14, r[c], tt * (tt - 1) / 2, w);         // C(C3(i,j), 2)
             if (ek) {
@@ -486,8 +490,9 @@ hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
 
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, w.C3,
-                       w.sumd, w.c3x2, stored ? w.ek : nullptr, nnz, w.ap2, w.ac3, w.d10, w.d14, w.k4v, w.d13);
+    hipLaunchKernelGGL(k_l2_rec, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.sumd, w.c3x2, w.l2rec);
+    hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.l2rec, w.C3,
+                       stored ? w.ek : nullptr, nnz, w.ap2, w.ac3, w.d10, w.d14, w.k4v, w.d13);
     return hipGetLastError();
 }
 

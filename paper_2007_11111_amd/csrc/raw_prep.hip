@@ -160,7 +160,7 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
 
 // lo[u] = |N-(u)| (entries < u); self-loop check; sum of lo.
 __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n,
-                                           i32* __restrict__ lo, DevPlan* plan) {
+                                           i32* __restrict__ lo, VRec* __restrict__ vrec, DevPlan* plan) {
     __shared__ i64 part[PT / WAVE];
     i64 sum = 0;
     u32 err = 0;
@@ -169,6 +169,7 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
         const i64 q = lower_bound_dev(ridx, b, e, (i32)u);
         if (q < e && ridx[q] == (i32)u) err |= ERR_SELFLOOP;
         lo[u] = (i32)(q - b);
+        vrec[u] = VRec{b, (i32)(q - b), (i32)(e - b)};
         sum += q - b;
     }
     sum = block_sum<PT>(sum, part);
@@ -183,30 +184,30 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
 //     thread of its mirror (u, v); work = d+(u) (the triangle pass).
 //   A diagonal entry gets rpos = -1 (the input check rejects it).
 //   rpos >= 0 marks the N- entries; ~rpos of an N+ entry locates its mirror.
-__global__ void k_rpos(const i64* __restrict__ roff, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
-                       const i32* __restrict__ lo, const i32* __restrict__ rdeg, i64 nnz, i32* __restrict__ rpos,
-                       i64* __restrict__ G, DevPlan* plan) {
+__global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
+                       i64 nnz, i32* __restrict__ rpos, i64* __restrict__ G, DevPlan* plan) {
     u32 err = 0;
     for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
         {
             const i64 u = rrow[p];
             const i32 v = ridx[p];
-            if (p > roff[u] && ridx[p - 1] == v) err |= ERR_DUP;
+            if (p > 0 && rrow[p - 1] == (i32)u && ridx[p - 1] == v) err |= ERR_DUP;
+            const VRec rv = vrec[v];  // one 16-byte load: start, |N-(v)|, degree
             i64 work = 0;
             if ((i64)v < u) {
-                const i64 b = roff[v] + lo[v], e = roff[v + 1];
+                const i64 b = rv.off + rv.lo, e = rv.off + rv.deg;
                 const i64 q = lower_bound_dev(ridx, b, e, (i32)u);
                 i32 rp = 0;  // on an asymmetric input: harmless, no wedges (the run stops there)
                 if (q < e && ridx[q] == (i32)u) {
-                    rp = (i32)(q - roff[v]);
-                    rpos[q] = ~(i32)(p - roff[u]);  // the mirror (v, u) learns where (u, v) sits
+                    rp = (i32)(q - rv.off);
+                    rpos[q] = ~(i32)(p - vrec[u].off);  // the mirror (v, u) learns where (u, v) sits
                 } else {
                     err |= ERR_ASYM;
                 }
                 rpos[p] = rp;
                 work = rp;
             } else if ((i64)v > u) {
-                work = rdeg[v] - lo[v];  // rpos[p] comes from the mirror's thread
+                work = rv.deg - rv.lo;  // rpos[p] comes from the mirror's thread
             } else {
                 rpos[p] = -1;
             }
@@ -332,10 +333,10 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
 
 hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream_t s) {
     hipError_t e;
-    hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.plan);
+    hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.vrec, w.plan);
     if (nnz > 0)
-        hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rrow, w.lo,
-                           w.rdeg, nnz, w.rpos, w.G, w.plan);
+        hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.vrec, w.ridx, w.rrow, nnz,
+                           w.rpos, w.G, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive_i64(w.G, w.G, nnz, w.partials, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, TT, 256)), dim3(TT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
@@ -358,6 +359,8 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.lo = c.take<i32>(nn);
     w.cntd = c.take<i64>(nn + 2);
     w.roff = c.take<i64>(nn + 1);
+    w.vrec = c.take<VRec>(nn);
+    w.l2rec = c.take<L2Rec>(nn);
     w.ridx = c.take<i32>(nnz);
     w.rpos = c.take<i32>(nnz);
     w.rrow = c.take<i32>(nnz);

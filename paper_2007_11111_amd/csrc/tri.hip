@@ -51,7 +51,7 @@ __device__ __forceinline__ void flush_c3(const u32* q, u32 nq, i32* __restrict__
     for (u32 i = lane; i < cnt; i += width) atomicAdd(&C3[q[i]], 1);
 }
 
-__global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i64* __restrict__ G,
                                                   const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
                                                   u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
                 bmap_insert(pm[wid], v, lane);
                 pre = (i32)(G[bu + lane] - gb);
                 len = (i32)(G[bu + lane + 1] - G[bu + lane]);
-                bv = roff[v] + lo[v];
+                { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
             }
             const u64 m = __ballot(lane < D && len > 0);
             if (lane < D && len > 0) {
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
     }
 }
 
-__global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
                                                  const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
                                                  u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
             bmap_insert(pm, v, k);
             pre = (i32)(G[bu + k] - gb);
             len = (i32)(G[bu + k + 1] - G[bu + k]);
-            bv = roff[v] + lo[v];
+            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
         }
         const i32 cidx = block_scan<LT>(len > 0 ? 1 : 0, wsum, &stot);
         if (k < D && len > 0) {
@@ -228,7 +228,7 @@ __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i3
     return (i64)C3[q] - 1;
 }
 
-__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                    const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                    const i32* __restrict__ rpos, const i32* __restrict__ list,
                                                    u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
@@ -275,9 +275,10 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
         i64 du = 0;
         if (lane < D) {
             // diamonds of u: C3(v_k, v_l) - 1 over the triangles (u, v_k, v_l)
-            const i64 rv = roff[vk];
-            i64 from = rv + lo[vk];
-            const i64 end = rv + rdeg[vk];
+            const VRec rec = vrec[vk];
+            const i64 rv = rec.off;
+            i64 from = rv + rec.lo;
+            const i64 end = rv + rec.deg;
             FOR_BITS(Bk, l, { du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l])); });
             const i64 kv = R + M + X;
             if (kv | dv) ek[rv + mk] = (dv << EK_SHIFT) | kv;
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
 // number of other triangles on the opposite edge, C3(v_k, v_l) - 1.  The
 // out-lists N+(v_k) are walked again as in the triangle pass; a hit y = v_l
 // sits at the walked entry e, whose C3 is final now.
-__global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                     const i32* __restrict__ lo, const i64* __restrict__ G,
                                                     const i32* __restrict__ list, u32 count,
                                                     const i32* __restrict__ C3, i64* __restrict__ d13) {
@@ -413,7 +414,7 @@ __global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff
             bmap_insert(pm, v, k);
             pre = (i32)(G[bu + k] - gb);
             len = (i32)(G[bu + k + 1] - G[bu + k]);
-            bv = roff[v] + lo[v];
+            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
         }
         const i32 cidx = block_scan<LT>(len > 0 ? 1 : 0, wsum, &stot);
         if (k < D && len > 0) {
@@ -462,10 +463,10 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
     if (tier == 0 && c0)
-        hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.G,
+        hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
     if (tier == 1 && c1)
-        hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
+        hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
     return hipGetLastError();
 }
@@ -473,12 +474,12 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
 hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier) {
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     if (tier == 0 && c0)
-        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
+        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.rdeg,
                            w.rpos, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
     if (tier == 1 && c1) {
         hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rpos,
                            w.tri_list + n, c1, w.C3, w.k4v, w.ek, w.bstore, w.boff);
-        hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.G,
+        hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.d13);
     }
     return hipGetLastError();
