@@ -63,50 +63,43 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
     __shared__ BucketMap<6> pm[NW];  // positions of N+(u): 64 buckets of 4
     __shared__ i32 flags[NW][WAVE];
     __shared__ u64 sB[NW][WAVE];
-    __shared__ i32 sR[NW];
     __shared__ u32 sQ[NW][TRI_QCAP];  // deferred C3 increments (entry indices)
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
-    for (i64 base = (i64)blockIdx.x * NW; base < (i64)count; base += (i64)gridDim.x * NW) {
-        const i64 it = base + wid;
-        const bool valid = it < (i64)count;
+    // every wavefront runs its own vertices; it shares no LDS with the others,
+    // so only wavefront-level fences order its steps
+    for (i64 it = (i64)blockIdx.x * NW + wid; it < (i64)count; it += (i64)gridDim.x * NW) {
         bmap_clear(pm[wid], lane, WAVE);
         sB[wid][lane] = 0;
-        __syncthreads();
-        i64 u = 0, bu = 0;
-        int D = 0, T = 0;
-        if (valid) {
-            u = list[it];
-            bu = roff[u] + lo[u];
-            D = (int)(roff[u + 1] - bu);
-            const i64 gb = G[bu];
-            T = (int)(G[bu + D] - gb);
-            i32 len = 0, pre = 0;
-            i64 bv = 0;
-            if (lane < D) {
-                const i32 v = ridx[bu + lane];
-                bmap_insert(pm[wid], v, lane);
-                pre = (i32)(G[bu + lane] - gb);
-                len = (i32)(G[bu + lane + 1] - G[bu + lane]);
-                { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
-            }
-            const u64 m = __ballot(lane < D && len > 0);
-            if (lane < D && len > 0) {
-                const int c = __popcll(m & lanemask_lt());
-                rbase[wid][c] = bv - pre;
-                rstart[wid][c] = pre;
-                rk[wid][c] = lane;
-            }
-            if (lane == 0) {
-                const int R = __popcll(m);
-                sR[wid] = R;
-                rstart[wid][R] = T;
-            }
+        wave_lds_fence();
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        const i64 gb = G[bu];
+        const int T = (int)(G[bu + D] - gb);
+        i32 len = 0, pre = 0;
+        i64 bv = 0;
+        if (lane < D) {
+            const i32 v = ridx[bu + lane];
+            bmap_insert(pm[wid], v, lane);
+            pre = (i32)(G[bu + lane] - gb);
+            len = (i32)(G[bu + lane + 1] - G[bu + lane]);
+            const VRec rv = vrec[v];
+            bv = rv.off + rv.lo;
         }
-        __syncthreads();
+        const u64 m = __ballot(lane < D && len > 0);
+        const i32 nruns = __popcll(m);
+        if (lane < D && len > 0) {
+            const int c = __popcll(m & lanemask_lt());
+            rbase[wid][c] = bv - pre;
+            rstart[wid][c] = pre;
+            rk[wid][c] = lane;
+        }
+        if (lane == 0) rstart[wid][nruns] = T;
+        wave_lds_fence();
         u32 nq = 0;  // wave-uniform
-        if (valid && T > 0) {
-            run_walk<4>(0, T, rbase[wid], rstart[wid], sR[wid], flags[wid], ridx,
+        if (T > 0) {
+            run_walk<4>(0, T, rbase[wid], rstart[wid], nruns, flags[wid], ridx,
                         [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
                 const i32 l = act ? bmap_find(pm[wid], y) : -1;
                 const bool hit = l >= 0;
@@ -114,20 +107,18 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, 
                 defer_c3(hit, e, sQ[wid], nq, C3, defer);
             });
         }
-        __syncthreads();
-        if (valid) {
-            flush_c3(sQ[wid], nq, C3, lane, WAVE);
-            // triangles on the edge (u, v_k): row k of B (v_l in N+(v_k)) plus
-            // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
-            const u64 row = sB[wid][lane];
-            const u64 col = wave_transpose64(row);
-            if (lane < D) {
-                const i32 c = __popcll(row) + __popcll(col);
-                if (c) atomicAdd(&C3[bu + lane], c);
-                if (store) bstore[boff[u] + lane] = row;
-            }
+        wave_lds_fence();
+        flush_c3(sQ[wid], nq, C3, lane, WAVE);
+        // triangles on the edge (u, v_k): row k of B (v_l in N+(v_k)) plus
+        // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
+        const u64 row = sB[wid][lane];
+        const u64 col = wave_transpose64(row);
+        if (lane < D) {
+            const i32 c = __popcll(row) + __popcll(col);
+            if (c) atomicAdd(&C3[bu + lane], c);
+            if (store) bstore[boff[u] + lane] = row;
         }
-        __syncthreads();
+        wave_lds_fence();  // the next vertex clears the map and the rows
     }
 }
 
@@ -228,18 +219,27 @@ __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i3
     return (i64)C3[q] - 1;
 }
 
-__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
-                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
-                                                   const i32* __restrict__ rpos, const i32* __restrict__ list,
-                                                   u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
+__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec,
+                                                   const i32* __restrict__ ridx, const i32* __restrict__ lo,
+                                                   const i32* __restrict__ rdeg, const i32* __restrict__ rpos,
+                                                   const i32* __restrict__ list, u32 count,
+                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                    i64* __restrict__ d13, i64* __restrict__ ek,
                                                    const u64* __restrict__ bstore, const i64* __restrict__ boff) {
-    // Each wavefront works alone on its vertices: row k of B and of C = B^T in
-    // lane k's registers, the rows l broadcast one after another (readlane), so
-    // every lane runs the same D iterations with no LDS traffic and no
-    // divergence.  Only the searches of the diamond term of u diverge.
+    // Each wavefront works alone on its vertices, edge by edge over the
+    // induced subgraph H on N+(u): lane k takes the edges (k, l), l in B_k
+    // (l > k).  With A = B | B^T, edge (k, l) lies on c = |A_k & A_l|
+    // triangles of H; k keeps its sums in registers, l's arrive by LDS
+    // atomics.  The triangles of H through k are half its sum of c, and u's
+    // 4-cliques the sum over all edges divided by three.  Diamonds: v_k gets
+    // C3(u, v_l) - 1 per edge at k; u gets C3(v_k, v_l) - 1 per edge, found by
+    // a galloping search of v_l in N+(v_k).
     constexpr int NW = WT / WAVE;
+    __shared__ u64 sA[NW][WAVE];
     __shared__ i32 sL[NW][WAVE];
+    __shared__ i32 sc3[NW][WAVE];
+    __shared__ u32 st2[NW][WAVE];
+    __shared__ u32 sdv[NW][WAVE];
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
     for (i64 it = (i64)blockIdx.x * NW + wid; it < (i64)count; it += (i64)gridDim.x * NW) {
@@ -254,42 +254,43 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff,
             c3k = C3[bu + lane];
             mk = ~rpos[bu + lane];  // position of u in row v_k
         }
-        const u64 Ck = wave_transpose64(Bk);
+        const u64 Ak = Bk | wave_transpose64(Bk);
+        sA[wid][lane] = Ak;
         lds_put(&sL[wid][lane], vk);
+        lds_put(&sc3[wid][lane], c3k);
+        lds_put(reinterpret_cast<i32*>(&st2[wid][lane]), 0);
+        lds_put(reinterpret_cast<i32*>(&sdv[wid][lane]), 0);
         wave_lds_fence();
-        // K4: R_k = sum over l in B_k of |B_k & B_l|, M_k = sum over j in C_k of
-        // |B_j & B_k|, X_k = sum over j in C_k of |B_j & C_k|.  Diamonds of v_k:
-        // C3(u, v_l) - 1 over the other vertex v_l of each of its triangles.
-        i64 R = 0, M = 0, X = 0, dv = 0;
-        for (int l = 0; l < D; ++l) {
-            const u64 Bl = (u64)(u32)__builtin_amdgcn_readlane((i32)(u32)Bk, l) |
-                           ((u64)(u32)__builtin_amdgcn_readlane((i32)(u32)(Bk >> 32), l) << 32);
-            const i64 cl = __builtin_amdgcn_readlane(c3k, l);
-            const bool inB = (Bk >> l) & 1ull, inC = (Ck >> l) & 1ull;
-            const i64 t = __popcll(Bk & Bl);
-            R += inB ? t : 0;
-            M += inC ? t : 0;
-            X += inC ? (i64)__popcll(Bl & Ck) : 0;
-            dv += (inB || inC) ? cl - 1 : 0;
-        }
-        i64 du = 0;
+        u32 tk = 0, dk = 0;
+        i64 R = 0, du = 0;
         if (lane < D) {
-            // diamonds of u: C3(v_k, v_l) - 1 over the triangles (u, v_k, v_l)
             const VRec rec = vrec[vk];
-            const i64 rv = rec.off;
-            i64 from = rv + rec.lo;
-            const i64 end = rv + rec.deg;
-            FOR_BITS(Bk, l, { du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l])); });
-            const i64 kv = R + M + X;
-            if (kv | dv) ek[rv + mk] = (dv << EK_SHIFT) | kv;
+            i64 from = rec.off + rec.lo;
+            const i64 end = rec.off + rec.deg;
+            const u32 ck = (u32)(c3k - 1);
+            FOR_BITS(Bk, l, {
+                const u32 c = (u32)__popcll(Ak & sA[wid][l]);
+                tk += c;
+                R += c;
+                dk += (u32)(lds_get(&sc3[wid][l]) - 1);
+                if (c) atomicAdd(&st2[wid][l], c);
+                if (ck) atomicAdd(&sdv[wid][l], ck);
+                du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l]));
+            });
+        }
+        wave_lds_fence();
+        if (lane < D) {
+            const i64 kv = (i64)((tk + st2[wid][lane]) >> 1);
+            const i64 dv = (i64)dk + sdv[wid][lane];
+            if (kv | dv) ek[vrec[vk].off + mk] = (dv << EK_SHIFT) | kv;
         }
         R = wave_sum(R);
         du = wave_sum(du);
         if (lane == 0) {
-            if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)R);
+            if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(R / 3));
             if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
         }
-        wave_lds_fence();  // the next vertex overwrites sL
+        wave_lds_fence();  // the next vertex overwrites the rows
     }
 }
 
