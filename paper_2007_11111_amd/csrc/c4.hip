@@ -58,24 +58,25 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
     const int grp = threadIdx.x / GT;
     const int gt = threadIdx.x % GT;
     const u32 mask = HSLOTS - 1;
-    for (i64 base = (i64)blockIdx.x * GROUPS; base < (i64)count; base += (i64)gridDim.x * GROUPS) {
-        const i64 it = base + grp;
-        const bool valid = it < (i64)count;
-        i64 u = 0, b = 0, m = 0, gb = 0, W = 0;
-        if (valid) {
-            u = list[it];
-            b = roff[u];
-            m = b + lo[u];
-            gb = G[b];
-            W = G[m] - gb;
-        }
+    // a one-wavefront group shares no LDS with the other groups: it runs its
+    // own vertices with wavefront fences; a whole-block group synchronizes
+    auto group_sync = [&]() {
+        if (WAVES_PER_U == 1) wave_lds_fence();
+        else __syncthreads();
+    };
+    for (i64 it = (i64)blockIdx.x * GROUPS + grp; it < (i64)count; it += (i64)gridDim.x * GROUPS) {
+        const i64 u = list[it];
+        const i64 b = roff[u];
+        const i64 m = b + lo[u];
+        const i64 gb = G[b];
+        const i64 W = G[m] - gb;
         for (int s = gt; s < HSLOTS; s += GT) {
             hk[grp][s] = -1;
             hc[grp][s] = 0;
         }
         for (int s = gt; s < LMAX; s += GT) msum[grp][s] = 0;
         if (gt == 0) red[grp] = 0;
-        __syncthreads();
+        group_sync();
         // pass A: count wedge ends
         for (i64 t = gt; t < W; t += GT) {
             i64 q;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
             wedge_item(G, roff, ridx, b, m, gb + t, q, w);
             hash_add(hk[grp], hc[grp], mask, w);
         }
-        __syncthreads();
+        group_sync();
         // pass C: cnt(w) - 1 to the middle vertex of every wedge; the sums go
         // to LDS per middle when the vertex's middles fit the array (a vertex
         // may have many middles without wedges), else straight to memory
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
         }
         accu = wave_sum(accu);
         if (lane_id() == 0 && accu) atomicAdd((unsigned long long*)&red[grp], (unsigned long long)accu);
-        __syncthreads();
+        group_sync();
         // the middles' sums, one global atomic per middle
         if (lsum) {
             for (i64 k = gt; k < m - b; k += GT) {
@@ -127,8 +128,8 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
                 if (v) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)v);
             }
         }
-        if (valid && gt == 0 && red[grp]) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red[grp]);
-        __syncthreads();
+        if (gt == 0 && red[grp]) atomicAdd((unsigned long long*)&c4v[u], (unsigned long long)red[grp]);
+        group_sync();
     }
 }
 
