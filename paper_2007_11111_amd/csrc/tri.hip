@@ -219,78 +219,123 @@ __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i3
     return (i64)C3[q] - 1;
 }
 
-__global__ void __launch_bounds__(WT) k_tri2s_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec,
-                                                   const i32* __restrict__ ridx, const i32* __restrict__ lo,
-                                                   const i32* __restrict__ rdeg, const i32* __restrict__ rpos,
-                                                   const i32* __restrict__ list, u32 count,
-                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
+static constexpr int T2_TASK = 8;  // vertices a wavefront takes at a time
+
+__global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
+                                                   const i32* __restrict__ rpos, const i32* __restrict__ list,
+                                                   u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                    i64* __restrict__ d13, i64* __restrict__ ek,
                                                    const u64* __restrict__ bstore, const i64* __restrict__ boff) {
-    // Each wavefront works alone on its vertices, edge by edge over the
-    // induced subgraph H on N+(u): lane k takes the edges (k, l), l in B_k
-    // (l > k).  With A = B | B^T, edge (k, l) lies on c = |A_k & A_l|
-    // triangles of H; k keeps its sums in registers, l's arrive by LDS
-    // atomics.  The triangles of H through k are half its sum of c, and u's
-    // 4-cliques the sum over all edges divided by three.  Diamonds: v_k gets
-    // C3(u, v_l) - 1 per edge at k; u gets C3(v_k, v_l) - 1 per edge, found by
-    // a galloping search of v_l in N+(v_k).
+    // Each wavefront works alone, on T2_TASK consecutive vertices at a time,
+    // packed into rounds: consecutive vertices whose out-degrees sum to at
+    // most 64 share the 64 lanes, vertex g's rows k on lanes off_g + k, its
+    // bitmap rows shifted to those lanes' bit positions (the 64 x 64
+    // transpose then transposes every vertex's block on its own).  Edge by
+    // edge over the induced subgraph H on N+(u): lane k takes the edges
+    // (k, l), l in B_k (l > k).  With A = B | B^T, edge (k, l) lies on
+    // c = |A_k & A_l| triangles of H; k keeps its sums in registers, l's
+    // arrive by LDS atomics.  The triangles of H through k are half its sum
+    // of c, and u's 4-cliques the sum over its edges divided by three.
+    // Diamonds: v_k gets C3(u, v_l) - 1 per edge at k; u gets C3(v_k, v_l) - 1
+    // per edge, found by a galloping search of v_l in N+(v_k).
     constexpr int NW = WT / WAVE;
     __shared__ u64 sA[NW][WAVE];
     __shared__ i32 sL[NW][WAVE];
     __shared__ i32 sc3[NW][WAVE];
     __shared__ u32 st2[NW][WAVE];
     __shared__ u32 sdv[NW][WAVE];
+    __shared__ i32 sflag[NW][WAVE];
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
-    for (i64 it = (i64)blockIdx.x * NW + wid; it < (i64)count; it += (i64)gridDim.x * NW) {
-        const i64 u = list[it];
-        const i64 bu = roff[u] + lo[u];
-        const int D = (int)(roff[u + 1] - bu);
-        u64 Bk = 0;
-        i32 vk = 0, c3k = 0, mk = 0;
-        if (lane < D) {
-            Bk = bstore[boff[u] + lane];
-            vk = ridx[bu + lane];
-            c3k = C3[bu + lane];
-            mk = ~rpos[bu + lane];  // position of u in row v_k
+    const u64 le = lane == WAVE - 1 ? ~0ull : ((1ull << (lane + 1)) - 1);
+    // tasks from the end of the list first: the list follows rank, and the
+    // vertices of high out-degree (long tasks) come last in it
+    const i64 ntasks = ((i64)count + T2_TASK - 1) / T2_TASK;
+    for (i64 tj = (i64)blockIdx.x * NW + wid; tj < ntasks; tj += (i64)gridDim.x * NW) {
+        const i64 t0 = (ntasks - 1 - tj) * T2_TASK;
+        const int ntask = (int)std::min<i64>(T2_TASK, (i64)count - t0);
+        // lanes i < ntask: vertex t0 + i
+        i64 u_i = 0, bu_i = 0, bo_i = 0;
+        i32 D_i = 0;
+        if (lane < ntask) {
+            u_i = list[t0 + lane];
+            const VRec r = vrec[u_i];
+            bu_i = r.off + r.lo;
+            D_i = r.deg - r.lo;
+            bo_i = boff[u_i];
         }
-        const u64 Ak = Bk | wave_transpose64(Bk);
-        sA[wid][lane] = Ak;
-        lds_put(&sL[wid][lane], vk);
-        lds_put(&sc3[wid][lane], c3k);
-        lds_put(reinterpret_cast<i32*>(&st2[wid][lane]), 0);
-        lds_put(reinterpret_cast<i32*>(&sdv[wid][lane]), 0);
-        wave_lds_fence();
-        u32 tk = 0, dk = 0;
-        i64 R = 0, du = 0;
-        if (lane < D) {
-            const VRec rec = vrec[vk];
-            i64 from = rec.off + rec.lo;
-            const i64 end = rec.off + rec.deg;
-            const u32 ck = (u32)(c3k - 1);
-            FOR_BITS(Bk, l, {
-                const u32 c = (u32)__popcll(Ak & sA[wid][l]);
-                tk += c;
-                R += c;
-                dk += (u32)(lds_get(&sc3[wid][l]) - 1);
-                if (c) atomicAdd(&st2[wid][l], c);
-                if (ck) atomicAdd(&sdv[wid][l], ck);
-                du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l]));
-            });
+        for (int next = 0; next < ntask;) {
+            // this round: vertices next .. next + P - 1, the longest run whose
+            // out-degrees sum to at most 64 (every out-degree is at most 64)
+            const i32 dd = (lane >= next && lane < ntask) ? D_i : 0;
+            const i32 incl = wave_incl_scan_i32(dd);
+            const u64 inr = __ballot(lane >= next && lane < ntask && incl <= WAVE);
+            const int P = __popcll(inr);
+            const i32 excl = incl - dd;
+            // lane L belongs to the vertex g whose lanes [excl_g, excl_g + D_g) hold it
+            lds_put(&sflag[wid][lane], 0);
+            wave_lds_fence();
+            if ((inr >> lane) & 1ull) lds_put(&sflag[wid][excl], 1);
+            wave_lds_fence();
+            const u64 starts = __ballot(lds_get(&sflag[wid][lane]) != 0);
+            const i32 used = __builtin_amdgcn_readlane(incl, next + P - 1);
+            const int g = next + __popcll(starts & le) - 1;  // vertex of this lane (valid when lane < used)
+            const bool act = lane < used;
+            const i64 u = __shfl(u_i, g, WAVE);
+            const i64 bu = __shfl(bu_i, g, WAVE);
+            const i64 bo = __shfl(bo_i, g, WAVE);
+            const i32 off_g = __shfl(excl, g, WAVE);
+            const i32 k = lane - off_g;
+            u64 Bk = 0;
+            i32 vk = 0, c3k = 0, mk = 0;
+            if (act) {
+                Bk = bstore[bo + k] << off_g;
+                vk = ridx[bu + k];
+                c3k = C3[bu + k];
+                mk = ~rpos[bu + k];  // position of u in row v_k
+            }
+            const u64 Ak = Bk | wave_transpose64(Bk);
+            sA[wid][lane] = Ak;
+            lds_put(&sL[wid][lane], vk);
+            lds_put(&sc3[wid][lane], c3k);
+            lds_put(reinterpret_cast<i32*>(&st2[wid][lane]), 0);
+            lds_put(reinterpret_cast<i32*>(&sdv[wid][lane]), 0);
+            wave_lds_fence();
+            u32 tk = 0, dk = 0;
+            i64 R = 0, du = 0, rk_off = 0;
+            if (act) {
+                const VRec rec = vrec[vk];
+                rk_off = rec.off;
+                i64 from = rec.off + rec.lo;
+                const i64 end = rec.off + rec.deg;
+                const u32 ck = (u32)(c3k - 1);
+                FOR_BITS(Bk, l, {
+                    const u32 c = (u32)__popcll(Ak & sA[wid][l]);
+                    tk += c;
+                    R += c;
+                    dk += (u32)(lds_get(&sc3[wid][l]) - 1);
+                    if (c) atomicAdd(&st2[wid][l], c);
+                    if (ck) atomicAdd(&sdv[wid][l], ck);
+                    du += c3_minus_1(ridx, C3, from, end, lds_get(&sL[wid][l]));
+                });
+            }
+            wave_lds_fence();
+            if (act) {
+                const i64 kv = (i64)((tk + st2[wid][lane]) >> 1);
+                const i64 dv = (i64)dk + sdv[wid][lane];
+                if (kv | dv) ek[rk_off + mk] = (dv << EK_SHIFT) | kv;
+            }
+            // per-vertex totals: runs of equal g among the active lanes
+            const WaveRuns wr = wave_runs(g, act);
+            R = run_total(R, wr);
+            du = run_total(du, wr);
+            if (wr.tail) {
+                if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(R / 3));
+                if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
+            }
+            wave_lds_fence();  // the next round overwrites the rows
+            next += P;
         }
-        wave_lds_fence();
-        if (lane < D) {
-            const i64 kv = (i64)((tk + st2[wid][lane]) >> 1);
-            const i64 dv = (i64)dk + sdv[wid][lane];
-            if (kv | dv) ek[vrec[vk].off + mk] = (dv << EK_SHIFT) | kv;
-        }
-        R = wave_sum(R);
-        du = wave_sum(du);
-        if (lane == 0) {
-            if (R) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(R / 3));
-            if (du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
-        }
-        wave_lds_fence();  // the next vertex overwrites the rows
     }
 }
 
@@ -475,7 +520,7 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
 hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier) {
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     if (tier == 0 && c0)
-        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.rdeg,
+        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE * T2_TASK)), dim3(WT), 0, s, w.vrec, w.ridx,
                            w.rpos, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
     if (tier == 1 && c1) {
         hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rpos,
