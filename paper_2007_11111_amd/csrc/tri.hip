@@ -51,74 +51,117 @@ __device__ __forceinline__ void flush_c3(const u32* q, u32 nq, i32* __restrict__
     for (u32 i = lane; i < cnt; i += width) atomicAdd(&C3[q[i]], 1);
 }
 
-__global__ void __launch_bounds__(WT) k_tri1_wave(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
-                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
+// Wave tier of the triangle pass.  A wavefront takes TASK consecutive
+// vertices of the tier list at a time and packs consecutive ones whose
+// out-degrees sum to at most 64 into one round: vertex g's out-neighbours on
+// lanes off_g + k, one shared position map keyed by (v, g) (v | g << 28, so
+// PACK needs n <= 2^28), the out-lists of all of them walked as one item
+// stream, and bitmap bits at the lanes' positions (the 64 x 64 transpose then
+// transposes every vertex's block on its own).  Tasks come from the end of
+// the list first, where the vertices of high out-degree sit.
+template <bool PACK>
+__global__ void __launch_bounds__(WT) k_tri1_wave(const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
                                                   u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
                                                   int defer) {
     constexpr int NW = WT / WAVE;
+    constexpr int TASK = PACK ? 8 : 1;
     __shared__ i64 rbase[NW][WAVE + 1];
     __shared__ i32 rstart[NW][WAVE + 1];
-    __shared__ i32 rk[NW][WAVE + 1];
-    __shared__ BucketMap<6> pm[NW];  // positions of N+(u): 64 buckets of 4
+    __shared__ i32 rk[NW][WAVE + 1];  // lane of run r, with its vertex slot above bit 8
+    __shared__ BucketMap<6> pm[NW];   // positions of the round's out-neighbours: 64 buckets of 4
     __shared__ i32 flags[NW][WAVE];
     __shared__ u64 sB[NW][WAVE];
     __shared__ u32 sQ[NW][TRI_QCAP];  // deferred C3 increments (entry indices)
     const int wid = threadIdx.x / WAVE;
     const int lane = lane_id();
+    const u64 le = lane == WAVE - 1 ? ~0ull : ((1ull << (lane + 1)) - 1);
+    auto key = [](i32 v, i32 g) { return PACK ? (v | (g << 28)) : v; };
     // every wavefront runs its own vertices; it shares no LDS with the others,
     // so only wavefront-level fences order its steps
-    for (i64 it = (i64)blockIdx.x * NW + wid; it < (i64)count; it += (i64)gridDim.x * NW) {
-        bmap_clear(pm[wid], lane, WAVE);
-        sB[wid][lane] = 0;
-        wave_lds_fence();
-        const i64 u = list[it];
-        const i64 bu = roff[u] + lo[u];
-        const int D = (int)(roff[u + 1] - bu);
-        const i64 gb = G[bu];
-        const int T = (int)(G[bu + D] - gb);
-        i32 len = 0, pre = 0;
-        i64 bv = 0;
-        if (lane < D) {
-            const i32 v = ridx[bu + lane];
-            bmap_insert(pm[wid], v, lane);
-            pre = (i32)(G[bu + lane] - gb);
-            len = (i32)(G[bu + lane + 1] - G[bu + lane]);
-            const VRec rv = vrec[v];
-            bv = rv.off + rv.lo;
+    const i64 ntasks = ((i64)count + TASK - 1) / TASK;
+    for (i64 tj = (i64)blockIdx.x * NW + wid; tj < ntasks; tj += (i64)gridDim.x * NW) {
+        const i64 t0 = (ntasks - 1 - tj) * TASK;
+        const int ntask = (int)std::min<i64>(TASK, (i64)count - t0);
+        i64 u_i = 0, bu_i = 0, bo_i = 0;
+        i32 D_i = 0;
+        if (lane < ntask) {
+            u_i = list[t0 + lane];
+            const VRec r = vrec[u_i];
+            bu_i = r.off + r.lo;
+            D_i = r.deg - r.lo;
+            bo_i = boff[u_i];
         }
-        const u64 m = __ballot(lane < D && len > 0);
-        const i32 nruns = __popcll(m);
-        if (lane < D && len > 0) {
-            const int c = __popcll(m & lanemask_lt());
-            rbase[wid][c] = bv - pre;
-            rstart[wid][c] = pre;
-            rk[wid][c] = lane;
+        for (int next = 0; next < ntask;) {
+            // this round: vertices next .. next + P - 1 (out-degrees sum to at most 64)
+            const i32 dd = (lane >= next && lane < ntask) ? D_i : 0;
+            const i32 incl = wave_incl_scan_i32(dd);
+            const u64 inr = __ballot(lane >= next && lane < ntask && incl <= WAVE);
+            const int P = __popcll(inr);
+            const i32 excl = incl - dd;
+            bmap_clear(pm[wid], lane, WAVE);
+            sB[wid][lane] = 0;
+            lds_put(&flags[wid][lane], 0);
+            wave_lds_fence();
+            if ((inr >> lane) & 1ull) lds_put(&flags[wid][excl], 1);
+            wave_lds_fence();
+            const u64 starts = __ballot(lds_get(&flags[wid][lane]) != 0);
+            wave_lds_fence();
+            const i32 used = __builtin_amdgcn_readlane(incl, next + P - 1);
+            const int gl = __popcll(starts & le) - 1;  // vertex slot of this lane in the round
+            const int g = next + gl;
+            const bool act = lane < used;
+            const i64 bu = __shfl(bu_i, g, WAVE);
+            const i64 bo = __shfl(bo_i, g, WAVE);
+            const i32 off_g = __shfl(excl, g, WAVE);
+            const i32 k = lane - off_g;
+            i32 len = 0;
+            i64 bv = 0;
+            if (act) {
+                const i32 v = ridx[bu + k];
+                bmap_insert(pm[wid], key(v, gl), lane);
+                const VRec rv = vrec[v];
+                bv = rv.off + rv.lo;
+                len = rv.deg - rv.lo;  // |N+(v)|: the items of this run
+            }
+            const i32 iincl = wave_incl_scan_i32(len);
+            const i32 pre = iincl - len;
+            const i32 T = __builtin_amdgcn_readlane(iincl, WAVE - 1);
+            const u64 m = __ballot(len > 0);
+            const i32 nruns = __popcll(m);
+            if (len > 0) {
+                const int c = __popcll(m & lanemask_lt());
+                rbase[wid][c] = bv - pre;
+                rstart[wid][c] = pre;
+                rk[wid][c] = lane | (gl << 8);
+            }
+            if (lane == 0) rstart[wid][nruns] = T;
+            wave_lds_fence();
+            u32 nq = 0;  // wave-uniform
+            if (T > 0) {
+                run_walk<4>(0, T, rbase[wid], rstart[wid], nruns, flags[wid], ridx,
+                            [&](bool a, i32, i32 r, i32 y, i64 e, u64, i32) {
+                    const i32 kr = a ? rk[wid][r] : 0;
+                    const i32 l = a ? bmap_find(pm[wid], key(y, kr >> 8)) : -1;
+                    const bool hit = l >= 0;
+                    if (hit) atomicOr((unsigned long long*)&sB[wid][kr & 0xff], 1ull << l);
+                    defer_c3(hit, e, sQ[wid], nq, C3, defer);
+                });
+            }
+            wave_lds_fence();
+            flush_c3(sQ[wid], nq, C3, lane, WAVE);
+            // triangles on the edge (u, v_k): row k of B (v_l in N+(v_k)) plus
+            // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
+            const u64 row = sB[wid][lane];
+            const u64 col = wave_transpose64(row);
+            if (act) {
+                const i32 c = __popcll(row) + __popcll(col);
+                if (c) atomicAdd(&C3[bu + k], c);
+                if (store) bstore[bo + k] = row >> off_g;
+            }
+            wave_lds_fence();  // the next round clears the map and the rows
+            next += P;
         }
-        if (lane == 0) rstart[wid][nruns] = T;
-        wave_lds_fence();
-        u32 nq = 0;  // wave-uniform
-        if (T > 0) {
-            run_walk<4>(0, T, rbase[wid], rstart[wid], nruns, flags[wid], ridx,
-                        [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
-                const i32 l = act ? bmap_find(pm[wid], y) : -1;
-                const bool hit = l >= 0;
-                if (hit) atomicOr((unsigned long long*)&sB[wid][rk[wid][r]], 1ull << l);
-                defer_c3(hit, e, sQ[wid], nq, C3, defer);
-            });
-        }
-        wave_lds_fence();
-        flush_c3(sQ[wid], nq, C3, lane, WAVE);
-        // triangles on the edge (u, v_k): row k of B (v_l in N+(v_k)) plus
-        // column k (v_k in N+(v_j)) of the induced subgraph on N+(u)
-        const u64 row = sB[wid][lane];
-        const u64 col = wave_transpose64(row);
-        if (lane < D) {
-            const i32 c = __popcll(row) + __popcll(col);
-            if (c) atomicAdd(&C3[bu + lane], c);
-            if (store) bstore[boff[u] + lane] = row;
-        }
-        wave_lds_fence();  // the next vertex clears the map and the rows
     }
 }
 
@@ -508,9 +551,14 @@ hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s) {
 hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier) {
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
-    if (tier == 0 && c0)
-        hipLaunchKernelGGL(k_tri1_wave, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
-                           w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+    if (tier == 0 && c0) {
+        if (n <= ((i64)1 << 28))  // position-map keys (v, slot) fit 31 bits
+            hipLaunchKernelGGL(k_tri1_wave<true>, dim3(tgrid(c0, WT / WAVE * 8)), dim3(WT), 0, s, w.vrec, w.ridx,
+                               w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+        else
+            hipLaunchKernelGGL(k_tri1_wave<false>, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.vrec, w.ridx,
+                               w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+    }
     if (tier == 1 && c1)
         hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
