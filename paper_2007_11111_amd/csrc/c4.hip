@@ -31,14 +31,30 @@ static constexpr int PT = 256;
 
 // ------------------------------------------------------------ small tiers
 
-// Wedge item t of vertex u (N- entries in [b, m)): the entry q = (u, v) and the
-// wedge end w = the o-th neighbour of v.
-__device__ __forceinline__ void wedge_item(const i64* __restrict__ G, const i64* __restrict__ roff,
-                                           const i32* __restrict__ ridx, i64 b, i64 m, i64 g, i64& q, i32& w) {
-    q = last_le_dev(G, b, m - 1, g);
-    const i32 v = ridx[q];
-    w = ridx[roff[v] + (g - G[q])];
-}
+// Wedge items of vertex u (N- entries in [b, m)), visited in increasing
+// order g: the entry q = (u, v) holding item g is found by one binary search
+// over the work prefix G for the first item, then by moving forward; the
+// wedge end is w = the (g - G[q])-th neighbour of v.
+struct WedgeCursor {
+    i64 q = -1, qs = 0, qe = 0, rs = 0;  // entry, its items [qs, qe), row start of its middle
+    // item g alone: one binary search (no cursor state kept)
+    __device__ __forceinline__ i32 once(const i64* __restrict__ G, const i64* __restrict__ roff,
+                                        const i32* __restrict__ ridx, i64 b, i64 m, i64 g) {
+        q = last_le_dev(G, b, m - 1, g);
+        return ridx[roff[ridx[q]] + (g - G[q])];
+    }
+    __device__ __forceinline__ i32 at(const i64* __restrict__ G, const i64* __restrict__ roff,
+                                      const i32* __restrict__ ridx, i64 b, i64 m, i64 g) {
+        if (q < 0 || g >= qe) {
+            q = q < 0 ? last_le_dev(G, b, m - 1, g) : q + 1;
+            while (G[q + 1] <= g) ++q;  // skip middles without wedges
+            qs = G[q];
+            qe = G[q + 1];
+            rs = roff[ridx[q]];
+        }
+        return ridx[rs + (g - qs)];
+    }
+};
 
 // LDS-hash tiers.  WAVES_PER_U = 1: one wavefront per vertex (4 per block,
 // 256-slot table each); WAVES_PER_U = 4: the whole block on one vertex with a
@@ -77,25 +93,37 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
         for (int s = gt; s < LMAX; s += GT) msum[grp][s] = 0;
         if (gt == 0) red[grp] = 0;
         group_sync();
+        // a workgroup's threads take ipt consecutive items each (one search,
+        // then a forward walk); a wavefront's lanes (at most two items each)
+        // take every GT-th item with a search per item
+        const i64 ipt = (W + GT - 1) / GT;
+        const i64 t0 = WAVES_PER_U == 1 ? gt : gt * ipt;
+        const i64 ts = WAVES_PER_U == 1 ? GT : 1;
         // pass A: count wedge ends
-        for (i64 t = gt; t < W; t += GT) {
-            i64 q;
-            i32 w;
-            wedge_item(G, roff, ridx, b, m, gb + t, q, w);
-            hash_add(hk[grp], hc[grp], mask, w);
+        {
+            WedgeCursor cur;
+            for (i64 s = 0; s < ipt; ++s) {
+                const i64 t = t0 + s * ts;
+                if (t >= W) break;
+                const i32 w = WAVES_PER_U == 1 ? cur.once(G, roff, ridx, b, m, gb + t)
+                                               : cur.at(G, roff, ridx, b, m, gb + t);
+                hash_add(hk[grp], hc[grp], mask, w);
+            }
         }
         group_sync();
         // pass C: cnt(w) - 1 to the middle vertex of every wedge; the sums go
         // to LDS per middle when the vertex's middles fit the array (a vertex
         // may have many middles without wedges), else straight to memory
         const bool lsum = m - b <= LMAX;
-        for (i64 t0 = 0; t0 < W; t0 += GT) {
-            const i64 t = t0 + gt;
+        WedgeCursor cur;
+        for (i64 s = 0; s < ipt; ++s) {  // items t0 + s * ts rise with the lane, so do their entries
+            const i64 t = t0 + s * ts;
             const bool act = t < W;
             i64 q = -1, val = 0;
             if (act) {
-                i32 w;
-                wedge_item(G, roff, ridx, b, m, gb + t, q, w);
+                const i32 w = WAVES_PER_U == 1 ? cur.once(G, roff, ridx, b, m, gb + t)
+                                               : cur.at(G, roff, ridx, b, m, gb + t);
+                q = cur.q;
                 val = hash_get(hk[grp], hc[grp], mask, w) - 1;
             }
             val = wave_seg_scan(val, q);
