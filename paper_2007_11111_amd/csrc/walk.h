@@ -272,16 +272,21 @@ __device__ __forceinline__ void bmap_insert(BucketMap<B>& m, i32 v, i32 position
 
 template <int B>
 __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
+    // keys are distinct, so at most one term of `hit` is non-zero; the sum
+    // needs all four keys, which keeps a bucket a single 16-byte read.  The
+    // first bucket decides almost every lookup; only a full bucket without
+    // the key sends the lane on to the next ones.
     u32 b = bucket_of<B>(v);
-    while (true) {
-        const int4 q = m.key[b];
-        // keys are distinct, so at most one term is non-zero; the sum needs all
-        // four keys, which keeps the bucket a single 16-byte read
-        const int hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
-        if (hit) return m.pos[4 * b + hit - 1];
-        if (q.w == -1) return -1;
-        b = (b + 1) & ((1u << B) - 1);
+    int4 q = m.key[b];
+    int hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
+    if (!hit && q.w != -1) {
+        do {
+            b = (b + 1) & ((1u << B) - 1);
+            q = m.key[b];
+            hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
+        } while (!hit && q.w != -1);
     }
+    return hit ? (i32)m.pos[4 * b + hit - 1] : -1;
 }
 
 }  // namespace fglt
