@@ -276,6 +276,18 @@ __device__ __forceinline__ u32 c4h_slot(i32 w) { return ((u32)w * 2654435761u) >
 
 __device__ __forceinline__ void c4h_add(u32* tab, i32 w, int cb) {
     u32 h = c4h_slot(w);
+    {  // the first slot in straight-line code; the loop below only on a collision
+        u32 e = tab[h];
+        if (e == 0) {
+            e = atomicCAS(&tab[h], 0u, ((u32)w << cb) | 1u);
+            if (e == 0) return;
+        }
+        if ((e >> cb) == (u32)w) {
+            atomicAdd(&tab[h], 1u);
+            return;
+        }
+        h = (h + 1) & (C4H_SLOTS - 1);
+    }
     while (true) {
         u32 e = tab[h];
         if (e == 0) {
@@ -293,12 +305,14 @@ __device__ __forceinline__ void c4h_add(u32* tab, i32 w, int cb) {
 
 __device__ __forceinline__ u32 c4h_get(const u32* tab, i32 w, int cb) {
     u32 h = c4h_slot(w);
-    while (true) {
-        const u32 e = tab[h];
-        if (e == 0) return 0;
-        if ((e >> cb) == (u32)w) return e & ((1u << cb) - 1u);
-        h = (h + 1) & (C4H_SLOTS - 1);
+    u32 e = tab[h];
+    if (e != 0 && (e >> cb) != (u32)w) {
+        do {
+            h = (h + 1) & (C4H_SLOTS - 1);
+            e = tab[h];
+        } while (e != 0 && (e >> cb) != (u32)w);
     }
+    return e & ((1u << cb) - 1u);  // 0 for an empty slot
 }
 
 __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict__ roff, const i32* __restrict__ ridx,

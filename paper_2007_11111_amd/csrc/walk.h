@@ -211,26 +211,31 @@ __device__ __forceinline__ u64 wave_transpose64(u64 m) {
 __device__ __forceinline__ u32 hslot(i32 w, u32 mask) { return ((u32)w * 2654435761u) & mask; }
 
 // Counting hash (open addressing, linear probing, keys -1 when empty).
+// The first slot is probed in straight-line code (it decides almost every
+// call at the tables' load); only a slot held by another key sends the lane
+// on to the next ones.
 __device__ __forceinline__ void hash_add(i32* keys, i32* cnts, u32 mask, i32 w) {
     u32 h = hslot(w, mask);
-    while (true) {
-        const i32 old = atomicCAS(&keys[h], -1, w);
-        if (old == -1 || old == w) {
-            atomicAdd(&cnts[h], 1);
-            return;
-        }
-        h = (h + 1) & mask;
+    i32 old = atomicCAS(&keys[h], -1, w);
+    if (old != -1 && old != w) {
+        do {
+            h = (h + 1) & mask;
+            old = atomicCAS(&keys[h], -1, w);
+        } while (old != -1 && old != w);
     }
+    atomicAdd(&cnts[h], 1);
 }
 
 __device__ __forceinline__ i32 hash_get(const i32* keys, const i32* cnts, u32 mask, i32 w) {
     u32 h = hslot(w, mask);
-    while (true) {
-        const i32 k = keys[h];
-        if (k == w) return cnts[h];
-        if (k == -1) return 0;
-        h = (h + 1) & mask;
+    i32 k = keys[h];
+    if (k != w && k != -1) {
+        do {
+            h = (h + 1) & mask;
+            k = keys[h];
+        } while (k != w && k != -1);
     }
+    return k == w ? cnts[h] : 0;
 }
 
 // Position map of up to 2^B distinct vertex ids in 2^B buckets of 4 slots:
