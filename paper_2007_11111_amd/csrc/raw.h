@@ -69,7 +69,8 @@ struct RawWs {
     L2Rec* l2rec; // [n] p2, c3 and degree of each vertex, for row pass 2
     i32* ridx;    // [nnz]
     i32* rrow;    // [nnz] row of each entry (rank space)
-    i32* rpos;    // [nnz] N- entry (u, v): position of u in row v; N+ entry (u, v): ~(position of u in row v)
+    i32* rpos;    // [nnz] N- entry (u, v): position of u in row v; -1 for N+ entries
+    i64* mir;     // [nnz] position of each entry's mirror (v, u)
     i64* G;       // [nnz+1] exclusive scan of per-entry work counts
     i32* C3;      // [nnz] triangle count per directed entry
     i64* ek;      // [max(nnz, n)] clique pass: packed 4-clique / diamond counts of the N+ entry (u, v)

@@ -131,31 +131,26 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
 // C3 of each N- entry copied from its mirror, and the row sums C3 e = 2 c3
 // (each triangle at v lies on two of its edges; Lemma 2).  When the clique
 // pass stores per-entry counts, their slots are cleared here.
-__global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                const i32* __restrict__ rpos, const i32* __restrict__ rrow,
-                                                i64 nnz, i32* __restrict__ C3, i64* __restrict__ c3x2,
-                                                i64* __restrict__ ek) {
+__global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ mir, const i32* __restrict__ ridx,
+                                                const i32* __restrict__ rrow, i64 nnz, i32* __restrict__ C3,
+                                                i64* __restrict__ c3x2, i64* __restrict__ ek) {
     row_chunks(nnz, [&](const i64* p) {
-        i32 r[RP_CH], rp[RP_CH], j[RP_CH], cv[RP_CH];
-        i64 rj[RP_CH];
+        i32 r[RP_CH], cv[RP_CH];
+        bool lower[RP_CH];
+        i64 src[RP_CH];
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const i64 q = p[c] < nnz ? p[c] : nnz - 1;
             r[c] = rrow[q];
-            rp[c] = rpos[q];
-            j[c] = ridx[q];
+            lower[c] = ridx[q] < r[c];  // an N- entry takes its mirror's count, an N+ entry keeps its own
+            src[c] = lower[c] ? mir[q] : q;
         }
 #pragma unroll
-        for (int c = 0; c < RP_CH; ++c) rj[c] = roff[j[c]];
-#pragma unroll
-        for (int c = 0; c < RP_CH; ++c) {
-            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
-            cv[c] = C3[rp[c] >= 0 ? rj[c] + rp[c] : q];  // an N+ entry keeps its own count
-        }
+        for (int c = 0; c < RP_CH; ++c) cv[c] = C3[src[c]];
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const bool act = p[c] < nnz;
-            if (act && rp[c] >= 0) C3[p[c]] = cv[c];
+            if (act && lower[c]) C3[p[c]] = cv[c];
             if (act && ek) ek[p[c]] = 0;
             add_run(c3x2, r[c], act ? cv[c] : 0, wave_runs(r[c], act));
         }
@@ -498,8 +493,8 @@ hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
 
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.rpos,
-                       w.rrow, nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
+    hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.mir, w.ridx, w.rrow,
+                       nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
     return hipGetLastError();
 }
 

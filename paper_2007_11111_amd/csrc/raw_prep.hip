@@ -177,15 +177,15 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
     if (err) atomicOr(&plan->err, err);
 }
 
-// rpos / work count per entry; duplicate and symmetry checks.
+// rpos / mirror / work count per entry; duplicate and symmetry checks.
 //   N- entry (u, v), v < u: rpos = position of u in row v (= number of
-//     neighbours of v below u, the wedge count of the 4-cycle pass);
-//   N+ entry (v, u), u > v: rpos = ~(position of v in row u), written by the
-//     thread of its mirror (u, v); work = d+(u) (the triangle pass).
+//     neighbours of v below u, the wedge count of the 4-cycle pass); the
+//     binary search that finds it gives both mirror positions;
+//   N+ entry (v, u), u > v: rpos = -1, work = d+(u) (the triangle pass).
 //   A diagonal entry gets rpos = -1 (the input check rejects it).
-//   rpos >= 0 marks the N- entries; ~rpos of an N+ entry locates its mirror.
 __global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
-                       i64 nnz, i32* __restrict__ rpos, i64* __restrict__ G, DevPlan* plan) {
+                       i64 nnz, i32* __restrict__ rpos, i64* __restrict__ mir, i64* __restrict__ G,
+                       DevPlan* plan) {
     u32 err = 0;
     for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
         {
@@ -200,15 +200,16 @@ __global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ri
                 i32 rp = 0;  // on an asymmetric input: harmless, no wedges (the run stops there)
                 if (q < e && ridx[q] == (i32)u) {
                     rp = (i32)(q - rv.off);
-                    rpos[q] = ~(i32)(p - vrec[u].off);  // the mirror (v, u) learns where (u, v) sits
+                    mir[p] = q;
+                    mir[q] = p;  // the mirror (v, u) learns where (u, v) sits
                 } else {
                     err |= ERR_ASYM;
+                    mir[p] = p;  // harmless: the run stops at the input check
                 }
                 rpos[p] = rp;
                 work = rp;
-            } else if ((i64)v > u) {
-                work = rv.deg - rv.lo;  // rpos[p] comes from the mirror's thread
             } else {
+                if ((i64)v > u) work = rv.deg - rv.lo;  // mir[p] comes from the mirror's thread
                 rpos[p] = -1;
             }
             G[p] = work;
@@ -336,7 +337,7 @@ hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream
     hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.vrec, w.plan);
     if (nnz > 0)
         hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.vrec, w.ridx, w.rrow, nnz,
-                           w.rpos, w.G, w.plan);
+                           w.rpos, w.mir, w.G, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive_i64(w.G, w.G, nnz, w.partials, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, TT, 256)), dim3(TT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,
@@ -363,6 +364,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.l2rec = c.take<L2Rec>(nn);
     w.ridx = c.take<i32>(nnz);
     w.rpos = c.take<i32>(nnz);
+    w.mir = c.take<i64>(nnz);
     w.rrow = c.take<i32>(nnz);
     w.G = c.take<i64>(nnz + 1);
     w.C3 = c.take<i32>(nnz);

@@ -265,7 +265,7 @@ __device__ __forceinline__ i64 c3_minus_1(const i32* __restrict__ ridx, const i3
 static constexpr int T2_TASK = 8;  // vertices a wavefront takes at a time
 
 __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
-                                                   const i32* __restrict__ rpos, const i32* __restrict__ list,
+                                                   const i64* __restrict__ mir, const i32* __restrict__ list,
                                                    u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                    i64* __restrict__ d13, i64* __restrict__ ek,
                                                    const u64* __restrict__ bstore, const i64* __restrict__ boff) {
@@ -330,12 +330,13 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec
             const i32 off_g = __shfl(excl, g, WAVE);
             const i32 k = lane - off_g;
             u64 Bk = 0;
-            i32 vk = 0, c3k = 0, mk = 0;
+            i32 vk = 0, c3k = 0;
+            i64 mk = 0;
             if (act) {
                 Bk = bstore[bo + k] << off_g;
                 vk = ridx[bu + k];
                 c3k = C3[bu + k];
-                mk = ~rpos[bu + k];  // position of u in row v_k
+                mk = mir[bu + k];  // the entry (v_k, u)
             }
             const u64 Ak = Bk | wave_transpose64(Bk);
             sA[wid][lane] = Ak;
@@ -345,10 +346,9 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec
             lds_put(reinterpret_cast<i32*>(&sdv[wid][lane]), 0);
             wave_lds_fence();
             u32 tk = 0, dk = 0;
-            i64 R = 0, du = 0, rk_off = 0;
+            i64 R = 0, du = 0;
             if (act) {
                 const VRec rec = vrec[vk];
-                rk_off = rec.off;
                 i64 from = rec.off + rec.lo;
                 const i64 end = rec.off + rec.deg;
                 const u32 ck = (u32)(c3k - 1);
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec
             if (act) {
                 const i64 kv = (i64)((tk + st2[wid][lane]) >> 1);
                 const i64 dv = (i64)dk + sdv[wid][lane];
-                if (kv | dv) ek[rk_off + mk] = (dv << EK_SHIFT) | kv;
+                if (kv | dv) ek[mk] = (dv << EK_SHIFT) | kv;
             }
             // per-vertex totals: runs of equal g among the active lanes
             const WaveRuns wr = wave_runs(g, act);
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec
 // comes from k_tri2_du_lds (a search per edge here costs more than walking
 // the out-lists again).
 __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                  const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                  const i32* __restrict__ lo, const i64* __restrict__ mir,
                                                   const i32* __restrict__ list, u32 count,
                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                   i64* __restrict__ ek,
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
         const int k = threadIdx.x;
         if (k < D) {
             const i64 kv = t2[k] >> 1, dv = dvs[k];
-            if (kv | dv) ek[roff[L[k]] + ~rpos[bu + k]] = (dv << EK_SHIFT) | kv;
+            if (kv | dv) ek[mir[bu + k]] = (dv << EK_SHIFT) | kv;
         }
         if (threadIdx.x == 0 && red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(red[0] / 3));
         __syncthreads();
@@ -569,9 +569,9 @@ hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s,
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE * T2_TASK)), dim3(WT), 0, s, w.vrec, w.ridx,
-                           w.rpos, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
+                           w.mir, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
     if (tier == 1 && c1) {
-        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.rpos,
+        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.mir,
                            w.tri_list + n, c1, w.C3, w.k4v, w.ek, w.bstore, w.boff);
         hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.d13);
