@@ -34,23 +34,25 @@ static constexpr int PT = 256;
 // Wedge items of vertex u (N- entries in [b, m)), visited in increasing
 // order g: the entry q = (u, v) holding item g is found by one binary search
 // over the work prefix G for the first item, then by moving forward; the
-// wedge end is w = the (g - G[q])-th neighbour of v.
+// wedge end is w = the (g - G[q])-th neighbour of v.  Row v starts at
+// mir[q] - rpos[q] (the mirror (v, u) sits rpos[q] = G[q+1] - G[q] entries
+// into it), so no lookup of v's row is needed.
 struct WedgeCursor {
     i64 q = -1, qs = 0, qe = 0, rs = 0;  // entry, its items [qs, qe), row start of its middle
     // item g alone: one binary search (no cursor state kept)
-    __device__ __forceinline__ i32 once(const i64* __restrict__ G, const i64* __restrict__ roff,
+    __device__ __forceinline__ i32 once(const i64* __restrict__ G, const i64* __restrict__ mir,
                                         const i32* __restrict__ ridx, i64 b, i64 m, i64 g) {
         q = last_le_dev(G, b, m - 1, g);
-        return ridx[roff[ridx[q]] + (g - G[q])];
+        return ridx[mir[q] - G[q + 1] + g];
     }
-    __device__ __forceinline__ i32 at(const i64* __restrict__ G, const i64* __restrict__ roff,
+    __device__ __forceinline__ i32 at(const i64* __restrict__ G, const i64* __restrict__ mir,
                                       const i32* __restrict__ ridx, i64 b, i64 m, i64 g) {
         if (q < 0 || g >= qe) {
             q = q < 0 ? last_le_dev(G, b, m - 1, g) : q + 1;
             while (G[q + 1] <= g) ++q;  // skip middles without wedges
             qs = G[q];
             qe = G[q + 1];
-            rs = roff[ridx[q]];
+            rs = mir[q] - (qe - qs);
         }
         return ridx[rs + (g - qs)];
     }
@@ -62,6 +64,7 @@ struct WedgeCursor {
 template <int WAVES_PER_U, int HSLOTS>
 __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                 const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                const i64* __restrict__ mir,
                                                 const i32* __restrict__ list, u32 count, i64* __restrict__ c4v) {
     constexpr int NW = PT / WAVE;
     constexpr int GROUPS = NW / WAVES_PER_U;  // vertices per block
@@ -105,8 +108,8 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
             for (i64 s = 0; s < ipt; ++s) {
                 const i64 t = t0 + s * ts;
                 if (t >= W) break;
-                const i32 w = WAVES_PER_U == 1 ? cur.once(G, roff, ridx, b, m, gb + t)
-                                               : cur.at(G, roff, ridx, b, m, gb + t);
+                const i32 w = WAVES_PER_U == 1 ? cur.once(G, mir, ridx, b, m, gb + t)
+                                               : cur.at(G, mir, ridx, b, m, gb + t);
                 hash_add(hk[grp], hc[grp], mask, w);
             }
         }
@@ -121,8 +124,8 @@ __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, co
             const bool act = t < W;
             i64 q = -1, val = 0;
             if (act) {
-                const i32 w = WAVES_PER_U == 1 ? cur.once(G, roff, ridx, b, m, gb + t)
-                                               : cur.at(G, roff, ridx, b, m, gb + t);
+                const i32 w = WAVES_PER_U == 1 ? cur.once(G, mir, ridx, b, m, gb + t)
+                                               : cur.at(G, mir, ridx, b, m, gb + t);
                 q = cur.q;
                 val = hash_get(hk[grp], hc[grp], mask, w) - 1;
             }
@@ -317,6 +320,7 @@ __device__ __forceinline__ u32 c4h_get(const u32* tab, i32 w, int cb) {
 
 __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                            const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                           const i64* __restrict__ mir,
                                                            const i32* __restrict__ list, u32 count,
                                                            u32* __restrict__ job_ctr, int cb, i64* __restrict__ c4v) {
     __shared__ u32 tab[C4H_SLOTS];
@@ -341,8 +345,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict
         const i32 L = lo[u];
         const i32 nch = (L + CB_THREADS - 1) / CB_THREADS;
         auto run_of = [&](i32 k, i64& s0, i32& len) {
-            s0 = roff[ridx[b + k]];
             len = rpos[b + k];  // neighbours of the middle below u: the first rpos entries of its row
+            s0 = mir[b + k] - len;
         };
         // pass A: count the wedge ends
         i32 T = 0;
@@ -469,6 +473,7 @@ __device__ __forceinline__ i64 wave_last_le(const i64* __restrict__ a, i64 cnt, 
 template <bool PACK16, bool TAB>
 __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                          const i64* __restrict__ mir,
                                                           const i32* __restrict__ tab, i64 K1,
                                                           const i32* __restrict__ hs, u32 nh,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
@@ -521,8 +526,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         i64 mrs = 0, mhi = 0;
         if (single && (i32)threadIdx.x < L) {
             mv = ridx[b + threadIdx.x];
-            mrs = roff[mv];
             mcut = rpos[b + threadIdx.x];
+            mrs = mir[b + threadIdx.x] - mcut;
             mhi = mrs + mcut;
         }
         i64 accu = 0;
@@ -537,8 +542,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     len = (i32)(mhi - a0);
                     mhi = a0;
                 } else {
-                    const i64 rs = roff[ridx[b + k]];
                     const i32 cut = rpos[b + k];
+                    const i64 rs = mir[b + k] - cut;
                     if (TAB) {
                         const i64 vrow = (i64)ridx[b + k] * K1;
                         const i32 a0 = std::min(tab[vrow + win], cut);
@@ -730,15 +735,15 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
         if ((e = hipMemsetAsync(w.c4_jobctr, 0, 2 * sizeof(u32), s)) != hipSuccess) return e;
     tm.mark(FGLT_SEG_C4_WAVE, s);
     if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                               w.G, w.c4_list, c0, w.c4v);
+                               w.G, w.mir, w.c4_list, c0, w.c4v);
     tm.mark(FGLT_SEG_C4_BLOCK, s);
     if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               w.lo, w.G, w.c4_list + n, c1, w.c4v);
+                               w.lo, w.G, w.mir, w.c4_list + n, c1, w.c4v);
     tm.mark(FGLT_SEG_C4_HASH, s);
     if (c2) {
         const int cb = 32 - std::max(1, bits_for_n(n));
         hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
-                           w.rpos, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
+                           w.rpos, w.mir, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
     }
     if (!c3) tm.mark(FGLT_SEG_C4_WINDOW, s);
     if (c3) {
@@ -758,7 +763,7 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
         tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
         const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
 #define C4W_LAUNCH(P16, TB)                                                                                    \
-    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
+    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, w.mir, \
                        w.c4_tab, K1, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
         if (pack16 && use_tab) C4W_LAUNCH(true, true);
         else if (pack16) C4W_LAUNCH(true, false);
