@@ -37,7 +37,6 @@ HBM_PEAK_GBPS = 8000.0
 # Algorithmic bytes per unit of work of each counting segment (see the kernel
 # notes in the sources): unit, bytes per unit.
 SEG_UNITS = {
-    "l1": ("entry", 8),          # index + gathered degree per directed entry
     "l2": ("entry", 36),         # row, index, C3, degree, p2 and c3 of the neighbour, clique counts
     "tri1_wave": ("item", 4),    # one out-list index per merge item
     "tri1_lds": ("item", 4),
@@ -49,7 +48,7 @@ SEG_UNITS = {
     "c4_block": ("wedge", 8),
     "c4_hash": ("wedge", 8),
     "c4_window": ("wedge", 8),
-    "fill": ("entry", 12),       # mirror position, index, C3 copy
+    "fill": ("entry", 16),       # row, index, mirror's C3, gathered degree
     "finalize": ("vertex", 232), # 13 accumulators + degree + id in, 128 B row out
 }
 
@@ -70,7 +69,7 @@ def seg_units(seg, st):
 SEG_KERNEL = {
     "c4_window": "k_c4_window", "c4_hash": "k_c4_hashbig", "c4_block": "k_c4_hash<4, 4096>",
     "c4_wave": "k_c4_hash<1, 256>", "tri1_wave": "k_tri1_wave", "tri1_lds": "k_tri1_lds",
-    "tri2_wave": "k_tri2s_wave", "l1": "k_l1", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
+    "tri2_wave": "k_tri2s_wave", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
 }
 
 

@@ -61,11 +61,11 @@ enum {
     FGLT_SEG_CHECK = 0,      /* input checks and the first synchronization      */
     FGLT_SEG_RELABEL,        /* degree ranking, relabelled and re-sorted rows    */
     FGLT_SEG_STRUCTURE,      /* N-/N+ split, mirror positions, work counts, tiers */
-    FGLT_SEG_L1,             /* row pass 1: A p1, A (p1-1)(p1-2)/2               */
     FGLT_SEG_TRI1_WAVE,      /* triangle pass (C3), wavefront tier                */
     FGLT_SEG_TRI1_LDS,       /* triangle pass, workgroup/LDS tier                 */
     FGLT_SEG_TRI1_GLOBAL,    /* triangle pass, workgroup/global-bitmap tier       */
-    FGLT_SEG_FILL,           /* C3 mirrored to the lower entries, c3 by row sums  */
+    FGLT_SEG_FILL,           /* C3 mirrored to the lower entries, c3 by row sums,
+                                row pass 1: A p1, A (p1-1)(p1-2)/2               */
     FGLT_SEG_TRI2_WAVE,      /* clique/diamond pass, wavefront tier               */
     FGLT_SEG_TRI2_LDS,       /* clique/diamond pass, LDS-bitmap tier              */
     FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */

@@ -85,8 +85,6 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     // 3. counting
     FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
-    tm.mark(FGLT_SEG_L1, s);
-    FGLT_HIP_TRY(launch_l1(n, nnz, w, s));
     // the clique pass reuses the triangle pass's bitmaps when the workspace holds them
     const bool stored = bitmap_words <= w.bstore_cap;
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));

@@ -131,7 +131,6 @@ struct SegTimer {
     }
 };
 
-hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s);
 // tri.hip
 hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s);
 hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier);

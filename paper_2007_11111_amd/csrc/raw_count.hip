@@ -1,9 +1,9 @@
 // raw_count.hip -- the counting passes of the transform, in rank space.
 //
-//   L1  row pass:   sum_j d_j (-> p2 = A p1 - p1) and sum_j C(d_j - 1, 2) (-> \hat d_7)
 //   TRI mode 1:     oriented triangle listing per vertex u over N+(u); C3 on
 //                   every oriented edge (C3 = A .* A^2, Lemma 2)
-//   FILL:           C3 copied to the mirrored entries; row sums 2 c3 = C3 e
+//   FILL:           C3 copied to the mirrored entries; row sums 2 c3 = C3 e, and row
+//                   pass 1: sum_j d_j (-> p2 = A p1 - p1), sum_j C(d_j - 1, 2) (-> \hat d_7)
 //   TRI mode 2:     the induced subgraph on N+(u) as LDS bitmaps; per vertex
 //                   4-cliques (T e / 6, Section IV-C) and off-cord diamonds
 //                   (D4,c e / 2) attributed to all four / three vertices
@@ -52,30 +52,6 @@ __device__ __forceinline__ void row_chunks(i64 nnz, F&& f) {
 __device__ __forceinline__ void add_run(i64* acc, i32 r, i64 v, const WaveRuns& w) {
     const i64 t = run_total(v, w);
     if (w.tail && t) atomicAdd((unsigned long long*)&acc[r], (unsigned long long)t);
-}
-
-__global__ void __launch_bounds__(PT) k_l1(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
-                                           const i32* __restrict__ rdeg, i64 nnz, i64* __restrict__ sumd,
-                                           i64* __restrict__ s7) {
-    row_chunks(nnz, [&](const i64* p) {
-        i32 r[RP_CH], j[RP_CH], dj[RP_CH];
-#pragma unroll
-        for (int c = 0; c < RP_CH; ++c) {
-            const i64 q = p[c] < nnz ? p[c] : nnz - 1;
-            r[c] = rrow[q];
-            j[c] = ridx[q];
-        }
-#pragma unroll
-        for (int c = 0; c < RP_CH; ++c) dj[c] = rdeg[j[c]];
-#pragma unroll
-        for (int c = 0; c < RP_CH; ++c) {
-            const bool act = p[c] < nnz;
-            const WaveRuns w = wave_runs(r[c], act);
-            const i64 d = act ? dj[c] : 0;
-            add_run(sumd, r[c], d, w);                          // A p1
-            add_run(s7, r[c], act ? (d - 1) * (d - 2) / 2 : 0, w);  // sum_j C(d_j - 1, 2)
-        }
-    });
 }
 
 // After the clique pass: A p2, A c3, C3 (p1 - 2) and C(C3, 2) by rows
@@ -128,31 +104,42 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
     });
 }
 
-// C3 of each N- entry copied from its mirror, and the row sums C3 e = 2 c3
-// (each triangle at v lies on two of its edges; Lemma 2).  When the clique
-// pass stores per-entry counts, their slots are cleared here.
+// After the triangle pass: C3 of each N- entry copied from its mirror, the
+// row sums C3 e = 2 c3 (each triangle at v lies on two of its edges;
+// Lemma 2), and row pass 1 of Table I: A p1 and sum_j C(d_j - 1, 2).  When
+// the clique pass stores per-entry counts, their slots are cleared here.
 __global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ mir, const i32* __restrict__ ridx,
-                                                const i32* __restrict__ rrow, i64 nnz, i32* __restrict__ C3,
-                                                i64* __restrict__ c3x2, i64* __restrict__ ek) {
+                                                const i32* __restrict__ rrow, const i32* __restrict__ rdeg,
+                                                i64 nnz, i32* __restrict__ C3, i64* __restrict__ c3x2,
+                                                i64* __restrict__ sumd, i64* __restrict__ s7,
+                                                i64* __restrict__ ek) {
     row_chunks(nnz, [&](const i64* p) {
-        i32 r[RP_CH], cv[RP_CH];
+        i32 r[RP_CH], j[RP_CH], cv[RP_CH], dj[RP_CH];
         bool lower[RP_CH];
         i64 src[RP_CH];
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const i64 q = p[c] < nnz ? p[c] : nnz - 1;
             r[c] = rrow[q];
-            lower[c] = ridx[q] < r[c];  // an N- entry takes its mirror's count, an N+ entry keeps its own
+            j[c] = ridx[q];
+            lower[c] = j[c] < r[c];  // an N- entry takes its mirror's count, an N+ entry keeps its own
             src[c] = lower[c] ? mir[q] : q;
         }
 #pragma unroll
-        for (int c = 0; c < RP_CH; ++c) cv[c] = C3[src[c]];
+        for (int c = 0; c < RP_CH; ++c) {
+            cv[c] = C3[src[c]];
+            dj[c] = rdeg[j[c]];
+        }
 #pragma unroll
         for (int c = 0; c < RP_CH; ++c) {
             const bool act = p[c] < nnz;
             if (act && lower[c]) C3[p[c]] = cv[c];
             if (act && ek) ek[p[c]] = 0;
-            add_run(c3x2, r[c], act ? cv[c] : 0, wave_runs(r[c], act));
+            const WaveRuns w = wave_runs(r[c], act);
+            const i64 d = act ? dj[c] : 0;
+            add_run(c3x2, r[c], act ? cv[c] : 0, w);
+            add_run(sumd, r[c], d, w);                              // A p1
+            add_run(s7, r[c], act ? (d - 1) * (d - 2) / 2 : 0, w);  // sum_j C(d_j - 1, 2)
         }
     });
 }
@@ -476,13 +463,6 @@ __global__ void k_net(i64 n, const i64* __restrict__ raw, i64* __restrict__ net)
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_l1(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
-    if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l1, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.rdeg, nnz,
-                       w.sumd, w.s7);
-    return hipGetLastError();
-}
-
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_l2_rec, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.sumd, w.c3x2, w.l2rec);
@@ -494,7 +474,7 @@ hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.mir, w.ridx, w.rrow,
-                       nnz, w.C3, w.c3x2, stored ? w.ek : nullptr);
+                       w.rdeg, nnz, w.C3, w.c3x2, w.sumd, w.s7, stored ? w.ek : nullptr);
     return hipGetLastError();
 }
 
