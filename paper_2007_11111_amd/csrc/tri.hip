@@ -6,23 +6,26 @@
 //   stream (coalesced, 64 consecutive items per wavefront step); each item y
 //   is looked up in an LDS position map of N+(u).  A hit at position l is a
 //   triangle (u, v_k, v_l): bit l of row k of the bitmap B (the induced
-//   subgraph on N+(u)) is set, and C3 of (v_k, v_l) counted by one global
+//   subgraph H on N+(u)) is set, and C3 of (v_k, v_l) counted by one global
 //   atomic; C3 of the edges (u, v_k) follows from B's rows and columns.  B is
-//   stored for the clique pass when the workspace holds it.
-// Clique / diamond pass from stored bitmaps: B is reloaded, its transpose C
-//   built in LDS, and every 4-clique {u < a < b < c} and every off-cord
+//   stored for the clique pass when the workspace holds it.  The wave tier
+//   packs several small vertices into one wavefront.
+// Clique / diamond pass from stored bitmaps: B is reloaded and A = B | B^T
+//   formed; every edge (k, l) of H lies on |A_k & A_l| triangles of H, each a
+//   4-clique with u, so every 4-clique {u < a < b < c} and every off-cord
 //   diamond of a triangle with lowest vertex u is attributed to its vertices
 //   (Section IV-C: T e / 6 and D4,c e / 2 without forming T or D4,c).  The
-//   diamond term of u needs C3 of the edge (v_k, v_l), found by a binary
-//   search of v_l in N+(v_k).  The counts of the N+ vertices are stored at the
-//   mirrored entries and summed by rows afterwards (no per-entry atomics).
+//   diamond term of u needs C3 of the edge (v_k, v_l): a galloping search of
+//   v_l in N+(v_k) in the wave tier, a second walk of the out-lists in the LDS
+//   tier.  The counts of the N+ vertices are stored at the mirrored entries
+//   and summed by rows afterwards (no per-entry atomics).
 #include <algorithm>
 
 #include "walk.h"
 
 namespace fglt {
 
-static constexpr int WT = 256;  // wave-tier block: 4 wavefronts, one vertex each
+static constexpr int WT = 256;  // wave-tier block: 4 independent wavefronts
 static constexpr int LT = 512;  // LDS-tier block: 8 wavefronts on one vertex
 
 // ------------------------------------------------------------------ triangle pass
