@@ -196,7 +196,6 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         const i32 T = (i32)(G[bu + D] - gb);
         bmap_clear(pm, threadIdx.x, LT);
         for (int q = threadIdx.x; q < D * W; q += LT) B[q] = 0;
-        if (threadIdx.x < D) Cnt[threadIdx.x] = 0;
         __syncthreads();
         const int k = threadIdx.x;  // D <= DM == LT: one out-neighbour per thread
         i32 len = 0, pre = 0;
@@ -225,18 +224,26 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
                     [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
                         const i32 l = act ? bmap_find(pm, y) : -1;
                         const bool hit = l >= 0;
-                        if (hit) {
-                            const i32 kk = rk[r];
-                            atomicAdd(&Cnt[kk], 1);
-                            atomicAdd(&Cnt[l], 1);
-                            atomicOr((unsigned long long*)&B[kk * W + (l >> 6)], 1ull << (l & 63));
-                        }
+                        if (hit) atomicOr((unsigned long long*)&B[rk[r] * W + (l >> 6)], 1ull << (l & 63));
                         defer_c3(hit, e, sQ[wv], nq, C3, defer);
                     });
         __syncthreads();
         flush_c3(sQ[wv], nq, C3, lane_id(), WAVE);
+        // C3 of the edge (u, v_k): the triangles in row k of B plus those in
+        // column k, counted by 64 x 64 block transposes (wavefront bj takes
+        // the columns bj * 64 .. bj * 64 + 63, W <= LT / 64)
+        if (wv < W) {
+            i32 cc = 0;
+            for (int bi = 0; bi < W; ++bi) {
+                const int row = bi * 64 + lane_id();
+                cc += __popcll(wave_transpose64(row < D ? B[row * W + wv] : 0ull));
+            }
+            Cnt[wv * 64 + lane_id()] = cc;
+        }
+        __syncthreads();
         if (k < D) {
-            const i32 c = Cnt[k];
+            i32 c = Cnt[k];
+            for (int z = 0; z < W; ++z) c += __popcll(B[k * W + z]);
             if (c) atomicAdd(&C3[bu + k], c);
             if (store)
                 for (int z = 0; z < W; ++z) bstore[boff[u] + (i64)k * W + z] = B[k * W + z];
