@@ -486,7 +486,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
     __shared__ i64 sj, sh, red;
-    __shared__ i32 wlo, whi;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
     for (int q = threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
@@ -500,8 +499,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             sj = j;
             sh = h;
             red = 0;
-            wlo = INT_MAX;
-            whi = -1;
         }
     }
     __syncthreads();
@@ -557,11 +554,12 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     }
                 }
             };
-            // pass A: count the wedge ends inside the window, note the touched
-            // range; with packed counts, also copy the ends with their middles
-            // to the workgroup's scratch (chunk by chunk while they fit), so
-            // that pass C streams them instead of gathering the rows again
-            i32 T = 0, lmin = INT_MAX, lmax = -1;
+            // pass A: count the wedge ends inside the window; with packed
+            // counts, also copy the ends with their middles to the
+            // workgroup's scratch (chunk by chunk while they fit), so that
+            // pass C streams them instead of gathering the rows again
+            i32 T = 0;
+            i64 wtot = 0;     // wedges of the window (block-uniform)
             i64 toff = 0;     // scratch words used (block-uniform)
             u64 stored = 0;   // chunks whose ends are in the scratch
             for (i32 ch = 0; ch < nch; ++ch) {
@@ -579,8 +577,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                             [&](bool act, i32 t, i32 r, i32 w, i64, u64, i32) {
                                 if (act) {
                                     c4w_inc<PACK16>(cnt, w - W0);
-                                    lmin = min(lmin, w);
-                                    lmax = max(lmax, w);
                                     if (keep) dst[t] = ((u32)(k0 + R.rk[r]) << 16) | (u32)(w - W0);
                                 }
                             });
@@ -588,17 +584,11 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     stored |= 1ull << ch;
                     toff += T;
                 }
+                wtot += T;
                 if (!single) __syncthreads();  // the next chunk overwrites the runs
             }
-            lmin = wave_min_i32(lmin);
-            lmax = wave_max_i32(lmax);
-            if (l == 0 && lmax >= 0) {
-                atomicMin(&wlo, lmin);
-                atomicMax(&whi, lmax);
-            }
             __syncthreads();
-            const i32 xlo = wlo - W0, xhi = whi - W0;
-            if (xhi < xlo) continue;  // no wedge end in this window (block-uniform)
+            if (wtot == 0) continue;  // no wedge in this window (block-uniform)
             // pass C: c - 1 to the middle of every wedge, streamed from the
             // scratch, else gathered again (one chunk: its runs are still in LDS)
             for (i32 ch = 0; ch < nch; ++ch) {
@@ -621,13 +611,13 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             }
             // pass B: C(c, 2) to every end w and to u (after the gathers, so
             // that these atomics hold back no load of the walks).  A window
-            // with few wedges for its touched range goes over the scratch copy
-            // of its wedges: the first wedge of each end takes the end's count
-            // and clears it, which also leaves the counters zero for the next
-            // window.  Otherwise the touched range is read word by word, then
-            // cleared.
+            // with fewer wedges than twice its counter words goes over the
+            // scratch copy of its wedges: the first wedge of each end takes the
+            // end's count and clears it, which also leaves the counters zero
+            // for the next window.  Otherwise the counters are read word by
+            // word, then cleared.
             const bool all_kept = nch <= MAXCH && stored == (nch == 64 ? ~0ull : ((1ull << nch) - 1));
-            const bool sparse = PACK16 && all_kept && toff < 2 * (i64)((xhi >> 1) - (xlo >> 1) + 1);
+            const bool sparse = PACK16 && all_kept && toff < 2 * (i64)C4W_WORDS;
             if (sparse) {
                 __syncthreads();  // every count has been read by pass C
                 for (i32 t = (i32)threadIdx.x; t < (i32)toff; t += CB_THREADS) {
@@ -642,7 +632,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     }
                 }
             } else if (PACK16) {  // word by word: two counts per word, most words zero
-                for (i32 q = (xlo >> 1) + (i32)threadIdx.x; q <= (xhi >> 1); q += CB_THREADS) {
+                for (i32 q = (i32)threadIdx.x; q < C4W_WORDS; q += CB_THREADS) {
                     const u32 wd = cnt[q];
                     if (wd == 0) continue;
 #pragma unroll
@@ -656,7 +646,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     }
                 }
             } else {
-                for (i32 x = xlo + (i32)threadIdx.x; x <= xhi; x += CB_THREADS) {
+                for (i32 x = (i32)threadIdx.x; x < C4W_WORDS; x += CB_THREADS) {
                     const i64 c = c4w_get<PACK16>(cnt, x);
                     if (c >= 2) {
                         const i64 pr = c * (c - 1) / 2;
@@ -667,12 +657,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             }
             __syncthreads();
             if (!sparse) {  // clear the touched counters for the next window
-                const i32 q0 = PACK16 ? xlo >> 1 : xlo, q1 = PACK16 ? xhi >> 1 : xhi;
-                for (i32 q = q0 + (i32)threadIdx.x; q <= q1; q += CB_THREADS) cnt[q] = 0;
-            }
-            if (threadIdx.x == 0) {
-                wlo = INT_MAX;
-                whi = -1;
+                for (i32 q = (i32)threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
             }
         }
         accu = wave_sum(accu);
