@@ -22,6 +22,7 @@
 // wavefront step, so the reads of each run are coalesced.
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "walk.h"
 
@@ -236,8 +237,11 @@ __device__ __forceinline__ void wave_share(i32 T, i32& ta, i32& tb) {
 // atomic sits between the gathers of the walk.
 // SMALL: every count is below 2^16, so a wavefront's prefix sums fit 32 bits
 // and the DPP scan applies.
-template <bool SMALL, class Get>
-__device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* __restrict__ ridx, i64* msum,
+__device__ __forceinline__ void lds_add(i64* p, i64 v) { atomicAdd((unsigned long long*)p, (unsigned long long)v); }
+__device__ __forceinline__ void lds_add(u32* p, i64 v) { atomicAdd(p, (u32)v); }  // sums below 2^32
+
+template <bool SMALL, class MS, class Get>
+__device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* __restrict__ ridx, MS* msum,
                                                   Get&& get) {
     i32 ta, tb;
     wave_share(T, ta, tb);
@@ -264,7 +268,7 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
                     const bool head = act && (l == 0 || ((mask >> l) & 1ull));
                     const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tend);
                     const i64 add = (tail ? P : 0) - (head ? P - val : 0);
-                    if (add) atomicAdd((unsigned long long*)&msum[R.rk[r]], (unsigned long long)add);
+                    if (add) lds_add(&msum[R.rk[r]], add);
                 });
 }
 
@@ -420,7 +424,7 @@ __device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
 // come from a DPP prefix sum and go to msum[middle - k0].  Four words in
 // flight per thread.
 __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs, i32 ce, i32 k0, const u32* cnt,
-                                             i64* msum) {
+                                             u32* msum) {
     constexpr int U = 4;
     const int l = lane_id();
     for (i32 b0 = cs; b0 < ce; b0 += U * CB_THREADS) {
@@ -430,23 +434,24 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
             const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
             iv[q] = t < ce ? sc[t] : 0u;
         }
-        const int nq = min(U, (ce - b0 + CB_THREADS - 1) / CB_THREADS);
-        for (int q = 0; q < nq; ++q) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (b0 + q * CB_THREADS >= ce) break;  // block-uniform
             const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
             const bool act = t < ce;
-            const i32 k = (i32)(iv[q] >> 16);
+            const u32 k = iv[q] >> 16;
             const u32 x = iv[q] & 0xffffu;
             const i32 val = act ? (i32)((cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu) - 1 : 0;
             const i32 P = wave_incl_scan_i32(val);
             // neighbours' middles by DPP wavefront shifts (lane 0 and lane 63 are ends anyway)
-            const i32 kp = __builtin_amdgcn_update_dpp(0, k, 0x138, 0xf, 0xf, false);  // wave_shr:1
-            const i32 kn = __builtin_amdgcn_update_dpp(0, k, 0x130, 0xf, 0xf, false);  // wave_shl:1
+            const u32 kp = (u32)__builtin_amdgcn_update_dpp(0, (i32)k, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const u32 kn = (u32)__builtin_amdgcn_update_dpp(0, (i32)k, 0x130, 0xf, 0xf, false);  // wave_shl:1
             const bool head = act && (l == 0 || kp != k);
             const bool tail = act && (l == WAVE - 1 || t + 1 >= ce || kn != k);
-            // a piece's sum is P(tail) - P(before its head): the tail adds P, the head
-            // takes away its exclusive prefix
-            const i64 add = (tail ? (i64)P : 0) - (head ? (i64)(P - val) : 0);
-            if (add) atomicAdd((unsigned long long*)&msum[k - k0], (unsigned long long)add);
+            // a piece's sum is P(tail) - P(before its head): the tail adds P, the
+            // head takes away its exclusive prefix (32-bit sums wrap consistently)
+            const u32 add = (tail ? (u32)P : 0u) - (head ? (u32)(P - val) : 0u);
+            if (add) atomicAdd(&msum[k - (u32)k0], add);
         }
     }
 }
@@ -482,14 +487,25 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     constexpr int MAXCH = 64;  // chunks of a vertex: |N-(u)| < 65536 when counts are packed
     __shared__ u32 cnt[C4W_WORDS];
     __shared__ RunLds R;
-    __shared__ i64 msum[CB_THREADS];
+    // middles' sums: with 16-bit counts a middle's sum stays below 2^32 (per
+    // window: at most 2^16 ends times counts below 2^16; over all windows of a
+    // one-chunk job: degree below 2^21 times counts below 2^10)
+    // With a scratch copy (16-bit counts), two buffers by chunk parity: a
+    // chunk's flush (each thread reads and clears its own entry) may still run
+    // while faster wavefronts stream the next chunk, which has no barrier
+    // before its atomics; the flush of that next chunk begins with one, so the
+    // chunk after it may reuse the buffer.  Gathered chunks start with a
+    // barrier of their own.
+    using MS = std::conditional_t<PACK16, u32, i64>;
+    constexpr int NMS = PACK16 ? 2 : 1;
+    __shared__ MS msum[NMS * CB_THREADS];
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
     __shared__ i64 sj, sh, red;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
     for (int q = threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
-    msum[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q < NMS * CB_THREADS; q += CB_THREADS) msum[q] = 0;
     if (wv == 0) {
         i64 j = 0;
         if (l == 0) j = atomicAdd(job_ctr, 1u);
@@ -592,20 +608,26 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             // pass C: c - 1 to the middle of every wedge, streamed from the
             // scratch, else gathered again (one chunk: its runs are still in LDS)
             for (i32 ch = 0; ch < nch; ++ch) {
-                if ((stored >> ch) & 1ull) {
-                    c4w_stream_c(sc, cst[ch], cst[ch + 1], ch * CB_THREADS, cnt, msum);
-                } else {
+                MS* const ms = msum + (ch % NMS) * CB_THREADS;
+                bool streamed = false;
+                if constexpr (PACK16) {  // only 16-bit counters keep a scratch copy
+                    if ((stored >> ch) & 1ull) {
+                        c4w_stream_c(sc, cst[ch], cst[ch + 1], ch * CB_THREADS, cnt, ms);
+                        streamed = true;
+                    }
+                }
+                if (!streamed) {
                     if (!single) T = flatten_runs(L, ch * CB_THREADS, run_of, R);
-                    attribute_middles<PACK16>(T, R, ridx, msum,
+                    attribute_middles<PACK16>(T, R, ridx, ms,
                                               [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
                 }
                 if (!single) {
                     __syncthreads();
                     const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
                     if (k < L) {
-                        const i64 m = msum[threadIdx.x];
+                        const i64 m = ms[threadIdx.x];
                         if (m) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)m);
-                        msum[threadIdx.x] = 0;
+                        ms[threadIdx.x] = 0;
                     }
                 }
             }
@@ -656,7 +678,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                 }
             }
             __syncthreads();
-            if (!sparse) {  // clear the touched counters for the next window
+            if (!sparse) {  // clear the counters for the next window
                 for (i32 q = (i32)threadIdx.x; q < C4W_WORDS; q += CB_THREADS) cnt[q] = 0;
             }
         }
