@@ -535,22 +535,25 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         // visited run (windows go top-down, so each run ends where the
         // previous window's run began); its LDS sum msum[k] collects the
         // middle's share over all windows
-        i32 mv = 0, mcut = 0;
+        // (with the window table, the table entry of the next window is loaded
+        // one window ahead)
+        i32 mv = 0, mcut = 0, tcur = 0, tnx = 0;
         i64 mrs = 0, mhi = 0;
         if (single && (i32)threadIdx.x < L) {
             mv = ridx[b + threadIdx.x];
             mcut = rpos[b + threadIdx.x];
             mrs = mir[b + threadIdx.x] - mcut;
             mhi = mrs + mcut;
+            if (TAB) tcur = tab[(i64)mv * K1 + wtop];
         }
         i64 accu = 0;
-        for (i32 win = wtop; win >= wbot; --win) {
+        for (i32 win = wtop; win >= wbot; --win, tcur = tnx) {
+            if (TAB && single && (i32)threadIdx.x < L && win > wbot) tnx = tab[(i64)mv * K1 + win - 1];
             const i32 W0 = win * WS;
             const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
             auto run_of = [&](i32 k, i64& s0, i32& len) {
                 if (single) {
-                    const i64 a0 = TAB ? mrs + std::min(tab[(i64)mv * K1 + win], mcut)
-                                       : lower_bound_dev(ridx, mrs, mhi, W0);
+                    const i64 a0 = TAB ? mrs + std::min(tcur, mcut) : lower_bound_dev(ridx, mrs, mhi, W0);
                     s0 = a0;
                     len = (i32)(mhi - a0);
                     mhi = a0;
@@ -642,15 +645,27 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             const bool sparse = PACK16 && all_kept && toff < 2 * (i64)C4W_WORDS;
             if (sparse) {
                 __syncthreads();  // every count has been read by pass C
-                for (i32 t = (i32)threadIdx.x; t < (i32)toff; t += CB_THREADS) {
-                    const u32 x = sc[t] & 0xffffu;
-                    const u32 sh = (x & 1u) << 4;
-                    const u32 old = atomicAnd(&cnt[x >> 1], ~(0xffffu << sh));
-                    const i64 c = (old >> sh) & 0xffffu;
-                    if (c >= 2) {
-                        const i64 pr = c * (c - 1) / 2;
-                        accu += pr;
-                        atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+                // four words in flight per thread: a load waits for the global
+                // atomics issued before it, so the loads go first
+                for (i32 t0 = (i32)threadIdx.x; t0 < (i32)toff; t0 += 4 * CB_THREADS) {
+                    u32 xv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const i32 t = t0 + q * CB_THREADS;
+                        xv[q] = t < (i32)toff ? sc[t] & 0xffffu : 0xffffffffu;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (xv[q] == 0xffffffffu) continue;
+                        const u32 x = xv[q];
+                        const u32 sh = (x & 1u) << 4;
+                        const u32 old = atomicAnd(&cnt[x >> 1], ~(0xffffu << sh));
+                        const i64 c = (old >> sh) & 0xffffu;
+                        if (c >= 2) {
+                            const i64 pr = c * (c - 1) / 2;
+                            accu += pr;
+                            atomicAdd((unsigned long long*)&c4v[W0 + x], (unsigned long long)pr);
+                        }
                     }
                 }
             } else if (PACK16) {  // word by word: two counts per word, most words zero

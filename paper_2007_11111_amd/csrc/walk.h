@@ -72,6 +72,23 @@ __device__ __forceinline__ u8 lds_get8(u8* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// Last index r in [0, R) with a[r] <= key, for a non-decreasing LDS array
+// with a[0] <= key and a key that is the same in every lane: each round the
+// 64 lanes probe evenly spaced entries, so R entries take about log64(R)
+// dependent LDS reads instead of log2(R).
+__device__ __forceinline__ i32 wave_last_le_lds(const i32* a, i32 R, i32 key) {
+    i32 lo_ = 0, hi_ = R;  // the answer lies in [lo_, hi_)
+    while (hi_ - lo_ > 1) {
+        const i32 step = (hi_ - lo_ + WAVE - 1) / WAVE;
+        const i32 p = lo_ + lane_id() * step;
+        const bool ok = p < hi_ && a[p] <= key;
+        const int c = __popcll(__ballot(ok));  // lanes 0 .. c-1 probe entries <= key
+        lo_ += (c - 1) * step;
+        hi_ = min(hi_, lo_ + step);
+    }
+    return lo_;
+}
+
 // The run walk, in groups of up to U steps of 64 items.  A group reads the
 // starts of the next 64 runs once (one per lane); it ends before the last of
 // them, so every item in it has a known run.  The run starts inside the group
@@ -89,7 +106,7 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
     const int l = lane_id();
     const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
     u8* const fb = reinterpret_cast<u8*>(flags);
-    i32 r0 = __builtin_amdgcn_readfirstlane((i32)last_le_dev(rstart, 0, R - 1, ta));  // run holding item ta
+    i32 r0 = __builtin_amdgcn_readfirstlane(wave_last_le_lds(rstart, R, ta));  // run holding item ta
     i32 t0 = ta;
     while (t0 < tb) {
         const i32 j = r0 + 1 + l;
