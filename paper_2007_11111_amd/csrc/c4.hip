@@ -546,6 +546,11 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             mhi = mrs + mcut;
             if (TAB) tcur = tab[(i64)mv * K1 + wtop];
         }
+        // more than one chunk: pass A loads the row data of the next chunk's
+        // middles (rpos, mir, ridx) while it walks the current chunk
+        i32 pc_cut = 0, pc_v = 0, pn_cut = 0, pn_v = 0;
+        i64 pc_mir = 0, pn_mir = 0;
+        bool prefetched = false;  // run_of takes the loaded values (pass A), else loads them
         i64 accu = 0;
         for (i32 win = wtop; win >= wbot; --win, tcur = tnx) {
             if (TAB && single && (i32)threadIdx.x < L && win > wbot) tnx = tab[(i64)mv * K1 + win - 1];
@@ -558,10 +563,10 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     len = (i32)(mhi - a0);
                     mhi = a0;
                 } else {
-                    const i32 cut = rpos[b + k];
-                    const i64 rs = mir[b + k] - cut;
+                    const i32 cut = prefetched ? pc_cut : rpos[b + k];
+                    const i64 rs = (prefetched ? pc_mir : mir[b + k]) - cut;
                     if (TAB) {
-                        const i64 vrow = (i64)ridx[b + k] * K1;
+                        const i64 vrow = (i64)(prefetched ? pc_v : ridx[b + k]) * K1;
                         const i32 a0 = std::min(tab[vrow + win], cut);
                         const i32 a1 = std::min(tab[vrow + win + 1], cut);
                         s0 = rs + a0;
@@ -581,8 +586,28 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             i64 wtot = 0;     // wedges of the window (block-uniform)
             i64 toff = 0;     // scratch words used (block-uniform)
             u64 stored = 0;   // chunks whose ends are in the scratch
+            prefetched = !single;
             for (i32 ch = 0; ch < nch; ++ch) {
+                if (!single) {
+                    const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
+                    if (ch == 0 && k < L) {
+                        pn_cut = rpos[b + k];
+                        pn_mir = mir[b + k];
+                        pn_v = ridx[b + k];
+                    }
+                    pc_cut = pn_cut;
+                    pc_mir = pn_mir;
+                    pc_v = pn_v;
+                }
                 T = flatten_runs(L, ch * CB_THREADS, run_of, R);
+                if (!single && ch + 1 < nch) {
+                    const i32 k = (ch + 1) * CB_THREADS + (i32)threadIdx.x;
+                    if (k < L) {
+                        pn_cut = rpos[b + k];
+                        pn_mir = mir[b + k];
+                        pn_v = ridx[b + k];
+                    }
+                }
                 const bool keep = PACK16 && ch < MAXCH && toff + T <= scr_cap;
                 if (keep && threadIdx.x == 0) {
                     cst[ch] = (i32)toff;
@@ -610,8 +635,11 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             if (wtot == 0) continue;  // no wedge in this window (block-uniform)
             // pass C: c - 1 to the middle of every wedge, streamed from the
             // scratch, else gathered again (one chunk: its runs are still in LDS)
+            prefetched = false;
             for (i32 ch = 0; ch < nch; ++ch) {
                 MS* const ms = msum + (ch % NMS) * CB_THREADS;
+                i32 fv = 0;  // the flush's middle, loaded before the chunk's wedges
+                if (!single && ch * CB_THREADS + (i32)threadIdx.x < L) fv = ridx[b + ch * CB_THREADS + threadIdx.x];
                 bool streamed = false;
                 if constexpr (PACK16) {  // only 16-bit counters keep a scratch copy
                     if ((stored >> ch) & 1ull) {
@@ -629,7 +657,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
                     if (k < L) {
                         const i64 m = ms[threadIdx.x];
-                        if (m) atomicAdd((unsigned long long*)&c4v[ridx[b + k]], (unsigned long long)m);
+                        if (m) atomicAdd((unsigned long long*)&c4v[fv], (unsigned long long)m);
                         ms[threadIdx.x] = 0;
                     }
                 }

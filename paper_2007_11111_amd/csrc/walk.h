@@ -18,28 +18,55 @@ namespace fglt {
     } while (0)
 
 
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP: shifts by
+// 1, 2, 4, 8 within each row of 16 lanes, then the row totals broadcast to
+// the rows above (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ __forceinline__ i32 wave_incl_scan_i32(i32 x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// The same scan for 64-bit values: both halves move together, the sum carries.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ i64 dpp_add_i64(i64 x) {
+    const u32 lo_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)x, CTRL, ROWS, 0xf, false);
+    const u32 hi_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)((u64)x >> 32), CTRL, ROWS, 0xf, false);
+    return x + (i64)(((u64)hi_ << 32) | lo_);
+}
+__device__ __forceinline__ i64 wave_incl_scan_i64(i64 x) {
+    x = dpp_add_i64<0x111, 0xf>(x);  // row_shr:1
+    x = dpp_add_i64<0x112, 0xf>(x);  // row_shr:2
+    x = dpp_add_i64<0x114, 0xf>(x);  // row_shr:4
+    x = dpp_add_i64<0x118, 0xf>(x);  // row_shr:8
+    x = dpp_add_i64<0x142, 0xa>(x);  // row_bcast:15
+    x = dpp_add_i64<0x143, 0xc>(x);  // row_bcast:31
+    return x;
+}
+
 // Exclusive scan of one value per thread over a block of NT threads; returns
 // the thread's prefix and writes the block total to *total.  Every thread of
-// the block must call it.
+// the block must call it.  Both levels scan with DPP, without LDS round trips.
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 8) return (T)wave_incl_scan_i64((i64)x);
+    else return (T)wave_incl_scan_i32((i32)x);
+}
+
 template <int NT, class T>
 __device__ __forceinline__ T block_scan(T v, T* wsum, T* total) {
     constexpr int NWV = NT / WAVE;
     const int l = lane_id(), wv = threadIdx.x / WAVE;
-    T x = v;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const T y = __shfl_up(x, o, WAVE);
-        if (l >= o) x += y;
-    }
+    const T x = wave_incl_scan(v);
     if (l == WAVE - 1) wsum[wv] = x;
     __syncthreads();
     if (threadIdx.x < WAVE) {
-        T y = threadIdx.x < NWV ? wsum[threadIdx.x] : 0;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const T z = __shfl_up(y, o, WAVE);
-            if ((int)threadIdx.x >= o) y += z;
-        }
+        const T y = wave_incl_scan(threadIdx.x < NWV ? wsum[threadIdx.x] : (T)0);
         if (threadIdx.x < NWV) wsum[threadIdx.x] = y;
         if (threadIdx.x == NWV - 1) *total = y;
     }
@@ -151,35 +178,6 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
     }
 }
 
-// Inclusive prefix sum over the 64 lanes of a wavefront with DPP: shifts by
-// 1, 2, 4, 8 within each row of 16 lanes, then the row totals broadcast to
-// the rows above (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
-__device__ __forceinline__ i32 wave_incl_scan_i32(i32 x) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return x;
-}
-
-// The same scan for 64-bit values: both halves move together, the sum carries.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ i64 dpp_add_i64(i64 x) {
-    const u32 lo_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)x, CTRL, ROWS, 0xf, false);
-    const u32 hi_ = (u32)__builtin_amdgcn_update_dpp(0, (i32)(u32)((u64)x >> 32), CTRL, ROWS, 0xf, false);
-    return x + (i64)(((u64)hi_ << 32) | lo_);
-}
-__device__ __forceinline__ i64 wave_incl_scan_i64(i64 x) {
-    x = dpp_add_i64<0x111, 0xf>(x);  // row_shr:1
-    x = dpp_add_i64<0x112, 0xf>(x);  // row_shr:2
-    x = dpp_add_i64<0x114, 0xf>(x);  // row_shr:4
-    x = dpp_add_i64<0x118, 0xf>(x);  // row_shr:8
-    x = dpp_add_i64<0x142, 0xa>(x);  // row_bcast:15
-    x = dpp_add_i64<0x143, 0xc>(x);  // row_bcast:31
-    return x;
-}
 
 // Runs of equal keys among the active lanes of a wavefront (active lanes
 // first, keys non-decreasing): `tail` on the last lane of each run, `h` the
