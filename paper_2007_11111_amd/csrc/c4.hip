@@ -420,39 +420,36 @@ __device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
 
 // Pass C from the scratch copy of a chunk's wedge ends, words
 // (middle << 16) | (end - W0) in middle order at sc[cs .. ce): every end gives
-// cnt - 1 to its middle; per wavefront step the sums of each middle's piece
-// come from a DPP prefix sum and go to msum[middle - k0].  Four words in
-// flight per thread.
+// cnt - 1 to its middle.  Each thread takes a group of 8 consecutive words
+// (two 16-byte loads; the scratch slice starts on a 256-byte boundary and
+// holds a multiple of 8 words), reads their counts, then sums them along its
+// pieces of the middles' runs, one LDS atomic per piece.  Words of a group
+// outside [cs, ce) are read but not counted (their low halves still index
+// the counters in range).
 __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs, i32 ce, i32 k0, const u32* cnt,
                                              u32* msum) {
-    constexpr int U = 4;
-    const int l = lane_id();
-    for (i32 b0 = cs; b0 < ce; b0 += U * CB_THREADS) {
-        u32 iv[U];
+    const i32 g1 = (ce + 7) >> 3;
+    for (i32 g = (cs >> 3) + (i32)threadIdx.x; g < g1; g += CB_THREADS) {
+        const uint4 qa = *reinterpret_cast<const uint4*>(sc + 8 * (i64)g);
+        const uint4 qb = *reinterpret_cast<const uint4*>(sc + 8 * (i64)g + 4);
+        const u32 wd[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+        u32 c[8];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
-            iv[q] = t < ce ? sc[t] : 0u;
-        }
+        for (int j = 0; j < 8; ++j) c[j] = (cnt[(wd[j] & 0xffffu) >> 1] >> ((wd[j] & 1u) << 4)) & 0xffffu;
+        const i32 jlo = cs - 8 * g, jhi = ce - 8 * g;  // words j in [jlo, jhi) belong to the chunk
+        u32 kc = 0xffffffffu, sum = 0;
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (b0 + q * CB_THREADS >= ce) break;  // block-uniform
-            const i32 t = b0 + q * CB_THREADS + (i32)threadIdx.x;
-            const bool act = t < ce;
-            const u32 k = iv[q] >> 16;
-            const u32 x = iv[q] & 0xffffu;
-            const i32 val = act ? (i32)((cnt[x >> 1] >> ((x & 1) << 4)) & 0xffffu) - 1 : 0;
-            const i32 P = wave_incl_scan_i32(val);
-            // neighbours' middles by DPP wavefront shifts (lane 0 and lane 63 are ends anyway)
-            const u32 kp = (u32)__builtin_amdgcn_update_dpp(0, (i32)k, 0x138, 0xf, 0xf, false);  // wave_shr:1
-            const u32 kn = (u32)__builtin_amdgcn_update_dpp(0, (i32)k, 0x130, 0xf, 0xf, false);  // wave_shl:1
-            const bool head = act && (l == 0 || kp != k);
-            const bool tail = act && (l == WAVE - 1 || t + 1 >= ce || kn != k);
-            // a piece's sum is P(tail) - P(before its head): the tail adds P, the
-            // head takes away its exclusive prefix (32-bit sums wrap consistently)
-            const u32 add = (tail ? (u32)P : 0u) - (head ? (u32)(P - val) : 0u);
-            if (add) atomicAdd(&msum[k - (u32)k0], add);
+        for (int j = 0; j < 8; ++j) {
+            if (j < jlo || j >= jhi) continue;
+            const u32 k = wd[j] >> 16;
+            if (k != kc) {  // a new piece: the previous one's sum goes out
+                if (sum) atomicAdd(&msum[kc - (u32)k0], sum);
+                kc = k;
+                sum = 0;
+            }
+            sum += c[j] - 1u;
         }
+        if (sum) atomicAdd(&msum[kc - (u32)k0], sum);
     }
 }
 
