@@ -498,6 +498,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ MS msum[NMS * CB_THREADS];
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
+    u32* const sink = scr + (i64)gridDim.x * scr_cap + lane_id();  // words nobody reads
     __shared__ i64 sj, sh, red;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
@@ -614,13 +615,15 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                 u32* const dst = sc + toff;
                 i32 ta, tb;
                 wave_share(T, ta, tb);
-                run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                            [&](bool act, i32 t, i32 r, i32 w, i64, u64, i32) {
-                                if (act) {
-                                    c4w_inc<PACK16>(cnt, w - W0);
-                                    if (keep) dst[t] = ((u32)(k0 + R.rk[r]) << 16) | (u32)(w - W0);
-                                }
-                            });
+                // every lane stores its word, an item that is not copied to the
+                // sink after the scratch: the walk keeps the next gathers in
+                // flight only where its stores do not depend on the path
+                run_walk_pipe<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
+                                 [&](bool act, i32 t, i32 r, i32 w, i64, u64, i32) {
+                                     if (act) c4w_inc<PACK16>(cnt, w - W0);
+                                     const u32 word = ((u32)(k0 + R.rk[act ? r : 0]) << 16) | (u32)(w - W0);
+                                     *(act && keep ? dst + t : sink) = word;
+                                 });
                 if (keep) {
                     stored |= 1ull << ch;
                     toff += T;

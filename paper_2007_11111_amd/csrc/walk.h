@@ -178,6 +178,108 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
     }
 }
 
+// The run walk with two groups in flight: the runs of the next group are
+// found and its gathers issued before the callbacks of the current group
+// run, so that the gathers' latency overlaps the per-item work.  Same
+// arguments and callback as run_walk, and ridx[0] must be readable.  The
+// overlap holds when the callback's vector memory operations do not depend
+// on the path either (the compiler counts loads in flight per path and
+// takes the smallest count).
+template <int U>
+struct WalkGroup {
+    i32 t0, t1;  // items [t0, t1), the same in every lane; empty when t0 >= the end
+    i32 rr[U];
+    u64 mm[U];
+    i64 ee[U];
+    i32 ww[U];
+};
+
+template <int U>
+__device__ __forceinline__ void walk_prep(WalkGroup<U>& G, i32& r0, i32& t0, i32 tb, const i64* rbase,
+                                          const i32* rstart, i32 R, i32* flags, const i32* __restrict__ ridx,
+                                          u64 le) {
+    G.t0 = t0;
+    G.t1 = t0;
+    if (t0 < tb) {
+        const int l = lane_id();
+        u8* const fb = reinterpret_cast<u8*>(flags);
+        const i32 j = r0 + 1 + l;
+        const i32 sj = rstart[j < R ? j : R];
+        const i32 st = j < R ? sj : 0x7fffffff;
+        const i32 t1 = min(min(tb, t0 + U * WAVE), __builtin_amdgcn_readlane(st, WAVE - 1));
+        const i64 esafe = rbase[r0] + t0;
+        lds_put(&flags[l], 0);
+        wave_lds_fence();
+        if ((u32)(st - t0) < (u32)(U * WAVE)) lds_put8(&fb[st - t0], 1);
+        wave_lds_fence();
+        u8 fl[U];
+#pragma unroll
+        for (int s = 0; s < U; ++s) fl[s] = lds_get8(&fb[s * WAVE + l]);
+        wave_lds_fence();
+        i32 before = 0;
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            G.mm[s] = __ballot(fl[s] != 0);
+            G.rr[s] = r0 + before + __popcll(G.mm[s] & le);
+            before += __popcll(G.mm[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            const i32 t = t0 + s * WAVE + l;
+            G.ee[s] = t < t1 ? rbase[G.rr[s]] + t : esafe;
+        }
+        G.t1 = t1;
+        r0 += __popcll(__ballot(st <= t1));
+        t0 = t1;
+    } else {  // an empty group still issues its gathers (of entry 0), so that
+              // the count of loads in flight does not depend on the path
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
+            G.rr[s] = 0;
+            G.mm[s] = 0;
+            G.ee[s] = 0;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < U; ++s) G.ww[s] = ridx[G.ee[s]];
+}
+
+template <int U, class F>
+__device__ __forceinline__ void walk_items(const WalkGroup<U>& G, F& f) {
+    const int l = lane_id();
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+        const i32 t = G.t0 + s * WAVE + l;
+        f(t < G.t1, t, G.rr[s], G.ww[s], G.ee[s], G.mm[s], G.t1);
+    }
+    // every gather of the group has landed here, also where a step had no
+    // active lane: otherwise the compiler, to reuse a gather's register in
+    // the next group, waits for every load in flight, the next group's too
+#pragma unroll
+    for (int s = 0; s < U; ++s) asm volatile("" ::"v"(G.ww[s]));
+}
+
+template <int U, class F>
+__device__ __forceinline__ void run_walk_pipe(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
+                                              const i32* __restrict__ ridx, F&& f) {
+    static_assert(U * WAVE <= (int)(WAVE * sizeof(i32)), "one flag byte per item of a group");
+    if (ta >= tb) return;
+    const int l = lane_id();
+    const u64 le = l == WAVE - 1 ? ~0ull : ((1ull << (l + 1)) - 1);
+    i32 r0 = __builtin_amdgcn_readfirstlane(wave_last_le_lds(rstart, R, ta));
+    i32 t0 = ta;
+    WalkGroup<U> A, B;
+    walk_prep(A, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+    while (true) {
+        walk_prep(B, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+        walk_items(A, f);
+        if (B.t0 >= tb) break;
+        walk_prep(A, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+        walk_items(B, f);
+        if (A.t0 >= tb) break;
+    }
+}
+
 
 // Runs of equal keys among the active lanes of a wavefront (active lanes
 // first, keys non-decreasing): `tail` on the last lane of each run, `h` the
