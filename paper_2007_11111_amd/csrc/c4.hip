@@ -498,7 +498,9 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ MS msum[NMS * CB_THREADS];
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
-    u32* const sink = scr + (i64)gridDim.x * scr_cap + lane_id();  // words nobody reads
+    // the last 64 words of the slice are a sink that nobody reads
+    const i64 scr_use = scr_cap - WAVE;
+    const u32 sink = (u32)(scr_use + lane_id());
     __shared__ i64 sj, sh, red;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
@@ -606,23 +608,25 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         pn_v = ridx[b + k];
                     }
                 }
-                const bool keep = PACK16 && ch < MAXCH && toff + T <= scr_cap;
+                const bool keep = PACK16 && ch < MAXCH && toff + T <= scr_use;
                 if (keep && threadIdx.x == 0) {
                     cst[ch] = (i32)toff;
                     cst[ch + 1] = (i32)(toff + T);
                 }
                 const i32 k0 = ch * CB_THREADS;
-                u32* const dst = sc + toff;
                 i32 ta, tb;
                 wave_share(T, ta, tb);
                 // every lane stores its word, an item that is not copied to the
-                // sink after the scratch: the walk keeps the next gathers in
-                // flight only where its stores do not depend on the path
-                run_walk_pipe<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                                 [&](bool act, i32 t, i32 r, i32 w, i64, u64, i32) {
+                // sink: the walk keeps the next gathers in flight only where
+                // its stores do not depend on the path.  32-bit byte offsets
+                // from the slice (below 2^22).
+                char* const scb = reinterpret_cast<char*>(sc);
+                run_walk_pipe<4>(ta, tb, R.rbase, R.rstart, R.rk, R.nruns, R.flags[wv], ridx,
+                                 [&](bool act, i32 t, i32 kr, i32 w) {
                                      if (act) c4w_inc<PACK16>(cnt, w - W0);
-                                     const u32 word = ((u32)(k0 + R.rk[act ? r : 0]) << 16) | (u32)(w - W0);
-                                     *(act && keep ? dst + t : sink) = word;
+                                     const u32 word = ((u32)(k0 + kr) << 16) | (u32)(w - W0);
+                                     const u32 off = act && keep ? (u32)toff + (u32)t : sink;
+                                     *reinterpret_cast<u32*>(scb + (off << 2)) = word;
                                  });
                 if (keep) {
                     stored |= 1ull << ch;

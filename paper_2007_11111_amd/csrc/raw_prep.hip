@@ -410,7 +410,7 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     // a multiple of 64 words, so that every workgroup's slice starts on a
     // 256-byte boundary (the pass C stream reads it 16 bytes at a time)
     w.c4_scr_cap = std::max<i64>(std::min<i64>((i64)1 << 20, nnz / 16), 1024) & ~(i64)63;
-    w.c4_scr = c.take<u32>(C4W_GRID * w.c4_scr_cap + WAVE);  // + a sink of one word per lane
+    w.c4_scr = c.take<u32>(C4W_GRID * w.c4_scr_cap);
     w.partials = c.take<i64>(scan_partials_size(std::max(nn + 2, nnz + 1)));
     w.ek = c.take<i64>(std::max(nnz, nn));
     w.sort.tmp = reinterpret_cast<i32*>(w.ek);  // dead once the relabelled rows are built

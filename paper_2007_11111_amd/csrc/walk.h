@@ -180,15 +180,18 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
 
 // The run walk with two groups in flight: the runs of the next group are
 // found and its gathers issued before the callbacks of the current group
-// run, so that the gathers' latency overlaps the per-item work.  Same
-// arguments and callback as run_walk, and ridx[0] must be readable.  The
-// overlap holds when the callback's vector memory operations do not depend
-// on the path either (the compiler counts loads in flight per path and
-// takes the smallest count).
+// run, so that the gathers' latency overlaps the per-item work.  Arguments as
+// for run_walk, plus rkey, an LDS array with one key per run that the group
+// reads together with the run bases (rbase and rkey hold R + 1 entries);
+// ridx[0] must be readable.  The callback
+// is f(active, item, key of its run, w).  The overlap holds when the
+// callback's vector memory operations do not depend on the path either (the
+// compiler counts loads in flight per path and takes the smallest count).
 template <int U>
 struct WalkGroup {
     i32 t0, t1;  // items [t0, t1), the same in every lane; empty when t0 >= the end
     i32 rr[U];
+    i32 kk[U];
     u64 mm[U];
     i64 ee[U];
     i32 ww[U];
@@ -196,8 +199,8 @@ struct WalkGroup {
 
 template <int U>
 __device__ __forceinline__ void walk_prep(WalkGroup<U>& G, i32& r0, i32& t0, i32 tb, const i64* rbase,
-                                          const i32* rstart, i32 R, i32* flags, const i32* __restrict__ ridx,
-                                          u64 le) {
+                                          const i32* rstart, const i32* rkey, i32 R, i32* flags,
+                                          const i32* __restrict__ ridx, u64 le) {
     G.t0 = t0;
     G.t1 = t0;
     if (t0 < tb) {
@@ -224,9 +227,13 @@ __device__ __forceinline__ void walk_prep(WalkGroup<U>& G, i32& r0, i32& t0, i32
             before += __popcll(G.mm[s]);
         }
 #pragma unroll
-        for (int s = 0; s < U; ++s) {
+        for (int s = 0; s < U; ++s) {  // read on every lane (run index clamped to R) and then
+                                       // selected, so that no read depends on the path
             const i32 t = t0 + s * WAVE + l;
-            G.ee[s] = t < t1 ? rbase[G.rr[s]] + t : esafe;
+            const i32 rc = min(G.rr[s], R);
+            const i64 bb = rbase[rc];
+            G.kk[s] = rkey[rc];
+            G.ee[s] = t < t1 ? bb + t : esafe;
         }
         G.t1 = t1;
         r0 += __popcll(__ballot(st <= t1));
@@ -236,6 +243,7 @@ __device__ __forceinline__ void walk_prep(WalkGroup<U>& G, i32& r0, i32& t0, i32
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             G.rr[s] = 0;
+            G.kk[s] = 0;
             G.mm[s] = 0;
             G.ee[s] = 0;
         }
@@ -250,7 +258,7 @@ __device__ __forceinline__ void walk_items(const WalkGroup<U>& G, F& f) {
 #pragma unroll
     for (int s = 0; s < U; ++s) {
         const i32 t = G.t0 + s * WAVE + l;
-        f(t < G.t1, t, G.rr[s], G.ww[s], G.ee[s], G.mm[s], G.t1);
+        f(t < G.t1, t, G.kk[s], G.ww[s]);
     }
     // every gather of the group has landed here, also where a step had no
     // active lane: otherwise the compiler, to reuse a gather's register in
@@ -260,8 +268,8 @@ __device__ __forceinline__ void walk_items(const WalkGroup<U>& G, F& f) {
 }
 
 template <int U, class F>
-__device__ __forceinline__ void run_walk_pipe(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
-                                              const i32* __restrict__ ridx, F&& f) {
+__device__ __forceinline__ void run_walk_pipe(i32 ta, i32 tb, const i64* rbase, const i32* rstart, const i32* rkey,
+                                              i32 R, i32* flags, const i32* __restrict__ ridx, F&& f) {
     static_assert(U * WAVE <= (int)(WAVE * sizeof(i32)), "one flag byte per item of a group");
     if (ta >= tb) return;
     const int l = lane_id();
@@ -269,12 +277,12 @@ __device__ __forceinline__ void run_walk_pipe(i32 ta, i32 tb, const i64* rbase, 
     i32 r0 = __builtin_amdgcn_readfirstlane(wave_last_le_lds(rstart, R, ta));
     i32 t0 = ta;
     WalkGroup<U> A, B;
-    walk_prep(A, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+    walk_prep(A, r0, t0, tb, rbase, rstart, rkey, R, flags, ridx, le);
     while (true) {
-        walk_prep(B, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+        walk_prep(B, r0, t0, tb, rbase, rstart, rkey, R, flags, ridx, le);
         walk_items(A, f);
         if (B.t0 >= tb) break;
-        walk_prep(A, r0, t0, tb, rbase, rstart, R, flags, ridx, le);
+        walk_prep(A, r0, t0, tb, rbase, rstart, rkey, R, flags, ridx, le);
         walk_items(B, f);
         if (A.t0 >= tb) break;
     }
