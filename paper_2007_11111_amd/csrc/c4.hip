@@ -423,15 +423,27 @@ __device__ __forceinline__ u32 c4w_get(const u32* cnt, i32 x) {
 // cnt - 1 to its middle.  Each thread takes a group of 8 consecutive words
 // (two 16-byte loads; the scratch slice starts on a 256-byte boundary and
 // holds a multiple of 8 words), reads their counts, then sums them along its
-// pieces of the middles' runs, one LDS atomic per piece.  Words of a group
-// outside [cs, ce) are read but not counted (their low halves still index
-// the counters in range).
+// pieces of the middles' runs, one LDS atomic per piece; the next group's
+// loads are in flight meanwhile.  Words of a group outside [cs, ce) are read
+// but not counted (their low halves still index the counters in range).
 __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs, i32 ce, i32 k0, const u32* cnt,
                                              u32* msum) {
     const i32 g1 = (ce + 7) >> 3;
-    for (i32 g = (cs >> 3) + (i32)threadIdx.x; g < g1; g += CB_THREADS) {
-        const uint4 qa = *reinterpret_cast<const uint4*>(sc + 8 * (i64)g);
-        const uint4 qb = *reinterpret_cast<const uint4*>(sc + 8 * (i64)g + 4);
+    i32 g = (cs >> 3) + (i32)threadIdx.x;
+    if (g >= g1) return;
+    auto load = [&](i32 gg, uint4& a, uint4& b) {
+        a = *reinterpret_cast<const uint4*>(sc + 8 * (i64)gg);
+        b = *reinterpret_cast<const uint4*>(sc + 8 * (i64)gg + 4);
+    };
+    uint4 qa, qb;
+    load(g, qa, qb);
+    while (true) {
+        // the next group's words are loaded before this group is summed; the
+        // last round loads its own group again, so that every round issues
+        // the same loads and the compiler need not wait for them early
+        const i32 gn = g + CB_THREADS;
+        uint4 na, nb;
+        load(min(gn, g1 - 1), na, nb);
         const u32 wd[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
         u32 c[8];
 #pragma unroll
@@ -450,6 +462,10 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
             sum += c[j] - 1u;
         }
         if (sum) atomicAdd(&msum[kc - (u32)k0], sum);
+        if (gn >= g1) break;
+        g = gn;
+        qa = na;
+        qb = nb;
     }
 }
 
