@@ -247,8 +247,8 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
     wave_share(T, ta, tb);
     const int l = lane_id();
     const int wv = (int)threadIdx.x / WAVE;
-    run_walk<4>(ta, tb, R.rbase, R.rstart, R.nruns, R.flags[wv], ridx,
-                [&](bool act, i32 t, i32 r, i32 w, i64, u64 mask, i32 tend) {
+    run_walk_keyed<4>(ta, tb, R.rbase, R.rstart, R.rk, R.nruns, R.flags[wv], ridx,
+                      [&](bool act, i32 t, i32 kr, i32 w, i64, u64 mask, i32 tend) {
                     // a run piece's sum is P(tail) - P(before its head): the tail
                     // adds the inclusive prefix, the head takes away its exclusive one
                     i64 P, val;
@@ -268,7 +268,7 @@ __device__ __forceinline__ void attribute_middles(i32 T, RunLds& R, const i32* _
                     const bool head = act && (l == 0 || ((mask >> l) & 1ull));
                     const bool tail = act && (l == WAVE - 1 || ((mask >> (l + 1)) & 1ull) || t + 1 >= tend);
                     const i64 add = (tail ? P : 0) - (head ? P - val : 0);
-                    if (add) lds_add(&msum[R.rk[r]], add);
+                    if (add) lds_add(&msum[kr], add);
                 });
 }
 

@@ -142,9 +142,9 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const VRec* __restrict__ vrec,
             wave_lds_fence();
             u32 nq = 0;  // wave-uniform
             if (T > 0) {
-                run_walk<4>(0, T, rbase[wid], rstart[wid], nruns, flags[wid], ridx,
-                            [&](bool a, i32, i32 r, i32 y, i64 e, u64, i32) {
-                    const i32 kr = a ? rk[wid][r] : 0;
+                run_walk_keyed<4>(0, T, rbase[wid], rstart[wid], rk[wid], nruns, flags[wid], ridx,
+                                  [&](bool a, i32, i32 rkey, i32 y, i64 e, u64, i32) {
+                    const i32 kr = a ? rkey : 0;
                     const i32 l = a ? bmap_find(pm[wid], key(y, kr >> 8)) : -1;
                     const bool hit = l >= 0;
                     if (hit) atomicOr((unsigned long long*)&sB[wid][kr & 0xff], 1ull << l);
@@ -220,11 +220,11 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
         __syncthreads();
         const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
         u32 nq = 0;  // wave-uniform
-        run_walk<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, sR, flags[wv], ridx,
-                    [&](bool act, i32, i32 r, i32 y, i64 e, u64, i32) {
+        run_walk_keyed<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, rk, sR, flags[wv], ridx,
+                          [&](bool act, i32, i32 kr, i32 y, i64 e, u64, i32) {
                         const i32 l = act ? bmap_find(pm, y) : -1;
                         const bool hit = l >= 0;
-                        if (hit) atomicOr((unsigned long long*)&B[rk[r] * W + (l >> 6)], 1ull << (l & 63));
+                        if (hit) atomicOr((unsigned long long*)&B[kr * W + (l >> 6)], 1ull << (l & 63));
                         defer_c3(hit, e, sQ[wv], nq, C3, defer);
                     });
         __syncthreads();

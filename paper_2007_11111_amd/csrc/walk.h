@@ -122,12 +122,15 @@ __device__ __forceinline__ i32 wave_last_le_lds(const i32* a, i32 R, i32 key) {
 // are marked as bytes in the wavefront's 256-byte flags row (cleared, marked,
 // then read back once per step: three LDS round trips per group); the run of
 // item ts + l is r0 + (starts in earlier steps) + (starts in [ts, ts + l]).
-// The U gathers w = ridx[e] of a group are issued together, then
-// f(active, item, run, w, e, run-start mask, group end) runs for each step.
-// Inactive lanes gather a valid dummy item, so no load is branched.
-template <int U, class F>
-__device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
-                                         const i32* __restrict__ ridx, F&& f) {
+// The run bases (and, keyed, the run keys) are read on every lane at the run
+// index clamped to R, so rbase (and rkey) hold R + 1 entries.  The U gathers
+// w = ridx[e] of a group are issued together, then
+// f(active, item, run, w, e, run-start mask, group end) runs for each step
+// (keyed: the run's key rkey[run] in place of the run).  Inactive lanes
+// gather a valid dummy item, so no load is branched.
+template <int U, bool KEYED, class F>
+__device__ __forceinline__ void run_walk_core(i32 ta, i32 tb, const i64* rbase, const i32* rstart, const i32* rkey,
+                                              i32 R, i32* flags, const i32* __restrict__ ridx, F&& f) {
     static_assert(U * WAVE <= (int)(WAVE * sizeof(i32)), "one flag byte per item of a group");
     if (ta >= tb) return;
     const int l = lane_id();
@@ -149,7 +152,7 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
 #pragma unroll
         for (int s = 0; s < U; ++s) fl[s] = lds_get8(&fb[s * WAVE + l]);
         wave_lds_fence();
-        i32 rr[U];
+        i32 rr[U], kk[U];
         u64 mm[U];
         i64 ee[U];
         i32 ww[U];
@@ -163,19 +166,33 @@ __device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const i32 t = t0 + s * WAVE + l;
-            const i64 e = rbase[rr[s]] + t;
-            ee[s] = t < t1 ? e : esafe;
+            const i32 rc = min(rr[s], R);
+            const i64 bb = rbase[rc];
+            kk[s] = KEYED ? rkey[rc] : rr[s];
+            ee[s] = t < t1 ? bb + t : esafe;
         }
 #pragma unroll
         for (int s = 0; s < U; ++s) ww[s] = ridx[ee[s]];
 #pragma unroll
         for (int s = 0; s < U; ++s) {
             const i32 t = t0 + s * WAVE + l;
-            f(t < t1, t, rr[s], ww[s], ee[s], mm[s], t1);
+            f(t < t1, t, kk[s], ww[s], ee[s], mm[s], t1);
         }
         r0 += __popcll(__ballot(st <= t1));  // the run holding item t1
         t0 = t1;
     }
+}
+
+template <int U, class F>
+__device__ __forceinline__ void run_walk(i32 ta, i32 tb, const i64* rbase, const i32* rstart, i32 R, i32* flags,
+                                         const i32* __restrict__ ridx, F&& f) {
+    run_walk_core<U, false>(ta, tb, rbase, rstart, nullptr, R, flags, ridx, f);
+}
+
+template <int U, class F>
+__device__ __forceinline__ void run_walk_keyed(i32 ta, i32 tb, const i64* rbase, const i32* rstart, const i32* rkey,
+                                               i32 R, i32* flags, const i32* __restrict__ ridx, F&& f) {
+    run_walk_core<U, true>(ta, tb, rbase, rstart, rkey, R, flags, ridx, f);
 }
 
 // The run walk with two groups in flight: the runs of the next group are
@@ -403,11 +420,13 @@ __device__ __forceinline__ void bmap_insert(BucketMap<B>& m, i32 v, i32 position
 template <int B>
 __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
     // keys are distinct, so at most one term of `hit` is non-zero; the sum
-    // needs all four keys, which keeps a bucket a single 16-byte read.  The
+    // needs all four keys, which keeps a bucket a single 16-byte read, and the
+    // bucket's four positions come in the same round trip (8 bytes).  The
     // first bucket decides almost every lookup; only a full bucket without
     // the key sends the lane on to the next ones.
     u32 b = bucket_of<B>(v);
     int4 q = m.key[b];
+    uint2 pp = *reinterpret_cast<const uint2*>(&m.pos[4 * b]);
     int hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
     if (!hit && q.w != -1) {
         do {
@@ -415,8 +434,11 @@ __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
             q = m.key[b];
             hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
         } while (!hit && q.w != -1);
+        pp = *reinterpret_cast<const uint2*>(&m.pos[4 * b]);
     }
-    return hit ? (i32)m.pos[4 * b + hit - 1] : -1;
+    if (!hit) return -1;
+    const u32 half = hit <= 2 ? pp.x : pp.y;
+    return (i32)((half >> (((hit - 1) & 1) << 4)) & 0xffffu);
 }
 
 }  // namespace fglt
