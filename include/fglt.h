@@ -130,6 +130,9 @@ typedef struct {
     int32_t c4_wave_max;    /* default 128; -1 disables the tier */
     int32_t c4_block_max;   /* default 2048; -1 disables the tier */
     int32_t c4_hash_max;    /* default 16384; -1 disables the tier */
+    int32_t c4_window_rows; /* window tier, how a middle's row is cut at the window
+                               boundaries: 0 (default) a per-entry table where it fits the
+                               workspace, else 1; 1 a per-vertex table; 2 binary searches */
 } fglt_raw_plan;
 
 /*

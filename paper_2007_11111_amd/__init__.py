@@ -71,7 +71,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
     (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
-    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max; with
+    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max and the
+    window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events)."""
     L = lib()
     assert offsets.dtype == torch.int64 and indices.dtype == torch.int32
@@ -91,7 +92,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     if plan:
         rp = RawPlan(int(plan.get("tri_wave_max", 0)), int(plan.get("tri_lds_max", 0)),
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
-                     int(plan.get("c4_hash_max", 0)))
+                     int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
                      int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0), ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st), _stream(stream)),

@@ -72,7 +72,8 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     tm.mark(FGLT_SEG_RELABEL, s);
     FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
     tm.mark(FGLT_SEG_STRUCTURE, s);
-    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers_from_plan(plan, n), s));
+    const Tiers tiers = tiers_from_plan(plan, n);
+    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers, s));
     i64 g_total = 0, bitmap_words = 0;
     if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
     if (hipMemcpyAsync(&bitmap_words, w.boff + n, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -93,7 +94,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
     tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
-    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, s, tm));
+    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, tiers.c4_rows, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
     if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));

@@ -488,15 +488,24 @@ __device__ __forceinline__ i64 wave_last_le(const i64* __restrict__ a, i64 cnt, 
 // Jobs: window-tier vertices in descending rank order (hs holds them in
 // ascending order); a vertex whose middles fit one chunk is one job over all
 // its windows, top window first; a larger one is one job per window.
-template <bool PACK16, bool TAB>
+// TABM: how a middle's run in a window is found -- 0: binary searches of its
+// row, 1: the window table of its vertex (tab), 2: the per-entry window table
+// (etab, 16-bit counts only: entries below 65536), whose reads for consecutive
+// middles are consecutive.
+template <bool PACK16, int TABM>
 __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
                                                           const i64* __restrict__ mir,
-                                                          const i32* __restrict__ tab, i64 K1,
+                                                          const i32* __restrict__ tab, i64 TS,
+                                                          const u16* __restrict__ etab, const i64* __restrict__ ebase,
                                                           const i32* __restrict__ hs, u32 nh,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
                                                           u32* __restrict__ scr, i64 scr_cap, i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
+    constexpr bool TAB = TABM > 0, ETAB = TABM == 2;
+    using TabT = std::conditional_t<PACK16, u16, i32>;  // the vertex table's entries
+    const TabT* const tabt = reinterpret_cast<const TabT*>(tab);
+    static_assert(!ETAB || PACK16, "the per-entry table holds 16-bit entries");
     constexpr int MAXCH = 64;  // chunks of a vertex: |N-(u)| < 65536 when counts are packed
     __shared__ u32 cnt[C4W_WORDS];
     __shared__ RunLds R;
@@ -547,6 +556,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
         const i32 wtop = single ? nwin - 1 : nwin - 1 - (i32)(j - jobpre[h]);
         const i32 wbot = single ? 0 : wtop;
+        const i64 eb = ETAB ? ebase[nh - 1 - h] : 0;  // this vertex's block of etab: [window][middle]
         // one chunk: thread k keeps middle k and the end of its not yet
         // visited run (windows go top-down, so each run ends where the
         // previous window's run began); its LDS sum msum[k] collects the
@@ -560,31 +570,38 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             mcut = rpos[b + threadIdx.x];
             mrs = mir[b + threadIdx.x] - mcut;
             mhi = mrs + mcut;
-            if (TAB) tcur = tab[(i64)mv * K1 + wtop];
+            if (TAB) tcur = ETAB ? (i32)etab[eb + (i64)wtop * L + threadIdx.x] : (i32)tabt[(i64)mv * TS + wtop];
         }
         // more than one chunk: pass A loads the row data of the next chunk's
-        // middles (rpos, mir, ridx) while it walks the current chunk
-        i32 pc_cut = 0, pc_v = 0, pn_cut = 0, pn_v = 0;
+        // middles (rpos, mir, and ridx or their etab entries) while it walks
+        // the current chunk
+        i32 pc_cut = 0, pc_v = 0, pn_cut = 0, pn_v = 0, pc_a1 = 0, pn_a1 = 0;
         i64 pc_mir = 0, pn_mir = 0;
         bool prefetched = false;  // run_of takes the loaded values (pass A), else loads them
         i64 accu = 0;
         for (i32 win = wtop; win >= wbot; --win, tcur = tnx) {
-            if (TAB && single && (i32)threadIdx.x < L && win > wbot) tnx = tab[(i64)mv * K1 + win - 1];
+            if (TAB && single && (i32)threadIdx.x < L && win > wbot)
+                tnx = ETAB ? (i32)etab[eb + (i64)(win - 1) * L + threadIdx.x] : (i32)tabt[(i64)mv * TS + win - 1];
             const i32 W0 = win * WS;
             const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
             auto run_of = [&](i32 k, i64& s0, i32& len) {
                 if (single) {
-                    const i64 a0 = TAB ? mrs + std::min(tcur, mcut) : lower_bound_dev(ridx, mrs, mhi, W0);
+                    const i64 a0 = TAB ? mrs + (ETAB ? tcur : std::min(tcur, mcut)) : lower_bound_dev(ridx, mrs, mhi, W0);
                     s0 = a0;
                     len = (i32)(mhi - a0);
                     mhi = a0;
                 } else {
                     const i32 cut = prefetched ? pc_cut : rpos[b + k];
                     const i64 rs = (prefetched ? pc_mir : mir[b + k]) - cut;
-                    if (TAB) {
-                        const i64 vrow = (i64)(prefetched ? pc_v : ridx[b + k]) * K1;
-                        const i32 a0 = std::min(tab[vrow + win], cut);
-                        const i32 a1 = std::min(tab[vrow + win + 1], cut);
+                    if (ETAB) {  // entries already clamped to the cut
+                        const i32 a0 = prefetched ? pc_v : (i32)etab[eb + (i64)win * L + k];
+                        const i32 a1 = prefetched ? pc_a1 : (i32)etab[eb + (i64)(win + 1) * L + k];
+                        s0 = rs + a0;
+                        len = a1 - a0;
+                    } else if (TAB) {
+                        const i64 vrow = (i64)(prefetched ? pc_v : ridx[b + k]) * TS;
+                        const i32 a0 = std::min((i32)tabt[vrow + win], cut);
+                        const i32 a1 = std::min((i32)tabt[vrow + win + 1], cut);
                         s0 = rs + a0;
                         len = a1 - a0;
                     } else {
@@ -609,11 +626,17 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     if (ch == 0 && k < L) {
                         pn_cut = rpos[b + k];
                         pn_mir = mir[b + k];
-                        pn_v = ridx[b + k];
+                        if (ETAB) {
+                            pn_v = etab[eb + (i64)win * L + k];
+                            pn_a1 = etab[eb + (i64)(win + 1) * L + k];
+                        } else {
+                            pn_v = ridx[b + k];
+                        }
                     }
                     pc_cut = pn_cut;
                     pc_mir = pn_mir;
                     pc_v = pn_v;
+                    pc_a1 = pn_a1;
                 }
                 T = flatten_runs(L, ch * CB_THREADS, run_of, R);
                 if (!single && ch + 1 < nch) {
@@ -621,7 +644,12 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     if (k < L) {
                         pn_cut = rpos[b + k];
                         pn_mir = mir[b + k];
-                        pn_v = ridx[b + k];
+                        if (ETAB) {
+                            pn_v = etab[eb + (i64)win * L + k];
+                            pn_a1 = etab[eb + (i64)(win + 1) * L + k];
+                        } else {
+                            pn_v = ridx[b + k];
+                        }
                     }
                 }
                 const bool keep = PACK16 && ch < MAXCH && toff + T <= scr_use;
@@ -769,15 +797,81 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     }
 }
 
-// Window table: tab[v * K1 + k] = number of neighbours of v with rank below k * WS.
-__global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 WS,
-                           i32* __restrict__ tab) {
+// Window table: tab[v * TS + k] = number of neighbours of v with rank below
+// k * WS, for k < K1; rows of TS entries start on 32-byte boundaries.  T is
+// u16 where every degree is below 65536, else i32.
+template <class T>
+__global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 TS, i64 WS,
+                           T* __restrict__ tab) {
     const i64 total = n * K1;
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
         const i64 v = q / K1, k = q - v * K1;
         const i64 b = roff[v], e = roff[v + 1];
         const i64 key = k * WS;
-        tab[q] = (i32)(key >= n ? e - b : lower_bound_dev(ridx, b, e, key) - b);
+        tab[v * TS + k] = (T)(key >= n ? e - b : lower_bound_dev(ridx, b, e, key) - b);
+    }
+}
+
+// Per-entry window table, sizes: the i-th window-tier vertex u (hs in
+// ascending order) has L = |N-(u)| middles and ceil(u / WS) windows; its
+// block holds one entry per middle and window boundary, and its middles
+// make ceil(L / ET_CHUNK) chunks of the build.
+static constexpr int ET_CHUNK = 256;
+
+__global__ void k_c4_ecount(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS,
+                            i64* __restrict__ ecnt, i64* __restrict__ ccnt) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (i64)gridDim.x * blockDim.x) {
+        const i64 u = hs[i];
+        ecnt[i] = (i64)lo[u] * ((u + WS - 1) / WS + 1);
+        ccnt[i] = ((i64)lo[u] + ET_CHUNK - 1) / ET_CHUNK;
+    }
+}
+
+// Per-entry window table: etab[ebase[i] + w * L + k] = the position in the
+// row of middle k (the k-th lower neighbour of u, the i-th window-tier
+// vertex) of its first neighbour of rank >= w * WS, at most its cut (the
+// position of u).  With 16-bit counts every row is shorter than 65536.  A
+// workgroup per chunk of ET_CHUNK middles (cpre: prefix of the chunk counts;
+// wavefront 0 finds the chunk's vertex); a thread reads its middle's row of
+// the 16-bit vertex table (row stride TS) with 16-byte loads and writes one
+// entry per window, consecutive across the threads.
+__global__ void __launch_bounds__(ET_CHUNK) k_c4_etab(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                      const i32* __restrict__ lo, const i32* __restrict__ rpos,
+                                                      const u16* __restrict__ tab, i64 TS,
+                                                      const i32* __restrict__ hs, u32 nh,
+                                                      const i64* __restrict__ cpre, const i64* __restrict__ ebase,
+                                                      i64 WS, u16* __restrict__ etab) {
+    __shared__ i64 si;
+    const i64 nchunks = cpre[nh];
+    for (i64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        if (threadIdx.x < WAVE) {
+            const i64 i = wave_last_le(cpre, nh, c);  // cpre[i] <= c < cpre[i + 1]
+            if (threadIdx.x == 0) si = i;
+        }
+        __syncthreads();
+        const i64 i = si;
+        const i64 u = hs[i];
+        const i64 L = lo[u];
+        const i64 k = (c - cpre[i]) * ET_CHUNK + threadIdx.x;
+        if (k < L) {
+            const i32 nwin = (i32)((u + WS - 1) / WS);
+            const i64 b = roff[u];
+            const i64 vrow = (i64)ridx[b + k] * TS;
+            const i32 cut = rpos[b + k];
+            u16* const out = etab + ebase[i] + k;
+            // 16-byte loads of 8 entries: the row starts on a 32-byte boundary
+            // and holds a multiple of 16 entries, so entries w0 .. w0 + 7 are inside it
+            const uint4* const row = reinterpret_cast<const uint4*>(tab + vrow);
+            for (i32 w0 = 0; w0 <= nwin; w0 += 8) {
+                const uint4 x = row[w0 / 8];
+                const i32 v[8] = {(i32)(x.x & 0xffffu), (i32)(x.x >> 16), (i32)(x.y & 0xffffu), (i32)(x.y >> 16),
+                                  (i32)(x.z & 0xffffu), (i32)(x.z >> 16), (i32)(x.w & 0xffffu), (i32)(x.w >> 16)};
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (w0 + q <= nwin) out[(i64)(w0 + q) * L] = (u16)std::min(v[q], cut);
+            }
+        }
+        __syncthreads();  // si is rewritten by the next chunk
     }
 }
 
@@ -797,8 +891,7 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 
 // ------------------------------------------------------------ launcher
 
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm) {
-    (void)nnz;
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
     const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
     hipError_t e;
     if (c2 || c3)
@@ -824,21 +917,46 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s,
         const bool pack16 = hp.d_max < 65536;
         const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
         const i64 K1 = (n + WS - 1) / WS + 1;
-        const bool use_tab = w.c4_tab != nullptr && n * K1 <= w.c4_tab_cap;
-        if (use_tab)
-            hipLaunchKernelGGL(k_c4_table, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n, K1,
-                               WS, w.c4_tab);
+        // the table's row stride: 32 bytes' worth of entries (16-bit entries with packed counts)
+        const i64 TS = pack16 ? (K1 + 15) & ~(i64)15 : (K1 + 7) & ~(i64)7;
+        const bool use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * TS * (pack16 ? 2 : 4) <= w.c4_tab_cap * 4;
+        if (use_tab) {
+            if (pack16)
+                hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+                                   n, K1, TS, WS, reinterpret_cast<u16*>(w.c4_tab));
+            else
+                hipLaunchKernelGGL(k_c4_table<i32>, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+                                   n, K1, TS, WS, w.c4_tab);
+        }
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS, w.c4_jobcnt);
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
+        // the per-entry window table lives in the stored bitmaps' memory, dead
+        // after the clique pass (16-bit entries, four per word)
+        u16* const etab = reinterpret_cast<u16*>(w.bstore);
+        const bool use_etab = rows_mode == 0 && pack16 && use_tab && hp.c4_etab <= 4 * w.bstore_cap;
+        if (use_etab) {
+            static_assert(2 * C4W_WORDS == C4W_SPAN, "the tier assignment sizes the table with this window");
+            // c4_jobcnt is free again once the job prefix is built: the chunk counts
+            i64* const cpre = w.c4_jobcnt;
+            hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS,
+                               w.c4_ebase, cpre);
+            if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c3, w.partials, s)) != hipSuccess) return e;
+            if ((e = scan_exclusive_i64(cpre, cpre, c3, w.partials, s)) != hipSuccess) return e;
+            // 16 workgroups per CU stride over the chunks (their count is on the device)
+            hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx,
+                               w.lo, w.rpos, reinterpret_cast<const u16*>(w.c4_tab), TS, hs, c3, cpre, w.c4_ebase,
+                               WS, etab);
+        }
         tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
         const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
-#define C4W_LAUNCH(P16, TB)                                                                                    \
-    hipLaunchKernelGGL((k_c4_window<P16, TB>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, w.mir, \
-                       w.c4_tab, K1, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
-        if (pack16 && use_tab) C4W_LAUNCH(true, true);
-        else if (pack16) C4W_LAUNCH(true, false);
-        else if (use_tab) C4W_LAUNCH(false, true);
-        else C4W_LAUNCH(false, false);
+#define C4W_LAUNCH(P16, TM)                                                                                    \
+    hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, w.mir, \
+                       w.c4_tab, TS, etab, w.c4_ebase, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
+        if (use_etab) C4W_LAUNCH(true, 2);
+        else if (pack16 && use_tab) C4W_LAUNCH(true, 1);
+        else if (pack16) C4W_LAUNCH(true, 0);
+        else if (use_tab) C4W_LAUNCH(false, 1);
+        else C4W_LAUNCH(false, 0);
 #undef C4W_LAUNCH
     }
     return hipGetLastError();

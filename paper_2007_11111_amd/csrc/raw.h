@@ -23,6 +23,7 @@ constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slo
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
 constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
+constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
 
 // Device statistics / plan words (one small block of device memory).
@@ -39,6 +40,7 @@ struct DevPlan {
     i64 tri_items_tier[3];
     i64 wedge_items_tier[4];
     i64 triangles;
+    i64 c4_etab;  // entries of the window tier's per-entry window table
 };
 
 // Per-vertex record of rank space, read with one 16-byte load where a kernel
@@ -85,8 +87,9 @@ struct RawWs {
     u64* tri_slots;     // NUM_TRI_SLOTS * tri_slot_words
     i64 tri_slot_words;
     i64* c4_segoff;     // [2] one segment over the window-tier list
-    i64* c4_jobcnt;     // [n] jobs per window-tier vertex
+    i64* c4_jobcnt;     // [n+1] jobs per window-tier vertex, then the prefix of their middle counts
     i64* c4_jobpre;     // [n+1] their exclusive scan
+    i64* c4_ebase;      // [n+1] start of each window-tier vertex's block of the per-entry window table
     u32* c4_jobctr;     // [4] job queue heads: window tier, hash tier
     i64* bcnt;          // [n] bitmap words per vertex (clique pass store)
     i64* boff;          // [n+1] their exclusive scan
@@ -112,6 +115,7 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
 struct Tiers {
     i64 tri_wave, tri_lds, c4_wave, c4_block, c4_hash;
     i64 c4_hash_lmax;  // largest |N-(u)| whose counts fit the packed hash words
+    int c4_rows;       // window tier's row cuts: 0 per-entry table where it fits, 1 per-vertex table, 2 searches
 };
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n);
 int bits_for_n(i64 n);   // bits of the largest rank n - 1 (0 for n <= 1)
@@ -139,7 +143,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
                       SegTimer& tm);
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s);
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, hipStream_t s, SegTimer& tm);
+hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);
 hipError_t launch_net(i64 n, const i64* raw, i64* net, hipStream_t s);

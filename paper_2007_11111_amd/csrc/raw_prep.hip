@@ -258,6 +258,7 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
     __shared__ i64 part[TT / WAVE];
     i64 dpmax = 0;
     i64 titems[3] = {0, 0, 0}, witems[4] = {0, 0, 0, 0};
+    i64 etab = 0;  // window tier: |N-(u)| x (windows + 1) entries of the per-entry window table
     for (i64 u0 = (i64)blockIdx.x * TT; u0 < n; u0 += (i64)gridDim.x * TT) {
         const i64 u = u0 + threadIdx.x;
         int tcls = -1, ccls = -1;
@@ -276,6 +277,7 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
             }
             if (tcls >= 0) titems[tcls] += T;
             if (ccls >= 0) witems[ccls] += W;
+            if (ccls == 3) etab += (m - b) * ((u + C4W_SPAN - 1) / C4W_SPAN + 1);
         }
         block_append<TT, 3>(tcls, (i32)u, plan->n_tri, tri_list, n, wt, bt);
         block_append<TT, 4>(ccls, (i32)u, plan->n_c4, c4_list, n, wc, bc);
@@ -292,6 +294,8 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
         const i64 wi = block_sum<TT>(witems[c], part);
         if (threadIdx.x == 0 && wi) atomicAdd((unsigned long long*)&plan->wedge_items_tier[c], (unsigned long long)wi);
     }
+    etab = block_sum<TT>(etab, part);
+    if (threadIdx.x == 0 && etab) atomicAdd((unsigned long long*)&plan->c4_etab, (unsigned long long)etab);
 }
 
 __global__ void __launch_bounds__(PT) k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo,
@@ -311,7 +315,7 @@ int bits_for_n(i64 n) {
 }
 
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
-    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0};
+    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0, 0};
     if (plan) {
         if (plan->tri_wave_max > 0) t.tri_wave = std::min<i64>(plan->tri_wave_max, TRI_WAVE_MAX);
         if (plan->tri_lds_max > 0) t.tri_lds = std::min<i64>(plan->tri_lds_max, TRI_LDS_MAX);
@@ -321,6 +325,7 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
         if (plan->c4_block_max < 0) t.c4_block = 0;
         if (plan->c4_hash_max > 0) t.c4_hash = std::min<i64>(plan->c4_hash_max, C4_HASH_MAX);
         if (plan->c4_hash_max < 0) t.c4_hash = 0;
+        if (plan->c4_window_rows == 1 || plan->c4_window_rows == 2) t.c4_rows = plan->c4_window_rows;
     }
     t.tri_lds = std::max(t.tri_lds, t.tri_wave);
     t.c4_block = std::max(t.c4_block, t.c4_wave);
@@ -395,12 +400,13 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.bstore_cap = std::max<i64>(2 * nnz, 64);
     w.bstore = c.take<u64>(w.bstore_cap);
     w.c4_segoff = c.take<i64>(2);
-    w.c4_jobcnt = c.take<i64>(nn);
+    w.c4_jobcnt = c.take<i64>(nn + 1);
     w.c4_jobpre = c.take<i64>(nn + 1);
+    w.c4_ebase = c.take<i64>(nn + 1);
     w.c4_jobctr = c.take<u32>(4);
     // window table: n x (ceil(n / 32768) + 1) entries when that stays within 1 GiB
     {
-        const i64 k1 = (nn + 32767) / 32768 + 1;
+        const i64 k1 = ((nn + 32767) / 32768 + 1 + 7) & ~(i64)7;  // rows padded to 8 entries
         const i64 entries = nn * k1;
         w.c4_tab_cap = entries * 4 <= ((i64)1 << 30) ? entries : 0;
         w.c4_tab = w.c4_tab_cap ? c.take<i32>(w.c4_tab_cap) : nullptr;

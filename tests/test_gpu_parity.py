@@ -223,6 +223,18 @@ def test_window_tier_several_windows(fg, plan):
     np.testing.assert_array_equal(got, oracle.net(off, idx))
 
 
+@pytest.mark.parametrize("rows", [1, 2])
+def test_window_tier_row_cuts(fg, rows):
+    """The window tier's other ways of cutting a middle's row at the window
+    boundaries (the default run above takes the per-entry table): the
+    per-vertex table (1) and binary searches of the rows (2)."""
+    g = graphgen.chung_lu(150_000, 2.1, 10.0, 6000.0, seed=11)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say(f"chung-lu 150k c4_window_rows={rows}")
+    got = gpu_raw(fg, off, idx, {"c4_window_rows": rows}, net=True)
+    np.testing.assert_array_equal(got, oracle.net(off, idx))
+
+
 def test_stats(fg):
     """Statistics: the triangle total is the sum of the per-vertex triangle
     counts (raw orbit 4) over three; the tiers partition the vertices with work."""
