@@ -891,23 +891,65 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 
 // ------------------------------------------------------------ launcher
 
+// A second stream of the calling thread on the current device (default
+// priority) with a fork and a join event, created on first use and kept for
+// the thread's lifetime.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static hipError_t aux_stream(AuxStream*& out) {
+    static constexpr int MAXDEV = 64;
+    thread_local AuxStream aux[MAXDEV];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    AuxStream& a = aux[dev];
+    if (!a.s) {
+        if ((e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    out = &a;
+    return hipSuccess;
+}
+
+// The hash tiers and the window tier's setup share no memory (the setup's
+// sort, scans, tables and job lists against the hash tiers' LDS tables and
+// atomic 4-cycle sums; each queue counter is cleared before the fork), so with
+// window-tier work the hash tiers run on a second stream while the setup runs
+// on the caller's stream, and the window kernel starts after both.  Their
+// segment marks then fall together: FGLT_SEG_C4_WAVE covers all of it.
 hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
     const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
     hipError_t e;
     if (c2 || c3)
         if ((e = hipMemsetAsync(w.c4_jobctr, 0, 2 * sizeof(u32), s)) != hipSuccess) return e;
     tm.mark(FGLT_SEG_C4_WAVE, s);
-    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
+    const bool forked = c3 && (c0 || c1 || c2);
+    AuxStream* aux = nullptr;
+    hipStream_t sh = s;  // the hash tiers' stream
+    if (forked) {
+        if ((e = aux_stream(aux)) != hipSuccess) return e;
+        if ((e = hipEventRecord(aux->fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(aux->s, aux->fork, 0)) != hipSuccess) return e;
+        sh = aux->s;
+    }
+    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, sh, w.roff, w.ridx, w.lo,
                                w.G, w.mir, w.c4_list, c0, w.c4v);
-    tm.mark(FGLT_SEG_C4_BLOCK, s);
-    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+    if (!forked) tm.mark(FGLT_SEG_C4_BLOCK, s);
+    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, sh, w.roff, w.ridx,
                                w.lo, w.G, w.mir, w.c4_list + n, c1, w.c4v);
-    tm.mark(FGLT_SEG_C4_HASH, s);
+    if (!forked) tm.mark(FGLT_SEG_C4_HASH, s);
     if (c2) {
         const int cb = 32 - std::max(1, bits_for_n(n));
-        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
+        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, sh, w.roff, w.ridx, w.lo,
                            w.rpos, w.mir, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
     }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (forked && (e = hipEventRecord(aux->join, aux->s)) != hipSuccess) return e;
     if (!c3) tm.mark(FGLT_SEG_C4_WINDOW, s);
     if (c3) {
         // window-tier vertices in ascending order, then the job counts
@@ -946,6 +988,11 @@ hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode,
             hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx,
                                w.lo, w.rpos, reinterpret_cast<const u16*>(w.c4_tab), TS, hs, c3, cpre, w.c4_ebase,
                                WS, etab);
+        }
+        if (forked) {  // the hash tiers have finished before the window kernel starts
+            if ((e = hipStreamWaitEvent(s, aux->join, 0)) != hipSuccess) return e;
+            tm.mark(FGLT_SEG_C4_BLOCK, s);
+            tm.mark(FGLT_SEG_C4_HASH, s);
         }
         tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
         const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
