@@ -71,13 +71,11 @@ enum {
     FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
     FGLT_SEG_L2,             /* row pass 2: A p2, A c3, C3 (p1-2), C(C3, 2), and the
                                 clique/diamond counts stored per entry            */
-    FGLT_SEG_C4_WAVE,        /* 4-cycle pass, wavefront tier; when the window tier
-                                has work, the three hash tiers (on a second stream)
-                                and the window tier's setup together, and the next
-                                two segments are empty                            */
-    FGLT_SEG_C4_BLOCK,       /* 4-cycle pass, workgroup tier                      */
-    FGLT_SEG_C4_HASH,        /* 4-cycle pass, packed-hash workgroup tier, then the
-                                window tier's setup (sort, window tables, jobs)   */
+    FGLT_SEG_C4_WAVE,        /* empty: the 4-cycle pass's wavefront, workgroup and
+                                packed-hash tiers and the window tier's setup run on
+                                a second stream beside the triangle segments       */
+    FGLT_SEG_C4_BLOCK,       /* empty (as above)                                  */
+    FGLT_SEG_C4_HASH,        /* 4-cycle pass: the window tier's per-entry table   */
     FGLT_SEG_C4_WINDOW,      /* 4-cycle pass, dense-counter window tier (kernel)  */
     FGLT_SEG_FINALIZE,       /* Table I assembly, Table II, scatter to caller order */
     FGLT_NSEG

@@ -14,6 +14,31 @@ int status_from_err(u32 err) {
     return FGLT_OK;
 }
 
+// A second stream of the calling thread on the current device (default
+// priority) with a fork and a join event, created on first use and kept for
+// the thread's lifetime.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static hipError_t aux_stream(AuxStream*& out) {
+    static constexpr int MAXDEV = 64;
+    thread_local AuxStream aux[MAXDEV];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    AuxStream& a = aux[dev];
+    if (!a.s) {
+        if ((e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    out = &a;
+    return hipSuccess;
+}
+
 int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
     if (hipMemcpyAsync(&hp, w.plan, sizeof(DevPlan), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return FGLT_EHIP;
@@ -86,6 +111,19 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     // 3. counting
     FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
+    // the 4-cycle pass's hash tiers and window setup share no memory with the
+    // triangle and clique passes: a second stream runs them alongside, and the
+    // window kernel (after the join) takes the whole GPU
+    AuxStream* aux = nullptr;
+    hipStream_t s4 = s;
+    if (hp.n_c4[0] || hp.n_c4[1] || hp.n_c4[2] || hp.n_c4[3]) {
+        FGLT_HIP_TRY(aux_stream(aux));
+        FGLT_HIP_TRY(hipEventRecord(aux->fork, s));
+        FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
+        s4 = aux->s;
+    }
+    FGLT_HIP_TRY(launch_c4_early(n, nnz, w, hp, tiers.c4_rows, s4));
+    if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     // the clique pass reuses the triangle pass's bitmaps when the workspace holds them
     const bool stored = bitmap_words <= w.bstore_cap;
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
@@ -94,7 +132,8 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
     tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
-    FGLT_HIP_TRY(launch_c4(n, nnz, w, hp, tiers.c4_rows, s, tm));
+    if (aux) FGLT_HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
+    FGLT_HIP_TRY(launch_c4_late(n, nnz, w, hp, tiers.c4_rows, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
     if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));

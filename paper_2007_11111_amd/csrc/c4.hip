@@ -891,121 +891,107 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 
 // ------------------------------------------------------------ launcher
 
-// A second stream of the calling thread on the current device (default
-// priority) with a fork and a join event, created on first use and kept for
-// the thread's lifetime.
-struct AuxStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+// The window tier's configuration, the same in both parts of the pass.
+struct C4WinCfg {
+    bool pack16, use_tab, use_etab;
+    i64 WS, K1, TS;
 };
 
-static hipError_t aux_stream(AuxStream*& out) {
-    static constexpr int MAXDEV = 64;
-    thread_local AuxStream aux[MAXDEV];
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
-    AuxStream& a = aux[dev];
-    if (!a.s) {
-        if ((e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
-        if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
-    }
-    out = &a;
-    return hipSuccess;
+static C4WinCfg c4_win_cfg(i64 n, const RawWs& w, const DevPlan& hp, int rows_mode) {
+    C4WinCfg c;
+    c.pack16 = hp.d_max < 65536;
+    c.WS = c.pack16 ? 2 * C4W_WORDS : C4W_WORDS;
+    c.K1 = (n + c.WS - 1) / c.WS + 1;
+    // the table's row stride: 32 bytes' worth of entries (16-bit entries with packed counts)
+    c.TS = c.pack16 ? (c.K1 + 15) & ~(i64)15 : (c.K1 + 7) & ~(i64)7;
+    c.use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * c.TS * (c.pack16 ? 2 : 4) <= w.c4_tab_cap * 4;
+    // the per-entry window table lives in the stored bitmaps' memory (16-bit
+    // entries, four per word)
+    c.use_etab = rows_mode == 0 && c.pack16 && c.use_tab && hp.c4_etab <= 4 * w.bstore_cap;
+    static_assert(2 * C4W_WORDS == C4W_SPAN, "the tier assignment sizes the table with this window");
+    return c;
 }
 
-// The hash tiers and the window tier's setup share no memory (the setup's
-// sort, scans, tables and job lists against the hash tiers' LDS tables and
-// atomic 4-cycle sums; each queue counter is cleared before the fork), so with
-// window-tier work the hash tiers run on a second stream while the setup runs
-// on the caller's stream, and the window kernel starts after both.  Their
-// segment marks then fall together: FGLT_SEG_C4_WAVE covers all of it.
-hipError_t launch_c4(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
+// Part one of the 4-cycle pass: the three hash tiers, then the window tier's
+// setup (its vertex list sorted, the vertex table, the job lists, the
+// per-entry table's offsets).  It reads only the structure and writes only
+// 4-cycle state (the sums, lists, tables, job arrays, and a sort buffer of its
+// own), so it may run on a second stream beside the triangle and clique
+// passes.
+hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s) {
+    (void)nnz;
     const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
     hipError_t e;
     if (c2 || c3)
         if ((e = hipMemsetAsync(w.c4_jobctr, 0, 2 * sizeof(u32), s)) != hipSuccess) return e;
-    tm.mark(FGLT_SEG_C4_WAVE, s);
-    const bool forked = c3 && (c0 || c1 || c2);
-    AuxStream* aux = nullptr;
-    hipStream_t sh = s;  // the hash tiers' stream
-    if (forked) {
-        if ((e = aux_stream(aux)) != hipSuccess) return e;
-        if ((e = hipEventRecord(aux->fork, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(aux->s, aux->fork, 0)) != hipSuccess) return e;
-        sh = aux->s;
-    }
-    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, sh, w.roff, w.ridx, w.lo,
+    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
                                w.G, w.mir, w.c4_list, c0, w.c4v);
-    if (!forked) tm.mark(FGLT_SEG_C4_BLOCK, s);
-    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, sh, w.roff, w.ridx,
+    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
                                w.lo, w.G, w.mir, w.c4_list + n, c1, w.c4v);
-    if (!forked) tm.mark(FGLT_SEG_C4_HASH, s);
     if (c2) {
         const int cb = 32 - std::max(1, bits_for_n(n));
-        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, sh, w.roff, w.ridx, w.lo,
+        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
                            w.rpos, w.mir, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (forked && (e = hipEventRecord(aux->join, aux->s)) != hipSuccess) return e;
-    if (!c3) tm.mark(FGLT_SEG_C4_WINDOW, s);
-    if (c3) {
-        // window-tier vertices in ascending order, then the job counts
-        i32* hs = w.c4_list + 3 * n;
-        hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c3);
-        if ((e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), w.sort, 1, s)) != hipSuccess) return e;
-        const bool pack16 = hp.d_max < 65536;
-        const i64 WS = pack16 ? 2 * C4W_WORDS : C4W_WORDS;
-        const i64 K1 = (n + WS - 1) / WS + 1;
-        // the table's row stride: 32 bytes' worth of entries (16-bit entries with packed counts)
-        const i64 TS = pack16 ? (K1 + 15) & ~(i64)15 : (K1 + 7) & ~(i64)7;
-        const bool use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * TS * (pack16 ? 2 : 4) <= w.c4_tab_cap * 4;
-        if (use_tab) {
-            if (pack16)
-                hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                                   n, K1, TS, WS, reinterpret_cast<u16*>(w.c4_tab));
-            else
-                hipLaunchKernelGGL(k_c4_table<i32>, dim3(grid_for(n * K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                                   n, K1, TS, WS, w.c4_tab);
-        }
-        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS, w.c4_jobcnt);
-        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
-        // the per-entry window table lives in the stored bitmaps' memory, dead
-        // after the clique pass (16-bit entries, four per word)
-        u16* const etab = reinterpret_cast<u16*>(w.bstore);
-        const bool use_etab = rows_mode == 0 && pack16 && use_tab && hp.c4_etab <= 4 * w.bstore_cap;
-        if (use_etab) {
-            static_assert(2 * C4W_WORDS == C4W_SPAN, "the tier assignment sizes the table with this window");
-            // c4_jobcnt is free again once the job prefix is built: the chunk counts
-            i64* const cpre = w.c4_jobcnt;
-            hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, WS,
-                               w.c4_ebase, cpre);
-            if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c3, w.partials, s)) != hipSuccess) return e;
-            if ((e = scan_exclusive_i64(cpre, cpre, c3, w.partials, s)) != hipSuccess) return e;
-            // 16 workgroups per CU stride over the chunks (their count is on the device)
-            hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx,
-                               w.lo, w.rpos, reinterpret_cast<const u16*>(w.c4_tab), TS, hs, c3, cpre, w.c4_ebase,
-                               WS, etab);
-        }
-        if (forked) {  // the hash tiers have finished before the window kernel starts
-            if ((e = hipStreamWaitEvent(s, aux->join, 0)) != hipSuccess) return e;
-            tm.mark(FGLT_SEG_C4_BLOCK, s);
-            tm.mark(FGLT_SEG_C4_HASH, s);
-        }
-        tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
-        const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
+    if (!c3) return hipSuccess;
+    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
+    // window-tier vertices in ascending order (the sort's buffer: c4_ebase,
+    // not yet in use; the shared one is the clique pass's memory)
+    i32* hs = w.c4_list + 3 * n;
+    hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c3);
+    SegSortWs ws = w.sort;
+    ws.tmp = reinterpret_cast<i32*>(w.c4_ebase);
+    if ((e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), ws, 1, s)) != hipSuccess) return e;
+    if (c.use_tab) {
+        if (c.pack16)
+            hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+                               n, c.K1, c.TS, c.WS, reinterpret_cast<u16*>(w.c4_tab));
+        else
+            hipLaunchKernelGGL(k_c4_table<i32>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
+                               n, c.K1, c.TS, c.WS, w.c4_tab);
+    }
+    hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, c.WS, w.c4_jobcnt);
+    if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
+    if (c.use_etab) {
+        // c4_jobcnt is free again once the job prefix is built: the chunk counts
+        hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, c.WS,
+                           w.c4_ebase, w.c4_jobcnt);
+        if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c3, w.partials, s)) != hipSuccess) return e;
+        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c3, w.partials, s)) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+// Part two: the per-entry window table (in the stored bitmaps' memory, so
+// after the clique pass) and the window kernel.
+hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
+    const u32 c3 = hp.n_c4[3];
+    tm.mark(FGLT_SEG_C4_WAVE, s);
+    tm.mark(FGLT_SEG_C4_BLOCK, s);
+    tm.mark(FGLT_SEG_C4_HASH, s);
+    if (!c3) {
+        tm.mark(FGLT_SEG_C4_WINDOW, s);
+        return hipSuccess;
+    }
+    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
+    const i32* hs = w.c4_list + 3 * n;
+    u16* const etab = reinterpret_cast<u16*>(w.bstore);
+    if (c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
+        hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
+                           w.rpos, reinterpret_cast<const u16*>(w.c4_tab), c.TS, hs, c3, w.c4_jobcnt, w.c4_ebase,
+                           c.WS, etab);
+    tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
+    const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
 #define C4W_LAUNCH(P16, TM)                                                                                    \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, w.mir, \
-                       w.c4_tab, TS, etab, w.c4_ebase, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
-        if (use_etab) C4W_LAUNCH(true, 2);
-        else if (pack16 && use_tab) C4W_LAUNCH(true, 1);
-        else if (pack16) C4W_LAUNCH(true, 0);
-        else if (use_tab) C4W_LAUNCH(false, 1);
-        else C4W_LAUNCH(false, 0);
+                       w.c4_tab, c.TS, etab, w.c4_ebase, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
+    if (c.use_etab) C4W_LAUNCH(true, 2);
+    else if (c.pack16 && c.use_tab) C4W_LAUNCH(true, 1);
+    else if (c.pack16) C4W_LAUNCH(true, 0);
+    else if (c.use_tab) C4W_LAUNCH(false, 1);
+    else C4W_LAUNCH(false, 0);
 #undef C4W_LAUNCH
-    }
     return hipGetLastError();
 }
 
