@@ -75,7 +75,8 @@ enum {
                                 packed-hash tiers and the window tier's setup run on
                                 a second stream beside the triangle segments       */
     FGLT_SEG_C4_BLOCK,       /* empty (as above)                                  */
-    FGLT_SEG_C4_HASH,        /* 4-cycle pass: the window tier's per-entry table   */
+    FGLT_SEG_C4_HASH,        /* empty: the window tier's per-entry table is built
+                                on the second stream beside row pass 2            */
     FGLT_SEG_C4_WINDOW,      /* 4-cycle pass, dense-counter window tier (kernel)  */
     FGLT_SEG_FINALIZE,       /* Table I assembly, Table II, scatter to caller order */
     FGLT_NSEG

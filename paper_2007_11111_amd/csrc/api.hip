@@ -19,7 +19,7 @@ int status_from_err(u32 err) {
 // the thread's lifetime.
 struct AuxStream {
     hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
 };
 
 static hipError_t aux_stream(AuxStream*& out) {
@@ -33,6 +33,7 @@ static hipError_t aux_stream(AuxStream*& out) {
     if (!a.s) {
         if ((e = hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&a.mid, hipEventDisableTiming)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
     }
     out = &a;
@@ -123,13 +124,20 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
         s4 = aux->s;
     }
     FGLT_HIP_TRY(launch_c4_early(n, nnz, w, hp, tiers.c4_rows, s4));
-    if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     // the clique pass reuses the triangle pass's bitmaps when the workspace holds them
     const bool stored = bitmap_words <= w.bstore_cap;
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
     tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
     FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
+    // the bitmaps are dead now: the window tier's per-entry table goes there,
+    // on the second stream beside row pass 2
+    if (aux) {
+        FGLT_HIP_TRY(hipEventRecord(aux->mid, s));
+        FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->mid, 0));
+    }
+    FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, hp, tiers.c4_rows, s4));
+    if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     tm.mark(FGLT_SEG_L2, s);
     FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
     if (aux) FGLT_HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));

@@ -963,9 +963,22 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
     return hipGetLastError();
 }
 
-// Part two: the per-entry window table (in the stored bitmaps' memory, so
-// after the clique pass) and the window kernel.
+// Part two: the per-entry window table, in the stored bitmaps' memory, so
+// after the clique pass (it may run on the second stream beside row pass 2).
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s) {
+    const u32 c3 = hp.n_c4[3];
+    if (!c3) return hipSuccess;
+    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
+    if (c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
+        hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
+                           w.rpos, reinterpret_cast<const u16*>(w.c4_tab), c.TS, w.c4_list + 3 * n, c3, w.c4_jobcnt,
+                           w.c4_ebase, c.WS, reinterpret_cast<u16*>(w.bstore));
+    return hipGetLastError();
+}
+
+// Part three: the window kernel.
 hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
+    (void)nnz;
     const u32 c3 = hp.n_c4[3];
     tm.mark(FGLT_SEG_C4_WAVE, s);
     tm.mark(FGLT_SEG_C4_BLOCK, s);
@@ -976,11 +989,7 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_
     }
     const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
     const i32* hs = w.c4_list + 3 * n;
-    u16* const etab = reinterpret_cast<u16*>(w.bstore);
-    if (c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
-        hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
-                           w.rpos, reinterpret_cast<const u16*>(w.c4_tab), c.TS, hs, c3, w.c4_jobcnt, w.c4_ebase,
-                           c.WS, etab);
+    const u16* const etab = reinterpret_cast<const u16*>(w.bstore);
     tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
     const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
 #define C4W_LAUNCH(P16, TM)                                                                                    \

@@ -144,6 +144,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);
 hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);
