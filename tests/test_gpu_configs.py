@@ -83,6 +83,13 @@ def test_workload_digest(fg, name):
         colsum = f_h.sum(0).tolist()
         raise AssertionError(f"net digest mismatch; column sums {colsum} vs oracle {d['net_colsum']}")
     _invariants(f_h, raw.cpu().numpy())
+    # the window tier's other row cuts (vertex table, binary searches) give the
+    # same digest; R-MAT 22 (d_max >= 65536) runs them with 32-bit counters
+    for rows in (1, 2):
+        say(f"workload {name}: c4_window_rows={rows}")
+        f2 = fg.net(fg.raw(off, idx, plan={"c4_window_rows": rows}))
+        torch.cuda.synchronize()
+        assert sha(f2.cpu().numpy()) == d["net_sha256"], f"net digest mismatch with c4_window_rows={rows}"
     # a stratified vertex sample recomputed live by the oracle (small degrees only:
     # the oracle's per-vertex cost grows with the square of the neighbourhood)
     deg = np.diff(off_h)
