@@ -419,26 +419,31 @@ __device__ __forceinline__ void bmap_insert(BucketMap<B>& m, i32 v, i32 position
 
 template <int B>
 __device__ __forceinline__ i32 bmap_find(const BucketMap<B>& m, i32 v) {
-    // keys are distinct, so at most one term of `hit` is non-zero; the sum
-    // needs all four keys, which keeps a bucket a single 16-byte read, and the
-    // bucket's four positions come in the same round trip (8 bytes).  The
-    // first bucket decides almost every lookup; only a full bucket without
-    // the key sends the lane on to the next ones.
+    // keys are distinct, so at most one slot of a bucket matches; its position
+    // is selected directly (one compare and one select per slot), with the
+    // bucket's four positions read in the same round trip as its keys.  The
+    // first bucket decides almost every lookup; only a full bucket without the
+    // key sends the lane on to the next ones.
     u32 b = bucket_of<B>(v);
     int4 q = m.key[b];
     uint2 pp = *reinterpret_cast<const uint2*>(&m.pos[4 * b]);
-    int hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
-    if (!hit && q.w != -1) {
+    auto pick = [&]() {
+        i32 r = q.x == v ? (i32)(pp.x & 0xffffu) : -1;
+        r = q.y == v ? (i32)(pp.x >> 16) : r;
+        r = q.z == v ? (i32)(pp.y & 0xffffu) : r;
+        r = q.w == v ? (i32)(pp.y >> 16) : r;
+        return r;
+    };
+    i32 r = pick();
+    if (r < 0 && q.w != -1) {
         do {
             b = (b + 1) & ((1u << B) - 1);
             q = m.key[b];
-            hit = (q.x == v) + 2 * (q.y == v) + 3 * (q.z == v) + 4 * (q.w == v);
-        } while (!hit && q.w != -1);
-        pp = *reinterpret_cast<const uint2*>(&m.pos[4 * b]);
+            pp = *reinterpret_cast<const uint2*>(&m.pos[4 * b]);
+            r = pick();
+        } while (r < 0 && q.w != -1);
     }
-    if (!hit) return -1;
-    const u32 half = hit <= 2 ? pp.x : pp.y;
-    return (i32)((half >> (((hit - 1) & 1) << 4)) & 0xffffu);
+    return r;
 }
 
 }  // namespace fglt
