@@ -187,6 +187,15 @@ def batch_leg(fg, torch, steps):
         fg.batch(vtx, off_d, idx_d, out=out)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
+    # graph-level totals of every graph of the batch (fglt_totals)
+    vtx_d = vtx.to("cuda", torch.int64)
+    tot = fg.totals(out, vtx_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tot = fg.totals(out, vtx_d)
+    torch.cuda.synchronize()
+    t_tot = (time.perf_counter() - t0) / steps
     # reference point: one fglt_raw + net per graph, one stream, same device
     dev = [(torch.from_numpy(o).cuda(), torch.from_numpy(i).cuda()) for o, i in csrs]
     for o, i in dev[:16]:
@@ -201,7 +210,7 @@ def batch_leg(fg, torch, steps):
     return {"graphs": G, "n_total": int(vtx[-1]), "nnz_total": int(idx.numel()),
             "ms_per_batch": 1e3 * t_batch, "graphs_per_s": G / t_batch,
             "per_graph_loop_ms": 1e3 * t_loop, "per_graph_loop_graphs_per_s": G / t_loop,
-            "speedup_vs_loop": t_loop / t_batch}
+            "speedup_vs_loop": t_loop / t_batch, "totals_ms": 1e3 * t_tot}
 
 
 def main():
@@ -269,6 +278,14 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     seg_avg = {k: v / args.steps for k, v in seg_sum.items()}
+    # graph-level totals of the workload (fglt_totals on the net frequencies), after the timed steps
+    fg.totals(out)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        fg.totals(out)
+    torch.cuda.synchronize()
+    totals_ms = 1e3 * (time.perf_counter() - t2) / args.steps
 
     # dominant counting segment and its roofline
     counted = {k: v for k, v in seg_avg.items() if k in SEG_UNITS}
@@ -284,7 +301,7 @@ def main():
                 "alg_bytes_per_launch": int(alg_bytes), "units_per_launch": int(units),
                 "unit_of_work": SEG_UNITS[dom][0], "bytes_per_unit": SEG_UNITS[dom][1]}
 
-    extra = {"build_csr_ms": round(build_ms, 3), "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
+    extra = {"build_csr_ms": round(build_ms, 3), "totals_ms": round(totals_ms, 4), "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
              "path_alg_gbps": round(path_bytes / (ms_per_step / 1e3) / 1e9, 2),
              "stats": {k: v for k, v in st.items() if k != "seg_ms"}}
     if not args.no_batch:

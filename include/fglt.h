@@ -166,6 +166,25 @@ int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indi
  */
 int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream);
 
+/*
+ * Graph-level totals (the relaxed, graph-level use of the encoding noted in
+ * the Sigma_16 section): for each graph g and orbit k,
+ *   totals[g][k] = (sum over the graph's vertices v of net[v][k]) / m_k,
+ * where m_k is the number of vertices of orbit k's graphlet in orbit k
+ * (Fig. 1; m = 1 2 2 1 3 2 2 3 1 1 2 1 4 2 2 4).  A net frequency counts the
+ * induced copies of its graphlet at one vertex, so every orbit of a graphlet
+ * gives that graphlet's number of induced copies in the graph.
+ *   num_graphs   G >= 0 (< 2^31)
+ *   vtx_offsets  [G+1] int64 on the device: graph g owns rows
+ *                vtx_offsets[g] .. vtx_offsets[g+1]-1 of net (clamped to
+ *                [0, n_total]); one graph: {0, n}
+ *   net          [n_total][16] int64 on the device (fglt_net's or fglt_batch's output)
+ *   totals       [G][16] int64 on the device, written
+ * Asynchronous on `stream`.  FGLT_EINVAL for a negative size or a NULL pointer.
+ */
+int fglt_totals(int64_t num_graphs, const int64_t* vtx_offsets, int64_t n_total, const int64_t* net,
+                int64_t* totals, void* stream);
+
 /* Execution plan of fglt_batch (host struct); NULL selects the defaults. */
 typedef struct {
     int32_t threads;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (default 256) */

@@ -135,6 +135,31 @@ def net(offsets, indices, vertices=None, threads: int = 0) -> np.ndarray:
     return raw_to_net(raw(offsets, indices, vertices, threads))
 
 
+# Fig. 1: how many vertices of orbit k's graphlet lie in orbit k (node;
+# edge; P3 ends, centre; triangle; P4 ends, inner; claw leaves, centre; paw
+# tip, base, centre; 4-cycle; diamond off-cord, on-cord; 4-clique).
+ORBIT_NODES = np.array([1, 2, 2, 1, 3, 2, 2, 3, 1, 1, 2, 1, 4, 2, 2, 4], dtype=np.int64)
+
+
+def totals(net_counts, vtx_offsets=None) -> np.ndarray:
+    """Graph-level totals: for each graph g (rows vtx_offsets[g] ..
+    vtx_offsets[g+1]-1 of the net frequencies; one graph when None) and orbit
+    k, the sum of the net frequencies of orbit k over the graph divided by
+    the orbit's vertex count in its graphlet -- the number of induced copies
+    of that graphlet (each copy is counted at every vertex it holds in orbit
+    k).  [G, 16] int64."""
+    f = np.ascontiguousarray(net_counts, dtype=np.int64).reshape(-1, NORB)
+    if vtx_offsets is None:
+        vtx_offsets = [0, f.shape[0]]
+    off = np.asarray(vtx_offsets, dtype=np.int64)
+    out = np.zeros((off.size - 1, NORB), dtype=np.int64)
+    for g in range(off.size - 1):
+        col = f[off[g]:off[g + 1]].sum(axis=0)
+        assert np.all(col % ORBIT_NODES == 0), "net frequencies whose orbit sums do not divide"
+        out[g] = col // ORBIT_NODES
+    return out
+
+
 def U16() -> np.ndarray:
     """Table II, U16 f = raw, as a dense 16x16 int64 matrix."""
     u = np.zeros((NORB, NORB), dtype=np.int64)

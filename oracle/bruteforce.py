@@ -39,6 +39,23 @@ import numpy as np
 NORB = 16
 
 
+def graphlet_copies(n: int, edges) -> np.ndarray:
+    """For each orbit k, the number of induced copies of orbit k's graphlet:
+    connected vertex sets S (|S| <= 4) whose induced subgraph puts some vertex
+    at orbit k, by enumeration (no orbit sizes are involved)."""
+    es = _edge_set(n, edges)
+    out = np.zeros(NORB, dtype=np.int64)
+    out[0] = n
+    for size in (2, 3, 4):
+        for S in combinations(range(n), size):
+            induced = [(a, b) for a, b in combinations(S, 2) if (a, b) in es]
+            if not _connected(S, induced):
+                continue
+            for k in {orbit_of(v, S, induced) for v in S}:
+                out[k] += 1
+    return out
+
+
 def orbit_of(v, verts, edges) -> int:
     """Index k of the graphlet/orbit of vertex v in the connected spanning
     graph (verts, edges); edges is a list of 2-tuples."""

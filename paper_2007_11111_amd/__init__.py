@@ -112,6 +112,26 @@ def net(raw_counts: torch.Tensor, out: torch.Tensor | None = None, stream=None):
     return out
 
 
+def totals(net_counts: torch.Tensor, vtx_offsets: torch.Tensor | None = None, stream=None):
+    """Graph-level totals -- ``fglt_totals``: for each graph (rows
+    vtx_offsets[g] .. vtx_offsets[g+1]-1 of the net frequencies; one graph when
+    vtx_offsets is None) and orbit k, the number of induced copies of orbit k's
+    graphlet.  Returns an int64 [G, 16] tensor."""
+    L = lib()
+    assert net_counts.dtype == torch.int64 and net_counts.is_cuda
+    net_counts = net_counts.contiguous()
+    n = int(net_counts.shape[0])
+    if vtx_offsets is None:
+        vtx_offsets = torch.tensor([0, n], dtype=torch.int64, device=net_counts.device)
+    assert vtx_offsets.dtype == torch.int64 and vtx_offsets.is_cuda
+    vtx_offsets = vtx_offsets.contiguous()
+    G = int(vtx_offsets.numel()) - 1
+    out = torch.empty((max(G, 0), NORBITS), dtype=torch.int64, device=net_counts.device)
+    check(L.fglt_totals(G, _ptr(vtx_offsets), n, _ptr(net_counts if n else None), _ptr(out), _stream(stream)),
+          "fglt_totals")
+    return out
+
+
 def transform(offsets: torch.Tensor, indices: torch.Tensor, **kw):
     """Net frequencies of every vertex (the graphlet transform over Sigma_16)."""
     return raw(offsets, indices, net=True, **kw)

@@ -96,6 +96,8 @@ def lib():
             L.fglt_raw.restype = ctypes.c_int
             L.fglt_net.argtypes = [i64, vp, vp, vp]
             L.fglt_net.restype = ctypes.c_int
+            L.fglt_totals.argtypes = [i64, vp, i64, vp, vp, vp]
+            L.fglt_totals.restype = ctypes.c_int
             if hasattr(L, "fglt_batch"):
                 L.fglt_batch_workspace.argtypes = [i32, i64, i64]
                 L.fglt_batch_workspace.restype = sz

@@ -70,3 +70,8 @@ def test_host_argument_checks_need_no_device(lib):
     lib.fglt_net.argtypes = [ctypes.c_int64, vp, vp, vp]
     assert lib.fglt_net(-3, None, None, None) == -1
     assert lib.fglt_net(0, None, None, None) == 0
+    lib.fglt_totals.restype = ctypes.c_int
+    lib.fglt_totals.argtypes = [ctypes.c_int64, vp, ctypes.c_int64, vp, vp, vp]
+    assert lib.fglt_totals(-1, None, 0, None, None, None) == -1
+    assert lib.fglt_totals(0, None, 0, None, None, None) == 0
+    assert lib.fglt_totals(2, None, 10, None, None, None) == -1

@@ -235,6 +235,28 @@ def test_window_tier_row_cuts(fg, rows):
     np.testing.assert_array_equal(got, oracle.net(off, idx))
 
 
+def test_totals(fg):
+    """Graph-level totals: one 20k-vertex graph (several parts per graph,
+    device atomics) and a batch of disjoint components, an empty one among
+    them (one workgroup per graph)."""
+    parts = [graphgen.erdos_renyi(3000, 0.003, seed=51), graphgen.chung_lu(8000, 2.2, 8.0, 300.0, seed=52),
+             graphgen.clique(30), graphgen.chung_lu(9000, 2.1, 8.0, 400.0, seed=53)]
+    sizes = [p.n for p in parts]
+    bounds = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(bounds[-1])
+    src = np.concatenate([p.src + bounds[i] for i, p in enumerate(parts)])
+    dst = np.concatenate([p.dst + bounds[i] for i, p in enumerate(parts)])
+    off, idx = oracle.canonical_csr(n, src, dst)
+    f = oracle.net(off, idx)
+    say(f"totals: n={n}, components {sizes}")
+    net = fg.raw(*to_dev(off, idx), net=True)
+    got = fg.totals(net).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.totals(f))
+    vo = np.array([0, bounds[1], bounds[1], bounds[2], bounds[3], bounds[4]], dtype=np.int64)  # an empty graph
+    got = fg.totals(net, torch.from_numpy(vo).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, oracle.totals(f, vo))
+
+
 def test_stats(fg):
     """Statistics: the triangle total is the sum of the per-vertex triangle
     counts (raw orbit 4) over three; the tiers partition the vertices with work."""

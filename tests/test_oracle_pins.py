@@ -291,3 +291,43 @@ def test_canonical_csr_definition():
     np.testing.assert_array_equal(idx, [1, 3, 0, 3, 0, 2])
     with pytest.raises(ValueError):
         oracle.canonical_csr(3, np.array([0]), np.array([3]))
+
+
+# ---------------------------------------------------------------- graph-level totals
+
+@pytest.mark.parametrize("seed", list(range(12)))
+def test_totals_vs_bruteforce_copies(seed):
+    """Column sums over orbit sizes against a direct count of induced copies."""
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(3, 10))
+    p = float(rng.choice([0.25, 0.5, 0.75]))
+    edges = random_graph(rng, n, p)
+    off, idx = csr_of(n, edges)
+    np.testing.assert_array_equal(oracle.totals(oracle.net(off, idx))[0], bruteforce.graphlet_copies(n, edges))
+
+
+def test_totals_closed_forms_and_batch():
+    C = math.comb
+    k6 = graphgen.clique(6)
+    st = graphgen.star(5)
+    exp_k6 = np.zeros(16, np.int64)
+    exp_k6[[0, 1, 4, 15]] = [6, C(6, 2), C(6, 3), C(6, 4)]
+    exp_st = np.zeros(16, np.int64)
+    exp_st[[0, 1, 2, 3, 7, 8]] = [6, 5, C(5, 2), C(5, 2), C(5, 3), C(5, 3)]
+    # the two as one batch: disjoint components, rows 0..5 and 6..11
+    n = k6.n + st.n
+    src = np.concatenate([k6.src, st.src + k6.n])
+    dst = np.concatenate([k6.dst, st.dst + k6.n])
+    off, idx = oracle.canonical_csr(n, src, dst)
+    t = oracle.totals(oracle.net(off, idx), [0, k6.n, n])
+    np.testing.assert_array_equal(t[0], exp_k6)
+    np.testing.assert_array_equal(t[1], exp_st)
+
+
+def test_totals_triangles_match_networkx():
+    g = graphgen.chung_lu(800, 2.3, 10.0, 200.0, seed=22)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    t = oracle.totals(oracle.net(off, idx))[0]
+    G = _nx_graph(off, idx)
+    assert t[4] == sum(nx.triangles(G).values()) // 3
+    assert t[1] == G.number_of_edges()
