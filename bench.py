@@ -286,6 +286,16 @@ def main():
         fg.totals(out)
     torch.cuda.synchronize()
     totals_ms = 1e3 * (time.perf_counter() - t2) / args.steps
+    # the transform with the sub-dictionary Sigma_5 (orbits 0-4) of the same graph
+    out5 = torch.empty((n, 5), dtype=torch.int64, device="cuda")
+    fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(args.steps):
+        fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
+    torch.cuda.synchronize()
+    sigma5_ms = 1e3 * (time.perf_counter() - t3) / args.steps
+    del out5
 
     # dominant counting segment and its roofline
     counted = {k: v for k, v in seg_avg.items() if k in SEG_UNITS}
@@ -301,7 +311,8 @@ def main():
                 "alg_bytes_per_launch": int(alg_bytes), "units_per_launch": int(units),
                 "unit_of_work": SEG_UNITS[dom][0], "bytes_per_unit": SEG_UNITS[dom][1]}
 
-    extra = {"build_csr_ms": round(build_ms, 3), "totals_ms": round(totals_ms, 4), "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
+    extra = {"build_csr_ms": round(build_ms, 3), "totals_ms": round(totals_ms, 4),
+             "sigma5_ms": round(sigma5_ms, 4), "sigma5_edges_per_s": round(m / (sigma5_ms / 1e3), 1), "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
              "path_alg_gbps": round(path_bytes / (ms_per_step / 1e3) / 1e9, 2),
              "stats": {k: v for k, v in st.items() if k != "seg_ms"}}
     if not args.no_batch:

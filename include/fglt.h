@@ -55,6 +55,11 @@ typedef enum {
 #define FGLT_NET 1u          /* write net frequencies (Table II applied) instead of raw */
 #define FGLT_TIMING 2u       /* time each launch segment with HIP events on `stream` (fills
                                 fglt_stats.seg_ms; adds a final synchronization)         */
+#define FGLT_SIGMA5 4u       /* the transform with the sub-dictionary Sigma_5 only (node,
+                                edge, the 2-path end and centre, triangle: orbits 0-4;
+                                Theorem 1): `out` is [n][5], and only the degree,
+                                triangle and 2-path steps run (no clique, diamond,
+                                second row pass or 4-cycle pass; their segments time 0) */
 
 /* Launch segments of fglt_raw, in execution order (indices into seg_ms). */
 enum {
@@ -144,9 +149,12 @@ typedef struct {
  *   offsets      [n+1] int64, offsets[0] == 0, non-decreasing, offsets[n] == nnz
  *   indices      [nnz] int32; the CSR must be canonical: symmetric, no
  *                self-loops, no repeated entry in a row (rows need not be sorted)
- *   out          out [n][16] int64
+ *   out          out [n][16] int64, or [n][5] with FGLT_SIGMA5
  *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
- *   flags        FGLT_NET, FGLT_TIMING or 0
+ *   flags        any of FGLT_NET, FGLT_TIMING and FGLT_SIGMA5, or 0.  With
+ *                FGLT_SIGMA5 the five columns are the first five of the full
+ *                transform (raw or net): the leading 5x5 block of U16 is the
+ *                whole conversion for orbits 0-4 (Section IV, Table II)
  *   plan         (host) optional tier thresholds, NULL for the defaults
  *   stats        (host) optional, filled on success
  * Returns FGLT_ENOTCANON for a CSR that breaks the contract (checked on the

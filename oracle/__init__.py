@@ -13,6 +13,9 @@ Contents
 * ``bruteforce`` (module) -- enumeration of every vertex subset of size <= 4,
   the definition of raw and net frequencies, for tiny graphs.
 * ``U16`` -- Table II as a dense integer matrix.
+* ``sigma5`` -- the transform with the sub-dictionary Sigma_5 (Theorem 1) by
+  sparse matrix products, independent of ``raw``.
+* ``totals`` -- graph-level induced-graphlet counts from net frequencies.
 """
 from __future__ import annotations
 
@@ -133,6 +136,34 @@ def raw_to_net(raw_counts) -> np.ndarray:
 def net(offsets, indices, vertices=None, threads: int = 0) -> np.ndarray:
     """Net frequencies: Table I followed by Table II."""
     return raw_to_net(raw(offsets, indices, vertices, threads))
+
+
+def sigma5(offsets, indices, net: bool = False) -> np.ndarray:
+    """The transform with the sub-dictionary Sigma_5 (the section on the
+    transform with Sigma_5, Theorem 1), by its own route and not through
+    ``raw``: with the adjacency matrix A (scipy's sparse product as the one
+    library step) d0 = e, d1 = p1 = A e, d2 = p2 = A p1 - p1,
+    d3 = p1 (p1 - 1) / 2 and d4 = c3 = (A .* A^2) e / 2, the triangles at each
+    vertex; net by the leading 5x5 block of Table II (f2 = d2 - 2 c3,
+    f3 = d3 - c3).  [n, 5] int64.  A^2 is formed whole, so this is for small
+    and medium graphs."""
+    import scipy.sparse as sp
+
+    off = np.asarray(offsets, dtype=np.int64)
+    idx = np.asarray(indices, dtype=np.int64)
+    n = off.size - 1
+    A = sp.csr_matrix((np.ones(idx.size, dtype=np.int64), idx, off), shape=(n, n))
+    e = np.ones(n, dtype=np.int64)
+    p1 = A @ e
+    p2 = A @ p1 - p1
+    c3 = np.asarray(A.multiply(A @ A).sum(axis=1), dtype=np.int64).reshape(n)
+    assert np.all(c3 % 2 == 0)
+    c3 //= 2
+    out = np.stack([e, p1, p2, p1 * (p1 - 1) // 2, c3], axis=1).astype(np.int64)
+    if net:
+        out[:, 2] -= 2 * c3
+        out[:, 3] -= c3
+    return out
 
 
 # Fig. 1: how many vertices of orbit k's graphlet lie in orbit k (node;

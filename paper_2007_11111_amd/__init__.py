@@ -15,7 +15,7 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, FGLT_TIMING, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_SIGMA5, FGLT_TIMING, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
     "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "FgltError", "Stats",
@@ -67,10 +67,11 @@ def raw_workspace_bytes(n: int, nnz: int) -> int:
 
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
         workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
-        timing: bool = False, stream=None):
+        timing: bool = False, sigma5: bool = False, stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
-    (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
+    ([n, 5] with sigma5=True: the transform with the sub-dictionary Sigma_5 of
+    Theorem 1, orbits 0-4 only) (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
     thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max and the
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events)."""
@@ -82,8 +83,10 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     n = int(offsets.numel()) - 1
     nnz = int(indices.numel())
     dev = offsets.device
+    cols = 5 if sigma5 else NORBITS
     if out is None:
-        out = torch.empty((max(n, 0), NORBITS), dtype=torch.int64, device=dev)
+        out = torch.empty((max(n, 0), cols), dtype=torch.int64, device=dev)
+    assert out.dtype == torch.int64 and out.is_contiguous() and out.device == dev and out.numel() >= n * cols
     ws_bytes = int(L.fglt_raw_workspace(n, nnz))
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -94,7 +97,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
                      int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
-                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0), ctypes.byref(rp) if rp is not None else None,
+                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | (FGLT_SIGMA5 if sigma5 else 0), ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st), _stream(stream)),
           "fglt_raw")
     return (out, st.as_dict()) if stats else out

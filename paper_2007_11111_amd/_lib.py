@@ -33,6 +33,7 @@ class FgltError(RuntimeError):
 
 
 FGLT_TIMING = 2
+FGLT_SIGMA5 = 4
 SEGMENTS = ["check", "relabel", "structure", "tri1_wave", "tri1_lds", "tri1_global", "fill",
             "tri2_wave", "tri2_lds", "tri2_global", "l2", "c4_wave", "c4_block", "c4_hash", "c4_window",
             "finalize"]

@@ -46,6 +46,43 @@ int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
     return FGLT_OK;
 }
 
+// The last timing event, the triangle total and the statistics of fglt_raw.
+int finish(int64_t n, RawWs& w, const DevPlan& hp, SegTimer& tm, fglt_stats* stats, hipStream_t s) {
+    int st = FGLT_OK;
+    if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
+    i64 triangles = -1;
+    if (stats) {
+        FGLT_HIP_TRY(launch_count_triangles(n, w, s));
+        DevPlan fin{};
+        if ((st = read_plan(w, fin, s))) return st;
+        triangles = fin.triangles / 6;  // twice at each of its three vertices
+    }
+
+    if (stats) {
+        stats->d_max = hp.d_max;
+        stats->dplus_max = hp.dplus_max;
+        stats->tri_items = hp.tri_items;
+        stats->wedge_items = hp.wedge_items;
+        for (int k = 0; k < 3; ++k) {
+            stats->tri_tier_vertices[k] = hp.n_tri[k];
+            stats->tri_items_tier[k] = hp.tri_items_tier[k];
+        }
+        for (int k = 0; k < 4; ++k) {
+            stats->c4_tier_vertices[k] = hp.n_c4[k];
+            stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
+        }
+        stats->triangles = triangles;
+        if (tm.on) {
+            for (int k = 0; k < FGLT_NSEG; ++k) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) return FGLT_EHIP;
+                stats->seg_ms[k] = ms;
+            }
+        }
+    }
+    return FGLT_OK;
+}
+
 }  // namespace
 
 extern "C" size_t fglt_raw_workspace(int64_t n, int64_t nnz) {
@@ -61,7 +98,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~(FGLT_NET | FGLT_TIMING)) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_SIGMA5)) return FGLT_EINVAL;
     if (stats) {
         *stats = fglt_stats{};
         stats->n = n;
@@ -112,6 +149,16 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     // 3. counting
     FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
+    if (flags & FGLT_SIGMA5) {
+        // Sigma_5 (Theorem 1): degrees, triangles per edge and vertex, and the
+        // neighbour-degree sums p2 are the whole transform
+        FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, false, s, tm));
+        tm.mark(FGLT_SEG_FILL, s);
+        FGLT_HIP_TRY(launch_fill_c3(nnz, w, false, s));
+        for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_FINALIZE; ++seg) tm.mark(seg, s);
+        FGLT_HIP_TRY(launch_finalize5(n, w, out, (flags & FGLT_NET) != 0, s));
+        return finish(n, w, hp, tm, stats, s);
+    }
     // the 4-cycle pass's hash tiers and window setup share no memory with the
     // triangle and clique passes: a second stream runs them alongside, and the
     // window kernel (after the join) takes the whole GPU
@@ -144,38 +191,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_c4_late(n, nnz, w, hp, tiers.c4_rows, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
-    if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
-    i64 triangles = -1;
-    if (stats) {
-        FGLT_HIP_TRY(launch_count_triangles(n, w, s));
-        DevPlan fin{};
-        if ((st = read_plan(w, fin, s))) return st;
-        triangles = fin.triangles / 6;  // twice at each of its three vertices
-    }
-
-    if (stats) {
-        stats->d_max = hp.d_max;
-        stats->dplus_max = hp.dplus_max;
-        stats->tri_items = hp.tri_items;
-        stats->wedge_items = hp.wedge_items;
-        for (int k = 0; k < 3; ++k) {
-            stats->tri_tier_vertices[k] = hp.n_tri[k];
-            stats->tri_items_tier[k] = hp.tri_items_tier[k];
-        }
-        for (int k = 0; k < 4; ++k) {
-            stats->c4_tier_vertices[k] = hp.n_c4[k];
-            stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
-        }
-        stats->triangles = triangles;
-        if (tm.on) {
-            for (int k = 0; k < FGLT_NSEG; ++k) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, tm.ev[k], tm.ev[k + 1]) != hipSuccess) return FGLT_EHIP;
-                stats->seg_ms[k] = ms;
-            }
-        }
-    }
-    return FGLT_OK;
+    return finish(n, w, hp, tm, stats, s);
 }
 
 extern "C" int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream) {

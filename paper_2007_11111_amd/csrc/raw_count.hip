@@ -444,6 +444,30 @@ __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __res
     }
 }
 
+// The transform with Sigma_5 (Theorem 1): the five tri-node orbits, raw
+// (Table I's first rows) or net (the leading 5x5 block of Table II, which no
+// quad-node orbit enters), scattered to caller order as [n][5].
+__global__ void k_finalize5(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
+                            const i64* __restrict__ sumd, const i64* __restrict__ c3x2, i64* __restrict__ out,
+                            int net) {
+    for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
+        const i64 d = rdeg[r];
+        const i64 c3 = c3x2[r] >> 1;
+        i64 f2 = sumd[r] - d;                    // p2
+        i64 f3 = d * (d - 1) / 2;                // C(p1, 2)
+        if (net) {
+            f2 -= 2 * c3;  // a triangle closes two of the 2-paths that end at the vertex
+            f3 -= c3;      // and one pair of its neighbours
+        }
+        i64* o = out + (i64)perm[r] * 5;
+        o[0] = 1;
+        o[1] = d;
+        o[2] = f2;
+        o[3] = f3;
+        o[4] = c3;
+    }
+}
+
 __global__ void k_net(i64 n, const i64* __restrict__ raw, i64* __restrict__ net) {
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
         i64 f[16];
@@ -547,6 +571,12 @@ hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7, w.c3x2,
                        w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize5(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize5, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.c3x2,
+                       out, net ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -90,6 +90,13 @@ def test_workload_digest(fg, name):
         f2 = fg.net(fg.raw(off, idx, plan={"c4_window_rows": rows}))
         torch.cuda.synchronize()
         assert sha(f2.cpu().numpy()) == d["net_sha256"], f"net digest mismatch with c4_window_rows={rows}"
+    # the transform with Sigma_5 gives the first five columns (raw and net)
+    say(f"workload {name}: sigma5")
+    s5n = fg.raw(off, idx, net=True, sigma5=True)
+    s5r = fg.raw(off, idx, sigma5=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s5n.cpu().numpy(), f_h[:, :5])
+    np.testing.assert_array_equal(s5r.cpu().numpy(), raw.cpu().numpy()[:, :5])
     # a stratified vertex sample recomputed live by the oracle (small degrees only:
     # the oracle's per-vertex cost grows with the square of the neighbourhood)
     deg = np.diff(off_h)

@@ -370,3 +370,48 @@ def test_errors(fg):
     exp = np.zeros((10, 16), np.int64)
     exp[:, 0] = 1
     np.testing.assert_array_equal(f, exp)
+
+
+# ------------------------------------------------------------------ the transform with Sigma_5
+
+def gpu_sigma5(fg, off, idx, plan=None, net=False):
+    o, i = to_dev(off, idx)
+    out = fg.raw(o, i, net=net, plan=plan, sigma5=True)
+    torch.cuda.synchronize()
+    assert tuple(out.shape) == (off.size - 1, 5)
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("plan", ["default", "wave", "block", "global"])
+def test_sigma5(fg, plan):
+    """FGLT_SIGMA5 ([n][5], Theorem 1) against the oracle's sparse-product
+    route, raw and net, with the triangle pass in each tier: the small random
+    graphs (a lone vertex, isolated vertices), K_600 and the ER config."""
+    graphs = _small_graphs()
+    k = graphgen.clique(600)
+    graphs.append((k.n, list(zip(k.src.tolist(), k.dst.tolist()))))
+    for gi, (n, edges) in enumerate(graphs):
+        say(f"sigma5 graph {gi} n={n} m={len(edges)} plan={plan}")
+        off, idx = csr_arrays(n, edges)
+        np.testing.assert_array_equal(gpu_sigma5(fg, off, idx, PLANS[plan]), oracle.sigma5(off, idx))
+        np.testing.assert_array_equal(gpu_sigma5(fg, off, idx, PLANS[plan], net=True), oracle.sigma5(off, idx, net=True))
+    g = graphgen.erdos_renyi(2000, 0.005, seed=1)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    np.testing.assert_array_equal(gpu_sigma5(fg, off, idx, PLANS[plan], net=True), oracle.sigma5(off, idx, net=True))
+
+
+def test_sigma5_medium_and_stats(fg):
+    """A 20k-vertex power-law graph against the first five columns of the
+    oracle's full transform; statistics and per-segment timing still come back,
+    with the skipped segments at zero."""
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    exp = oracle.net(off, idx)[:, :5]
+    o, i = to_dev(off, idx)
+    out, st = fg.raw(o, i, net=True, sigma5=True, stats=True, timing=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), exp)
+    assert st["triangles"] == int(exp[:, 4].sum()) // 3
+    seg = st["seg_ms"]
+    for name in ("tri2_wave", "tri2_lds", "tri2_global", "l2", "c4_window"):
+        assert seg[name] < 0.05, (name, seg[name])

@@ -331,3 +331,57 @@ def test_totals_triangles_match_networkx():
     G = _nx_graph(off, idx)
     assert t[4] == sum(nx.triangles(G).values()) // 3
     assert t[1] == G.number_of_edges()
+
+
+# ---------------------------------------------------------------- the transform with Sigma_5
+
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_sigma5_vs_bruteforce(seed):
+    """Theorem 1's five orbits against enumeration of every subset of <= 3
+    vertices (the brute force's first five columns), raw and net."""
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 10))
+    p = float(rng.choice([0.2, 0.5, 0.8, 1.0]))
+    edges = random_graph(rng, n, p)
+    off, idx = csr_of(n, edges)
+    raw, net = bruteforce.frequencies(n, edges)
+    np.testing.assert_array_equal(oracle.sigma5(off, idx), raw[:, :5])
+    np.testing.assert_array_equal(oracle.sigma5(off, idx, net=True), net[:, :5])
+
+
+def test_sigma5_closed_forms():
+    """K_n: every 2-path closes, so the net path orbits vanish; a star's
+    centre holds C(k, 2) bi-forks and its leaves k - 1 paths each; a cycle of
+    length >= 4 has no triangle."""
+    for n in (1, 2, 3, 7):
+        g = graphgen.clique(n)
+        off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+        d = n - 1
+        np.testing.assert_array_equal(oracle.sigma5(off, idx), np.tile([1, d, d * (d - 1), C(d, 2), C(d, 2)], (n, 1)))
+        np.testing.assert_array_equal(oracle.sigma5(off, idx, net=True), np.tile([1, d, 0, 0, C(d, 2)], (n, 1)))
+    k = 6
+    g = graphgen.star(k)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.sigma5(off, idx, net=True)
+    centre = int(np.argmax(np.diff(off)))
+    np.testing.assert_array_equal(f[centre], [1, k, 0, C(k, 2), 0])
+    leaves = np.delete(f, centre, axis=0)
+    np.testing.assert_array_equal(leaves, np.tile([1, 1, k - 1, 0, 0], (k, 1)))
+    g = graphgen.cycle(9)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    np.testing.assert_array_equal(oracle.sigma5(off, idx, net=True), np.tile([1, 2, 2, 1, 0], (9, 1)))
+
+
+@pytest.mark.parametrize("which", ["er", "cl"])
+def test_sigma5_matches_full_transform_and_networkx(which):
+    """The leading block of Table II is the whole conversion for orbits 0-4:
+    the sparse-product route equals the first five columns of the per-vertex
+    evaluation of Table I (raw and net), and c3 equals networkx's triangle
+    count at each vertex."""
+    g = graphgen.erdos_renyi(2000, 0.005, seed=1) if which == "er" else graphgen.chung_lu(3000, 2.2, 12.0, 300.0, seed=5)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    raw = oracle.raw(off, idx)
+    np.testing.assert_array_equal(oracle.sigma5(off, idx), raw[:, :5])
+    np.testing.assert_array_equal(oracle.sigma5(off, idx, net=True), oracle.raw_to_net(raw)[:, :5])
+    tri = nx.triangles(_nx_graph(off, idx))
+    np.testing.assert_array_equal(oracle.sigma5(off, idx)[:, 4], [tri[v] for v in range(g.n)])
