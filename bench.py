@@ -222,6 +222,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sigma5", action="store_true", help="skip the Sigma_5 leg (keeps profiles to the full path)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--traffic-from", metavar="DIR",
@@ -287,15 +288,17 @@ def main():
     torch.cuda.synchronize()
     totals_ms = 1e3 * (time.perf_counter() - t2) / args.steps
     # the transform with the sub-dictionary Sigma_5 (orbits 0-4) of the same graph
-    out5 = torch.empty((n, 5), dtype=torch.int64, device="cuda")
-    fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for _ in range(args.steps):
+    sigma5_ms = None
+    if not args.no_sigma5:
+        out5 = torch.empty((n, 5), dtype=torch.int64, device="cuda")
         fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
-    torch.cuda.synchronize()
-    sigma5_ms = 1e3 * (time.perf_counter() - t3) / args.steps
-    del out5
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(args.steps):
+            fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
+        torch.cuda.synchronize()
+        sigma5_ms = 1e3 * (time.perf_counter() - t3) / args.steps
+        del out5
 
     # dominant counting segment and its roofline
     counted = {k: v for k, v in seg_avg.items() if k in SEG_UNITS}
@@ -312,7 +315,8 @@ def main():
                 "unit_of_work": SEG_UNITS[dom][0], "bytes_per_unit": SEG_UNITS[dom][1]}
 
     extra = {"build_csr_ms": round(build_ms, 3), "totals_ms": round(totals_ms, 4),
-             "sigma5_ms": round(sigma5_ms, 4), "sigma5_edges_per_s": round(m / (sigma5_ms / 1e3), 1), "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
+             "sigma5_ms": round(sigma5_ms, 4) if sigma5_ms else None,
+             "sigma5_edges_per_s": round(m / (sigma5_ms / 1e3), 1) if sigma5_ms else None, "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
              "path_alg_gbps": round(path_bytes / (ms_per_step / 1e3) / 1e9, 2),
              "stats": {k: v for k, v in st.items() if k != "seg_ms"}}
     if not args.no_batch:
