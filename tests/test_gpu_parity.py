@@ -372,6 +372,32 @@ def test_errors(fg):
     np.testing.assert_array_equal(f, exp)
 
 
+def test_max_degree(fg):
+    """The largest admitted degree, 2^21 - 1, at the centre of a star: C(d, 3)
+    there is within a factor 6 of the int64 limit and the product
+    d (d - 1) (d - 2) just fits; the Sigma_5 transform agrees; one more leaf
+    is rejected with FGLT_EOVERFLOW before any counting."""
+    k = (1 << 21) - 1
+    g = graphgen.star(k)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say(f"star at the degree limit, k={k}")
+    f = gpu_raw(fg, off, idx, net=True)
+    centre = np.zeros(16, dtype=np.int64)
+    centre[[0, 1, 3, 8]] = [1, k, C(k, 2), C(k, 3)]
+    leaf = np.zeros(16, dtype=np.int64)
+    leaf[[0, 1, 2, 7]] = [1, 1, k - 1, C(k - 1, 2)]
+    np.testing.assert_array_equal(f[0], centre)
+    assert (f[1:] == leaf).all()
+    o, i = to_dev(off, idx)
+    f5 = fg.raw(o, i, net=True, sigma5=True)
+    torch.cuda.synchronize()
+    assert (f5.cpu().numpy() == f[:, :5]).all()
+    g = graphgen.star(k + 1)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    say("star one past the degree limit")
+    assert _status(fg, off, idx) == -4
+
+
 # ------------------------------------------------------------------ the transform with Sigma_5
 
 def gpu_sigma5(fg, off, idx, plan=None, net=False):
