@@ -95,3 +95,76 @@ def test_mutant_is_caught(tmp_path, name, old, new):
             caught = True
             break
     assert caught, f"mutant '{name}' survived every pin"
+
+
+# The same for the Python parts of the oracle: the Sigma_5 route by sparse
+# products and the graph-level totals.  A mutant is the function's source
+# with one planted mistake, compiled into a copy of the oracle's namespace.
+PY_MUTANTS = [
+    ("sigma5", "p2 keeps the walk back", "p2 = A @ p1 - p1", "p2 = A @ p1"),
+    ("sigma5", "c3 not halved", "c3 //= 2", "c3 //= 1"),
+    ("sigma5", "c3 without the edge mask", "A.multiply(A @ A)", "(A @ A)"),
+    ("sigma5", "C(p1, 2) shifted", "p1 * (p1 - 1) // 2", "p1 * (p1 + 1) // 2"),
+    ("sigma5", "net d2 takes c3 once", "out[:, 2] -= 2 * c3", "out[:, 2] -= c3"),
+    ("sigma5", "net d3 takes c3 twice", "out[:, 3] -= c3", "out[:, 3] -= 2 * c3"),
+    ("totals", "no division by m_k", "out[g] = col // ORBIT_NODES", "out[g] = col"),
+    ("totals", "every graph's rows", "col = f[off[g]:off[g + 1]].sum(axis=0)", "col = f.sum(axis=0)"),
+]
+
+
+def _mutated(fn, old, new):
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, fn)))
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant of oracle.{fn}>", "exec"), ns)
+    return ns[fn]
+
+
+def _edges_of(n, off, idx):
+    return [(i, int(j)) for i in range(n) for j in idx[off[i]:off[i + 1]] if i < j]
+
+
+def _sigma5_ok(f):
+    for n, off, idx, (br, bn) in _CASES:
+        try:
+            if not (np.array_equal(f(off, idx), br[:, :5]) and np.array_equal(f(off, idx, net=True), bn[:, :5])):
+                return False
+        except Exception:
+            return False
+    return True
+
+
+def _totals_ok(f):
+    # each case alone, then the first two cases as one batch of two graphs
+    for n, off, idx, (_, bn) in _CASES:
+        try:
+            if not np.array_equal(f(bn)[0], bruteforce.graphlet_copies(n, _edges_of(n, off, idx))):
+                return False
+        except Exception:
+            return False
+    (n1, o1, i1, (_, b1)), (n2, o2, i2, (_, b2)) = _CASES[0], _CASES[1]
+    exp = np.stack([bruteforce.graphlet_copies(n1, _edges_of(n1, o1, i1)),
+                    bruteforce.graphlet_copies(n2, _edges_of(n2, o2, i2))])
+    try:
+        return np.array_equal(f(np.concatenate([b1, b2]), [0, n1, n1 + n2]), exp)
+    except Exception:
+        return False
+
+
+def test_python_pins_accept_the_oracle():
+    global _CASES
+    if _CASES is None:
+        _CASES = _cases()
+    assert _sigma5_ok(oracle.sigma5) and _totals_ok(oracle.totals)
+
+
+@pytest.mark.parametrize("fn,name,old,new", PY_MUTANTS, ids=[f"{m[0]}: {m[1]}" for m in PY_MUTANTS])
+def test_python_mutant_is_caught(fn, name, old, new):
+    global _CASES
+    if _CASES is None:
+        _CASES = _cases()
+    f = _mutated(fn, old, new)
+    ok = _sigma5_ok(f) if fn == "sigma5" else _totals_ok(f)
+    assert not ok, f"mutant '{name}' of oracle.{fn} survived every pin"
