@@ -86,7 +86,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     cols = 5 if sigma5 else NORBITS
     if out is None:
         out = torch.empty((max(n, 0), cols), dtype=torch.int64, device=dev)
-    assert out.dtype == torch.int64 and out.is_contiguous() and out.device == dev and out.numel() >= n * cols
+    if out.dtype != torch.int64 or not out.is_contiguous() or out.device != dev or tuple(out.shape) != (max(n, 0), cols):
+        raise ValueError(f"out must be a contiguous int64 tensor of shape ({n}, {cols}) on {dev}")
     ws_bytes = int(L.fglt_raw_workspace(n, nnz))
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
