@@ -171,6 +171,44 @@ def cpu_baseline(off, idx, m, sample, seed=0):
     }
 
 
+def serving_leg(fg, torch, num=24, qps=100.0, seed=5):
+    """Serving: Poisson arrivals (rate qps) of Chung-Lu requests with
+    n = 10^U[3,6] through the HBM-budget server (GpuExecutor, four streams);
+    latency from submission to result, after one warm-up request."""
+    import graphgen
+    from paper_2007_11111_amd.server import GpuExecutor, Server
+    csrs = []
+    for g in graphgen.serving_requests(num, seed):
+        o, i = fg.build_csr(g.n, torch.from_numpy(g.src).cuda(), torch.from_numpy(g.dst).cuda())
+        csrs.append((o.cpu().numpy(), i.cpu().numpy()))
+    arrivals = graphgen.poisson_arrivals(num, qps, seed)
+    srv = Server(GpuExecutor(), budget_bytes=64 << 30, streams=4)
+    lat = []
+    try:
+        srv.submit(*csrs[0]).result(timeout=300).release()
+        futs = []
+        t0 = time.perf_counter()
+        for k, (o, i) in enumerate(csrs):
+            wait = t0 + arrivals[k] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            ts = time.perf_counter()
+            f = srv.submit(o, i)
+            f.add_done_callback(lambda _f, ts=ts: lat.append(time.perf_counter() - ts))
+            futs.append(f)
+        for f in futs:
+            f.result(timeout=300).release()
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
+    lat_ms = 1e3 * np.array(lat)
+    edges = sum(int(i.size) // 2 for _, i in csrs)
+    return {"requests": num, "qps_offered": qps, "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "max_ms": round(float(lat_ms.max()), 3),
+            "mean_n": round(float(np.mean([o.size - 1 for o, _ in csrs])), 1), "edges": edges,
+            "wall_s": round(wall, 3)}
+
+
 def batch_leg(fg, torch, steps):
     import graphgen
     import oracle
@@ -222,6 +260,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sigma5", action="store_true", help="skip the Sigma_5 leg (keeps profiles to the full path)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration) and exit")
@@ -321,6 +360,8 @@ def main():
              "stats": {k: v for k, v in st.items() if k != "seg_ms"}}
     if not args.no_batch:
         extra["batch"] = batch_leg(fg, torch, steps=max(3, args.steps))
+    if not args.no_serving:
+        extra["serving"] = serving_leg(fg, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
