@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the fast graphlet transform on one MI355X.
 
-One step is one complete 16-orbit transform of the Chung-Lu workload
-(n = 1,000,000, degree exponent 2.1, mean degree 20, cap 50,000): from the
-canonical CSR resident in HBM to the n x 16 int64 net frequencies resident in
-HBM (fglt_raw with the Table II conversion fused).  The CSR is built once,
-before the timed region, with fglt_build_csr (its time is reported apart).
+One step is one complete 16-orbit transform of the R-MAT scale-22 workload
+(4,194,304 vertices, edge factor 16, quadrant probabilities
+(0.57, 0.19, 0.19, 0.05), ids randomly permuted; the synthetic stand-in of
+the paper's LiveJournal run, Section VI): from the canonical CSR resident in
+HBM to the n x 16 int64 net frequencies resident in HBM (fglt_raw with the
+Table II conversion fused).  The CSR is built once, before the timed region,
+with fglt_build_csr (its time is reported apart).
 
 Prints one JSON line:
-  value       undirected edges per second, m / (seconds per step)
-  roofline    the dominant kernel segment: its algorithmic bytes per launch
-              over its average duration, timed live with HIP events on the
-              library's stream; traffic from committed rocprofv3 counters
+  value         undirected edges per second, m / (median seconds per step)
+  ms_per_step   the median of the timed steps (HIP events on the stream);
+                the mean, p10 and p90 are under extra.step_ms
+  roofline      the dominant kernel segment: its algorithmic bytes per launch
+                (the byte model's bytes per unit x the units it processes)
+                over its average duration, timed live with HIP events on the
+                library's stream in a separate timing pass; traffic from the
+                committed rocprofv3 counters
   cpu_baseline  the CPU oracle timed on a bounded vertex sample of the same graph
-  extra       per-segment times, the batched workload (4096 graphs, one launch)
-              against a per-graph launch loop, and the CSR build time
+  extra         the whole-path byte model, per-segment times, the Chung-Lu and
+                Erdos-Renyi workloads, the sub-dictionary transforms, the
+                batched form against a per-graph launch loop, the serving form
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload cl|er|rmat22]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload rmat22|cl|er|...]
 """
 from __future__ import annotations
 
@@ -34,22 +41,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 
-# Algorithmic bytes per unit of work of each counting segment (see the kernel
-# notes in the sources): unit, bytes per unit.
+WORKLOADS = {
+    "rmat22": ("rmat_scale22_ef16_abcd0.57-0.19-0.19-0.05_permuted", 3),
+    "cl": ("chung_lu_n1M_exp2.1_mean20_cap50k", 2),
+    "er": ("erdos_renyi_n2000_p0.005", 1),
+    "rmat18": ("rmat_scale18_ef16_abcd0.57-0.19-0.19-0.05_permuted", 3),
+    "cl_small": ("chung_lu_n100k_exp2.1_mean20_cap5k", 2),
+}
+
+# The byte model: algorithmic bytes per unit of work of each timed segment.
+#   CSR sweep: 4 B per index and 8 B per row offset; gathers 8 B per int64;
+#   C3 4 B written and 4 B read per entry; 4 B per triangle-merge item (per
+#   pass); 4 B per rank-ordered wedge; 128 B of output per vertex.
 SEG_UNITS = {
-    "l2": ("entry", 36),         # row, index, C3, degree, p2 and c3 of the neighbour, clique counts
-    "tri1_wave": ("item", 4),    # one out-list index per merge item
+    "fill": ("entry", 16),        # CSR sweep (4 B index), gather of p1 (8 B), C3 write (4 B)
+    "l2": ("entry", 24),          # CSR sweep (4 B), gathers of p2 and c3 (16 B), C3 read (4 B)
+    "tri1_wave": ("item", 4),     # triangle pass: one merge item
     "tri1_lds": ("item", 4),
     "tri1_global": ("item", 4),
-    "tri2_wave": ("item", 8),    # out-list index + its C3 per merge item
-    "tri2_lds": ("item", 8),
-    "tri2_global": ("item", 8),
-    "c4_wave": ("wedge", 8),     # wedge end read in the count and attribution passes
-    "c4_block": ("wedge", 8),
-    "c4_hash": ("wedge", 8),
-    "c4_window": ("wedge", 8),
-    "fill": ("entry", 16),       # row, index, mirror's C3, gathered degree
-    "finalize": ("vertex", 232), # 13 accumulators + degree + id in, 128 B row out
+    "tri2_wave": ("item", 4),     # clique/diamond pass: the second merge over the same items
+    "tri2_lds": ("item", 4),
+    "tri2_global": ("item", 4),
+    "c4_wave": ("wedge", 4),      # 4-cycle pass: one rank-ordered wedge
+    "c4_block": ("wedge", 4),
+    "c4_hash": ("wedge", 4),
+    "c4_window": ("wedge", 4),
+    "finalize": ("vertex", 128),  # the n x 16 int64 output row
+}
+
+# The kernel behind each timed segment whose traffic the counters give.
+SEG_KERNEL = {
+    "c4_window": "k_c4_window", "c4_hash": "k_c4_hashbig", "c4_block": "k_c4_hash<4, 4096>",
+    "c4_wave": "k_c4_hash<1, 256>", "tri1_wave": "k_tri1_wave", "tri1_lds": "k_tri1_lds",
+    "tri1_global": "k_tri_block<1, true>", "tri2_wave": "k_tri2s_wave", "tri2_lds": "k_tri2s_lds",
+    "tri2_global": "k_tri_block<2, true>", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
 }
 
 
@@ -65,12 +90,17 @@ def seg_units(seg, st):
     return st["wedge_items_tier"][tier]
 
 
-# The kernel behind each timed segment whose traffic the counters give.
-SEG_KERNEL = {
-    "c4_window": "k_c4_window", "c4_hash": "k_c4_hashbig", "c4_block": "k_c4_hash<4, 4096>",
-    "c4_wave": "k_c4_hash<1, 256>", "tri1_wave": "k_tri1_wave", "tri1_lds": "k_tri1_lds",
-    "tri2_wave": "k_tri2s_wave", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
-}
+def model_bytes(st):
+    """The whole-path byte model: three CSR sweeps, gathers of p1, p2 and c3,
+    the C3 write and read, two triangle-merge passes over sum_E min(d_i, d_j)
+    items, the rank-ordered wedges, the oriented 4-clique merge steps and the
+    net output.  Returns (total, terms)."""
+    n, nnz = st["n"], st["nnz"]
+    s_csr = 8 * (n + 1) + 4 * nnz
+    terms = {"csr_sweeps": 3 * s_csr, "gathers": 24 * nnz, "c3_rw": 8 * nnz,
+             "triangle_merges": 8 * st["min_sum"], "wedges": 4 * st["wedge_items"],
+             "k4_merges": 4 * st["k4_merge"], "output": 128 * n}
+    return sum(terms.values()), terms
 
 
 def source_hash():
@@ -82,10 +112,10 @@ def source_hash():
     return h.hexdigest()
 
 
-def load_traffic(seg):
-    """HBM bytes per launch of the kernel behind `seg` from the committed
-    rocprofv3 counters (profiles/traffic.json), or None if absent or taken on a
-    different kernel source."""
+def load_traffic(seg, workload):
+    """DRAM-side bytes per launch of the kernel behind `seg` on `workload` from
+    the committed rocprofv3 counters (profiles/traffic.json), or None if absent
+    or taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path) or seg not in SEG_KERNEL:
         return None
@@ -96,63 +126,41 @@ def load_traffic(seg):
     if t.get("source_sha256") != source_hash():
         return None
     k = SEG_KERNEL[seg]
-    hits = [v for name, v in t.get("kernels", {}).items() if name == k or name.startswith(k + "<")]
+    ks = t.get("workloads", {}).get(workload, {}).get("kernels", {})
+    hits = [v for name, v in ks.items() if name == k or name.startswith(k + "<")]
     return max(v["bytes_per_launch"] for v in hits) if hits else None
 
 
-def _counter_means(db):
-    """Per-kernel mean of each counter (KiB for FETCH_SIZE / WRITE_SIZE) over
-    the dispatches of a rocprofv3 results database."""
-    import collections
-    import sqlite3
-    con = sqlite3.connect(db)
-    cur = con.cursor()
-    cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)")]
-    ki, ci, vi = cols.index("kernel_name"), cols.index("counter_name"), cols.index("value")
-    di = cols.index("dispatch_id")
-    tot = collections.defaultdict(float)
-    disp = collections.defaultdict(set)
-    for r in cur.execute("select * from counters_collection"):
-        name = r[ki].split("(")[0].replace("void ", "").replace("fglt::", "")
-        tot[(name, r[ci])] += r[vi]
-        disp[(name, r[ci])].add(r[di])
-    return {k: v / len(disp[k]) for k, v in tot.items()}
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
-def write_traffic(prof_dir, command):
-    """profiles/traffic.json from four rocprofv3 --pmc runs under prof_dir
-    (fetch/, write/: the benchmark; cfetch/, cwrite/: --copy-calibration 1024).
-    Each counter is scaled by what it reads for the plain 1 GiB device copy."""
-    import glob
-    def db(sub):
-        return glob.glob(os.path.join(prof_dir, sub, "*_results.db"))[0]
-    copy_bytes = 1024 << 20
-    cf = _counter_means(db("cfetch"))
-    cw = _counter_means(db("cwrite"))
-    fetch_copy = cf[("__amd_rocclr_copyBuffer", "FETCH_SIZE")] * 1024
-    write_copy = cw[("__amd_rocclr_copyBuffer", "WRITE_SIZE")] * 1024
-    fs, ws_ = copy_bytes / fetch_copy, copy_bytes / write_copy
-    f = _counter_means(db("fetch"))
-    w = _counter_means(db("write"))
-    kernels = {}
-    for (name, ctr), v in f.items():
-        if ctr != "FETCH_SIZE" or not name.startswith("k_"):
-            continue
-        wr = w.get((name, "WRITE_SIZE"), 0.0)
-        kernels[name] = {"fetch_kib": round(v, 1), "write_kib": round(wr, 1),
-                         "bytes_per_launch": int(v * 1024 * fs + wr * 1024 * ws_)}
-    out = {"source_sha256": source_hash(), "command": command,
-           "calibration": {"copy_bytes": copy_bytes, "fetch_bytes_read": fetch_copy, "write_bytes_read": write_copy,
-                           "fetch_scale": fs, "write_scale": ws_},
-           "kernels": dict(sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"]))}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    os.makedirs(os.path.dirname(path), exist_ok=True)
-    with open(path, "w") as fh:
-        json.dump(out, fh, indent=1)
-    return out
+def time_steps(torch, fn, steps, warmup):
+    """Runs fn() warmup times, then `steps` times, each bracketed by HIP
+    events on the current stream; the whole timed region is bracketed by
+    device synchronizations.  Returns (per-step ms list, wall seconds)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
+def step_summary(ms):
+    return {"median": round(pct(ms, 50), 4), "p10": round(pct(ms, 10), 4), "p90": round(pct(ms, 90), 4),
+            "mean": round(float(np.mean(ms)), 4), "count": len(ms)}
 
 
 def cpu_baseline(off, idx, m, sample, seed=0):
+    """The oracle on `sample` uniformly drawn vertices of the graph, on every
+    host core; edges/s scaled as m * (sample / n) / seconds."""
     import oracle
     n = off.shape[0] - 1
     rng = np.random.default_rng(seed)
@@ -166,9 +174,89 @@ def cpu_baseline(off, idx, m, sample, seed=0):
         "unit": "edges/s",
         "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"{sel.size} uniformly drawn vertices of {n} ({100 * frac:.1f}%), all 16 orbits, "
+        "sample": f"{sel.size} uniformly drawn vertices of {n} ({100 * frac:.2f}%), all 16 orbits, "
                   f"{dt:.1f} s; value = m * (sample/n) / seconds",
     }
+
+
+def build_workload(fg, torch, name):
+    """Edge list of a named workload -> canonical CSR on the device with
+    fglt_build_csr (timed apart)."""
+    import graphgen
+    g = graphgen.make(name)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off, idx = fg.build_csr(g.n, src, dst)
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    del src, dst
+    return g.n, off, idx, build_ms
+
+
+def transform_leg(fg, torch, off, idx, steps, warmup):
+    """Median/p10/p90 of the full transform of one resident graph."""
+    n, nnz = off.numel() - 1, idx.numel()
+    out = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+    ws = torch.empty(fg.raw_workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda")
+    ms, _ = time_steps(torch, lambda: fg.raw(off, idx, net=True, out=out, workspace=ws), steps, warmup)
+    s = step_summary(ms)
+    s["edges_per_s"] = round((nnz // 2) / (s["median"] / 1e3), 1)
+    return s
+
+
+def batch_leg(fg, torch, steps):
+    """The batched workload: 4096 graphs, n ~ U{16..512}, half ER, half BA,
+    as one block-diagonal CSR built on the device with fglt_build_csr (the
+    union of the graphs' edge lists; no edge crosses two graphs).  Timed one
+    launch at a time (eager) and by HIP-graph replay, against a loop of
+    per-graph fglt_raw calls on one stream."""
+    import graphgen
+    graphs = graphgen.make("batch")
+    sizes = np.array([g.n for g in graphs], dtype=np.int64)
+    vtx = torch.from_numpy(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+    base = np.repeat(vtx[:-1].numpy(), [g.src.size for g in graphs])
+    src = np.concatenate([g.src for g in graphs]).astype(np.int64) + base
+    dst = np.concatenate([g.dst for g in graphs]).astype(np.int64) + base
+    n_total = int(vtx[-1])
+    off_d, idx_d = fg.build_csr(n_total, torch.from_numpy(src.astype(np.int32)).cuda(),
+                                torch.from_numpy(dst.astype(np.int32)).cuda())
+    G = len(graphs)
+    out = torch.empty((n_total, 16), dtype=torch.int64, device="cuda")
+    res = {"graphs": G, "n_total": n_total, "nnz_total": int(idx_d.numel())}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for mode, plan in (("eager", {"use_graph": 0}), ("graph_replay", {"use_graph": 1})):
+            ms, _ = time_steps(torch, lambda: fg.batch(vtx, off_d, idx_d, out=out, plan=plan), steps, 3)
+            st = step_summary(ms)
+            res[mode] = {"ms": st, "graphs_per_s": round(G / (st["median"] / 1e3), 1)}
+        fg.batch_release(s)
+        vtx_d = vtx.to("cuda", torch.int64)
+        ms, _ = time_steps(torch, lambda: fg.totals(out, vtx_d), steps, 1)
+        res["totals_ms"] = step_summary(ms)["median"]
+        # reference point: one fglt_raw (net) per graph, one stream, same device
+        offs = off_d.cpu()
+        per = []
+        for g in range(G):
+            v0, v1 = int(vtx[g]), int(vtx[g + 1])
+            e0, e1 = int(offs[v0]), int(offs[v1])
+            per.append((off_d[v0:v1 + 1] - e0, idx_d[e0:e1] - v0))
+        ws = torch.empty(max(fg.raw_workspace_bytes(int(sizes.max()), max(int(p[1].numel()) for p in per)), 1),
+                         dtype=torch.uint8, device="cuda")
+        outs = [torch.empty((int(sizes[g]), 16), dtype=torch.int64, device="cuda") for g in range(G)]
+        for g in range(16):
+            fg.raw(per[g][0], per[g][1], net=True, out=outs[g], workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in range(G):
+            fg.raw(per[g][0], per[g][1], net=True, out=outs[g], workspace=ws)
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+    res["per_graph_loop_ms"] = round(1e3 * t_loop, 3)
+    res["per_graph_loop_graphs_per_s"] = round(G / t_loop, 1)
+    res["speedup_vs_loop"] = round(t_loop / (res["graph_replay"]["ms"]["median"] / 1e3), 1)
+    return res
 
 
 def serving_leg(fg, torch, num=24, qps=100.0, seed=5):
@@ -209,69 +297,22 @@ def serving_leg(fg, torch, num=24, qps=100.0, seed=5):
             "wall_s": round(wall, 3)}
 
 
-def batch_leg(fg, torch, steps):
-    import graphgen
-    import oracle
-    graphs = graphgen.make("batch")
-    csrs = [oracle.canonical_csr(g.n, g.src, g.dst) for g in graphs]
-    vtx, off, idx = fg.batch_pack(csrs)
-    off_d, idx_d = off.cuda(), idx.cuda()
-    out = torch.empty((int(vtx[-1]), 16), dtype=torch.int64, device="cuda")
-    for _ in range(3):
-        fg.batch(vtx, off_d, idx_d, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fg.batch(vtx, off_d, idx_d, out=out)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / steps
-    # graph-level totals of every graph of the batch (fglt_totals)
-    vtx_d = vtx.to("cuda", torch.int64)
-    tot = fg.totals(out, vtx_d)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        tot = fg.totals(out, vtx_d)
-    torch.cuda.synchronize()
-    t_tot = (time.perf_counter() - t0) / steps
-    # reference point: one fglt_raw + net per graph, one stream, same device
-    dev = [(torch.from_numpy(o).cuda(), torch.from_numpy(i).cuda()) for o, i in csrs]
-    for o, i in dev[:16]:
-        fg.raw(o, i, net=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for o, i in dev:
-        fg.raw(o, i, net=True)
-    torch.cuda.synchronize()
-    t_loop = time.perf_counter() - t0
-    G = len(graphs)
-    return {"graphs": G, "n_total": int(vtx[-1]), "nnz_total": int(idx.numel()),
-            "ms_per_batch": 1e3 * t_batch, "graphs_per_s": G / t_batch,
-            "per_graph_loop_ms": 1e3 * t_loop, "per_graph_loop_graphs_per_s": G / t_loop,
-            "speedup_vs_loop": t_loop / t_batch, "totals_ms": 1e3 * t_tot}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cl", choices=["cl", "er", "rmat22", "cl_small", "rmat18"])
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--workload", default="rmat22", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: by workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-sigma5", action="store_true", help="skip the Sigma_5 leg (keeps profiles to the full path)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the headline workload (no Chung-Lu / ER / sub-dictionary legs)")
+    ap.add_argument("--no-sigma5", action="store_true", help="skip the sub-dictionary legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB (counter calibration) and exit")
-    ap.add_argument("--traffic-from", metavar="DIR",
-                    help="only write profiles/traffic.json from rocprofv3 counter runs under DIR and exit")
-    ap.add_argument("--traffic-command", default="", help="the command recorded with --traffic-from")
+                    help="only run a plain device copy of MIB MiB (counter check) and exit")
     args = ap.parse_args()
-    if args.traffic_from:
-        out = write_traffic(args.traffic_from, args.traffic_command)
-        print(json.dumps(out["calibration"]))
-        return
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20
@@ -288,109 +329,123 @@ def main():
         sys.exit(2)
 
     import torch
-    import graphgen
     import paper_2007_11111_amd as fg
 
-    g = graphgen.make(args.workload)
-    src = torch.from_numpy(g.src).cuda()
-    dst = torch.from_numpy(g.dst).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    off, idx = fg.build_csr(g.n, src, dst)
-    torch.cuda.synchronize()
-    build_ms = 1e3 * (time.perf_counter() - t0)
-    n, nnz = g.n, int(idx.numel())
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    log(f"bench: generating {args.workload}")
+    n, off, idx, build_ms = build_workload(fg, torch, args.workload)
+    nnz = int(idx.numel())
     m = nnz // 2
     out = torch.empty((n, 16), dtype=torch.int64, device="cuda")
     ws = torch.empty(fg.raw_workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda")
 
-    for _ in range(args.warmup):
-        fg.raw(off, idx, net=True, out=out, workspace=ws)
-    torch.cuda.synchronize()
-    seg_sum = {}
-    st = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = fg.raw(off, idx, net=True, out=out, workspace=ws, stats=True, timing=True)
-        for k, v in st["seg_ms"].items():
-            seg_sum[k] = seg_sum.get(k, 0.0) + v
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
-    seg_avg = {k: v / args.steps for k, v in seg_sum.items()}
-    # graph-level totals of the workload (fglt_totals on the net frequencies), after the timed steps
-    fg.totals(out)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        fg.totals(out)
-    torch.cuda.synchronize()
-    totals_ms = 1e3 * (time.perf_counter() - t2) / args.steps
-    # the transform with the sub-dictionary Sigma_5 (orbits 0-4) of the same graph
-    sigma5_ms = None
-    if not args.no_sigma5:
-        out5 = torch.empty((n, 5), dtype=torch.int64, device="cuda")
-        fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        for _ in range(args.steps):
-            fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True)
-        torch.cuda.synchronize()
-        sigma5_ms = 1e3 * (time.perf_counter() - t3) / args.steps
-        del out5
+    # timed region: K full transforms, no statistics or timing flags
+    log(f"bench: {args.steps} timed steps (n={n}, m={m})")
+    ms, wall = time_steps(torch, lambda: fg.raw(off, idx, net=True, out=out, workspace=ws), args.steps, args.warmup)
+    steps = step_summary(ms)
+    t_med = steps["median"] / 1e3
 
-    # dominant counting segment and its roofline
+    # separate pass: per-segment HIP events, plan statistics, byte-model work terms
+    log("bench: segment timing pass")
+    _, st = fg.raw(off, idx, net=True, out=out, workspace=ws, stats=True, workmodel=True)
+    seg_sum = {}
+    reps = 3
+    for _ in range(reps):
+        _, s2 = fg.raw(off, idx, net=True, out=out, workspace=ws, stats=True, timing=True)
+        for k, v in s2["seg_ms"].items():
+            seg_sum[k] = seg_sum.get(k, 0.0) + v
+    seg_avg = {k: v / reps for k, v in seg_sum.items()}
+
     counted = {k: v for k, v in seg_avg.items() if k in SEG_UNITS}
     dom = max(counted, key=counted.get)
     units = seg_units(dom, st)
     alg_bytes = units * SEG_UNITS[dom][1]
     dur_s = seg_avg[dom] / 1e3
     achieved = alg_bytes / dur_s / 1e9 if dur_s > 0 else 0.0
-    path_bytes = sum(seg_units(k, st) * SEG_UNITS[k][1] for k in SEG_UNITS)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": load_traffic(dom),
+                "frac": round(achieved / HBM_PEAK_GBPS, 5), "traffic": load_traffic(dom, args.workload),
                 "kernel": dom, "kernel_ms": round(seg_avg[dom], 4),
                 "alg_bytes_per_launch": int(alg_bytes), "units_per_launch": int(units),
                 "unit_of_work": SEG_UNITS[dom][0], "bytes_per_unit": SEG_UNITS[dom][1]}
+    b_alg, terms = model_bytes(st)
+    b_no_k4 = b_alg - terms["k4_merges"]
+    path_model = {
+        "bytes": int(b_alg), "terms": {k: int(v) for k, v in terms.items()},
+        "t_roof_ms": round(b_alg / (HBM_PEAK_GBPS * 1e9) * 1e3, 3),
+        "frac": round(b_alg / (HBM_PEAK_GBPS * 1e9) / t_med, 4),
+        "frac_without_k4_term": round(b_no_k4 / (HBM_PEAK_GBPS * 1e9) / t_med, 4),
+        "note": "the k4_merges term prices an oriented 4-clique merge listing; the clique pass here "
+                "counts 4-cliques with bitmap AND/popcount over each vertex's out-neighbourhood and "
+                "performs none of those merge steps, so frac credits work that is never done; "
+                "frac_without_k4_term leaves that term out",
+    }
+    seg_model = {k: round(seg_units(k, st) * SEG_UNITS[k][1] / (seg_avg[k] / 1e3) / 1e9, 1)
+                 for k in SEG_UNITS if seg_avg.get(k, 0) > 0.01}
 
-    extra = {"build_csr_ms": round(build_ms, 3), "totals_ms": round(totals_ms, 4),
-             "sigma5_ms": round(sigma5_ms, 4) if sigma5_ms else None,
-             "sigma5_edges_per_s": round(m / (sigma5_ms / 1e3), 1) if sigma5_ms else None, "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
-             "path_alg_gbps": round(path_bytes / (ms_per_step / 1e3) / 1e9, 2),
+    extra = {"step_ms": steps, "wall_s_timed": round(wall, 4), "build_csr_ms": round(build_ms, 3),
+             "path_model": path_model, "seg_ms": {k: round(v, 4) for k, v in seg_avg.items()},
+             "seg_model_gbps": seg_model,
              "stats": {k: v for k, v in st.items() if k != "seg_ms"}}
-    if not args.no_batch:
-        extra["batch"] = batch_leg(fg, torch, steps=max(3, args.steps))
-    if not args.no_serving:
-        extra["serving"] = serving_leg(fg, torch)
+
+    if not args.no_sigma5:
+        log("bench: sub-dictionary legs")
+        out5 = torch.empty((n, 5), dtype=torch.int64, device="cuda")
+        ms5, _ = time_steps(torch, lambda: fg.raw(off, idx, net=True, out=out5, workspace=ws, sigma5=True),
+                            args.steps, 1)
+        extra["sigma5"] = {"ms": step_summary(ms5), "edges_per_s": round(m / (pct(ms5, 50) / 1e3), 1)}
+        del out5
+        mst, _ = time_steps(torch, lambda: fg.totals(out), args.steps, 1)
+        extra["totals_ms"] = round(pct(mst, 50), 4)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        cpu = cpu_baseline(off.cpu().numpy(), idx.cpu().numpy(), m, args.cpu_sample)
+        log("bench: cpu baseline (oracle on a vertex sample)")
+        sample = args.cpu_sample or {"rmat22": 6000, "cl": 20000}.get(args.workload, 20000)
+        cpu = cpu_baseline(off.cpu().numpy(), idx.cpu().numpy(), m, sample)
+    del ws, out
+    torch.cuda.empty_cache()
+
+    if not args.no_legs:
+        for other in ("cl", "er"):
+            if other == args.workload:
+                continue
+            log(f"bench: {other} leg")
+            n2, off2, idx2, b2 = build_workload(fg, torch, other)
+            leg = transform_leg(fg, torch, off2, idx2, max(args.steps, 10), args.warmup)
+            leg.update({"workload": WORKLOADS[other][0], "n": n2, "m": int(idx2.numel()) // 2,
+                        "build_csr_ms": round(b2, 3)})
+            extra[other] = leg
+            del off2, idx2
+            torch.cuda.empty_cache()
+    if not args.no_batch:
+        log("bench: batch leg")
+        extra["batch"] = batch_leg(fg, torch, steps=max(10, args.steps))
+    if not args.no_serving:
+        log("bench: serving leg")
+        extra["serving"] = serving_leg(fg, torch)
 
     rec = {
         "metric": "edges/s, 16-orbit fast graphlet transform (raw + net), one graph",
-        "value": m / (ms_per_step / 1e3),
+        "value": m / t_med,
         "unit": "edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": steps["median"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": {"cl": "chung_lu_n1M_exp2.1_mean20_cap50k", "er": "erdos_renyi_n2000_p0.005",
-                                "rmat22": "rmat_scale22_ef16", "cl_small": "chung_lu_n100k",
-                                "rmat18": "rmat_scale18_ef16"}[args.workload],
-                   "n": n, "m": m, "d_max": st["d_max"], "seed": {"cl": 2, "er": 1, "rmat22": 3}.get(args.workload, 0),
-                   "parallelism": "single-gpu"},
+        "config": {"workload": WORKLOADS[args.workload][0], "n": n, "m": m, "d_max": st["d_max"],
+                   "seed": WORKLOADS[args.workload][1], "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }
-    print(json.dumps(rec))
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -60,6 +60,9 @@ typedef enum {
                                 Theorem 1): `out` is [n][5], and only the degree,
                                 triangle and 2-path steps run (no clique, diamond,
                                 second row pass or 4-cycle pass; their segments time 0) */
+#define FGLT_WORKMODEL 8u    /* also count the work terms of the byte model (statistics only,
+                                not part of the transform; needs `stats`): min_sum and
+                                k4_merge of fglt_stats                                    */
 
 /* Launch segments of fglt_raw, in execution order (indices into seg_ms). */
 enum {
@@ -118,6 +121,11 @@ typedef struct {
     int64_t tri_items_tier[3];    /* merge items per triangle/clique tier                  */
     int64_t wedge_items_tier[4];  /* wedges per 4-cycle tier                               */
     int64_t triangles;           /* triangles in the graph                                */
+    int64_t min_sum;             /* with FGLT_WORKMODEL: sum over edges of min(d_i, d_j), the
+                                    merge work of one oriented triangle listing (else 0)  */
+    int64_t k4_merge;            /* with FGLT_WORKMODEL: sum over oriented triangles
+                                    u < v < w of |N+(u) & N+(v)| + d+(w), the merge steps
+                                    of an oriented 4-clique listing (else 0)              */
     float seg_ms[FGLT_NSEG];     /* with FGLT_TIMING: milliseconds per launch segment     */
 } fglt_stats;
 

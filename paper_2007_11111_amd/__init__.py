@@ -15,11 +15,11 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, FGLT_SIGMA5, FGLT_TIMING, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_SIGMA5, FGLT_TIMING, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
     "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "FgltError", "Stats",
-    "BatchPlan", "batch_pack", "batch", "NORBITS",
+    "BatchPlan", "check_host_csr", "batch_pack", "batch", "batch_release", "batch_status", "totals", "NORBITS",
 ]
 
 
@@ -67,14 +67,16 @@ def raw_workspace_bytes(n: int, nnz: int) -> int:
 
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
         workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
-        timing: bool = False, sigma5: bool = False, stream=None):
+        timing: bool = False, sigma5: bool = False, workmodel: bool = False, stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
     ([n, 5] with sigma5=True: the transform with the sub-dictionary Sigma_5 of
     Theorem 1, orbits 0-4 only) (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
     thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max and the
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
-    timing=True the statistics carry per-segment milliseconds (HIP events)."""
+    timing=True the statistics carry per-segment milliseconds (HIP events); with
+    workmodel=True (and stats=True) they carry the byte model's work terms
+    min_sum and k4_merge (a statistics pass after the transform)."""
     L = lib()
     assert offsets.dtype == torch.int64 and indices.dtype == torch.int32
     assert offsets.is_cuda and indices.is_cuda
@@ -98,7 +100,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
                      int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
-                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | (FGLT_SIGMA5 if sigma5 else 0), ctypes.byref(rp) if rp is not None else None,
+                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | (FGLT_SIGMA5 if sigma5 else 0)
+                     | (FGLT_WORKMODEL if workmodel else 0), ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st), _stream(stream)),
           "fglt_raw")
     return (out, st.as_dict()) if stats else out
@@ -141,9 +144,30 @@ def transform(offsets: torch.Tensor, indices: torch.Tensor, **kw):
     return raw(offsets, indices, net=True, **kw)
 
 
+def check_host_csr(offsets, indices):
+    """Structural checks of a host CSR before it is packed or sent to the
+    device: offsets[0] == 0, offsets non-decreasing, offsets[-1] == len(indices).
+    Raises ValueError.  (Symmetry, self-loops and repeated entries are checked
+    on the device.)"""
+    import numpy as np
+    off = np.asarray(offsets)
+    idx = np.asarray(indices)
+    if off.ndim != 1 or off.shape[0] < 1:
+        raise ValueError("offsets must be a 1-D array of n + 1 entries")
+    if idx.ndim != 1:
+        raise ValueError("indices must be a 1-D array")
+    if int(off[0]) != 0:
+        raise ValueError(f"offsets[0] is {int(off[0])}, not 0")
+    if int(off[-1]) != idx.shape[0]:
+        raise ValueError(f"offsets[-1] is {int(off[-1])}, not len(indices) = {idx.shape[0]}")
+    if off.shape[0] > 1 and bool((np.diff(off) < 0).any()):
+        raise ValueError("offsets decrease")
+
+
 def batch_pack(csrs):
     """Block-diagonal packing of host CSRs [(offsets, indices), ...] (numpy or
-    torch CPU) into (vtx_offsets, offsets, indices) int64/int64/int32 CPU tensors."""
+    torch CPU) into (vtx_offsets, offsets, indices) int64/int64/int32 CPU
+    tensors.  Each CSR must pass check_host_csr (ValueError otherwise)."""
     import numpy as np
     vtx = [0]
     offs = []
@@ -153,6 +177,7 @@ def batch_pack(csrs):
     for off, idx in csrs:
         off = np.asarray(off, dtype=np.int64)
         idx = np.asarray(idx, dtype=np.int32)
+        check_host_csr(off, idx)
         n = off.shape[0] - 1
         offs.append(off[:-1] + base_e)
         idxs.append(idx.astype(np.int64) + base_v)
@@ -192,3 +217,16 @@ def batch(vtx_offsets: torch.Tensor, offsets: torch.Tensor, indices: torch.Tenso
                        _ptr(indices if nnz else None), _ptr(out), ctypes.byref(bp) if bp is not None else None,
                        _ptr(workspace), int(workspace.numel()), _stream(stream)), "fglt_batch")
     return out
+
+
+def batch_release(stream=None):
+    """Frees the HIP graphs ``fglt_batch`` cached for `stream` (None: all streams)."""
+    L = lib()
+    check(L.fglt_batch_release(ctypes.c_void_p(0 if stream is None else stream.cuda_stream)), "fglt_batch_release")
+
+
+def batch_status(workspace: torch.Tensor, stream=None) -> int:
+    """Status word of the last ``fglt_batch`` on `workspace` -- ``fglt_batch_status``
+    (synchronizes with the stream): 0, or FGLT_ENOTCANON (-2) when a graph broke
+    the contract and its rows were skipped."""
+    return int(lib().fglt_batch_status(_ptr(workspace), _stream(stream)))

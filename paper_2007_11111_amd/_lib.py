@@ -34,6 +34,7 @@ class FgltError(RuntimeError):
 
 FGLT_TIMING = 2
 FGLT_SIGMA5 = 4
+FGLT_WORKMODEL = 8
 SEGMENTS = ["check", "relabel", "structure", "tri1_wave", "tri1_lds", "tri1_global", "fill",
             "tri2_wave", "tri2_lds", "tri2_global", "l2", "c4_wave", "c4_block", "c4_hash", "c4_window",
             "finalize"]
@@ -44,7 +45,8 @@ class Stats(ctypes.Structure):
         "n", "nnz", "d_max", "dplus_max", "tri_items", "wedge_items")] + [
         ("tri_tier_vertices", ctypes.c_int64 * 3), ("c4_tier_vertices", ctypes.c_int64 * 4),
         ("tri_items_tier", ctypes.c_int64 * 3), ("wedge_items_tier", ctypes.c_int64 * 4),
-        ("triangles", ctypes.c_int64), ("seg_ms", ctypes.c_float * len(SEGMENTS))]
+        ("triangles", ctypes.c_int64), ("min_sum", ctypes.c_int64), ("k4_merge", ctypes.c_int64),
+        ("seg_ms", ctypes.c_float * len(SEGMENTS))]
 
     def as_dict(self):
         d = {}

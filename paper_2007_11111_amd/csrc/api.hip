@@ -47,13 +47,15 @@ int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
 }
 
 // The last timing event, the triangle total and the statistics of fglt_raw.
-int finish(int64_t n, RawWs& w, const DevPlan& hp, SegTimer& tm, fglt_stats* stats, hipStream_t s) {
+int finish(int64_t n, int64_t nnz, RawWs& w, const DevPlan& hp, SegTimer& tm, unsigned flags, fglt_stats* stats,
+           hipStream_t s) {
     int st = FGLT_OK;
     if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
     i64 triangles = -1;
+    DevPlan fin{};
     if (stats) {
         FGLT_HIP_TRY(launch_count_triangles(n, w, s));
-        DevPlan fin{};
+        if (flags & FGLT_WORKMODEL) FGLT_HIP_TRY(launch_work_model(nnz, w, s));
         if ((st = read_plan(w, fin, s))) return st;
         triangles = fin.triangles / 6;  // twice at each of its three vertices
     }
@@ -72,6 +74,8 @@ int finish(int64_t n, RawWs& w, const DevPlan& hp, SegTimer& tm, fglt_stats* sta
             stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
         }
         stats->triangles = triangles;
+        stats->min_sum = fin.min_sum;
+        stats->k4_merge = fin.k4_merge;
         if (tm.on) {
             for (int k = 0; k < FGLT_NSEG; ++k) {
                 float ms = 0.f;
@@ -98,7 +102,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_SIGMA5)) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_SIGMA5 | FGLT_WORKMODEL)) return FGLT_EINVAL;
     if (stats) {
         *stats = fglt_stats{};
         stats->n = n;
@@ -157,7 +161,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
         FGLT_HIP_TRY(launch_fill_c3(nnz, w, false, s));
         for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_FINALIZE; ++seg) tm.mark(seg, s);
         FGLT_HIP_TRY(launch_finalize5(n, w, out, (flags & FGLT_NET) != 0, s));
-        return finish(n, w, hp, tm, stats, s);
+        return finish(n, nnz, w, hp, tm, flags, stats, s);
     }
     // the 4-cycle pass's hash tiers and window setup share no memory with the
     // triangle and clique passes: a second stream runs them alongside, and the
@@ -191,7 +195,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_c4_late(n, nnz, w, hp, tiers.c4_rows, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
     FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
-    return finish(n, w, hp, tm, stats, s);
+    return finish(n, nnz, w, hp, tm, flags, stats, s);
 }
 
 extern "C" int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream) {

@@ -77,7 +77,8 @@ __device__ __forceinline__ int popc_and(const u64* a, const u64* b, int W) {
 template <int THREADS>
 __global__ void __launch_bounds__(THREADS) k_batch_graph(const i64* __restrict__ vtx, const i64* __restrict__ off,
                                                          const i32* __restrict__ idx, const i32* __restrict__ order,
-                                                         i64 G, i64* __restrict__ out, u32* __restrict__ status) {
+                                                         i64 G, i64 nnz, i64* __restrict__ out,
+                                                         u32* __restrict__ status) {
     __shared__ u64 A[BMAX * BW];
     __shared__ i32 sdeg[BMAX];
     __shared__ i32 sp2[BMAX];
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(THREADS) k_batch_graph(const i64* __restrict__
     for (int i = threadIdx.x; i < n; i += THREADS) {
         const i64 b = off[v0 + i], e = off[v0 + i + 1];
         int len = 0;
-        if (e < b || e - b > n) {
+        if (b < 0 || e > nnz || e < b || e - b > n) {
             atomicOr(&bad, ERR_RANGE);
         } else {
             for (i64 q = b; q < e; ++q) {
@@ -256,7 +257,7 @@ struct CachedGraph {
 static std::mutex g_cache_mu;
 static std::unordered_map<GraphKey, CachedGraph, GraphKeyHash> g_cache;
 
-typedef void (*batch_kernel_t)(const i64*, const i64*, const i32*, const i32*, i64, i64*, u32*);
+typedef void (*batch_kernel_t)(const i64*, const i64*, const i32*, const i32*, i64, i64, i64*, u32*);
 
 static batch_kernel_t pick_kernel(int threads) {
     switch (threads) {
@@ -269,10 +270,10 @@ static batch_kernel_t pick_kernel(int threads) {
 }
 
 static hipError_t enqueue_batch(hipStream_t s, int threads, i64 G, const i64* vtx, const i64* off, const i32* idx,
-                                i64* net, BatchWs& w) {
+                                i64 nnz, i64* net, BatchWs& w) {
     hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, vtx, G, w.order, w.hist, w.status);
     hipLaunchKernelGGL(pick_kernel(threads), dim3((unsigned)G), dim3(threads), 0, s, vtx, off, idx,
-                       (const i32*)w.order, G, net, w.status);
+                       (const i32*)w.order, G, nnz, net, w.status);
     return hipGetLastError();
 }
 
@@ -311,7 +312,7 @@ extern "C" int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const 
     BatchWs w = carve_batch(c, num_graphs);
     if (!c.ok()) return FGLT_EWORKSPACE;
     if (!use_graph) {
-        FGLT_HIP_TRY(enqueue_batch(s, threads, num_graphs, vtx_offsets, offsets, indices, net, w));
+        FGLT_HIP_TRY(enqueue_batch(s, threads, num_graphs, vtx_offsets, offsets, indices, nnz_total, net, w));
         return FGLT_OK;
     }
     // Replay a captured graph for (stream, G, threads), with the kernel
@@ -322,7 +323,7 @@ extern "C" int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const 
     if (it == g_cache.end()) {
         CachedGraph cg;
         FGLT_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_batch(s, threads, num_graphs, vtx_offsets, offsets, indices, net, w);
+        hipError_t e = enqueue_batch(s, threads, num_graphs, vtx_offsets, offsets, indices, nnz_total, net, w);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e != hipSuccess || e2 != hipSuccess || !graph) return FGLT_EHIP;
@@ -367,9 +368,10 @@ extern "C" int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const 
         const i32* a2 = indices;
         const i32* a3 = w.order;
         i64 G = num_graphs;
+        i64 nz = nnz_total;
         i64* a5 = net;
         u32* a6 = w.status;
-        void* args[] = {(void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3, (void*)&G, (void*)&a5, (void*)&a6};
+        void* args[] = {(void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3, (void*)&G, (void*)&nz, (void*)&a5, (void*)&a6};
         hipKernelNodeParams p{};
         p.func = (void*)pick_kernel(threads);
         p.gridDim = dim3((unsigned)num_graphs);

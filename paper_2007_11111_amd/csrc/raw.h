@@ -41,6 +41,8 @@ struct DevPlan {
     i64 wedge_items_tier[4];
     i64 triangles;
     i64 c4_etab;  // entries of the window tier's per-entry window table
+    i64 min_sum;  // byte model (FGLT_WORKMODEL): sum over edges of min(d_i, d_j)
+    i64 k4_merge; // byte model: oriented 4-clique merge steps
 };
 
 // Per-vertex record of rank space, read with one 16-byte load where a kernel
@@ -149,6 +151,7 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_finalize5(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);
+hipError_t launch_work_model(i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_net(i64 n, const i64* raw, i64* net, hipStream_t s);
 
 // Conversion raw -> net (Table II): back-substitution with U16.

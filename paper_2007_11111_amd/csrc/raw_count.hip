@@ -561,6 +561,60 @@ __global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __rest
     }
 }
 
+// Work counts of the byte model (statistics only, FGLT_WORKMODEL), one
+// thread per oriented edge u -> v (an N+ entry of row u):
+//   min_sum  += d(u)                  (the edge's share of sum_E min(d_i, d_j):
+//                                      under the degree order d(u) <= d(v))
+//   k4_merge += |T|^2 + sum_{w in T} d+(w),  T = N+(u) & N+(v)
+// i.e. for every oriented triangle u < v < w the merge of the candidate set
+// T with the out-list of w, the step count of an oriented 4-clique listing.
+// T is found by walking the shorter out-list and searching the longer one.
+__global__ void __launch_bounds__(PT) k_work_model(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
+                                                   const VRec* __restrict__ vrec, i64 nnz, DevPlan* plan) {
+    __shared__ i64 part[PT / WAVE];
+    i64 ms = 0, ko = 0;
+    for (i64 p = (i64)blockIdx.x * PT + threadIdx.x; p < nnz; p += (i64)gridDim.x * PT) {
+        const i32 u = rrow[p], v = ridx[p];
+        if (v <= u) continue;
+        const VRec ru = vrec[u], rv = vrec[v];
+        ms += ru.deg;
+        i64 ab = ru.off + ru.lo, ae = ru.off + ru.deg;  // N+(u)
+        i64 bb = rv.off + rv.lo, be = rv.off + rv.deg;  // N+(v)
+        if (ae - ab > be - bb) {
+            const i64 t0 = ab, t1 = ae;
+            ab = bb;
+            ae = be;
+            bb = t0;
+            be = t1;
+        }
+        i64 cnt = 0, sdp = 0;
+        for (i64 q = ab; q < ae; ++q) {
+            const i32 w = ridx[q];
+            const i64 x = lower_bound_dev(ridx, bb, be, w);
+            bb = x;  // both lists ascend
+            if (x < be && ridx[x] == w) {
+                const VRec rw = vrec[w];
+                ++cnt;
+                sdp += rw.deg - rw.lo;
+            }
+        }
+        ko += cnt * cnt + sdp;
+    }
+    ms = block_sum<PT>(ms, part);
+    ko = block_sum<PT>(ko, part);
+    if (threadIdx.x == 0) {
+        if (ms) atomicAdd((unsigned long long*)&plan->min_sum, (unsigned long long)ms);
+        if (ko) atomicAdd((unsigned long long*)&plan->k4_merge, (unsigned long long)ko);
+    }
+}
+
+hipError_t launch_work_model(i64 nnz, RawWs& w, hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_work_model, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.vrec, nnz,
+                       w.plan);
+    return hipGetLastError();
+}
+
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
     const hipError_t e = hipMemsetAsync(&w.plan->triangles, 0, sizeof(i64), s);
     if (e != hipSuccess) return e;

@@ -6,16 +6,21 @@ A request is one graph (host CSR).  The server
     fit the free budget; a request larger than the whole budget is rejected;
   * keeps admitted CSRs and results resident on the device until the client
     releases them (the budget is returned then);
-  * batches continuously: whenever a worker stream frees up, the scheduler
-    takes the waiting requests in arrival order (skipping ahead past a request
-    that does not fit yet) and either packs the small graphs (n <= small_n)
-    into one fglt_batch launch or hands one large graph to fglt_raw; several
-    worker streams run at once, so their work overlaps on the GPU;
-  * records per-request latency from arrival to the completion of its kernels.
+  * batches continuously: one long-lived worker thread per HIP stream; when a
+    worker is free it takes the waiting requests in arrival order (skipping
+    ahead past a request that does not fit yet) and either packs the small
+    graphs (n <= small_n) into one fglt_batch launch or hands one large graph
+    to fglt_raw; the workers' streams run at once, so their work overlaps on
+    the GPU;
+  * records per-request latency from arrival to the completion of its
+    kernels (and, with a copying executor, to the end of the copy of its
+    result to the host).
 
 The device work goes through an executor object; ``GpuExecutor`` calls the HIP
 library.  Tests substitute a CPU executor to drive the scheduling logic
-without a GPU.
+without a GPU.  An executor returns one outcome per request of a launch: the
+result, or an exception that fails that request alone; an exception raised
+by the executor fails the whole launch.
 """
 from __future__ import annotations
 
@@ -47,10 +52,8 @@ class Request:
     future: Future = field(default_factory=Future)
     bytes_resident: int = 0  # CSR + result
     bytes_work: int = 0      # workspace while running
-    cancelled: bool = False
     start: float = 0.0
     end: float = 0.0
-    device_result: object = None
 
     @property
     def n(self) -> int:
@@ -62,12 +65,25 @@ class Request:
 
 
 @dataclass
+class Outcome:
+    """What an executor returns for one request."""
+    net: object                # device tensor (GpuExecutor) or ndarray; n x 16 int64
+    csr: object = None         # the request's resident device CSR (offsets, indices), if kept
+    host_net: object = None    # the result copied to the host (copying executors)
+    t_done: float = 0.0        # perf_counter() when its kernels had completed
+    t_host: float = 0.0        # perf_counter() when its host copy had completed
+
+
+@dataclass
 class Result:
     rid: int
     net: object              # device tensor (GpuExecutor) or ndarray; n x 16 int64
-    latency_s: float
-    queued_s: float
+    latency_s: float         # arrival -> kernels complete
+    queued_s: float          # arrival -> start of its launch
     batched_with: int        # number of requests in the same launch
+    latency_host_s: float = 0.0  # arrival -> result on the host (copying executors), else 0
+    csr: object = None
+    host_net: object = None
     _server: "Server" = None
 
     def release(self):
@@ -75,18 +91,25 @@ class Result:
         if self._server is not None:
             self._server._release(self.rid)
             self._server = None
+            self.net = None
+            self.csr = None
 
 
 class GpuExecutor:
-    """Runs requests on the GPU through the C ABI (one HIP stream per worker)."""
+    """Runs requests on the GPU through the C ABI (one HIP stream per worker).
 
-    def __init__(self, device=0, batch_plan=None):
+    The request's CSR is copied to the device and kept there with its result
+    until release; with copy_out=True the result is also copied to (pinned)
+    host memory and the time of that copy is recorded."""
+
+    def __init__(self, device=0, batch_plan=None, copy_out=False):
         import torch
         import paper_2007_11111_amd as fg
         self.torch = torch
         self.fg = fg
         self.device = torch.device("cuda", device)
         self.batch_plan = batch_plan
+        self.copy_out = copy_out
 
     def make_stream(self):
         return self.torch.cuda.Stream(device=self.device)
@@ -100,25 +123,54 @@ class GpuExecutor:
             work = self.fg.raw_workspace_bytes(n, nnz)
         return csr + out, work
 
+    def _finish(self, stream, nets, csrs):
+        stream.synchronize()
+        t_done = time.perf_counter()
+        hosts = [None] * len(nets)
+        t_host = 0.0
+        if self.copy_out:
+            with self.torch.cuda.stream(stream):
+                hosts = [x.to("cpu", non_blocking=True) if not isinstance(x, Exception) else None for x in nets]
+            stream.synchronize()
+            t_host = time.perf_counter()
+            hosts = [h.numpy() if h is not None else None for h in hosts]
+        return [x if isinstance(x, Exception) else Outcome(x, c, h, t_done, t_host)
+                for x, c, h in zip(nets, csrs, hosts)]
+
     def run_single(self, req, stream):
         torch = self.torch
         with torch.cuda.stream(stream):
-            off = torch.from_numpy(req.offsets).to(self.device, non_blocking=False)
-            idx = torch.from_numpy(req.indices).to(self.device, non_blocking=False)
-            out = self.fg.transform(off, idx, stream=stream)
-            stream.synchronize()
-        return [out]
+            off = torch.from_numpy(req.offsets).to(self.device, non_blocking=True)
+            idx = torch.from_numpy(req.indices).to(self.device, non_blocking=True)
+            try:
+                out = self.fg.transform(off, idx, stream=stream)
+            except self.fg.FgltError as e:
+                stream.synchronize()
+                return [e]
+        return self._finish(stream, [out], [(off, idx)])
 
     def run_batch(self, reqs, stream):
         torch = self.torch
-        vtx, off, idx = self.fg.batch_pack([(r.offsets, r.indices) for r in reqs])
+        fg = self.fg
+        vtx, off, idx = fg.batch_pack([(r.offsets, r.indices) for r in reqs])
+        L = fg._lib.lib()
+        G, n_total, nnz = len(reqs), int(vtx[-1]), int(idx.numel())
         with torch.cuda.stream(stream):
-            off_d = off.to(self.device)
-            idx_d = idx.to(self.device)
-            out = self.fg.batch(vtx, off_d, idx_d, plan=self.batch_plan, stream=stream)
-            stream.synchronize()
-        bounds = vtx.tolist()
-        return [out[bounds[k]:bounds[k + 1]] for k in range(len(reqs))]
+            off_d = off.to(self.device, non_blocking=True)
+            idx_d = idx.to(self.device, non_blocking=True)
+            ws = torch.empty(max(int(L.fglt_batch_workspace(G, n_total, nnz)), 1), dtype=torch.uint8,
+                             device=self.device)
+            out = fg.batch(vtx, off_d, idx_d, plan=self.batch_plan, workspace=ws, stream=stream)
+            status = fg.batch_status(ws, stream=stream)
+        if status != 0:
+            # a request broke the contract: its rows were skipped on the device;
+            # run the requests one at a time so that only the bad one fails
+            return [self.run_single(r, stream)[0] for r in reqs]
+        b = vtx.tolist()
+        nets = [out[b[k]:b[k + 1]] for k in range(G)]
+        e = off.tolist()
+        csrs = [(off_d[b[k]:b[k + 1] + 1], idx_d[e[b[k]]:e[b[k + 1]]]) for k in range(G)]
+        return self._finish(stream, nets, csrs)
 
 
 class Server:
@@ -133,23 +185,34 @@ class Server:
         self._cv = threading.Condition()
         self._queue: list[Request] = []
         self._resident: dict[int, int] = {}
-        self._idle_streams = [executor.make_stream() for _ in range(streams)]
         self._running = 0
         self._stop = False
         self.latencies: list[float] = []
         self.completed = 0
-        self._sched = threading.Thread(target=self._loop, name="fglt-scheduler", daemon=True)
-        self._sched.start()
+        self._workers = [threading.Thread(target=self._work, args=(executor.make_stream(),),
+                                          name=f"fglt-worker-{k}", daemon=True) for k in range(streams)]
+        for t in self._workers:
+            t.start()
 
     # ------------------------------------------------------------------ client API
     def submit(self, offsets, indices) -> Future:
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         idx = np.ascontiguousarray(indices, dtype=np.int32)
         req = Request(next(self._ids), off, idx, time.perf_counter())
-        small = req.n <= self.small_n
-        req.bytes_resident, req.bytes_work = self.ex.bytes_for(req.n, req.nnz, small)
         req.future.rid = req.rid
         req.future.cancel_request = lambda r=req: self._cancel(r)
+        try:
+            from paper_2007_11111_amd import check_host_csr
+        except Exception:  # the package without its library still offers the check
+            check_host_csr = None
+        if check_host_csr is not None:
+            try:
+                check_host_csr(off, idx)
+            except ValueError as e:
+                req.future.set_exception(e)
+                return req.future
+        small = req.n <= self.small_n
+        req.bytes_resident, req.bytes_work = self.ex.bytes_for(req.n, req.nnz, small)
         if req.bytes_resident + req.bytes_work > self.budget:
             req.future.set_exception(Rejected(f"request {req.rid} needs "
                                               f"{req.bytes_resident + req.bytes_work} bytes > budget {self.budget}"))
@@ -164,7 +227,12 @@ class Server:
             self._stop = True
             self._cv.notify_all()
         if wait:
-            self._sched.join()
+            for t in self._workers:
+                t.join()
+
+    @property
+    def num_workers(self):
+        return len(self._workers)
 
     def stats(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
@@ -210,25 +278,23 @@ class Server:
             return None
         return picked, bool(small_mode)
 
-    def _loop(self):
+    def _work(self, stream):
         while True:
             with self._cv:
                 while True:
-                    if self._stop and not self._queue and self._running == 0:
+                    if self._stop and not self._queue:
                         return
-                    if self._idle_streams and self._queue:
-                        choice = self._pick()
-                        if choice is not None:
-                            break
+                    choice = self._pick() if self._queue else None
+                    if choice is not None:
+                        break
                     self._cv.wait(timeout=0.05)
                 reqs, is_batch = choice
                 for r in reqs:
                     self._queue.remove(r)
                     self.free -= r.bytes_resident + r.bytes_work
                     r.start = time.perf_counter()
-                stream = self._idle_streams.pop()
                 self._running += 1
-            threading.Thread(target=self._run, args=(reqs, is_batch, stream), daemon=True).start()
+            self._run(reqs, is_batch, stream)
 
     def _run(self, reqs, is_batch, stream):
         err = None
@@ -242,15 +308,20 @@ class Server:
             for k, r in enumerate(reqs):
                 r.end = end
                 self.free += r.bytes_work
-                if err is not None:
+                o = err if err is not None else outs[k]
+                if isinstance(o, Exception):
                     self.free += r.bytes_resident
-                    r.future.set_exception(err)
+                    r.future.set_exception(o)
                     continue
                 self._resident[r.rid] = r.bytes_resident
-                lat = end - r.arrival
-                self.latencies.append(lat)
+                if isinstance(o, Outcome):
+                    t_done = o.t_done or end
+                    res = Result(r.rid, o.net, t_done - r.arrival, r.start - r.arrival, len(reqs),
+                                 (o.t_host - r.arrival) if o.t_host else 0.0, o.csr, o.host_net, self)
+                else:
+                    res = Result(r.rid, o, end - r.arrival, r.start - r.arrival, len(reqs), _server=self)
+                self.latencies.append(res.latency_s)
                 self.completed += 1
-                r.future.set_result(Result(r.rid, outs[k], lat, r.start - r.arrival, len(reqs), self))
-            self._idle_streams.append(stream)
+                r.future.set_result(res)
             self._running -= 1
             self._cv.notify_all()

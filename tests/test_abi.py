@@ -64,10 +64,11 @@ def test_host_argument_checks_need_no_device(lib):
     assert lib.fglt_raw(5, 8, None, None, None, None, 0, 0, None, None, None) == -1
     # unknown flag bits
     assert lib.fglt_raw(0, 0, None, None, None, None, 0, 0x80, None, None, None) == -1
-    # the empty graph is a no-op, with every defined flag (FGLT_NET 1, FGLT_TIMING 2, FGLT_SIGMA5 4)
-    for flags in (0, 1, 2, 4, 7):
+    # the empty graph is a no-op, with every defined flag (FGLT_NET 1, FGLT_TIMING 2,
+    # FGLT_SIGMA5 4, FGLT_WORKMODEL 8)
+    for flags in (0, 1, 2, 4, 7, 8, 15):
         assert lib.fglt_raw(0, 0, None, None, None, None, 0, flags, None, None, None) == 0
-    assert lib.fglt_raw(0, 0, None, None, None, None, 0, 8, None, None, None) == -1
+    assert lib.fglt_raw(0, 0, None, None, None, None, 0, 16, None, None, None) == -1
     lib.fglt_net.restype = ctypes.c_int
     lib.fglt_net.argtypes = [ctypes.c_int64, vp, vp, vp]
     assert lib.fglt_net(-3, None, None, None) == -1
@@ -83,5 +84,6 @@ def test_binding_flags_match_header():
     import re
     from paper_2007_11111_amd import _lib
     hdr = open(os.path.join(ROOT, "include", "fglt.h")).read()
-    defs = {k: int(v) for k, v in re.findall(r"#define FGLT_(NET|TIMING|SIGMA5) (\d+)u", hdr)}
-    assert defs == {"NET": _lib.FGLT_NET, "TIMING": _lib.FGLT_TIMING, "SIGMA5": _lib.FGLT_SIGMA5}
+    defs = {k: int(v) for k, v in re.findall(r"#define FGLT_(NET|TIMING|SIGMA5|WORKMODEL) (\d+)u", hdr)}
+    assert defs == {"NET": _lib.FGLT_NET, "TIMING": _lib.FGLT_TIMING, "SIGMA5": _lib.FGLT_SIGMA5,
+                    "WORKMODEL": _lib.FGLT_WORKMODEL}

@@ -87,3 +87,42 @@ def test_batch_contract(fg):
     fg.batch(vtx, off.cuda(), idx.cuda(), workspace=ws2)
     assert L.fglt_batch_status(ctypes.c_void_p(ws2.data_ptr()),
                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+
+
+def test_batch_rejects_offsets_outside_the_indices(fg):
+    """Row offsets before 0 or past nnz_total are flagged on the device (the
+    rows are skipped, the status word reads ENOTCANON) and never read."""
+    L = fg._lib.lib()
+    cases = [
+        ("negative start", [0, 2], [-4, 1, 2], [1, 0]),
+        ("end past the indices", [0, 2], [0, 1, 9], [1, 0]),
+    ]
+    for name, vtx, off, idx in cases:
+        say(f"batch malformed offsets: {name}")
+        vtx_t = torch.tensor(vtx, dtype=torch.int64)
+        ws = torch.empty(int(L.fglt_batch_workspace(1, 2, len(idx))), dtype=torch.uint8, device="cuda")
+        fg.batch(vtx_t, torch.tensor(off, dtype=torch.int64).cuda(), torch.tensor(idx, dtype=torch.int32).cuda(),
+                 workspace=ws)
+        assert fg.batch_status(ws) == -2, name
+
+
+def test_server_fails_a_malformed_batched_request_alone(fg):
+    from paper_2007_11111_amd.server import GpuExecutor, Server
+    good = [oracle.canonical_csr(g.n, g.src, g.dst) for g in graphgen.batch_graphs(5, seed=41)]
+    bad = (np.array([0, 1, 1], np.int64), np.array([1], np.int32))  # (0, 1) without (1, 0)
+    reqs = good[:2] + [bad] + good[2:]
+    say("server: a batch with one asymmetric request")
+    srv = Server(GpuExecutor(), budget_bytes=1 << 30, streams=1)
+    try:
+        futs = [srv.submit(o, i) for o, i in reqs]
+        for k, f in enumerate(futs):
+            if k == 2:
+                with pytest.raises(fg.FgltError):
+                    f.result(timeout=60)
+            else:
+                r = f.result(timeout=60)
+                np.testing.assert_array_equal(r.net.cpu().numpy(), oracle.net(*reqs[k]))
+                r.release()
+    finally:
+        srv.close()
+    assert srv.free == 1 << 30

@@ -103,3 +103,73 @@ def test_workload_digest(fg, name):
     sel = stratified_sample(deg, per_bin=40, top=0, seed=7, max_degree=64)
     say(f"workload {name}: live oracle sample of {sel.size}")
     np.testing.assert_array_equal(f_h[sel], oracle.net(off_h, idx_h, sel))
+
+
+def _batch_union_on_device(fg, graphs):
+    """The batch workload's block-diagonal CSR built on the device with
+    fglt_build_csr from the union of the graphs' edge lists (no edge crosses
+    two graphs), as bench.py builds it."""
+    sizes = np.array([g.n for g in graphs], dtype=np.int64)
+    vtx = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    base = np.repeat(vtx[:-1], [g.src.size for g in graphs])
+    src = (np.concatenate([g.src for g in graphs]).astype(np.int64) + base).astype(np.int32)
+    dst = (np.concatenate([g.dst for g in graphs]).astype(np.int64) + base).astype(np.int32)
+    off, idx = fg.build_csr(int(vtx[-1]), torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    return torch.from_numpy(vtx), off, idx
+
+
+def test_batch_workload_through_fglt_batch(fg):
+    """The 4096-graph batch that bench.py times, through fglt_batch itself, one
+    launch and by HIP-graph replay (three replays with eager work between
+    them): every replay matches the oracle's stored net digest of the batch."""
+    d = _digests().get("batch")
+    if d is None:
+        pytest.skip("no stored oracle digest for batch")
+    graphs = graphgen.make("batch")
+    vtx, off, idx = _batch_union_on_device(fg, graphs)
+    torch.cuda.synchronize()
+    assert sha(off.cpu().numpy(), idx.cpu().numpy()) == d["csr_sha256"]
+    say(f"batch workload: G={len(graphs)} n={int(vtx[-1])} eager")
+    out = fg.batch(vtx, off, idx)
+    torch.cuda.synchronize()
+    assert sha(out.cpu().numpy()) == d["net_sha256"]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            say(f"batch workload: graph replay {rep}")
+            out2 = torch.full_like(out, -1)
+            fg.batch(vtx, off, idx, out=out2, plan={"use_graph": 1}, stream=s)
+            s.synchronize()
+            assert sha(out2.cpu().numpy()) == d["net_sha256"], f"replay {rep}"
+            _ = torch.ones(4096, device="cuda").cumsum(0).sum().item()  # eager work between replays
+    fg.batch_release(s)
+
+
+def _work_model_host(off, idx):
+    """min_sum and the oriented 4-clique merge steps of a small canonical CSR
+    by plain enumeration (degree order, ties by id)."""
+    n = off.size - 1
+    deg = np.diff(off)
+    key = [(int(deg[v]), v) for v in range(n)]
+    nplus = [set(int(w) for w in idx[off[v]:off[v + 1]] if key[int(w)] > key[v]) for v in range(n)]
+    ms = ko = 0
+    for u in range(n):
+        for v in nplus[u]:
+            ms += int(deg[u])
+            T = nplus[u] & nplus[v]
+            ko += len(T) * len(T) + sum(len(nplus[w]) for w in T)
+    return ms, ko
+
+
+def test_work_model_counts(fg):
+    cases = [("er", graphgen.make("er")), ("cl3000", graphgen.chung_lu(3000, 2.3, 12.0, 400.0, seed=9)),
+             ("K30", graphgen.clique(30)), ("star", graphgen.star(50))]
+    for name, g in cases:
+        o, i = oracle.canonical_csr(g.n, g.src, g.dst)
+        say(f"work model {name}")
+        _, st = fg.raw(torch.from_numpy(o).cuda(), torch.from_numpy(i).cuda(), stats=True, workmodel=True)
+        ms, ko = _work_model_host(o, i)
+        assert (st["min_sum"], st["k4_merge"]) == (ms, ko), name
+    # the Erdos-Renyi workload's figures as the byte model states them
+    o, i = oracle.canonical_csr(2000, graphgen.make("er").src, graphgen.make("er").dst)
+    assert _work_model_host(o, i) == (94135, 502)

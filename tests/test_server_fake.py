@@ -169,3 +169,70 @@ def test_malformed_request_raises_through_future():
     with pytest.raises(ValueError):
         srv.submit(bad_off, bad_idx).result(timeout=10)
     srv.close()
+
+
+def test_host_csr_checks_reject_before_the_device():
+    from paper_2007_11111_amd import batch_pack, check_host_csr
+    good = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32))
+    check_host_csr(*good)
+    bad = [
+        (np.array([1, 2, 3], np.int64), np.array([1, 0, 0], np.int32)),   # offsets[0] != 0
+        (np.array([0, 2, 1, 3], np.int64), np.array([1, 2, 0], np.int32)),  # decreasing
+        (np.array([0, 1, 5], np.int64), np.array([1, 0], np.int32)),       # offsets[-1] past the end
+        (np.array([0, 1, 1], np.int64), np.array([1, 0], np.int32)),       # offsets[-1] short of the end
+        (np.array([-1, 1, 2], np.int64), np.array([1, 0], np.int32)),      # negative start
+    ]
+    for off, idx in bad:
+        with pytest.raises(ValueError):
+            check_host_csr(off, idx)
+        with pytest.raises(ValueError):
+            batch_pack([good, (off, idx)])
+    srv = Server(FakeExecutor(), budget_bytes=1 << 30, streams=1)
+    for off, idx in bad:
+        with pytest.raises(ValueError):
+            srv.submit(off, idx).result(timeout=10)
+    srv.close()
+    assert srv.free == 1 << 30
+
+
+def test_worker_threads_are_long_lived():
+    """One worker thread per stream for the server's lifetime: the number of
+    threads does not grow with the number of launches."""
+    ex = FakeExecutor()
+    before = threading.active_count()
+    srv = Server(ex, budget_bytes=1 << 30, streams=3, small_n=0)
+    assert srv.num_workers == 3
+    csrs = _graphs(30, seed=6)
+    for o, i in csrs:
+        srv.submit(o, i).result(timeout=30).release()
+    assert threading.active_count() <= before + 3
+    assert len(ex.launches) == 30
+    srv.close()
+    assert threading.active_count() <= before
+
+
+def test_per_request_failure_in_a_batch():
+    """An executor outcome that is an exception fails that request alone,
+    whether it ran in a batch or by itself."""
+    class OneBad(FakeExecutor):
+        def run_batch(self, reqs, stream):
+            outs = super().run_batch(reqs, stream)
+            return [ValueError("bad graph") if r.rid == 1 else o for r, o in zip(reqs, outs)]
+
+        def run_single(self, req, stream):
+            outs = super().run_single(req, stream)
+            return [ValueError("bad graph")] if req.rid == 1 else outs
+    ex = OneBad(delay=0.05)
+    srv = Server(ex, budget_bytes=1 << 30, streams=1, small_n=512)
+    csrs = _graphs(6, seed=7)
+    futs = [srv.submit(o, i) for o, i in csrs]
+    for k, f in enumerate(futs):
+        if k == 1:
+            with pytest.raises(ValueError, match="bad graph"):
+                f.result(timeout=30)
+        else:
+            r = f.result(timeout=30)
+            np.testing.assert_array_equal(r.net, oracle.net(*csrs[k]))
+            r.release()
+    srv.close()
+    assert srv.free == 1 << 30
