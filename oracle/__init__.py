@@ -196,3 +196,36 @@ def U16() -> np.ndarray:
     u = np.zeros((NORB, NORB), dtype=np.int64)
     _load().oracle_u16(_p64(u))
     return u
+
+
+def subdict_columns(mask) -> list:
+    """The index set s of a sub-dictionary, ascending, from a 16-bit mask or
+    an iterable of orbit numbers.  Table II's caption admits any s with
+    {0, 1} <= s <= {0, ..., 15}."""
+    if isinstance(mask, (int, np.integer)):
+        s = [k for k in range(NORB) if (int(mask) >> k) & 1]
+    else:
+        s = sorted({int(k) for k in mask})
+    if not s or s[0] != 0 or (len(s) < 2 or s[1] != 1) or s[-1] >= NORB:
+        raise ValueError(f"a sub-dictionary must contain orbits 0 and 1 and lie in 0..15: {s}")
+    return s
+
+
+def subdict(raw_counts, mask, net: bool = True) -> np.ndarray:
+    """The transform with the sub-dictionary of index set s (Section V: the
+    conversion of a sub-dictionary is the sub-matrix U16(s, s) of Table II).
+    From the 16 raw frequencies of each vertex it keeps the columns s; with
+    ``net`` it solves U16(s, s) f_s = raw_s by back-substitution from the
+    highest orbit down (U16(s, s) is unit upper triangular, so the solve is
+    exact in integers).  [rows, |s|] int64, columns in ascending orbit order."""
+    s = subdict_columns(mask)
+    r = np.ascontiguousarray(raw_counts, dtype=np.int64).reshape(-1, NORB)
+    out = r[:, s].copy()
+    if not net:
+        return out
+    u = U16()[np.ix_(s, s)]
+    for a in range(len(s) - 1, -1, -1):
+        for b in range(a + 1, len(s)):
+            if u[a, b]:
+                out[:, a] -= u[a, b] * out[:, b]
+    return out

@@ -109,6 +109,12 @@ PY_MUTANTS = [
     ("sigma5", "net d3 takes c3 twice", "out[:, 3] -= c3", "out[:, 3] -= 2 * c3"),
     ("totals", "no division by m_k", "out[g] = col // ORBIT_NODES", "out[g] = col"),
     ("totals", "every graph's rows", "col = f[off[g]:off[g + 1]].sum(axis=0)", "col = f.sum(axis=0)"),
+    ("subdict", "sign flipped", "out[:, a] -= u[a, b] * out[:, b]", "out[:, a] += u[a, b] * out[:, b]"),
+    ("subdict", "forward order", "for a in range(len(s) - 1, -1, -1):", "for a in range(len(s)):"),
+    ("subdict", "transposed block", "u = U16()[np.ix_(s, s)]", "u = U16().T[np.ix_(s, s)]"),
+    ("subdict", "raw-only output converted", "if not net:", "if net is None:"),
+    ("subdict", "inner loop misses the last orbit", "for b in range(a + 1, len(s)):",
+     "for b in range(a + 1, len(s) - 1):"),
 ]
 
 
@@ -153,11 +159,27 @@ def _totals_ok(f):
         return False
 
 
+def _subdict_ok(f):
+    from tests.test_oracle_pins import CLOSED, OPEN, _relative_net
+    u = oracle.U16()
+    for n, off, idx, (br, bn) in _CASES:
+        r = oracle.raw(off, idx)
+        for s in CLOSED + OPEN:
+            try:
+                if not np.array_equal(f(r, s, net=False), br[:, s]):
+                    return False
+                if not np.array_equal(f(r, s), bn[:, s] if s in CLOSED else _relative_net(bn, s, u)):
+                    return False
+            except Exception:
+                return False
+    return True
+
+
 def test_python_pins_accept_the_oracle():
     global _CASES
     if _CASES is None:
         _CASES = _cases()
-    assert _sigma5_ok(oracle.sigma5) and _totals_ok(oracle.totals)
+    assert _sigma5_ok(oracle.sigma5) and _totals_ok(oracle.totals) and _subdict_ok(oracle.subdict)
 
 
 @pytest.mark.parametrize("fn,name,old,new", PY_MUTANTS, ids=[f"{m[0]}: {m[1]}" for m in PY_MUTANTS])
@@ -166,5 +188,5 @@ def test_python_mutant_is_caught(fn, name, old, new):
     if _CASES is None:
         _CASES = _cases()
     f = _mutated(fn, old, new)
-    ok = _sigma5_ok(f) if fn == "sigma5" else _totals_ok(f)
+    ok = {"sigma5": _sigma5_ok, "totals": _totals_ok, "subdict": _subdict_ok}[fn](f)
     assert not ok, f"mutant '{name}' of oracle.{fn} survived every pin"

@@ -385,3 +385,91 @@ def test_sigma5_matches_full_transform_and_networkx(which):
     np.testing.assert_array_equal(oracle.sigma5(off, idx, net=True), oracle.raw_to_net(raw)[:, :5])
     tri = nx.triangles(_nx_graph(off, idx))
     np.testing.assert_array_equal(oracle.sigma5(off, idx)[:, 4], [tri[v] for v in range(g.n)])
+
+
+# ---------------------------------------------------------------- sub-dictionaries (Section V)
+
+def _upward_closed(s, u):
+    """Every orbit of s brings every higher orbit its row of U16 reaches."""
+    return all(c in s for k in s for c in range(16) if c != k and u[k, c])
+
+
+# index sets that are closed under Table II (net = those columns of the full net)
+CLOSED = [[0, 1], [0, 1, 2, 3, 4], [0, 1, 15], [0, 1, 14, 15], [0, 1, 13, 15], [0, 1, 8, 11, 14, 15],
+          [0, 1, 12, 13, 14, 15], [0, 1, 4, 9, 13, 15], list(range(16))]
+# and sets that are not (net relative to the sub-dictionary)
+OPEN = [[0, 1, 2, 3], [0, 1, 5, 6, 7, 8], [0, 1, 2, 3, 4, 12], [0, 1, 9, 10, 11], [0, 1, 3, 12, 15],
+        [0, 1, 5, 13], [0, 1, 6, 7, 14]]
+
+
+def test_subdict_sets_are_classified(table2):
+    for s in CLOSED:
+        assert _upward_closed(s, table2), s
+    for s in OPEN:
+        assert not _upward_closed(s, table2), s
+    for bad in ([0, 2, 3], [1, 4], [0], [0, 1, 16]):
+        with pytest.raises(ValueError):
+            oracle.subdict_columns(bad)
+
+
+def test_subdict_fig2(fig2):
+    """Fig. 2's printed tables: on a closed index set the sub-dictionary's net
+    frequencies are the printed net columns; raw-only output is the printed
+    raw columns."""
+    for s in CLOSED:
+        np.testing.assert_array_equal(oracle.subdict(fig2["raw"], s), fig2["net"][:, s])
+        np.testing.assert_array_equal(oracle.subdict(fig2["raw"], s, net=False), fig2["raw"][:, s])
+
+
+def _relative_net(net_bf, s, u):
+    """U16(s, s)^{-1} U16(s, :) f for brute-force net frequencies f: what the
+    sub-dictionary's conversion gives when the raw counts of s are U16(s, :) f
+    (Table II), solved here with exact rational elimination."""
+    from fractions import Fraction
+    us = [[Fraction(int(u[a, b])) for b in s] for a in s]
+    rhs = (u[s, :] @ net_bf.T).T  # [n, |s|] raw counts of s
+    out = np.zeros((net_bf.shape[0], len(s)), dtype=np.int64)
+    for v in range(net_bf.shape[0]):
+        # Gauss-Jordan on the |s| x |s| system
+        m = [row[:] + [Fraction(int(rhs[v, a]))] for a, row in enumerate(us)]
+        k = len(s)
+        for col in range(k):
+            piv = next(r for r in range(col, k) if m[r][col] != 0)
+            m[col], m[piv] = m[piv], m[col]
+            for r in range(k):
+                if r != col and m[r][col] != 0:
+                    fac = m[r][col] / m[col][col]
+                    m[r] = [x - fac * y for x, y in zip(m[r], m[col])]
+        for a in range(k):
+            x = m[a][k] / m[a][a]
+            assert x.denominator == 1
+            out[v, a] = int(x)
+    return out
+
+
+@pytest.mark.parametrize("seed", list(range(6)))
+def test_subdict_vs_bruteforce(seed, table2):
+    """On random small graphs: closed sets give the brute-force net columns;
+    every set gives U16(s,s)^{-1} U16(s,:) f for the brute-force net f, and
+    raw-only output gives the brute-force raw columns."""
+    rng = np.random.default_rng(6000 + seed)
+    n = int(rng.integers(5, 10))
+    edges = random_graph(rng, n, float(rng.choice([0.4, 0.6, 0.8])))
+    off, idx = csr_of(n, edges)
+    rbf, fbf = bruteforce.frequencies(n, edges)
+    r = oracle.raw(off, idx)
+    for s in CLOSED + OPEN:
+        np.testing.assert_array_equal(oracle.subdict(r, s, net=False), rbf[:, s])
+        got = oracle.subdict(r, s)
+        np.testing.assert_array_equal(got, _relative_net(fbf, s, table2))
+        if s in CLOSED:
+            np.testing.assert_array_equal(got, fbf[:, s])
+
+
+def test_subdict_open_set_differs_from_full_columns():
+    """On K5 a set without the triangle orbit keeps every 2-path: sigma_2 and
+    sigma_3 stay raw (12 and 6 per vertex), where the full net has 0."""
+    g = graphgen.clique(5)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    f = oracle.subdict(oracle.raw(off, idx), [0, 1, 2, 3])
+    np.testing.assert_array_equal(f, np.tile([1, 4, 12, 6], (5, 1)))
