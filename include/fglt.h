@@ -55,11 +55,21 @@ typedef enum {
 #define FGLT_NET 1u          /* write net frequencies (Table II applied) instead of raw */
 #define FGLT_TIMING 2u       /* time each launch segment with HIP events on `stream` (fills
                                 fglt_stats.seg_ms; adds a final synchronization)         */
-#define FGLT_SIGMA5 4u       /* the transform with the sub-dictionary Sigma_5 only (node,
-                                edge, the 2-path end and centre, triangle: orbits 0-4;
-                                Theorem 1): `out` is [n][5], and only the degree,
-                                triangle and 2-path steps run (no clique, diamond,
-                                second row pass or 4-cycle pass; their segments time 0) */
+/* Sub-dictionary transforms (Section V; Table II's caption): bits 16..31 of
+ * the flags hold the index set s of a sub-dictionary Sigma of Sigma_16 as a
+ * mask (bit k = orbit k), which must contain orbits 0 and 1; 0 there means
+ * all 16 orbits.  `out` is then [n][|s|], the orbits of s in ascending order:
+ * raw frequencies, or with FGLT_NET the sub-dictionary's net frequencies
+ * f_s = U16(s,s)^{-1} \hat f_s (the sub-matrix of Table II on s).  Where s
+ * holds, with each orbit, every higher orbit its row of U16 reaches (as
+ * {0..4} does), f_s equals those columns of the full net transform; other
+ * sets give net frequencies relative to Sigma.  Only the passes that the
+ * orbits of s need are run: the triangle pass for any of 4, 5, 6, 9, 10, 11,
+ * 13, 14, 15; the clique/diamond pass for 13 or 15; the second row pass for
+ * 5, 9, 10, 14 (or 13, 15); the 4-cycle pass (and its work lists) for 12. */
+#define FGLT_SIGMA(mask) ((unsigned)((mask) & 0xffffu) << 16)
+#define FGLT_SIGMA_MASK(flags) (((flags) >> 16) & 0xffffu)
+#define FGLT_SIGMA5 FGLT_SIGMA(0x001fu)  /* Theorem 1: orbits 0-4, [n][5] */
 #define FGLT_WORKMODEL 8u    /* also count the work terms of the byte model (statistics only,
                                 not part of the transform; needs `stats`): min_sum and
                                 k4_merge of fglt_stats                                    */
@@ -157,12 +167,11 @@ typedef struct {
  *   offsets      [n+1] int64, offsets[0] == 0, non-decreasing, offsets[n] == nnz
  *   indices      [nnz] int32; the CSR must be canonical: symmetric, no
  *                self-loops, no repeated entry in a row (rows need not be sorted)
- *   out          out [n][16] int64, or [n][5] with FGLT_SIGMA5
+ *   out          out [n][16] int64, or [n][|s|] with a sub-dictionary FGLT_SIGMA(s)
  *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
- *   flags        any of FGLT_NET, FGLT_TIMING and FGLT_SIGMA5, or 0.  With
- *                FGLT_SIGMA5 the five columns are the first five of the full
- *                transform (raw or net): the leading 5x5 block of U16 is the
- *                whole conversion for orbits 0-4 (Section IV, Table II)
+ *   flags        FGLT_NET, FGLT_TIMING, FGLT_WORKMODEL and a sub-dictionary
+ *                FGLT_SIGMA(s), or 0; a mask without orbits 0 and 1 is
+ *                FGLT_EINVAL
  *   plan         (host) optional tier thresholds, NULL for the defaults
  *   stats        (host) optional, filled on success
  * Returns FGLT_ENOTCANON for a CSR that breaks the contract (checked on the

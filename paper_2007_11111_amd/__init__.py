@@ -15,10 +15,10 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, FGLT_SIGMA5, FGLT_TIMING, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_SIGMA, FGLT_TIMING, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
-    "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "FgltError", "Stats",
+    "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "sigma_mask", "FgltError", "Stats",
     "BatchPlan", "check_host_csr", "batch_pack", "batch", "batch_release", "batch_status", "totals", "NORBITS",
 ]
 
@@ -61,17 +61,37 @@ def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, stream=None):
     return offsets, indices[:m]
 
 
+def sigma_mask(sigma) -> int:
+    """16-bit orbit mask of a sub-dictionary (0: all 16 orbits) from None, an
+    int mask, or an iterable of orbit numbers."""
+    if sigma is None:
+        return 0
+    if isinstance(sigma, int):
+        mask = sigma
+    else:
+        mask = 0
+        for k in sigma:
+            if not 0 <= int(k) < NORBITS:
+                raise ValueError(f"orbit {k} is outside 0..15")
+            mask |= 1 << int(k)
+    if not 0 < mask <= 0xFFFF or mask & 3 != 3:
+        raise ValueError(f"a sub-dictionary mask must hold orbits 0 and 1 and fit 16 bits: {mask:#x}")
+    return 0 if mask == 0xFFFF else mask
+
+
 def raw_workspace_bytes(n: int, nnz: int) -> int:
     return int(lib().fglt_raw_workspace(int(n), int(nnz)))
 
 
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
         workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
-        timing: bool = False, sigma5: bool = False, workmodel: bool = False, stream=None):
+        timing: bool = False, sigma=None, sigma5: bool = False, workmodel: bool = False, stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
-    ([n, 5] with sigma5=True: the transform with the sub-dictionary Sigma_5 of
-    Theorem 1, orbits 0-4 only) (and a dict of plan statistics when stats=True).  ``plan`` may set the tier
+    (and a dict of plan statistics when stats=True).  ``sigma`` selects a
+    sub-dictionary (Section V): a 16-bit mask or an iterable of orbit numbers
+    that holds 0 and 1; the result is then [n, |s|], the orbits of s in
+    ascending order, net by U16(s, s).  sigma5=True is sigma=0x1F (Theorem 1).  ``plan`` may set the tier
     thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max and the
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events); with
@@ -85,7 +105,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     n = int(offsets.numel()) - 1
     nnz = int(indices.numel())
     dev = offsets.device
-    cols = 5 if sigma5 else NORBITS
+    mask = sigma_mask(0x1F if sigma5 else sigma)
+    cols = bin(mask).count("1") if mask else NORBITS
     if out is None:
         out = torch.empty((max(n, 0), cols), dtype=torch.int64, device=dev)
     if out.dtype != torch.int64 or not out.is_contiguous() or out.device != dev or tuple(out.shape) != (max(n, 0), cols):
@@ -100,7 +121,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
                      int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
-                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | (FGLT_SIGMA5 if sigma5 else 0)
+                     int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | FGLT_SIGMA(mask)
                      | (FGLT_WORKMODEL if workmodel else 0), ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st), _stream(stream)),
           "fglt_raw")

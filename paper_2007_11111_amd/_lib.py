@@ -33,8 +33,15 @@ class FgltError(RuntimeError):
 
 
 FGLT_TIMING = 2
-FGLT_SIGMA5 = 4
 FGLT_WORKMODEL = 8
+
+
+def FGLT_SIGMA(mask: int) -> int:
+    """Flag bits of a sub-dictionary with index set `mask` (bit k = orbit k)."""
+    return (int(mask) & 0xFFFF) << 16
+
+
+FGLT_SIGMA5 = FGLT_SIGMA(0x1F)
 SEGMENTS = ["check", "relabel", "structure", "tri1_wave", "tri1_lds", "tri1_global", "fill",
             "tri2_wave", "tri2_lds", "tri2_global", "l2", "c4_wave", "c4_block", "c4_hash", "c4_window",
             "finalize"]

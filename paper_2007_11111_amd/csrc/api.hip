@@ -1,6 +1,7 @@
 // api.hip -- C ABI entry points of the single-graph transform (fglt_raw,
 // fglt_net) and the status helpers.  See include/fglt.h.
 #include <algorithm>
+#include <initializer_list>
 
 #include "raw.h"
 
@@ -38,6 +39,29 @@ static hipError_t aux_stream(AuxStream*& out) {
     }
     out = &a;
     return hipSuccess;
+}
+
+// The passes that the orbits of a sub-dictionary need (Table I): the
+// triangle pass for any orbit that reads C3 or c3, the clique/diamond pass
+// for the diamond off-cord and 4-clique orbits, row pass 2 for the sums over
+// neighbours of p2, c3 and C3 (and the clique pass's per-entry counts, which
+// it sums), the 4-cycle pass for the 4-cycle orbit.  Degrees, p2 and
+// A C(p1-1, 2) (row pass 1) always run.
+struct SubPasses {
+    bool tri, clique, l2, c4;
+};
+static SubPasses sub_passes(unsigned s) {
+    auto any = [s](std::initializer_list<int> ks) {
+        for (int k : ks)
+            if ((s >> k) & 1u) return true;
+        return false;
+    };
+    SubPasses p;
+    p.c4 = any({12});
+    p.clique = any({13, 15});
+    p.l2 = p.clique || any({5, 9, 10, 14});
+    p.tri = p.l2 || any({4, 6, 11});
+    return p;
 }
 
 int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
@@ -96,13 +120,17 @@ extern "C" size_t fglt_raw_workspace(int64_t n, int64_t nnz) {
     return c.used;
 }
 
-extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out,
-                        void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats,
-                        void* stream) {
+int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out, void* ws,
+                  size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats, void* stream,
+                  bool one_stream) {
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_SIGMA5 | FGLT_WORKMODEL)) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_WORKMODEL | FGLT_SIGMA(0xffffu))) return FGLT_EINVAL;
+    // the sub-dictionary (Section V): every orbit by default; {0, 1} in any subset
+    const unsigned smask = FGLT_SIGMA_MASK(flags) ? FGLT_SIGMA_MASK(flags) : 0xffffu;
+    if ((smask & 3u) != 3u) return FGLT_EINVAL;
+    const SubPasses sp = sub_passes(smask);
     if (stats) {
         *stats = fglt_stats{};
         stats->n = n;
@@ -140,7 +168,7 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
     tm.mark(FGLT_SEG_STRUCTURE, s);
     const Tiers tiers = tiers_from_plan(plan, n);
-    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers, s));
+    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers, sp.c4, s));
     i64 g_total = 0, bitmap_words = 0;
     if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
     if (hipMemcpyAsync(&bitmap_words, w.boff + n, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -153,34 +181,32 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     // 3. counting
     FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
     if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
-    if (flags & FGLT_SIGMA5) {
-        // Sigma_5 (Theorem 1): degrees, triangles per edge and vertex, and the
-        // neighbour-degree sums p2 are the whole transform
-        FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, false, s, tm));
-        tm.mark(FGLT_SEG_FILL, s);
-        FGLT_HIP_TRY(launch_fill_c3(nnz, w, false, s));
-        for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_FINALIZE; ++seg) tm.mark(seg, s);
-        FGLT_HIP_TRY(launch_finalize5(n, w, out, (flags & FGLT_NET) != 0, s));
-        return finish(n, nnz, w, hp, tm, flags, stats, s);
-    }
+    const bool net = (flags & FGLT_NET) != 0;
     // the 4-cycle pass's hash tiers and window setup share no memory with the
     // triangle and clique passes: a second stream runs them alongside, and the
     // window kernel (after the join) takes the whole GPU
     AuxStream* aux = nullptr;
     hipStream_t s4 = s;
-    if (hp.n_c4[0] || hp.n_c4[1] || hp.n_c4[2] || hp.n_c4[3]) {
+    if (!one_stream && (hp.n_c4[0] || hp.n_c4[1] || hp.n_c4[2] || hp.n_c4[3])) {
         FGLT_HIP_TRY(aux_stream(aux));
         FGLT_HIP_TRY(hipEventRecord(aux->fork, s));
         FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
         s4 = aux->s;
     }
     FGLT_HIP_TRY(launch_c4_early(n, nnz, w, hp, tiers.c4_rows, s4));
-    // the clique pass reuses the triangle pass's bitmaps when the workspace holds them
-    const bool stored = bitmap_words <= w.bstore_cap;
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
+    // the clique pass reuses the triangle pass's bitmaps when the workspace
+    // holds them.  A sub-dictionary runs only the passes its orbits need (no
+    // 4-cycle work lists were built without the 4-cycle orbit, so its tiers
+    // are empty and the second stream stays idle).
+    const bool stored = sp.clique && bitmap_words <= w.bstore_cap;
+    if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
+    else
+        for (int seg = FGLT_SEG_TRI1_WAVE; seg <= FGLT_SEG_TRI1_GLOBAL; ++seg) tm.mark(seg, s);
     tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
-    FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
+    if (sp.clique) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
+    else
+        for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_TRI2_GLOBAL; ++seg) tm.mark(seg, s);
     // the bitmaps are dead now: the window tier's per-entry table goes there,
     // on the second stream beside row pass 2
     if (aux) {
@@ -190,12 +216,19 @@ extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const in
     FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, hp, tiers.c4_rows, s4));
     if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     tm.mark(FGLT_SEG_L2, s);
-    FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
+    if (sp.l2) FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
     if (aux) FGLT_HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
     FGLT_HIP_TRY(launch_c4_late(n, nnz, w, hp, tiers.c4_rows, s, tm));
     tm.mark(FGLT_SEG_FINALIZE, s);
-    FGLT_HIP_TRY(launch_finalize(n, w, out, (flags & FGLT_NET) != 0, s));
+    if (smask == 0xffffu) FGLT_HIP_TRY(launch_finalize(n, w, out, net, s));
+    else FGLT_HIP_TRY(launch_finalize_sub(n, w, out, net, smask, s));
     return finish(n, nnz, w, hp, tm, flags, stats, s);
+}
+
+extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out,
+                        void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats,
+                        void* stream) {
+    return raw_run(n, nnz, offsets, indices, out, ws, ws_bytes, flags, plan, stats, stream, false);
 }
 
 extern "C" int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream) {

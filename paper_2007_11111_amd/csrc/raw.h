@@ -110,6 +110,12 @@ struct RawWs {
 
 RawWs carve_raw(Carver& c, i64 n, i64 nnz);
 
+// The single-graph transform behind fglt_raw (api.hip).  With one_stream the
+// 4-cycle pass's setup runs on `stream` too, so no second stream is created.
+int raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out, void* ws,
+            size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats, void* stream,
+            bool one_stream);
+
 // prep (raw_prep.hip)
 hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s);
 hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
@@ -121,7 +127,7 @@ struct Tiers {
 };
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n);
 int bits_for_n(i64 n);   // bits of the largest rank n - 1 (0 for n <= 1)
-hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, hipStream_t s);
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, bool with_c4, hipStream_t s);
 
 // counting (raw_count.hip)
 // Optional event marks between launches (FGLT_TIMING).
@@ -149,7 +155,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
 hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);
 hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
-hipError_t launch_finalize5(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
+hipError_t launch_finalize_sub(i64 n, RawWs& w, i64* out, bool net, unsigned mask, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);
 hipError_t launch_work_model(i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_net(i64 n, const i64* raw, i64* net, hipStream_t s);
@@ -169,6 +175,30 @@ __device__ __forceinline__ void raw_to_net16(i64* f) {
     f[5] -= 2 * f[9] + f[10] + 2 * f[12] + 4 * f[13] + 2 * f[14] + 6 * f[15];
     f[3] -= f[4];
     f[2] -= 2 * f[4];
+}
+
+// The conversion of a sub-dictionary with index set s (bit k = orbit k):
+// U16(s, s) f_s = raw_s, the sub-matrix of Table II on s (Section V).  The
+// orbits outside s are held at zero and never updated, so every row of the
+// back-substitution reads only the orbits of s.
+__device__ __forceinline__ void raw_to_net_sub(i64* f, unsigned s) {
+#define IN(k) ((s >> (k)) & 1u)
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (!IN(k)) f[k] = 0;
+    if (IN(14)) f[14] -= 3 * f[15];
+    if (IN(13)) f[13] -= 3 * f[15];
+    if (IN(12)) f[12] -= f[13] + f[14] + 3 * f[15];
+    if (IN(11)) f[11] -= 2 * f[14] + 3 * f[15];
+    if (IN(10)) f[10] -= 2 * f[13] + 2 * f[14] + 6 * f[15];
+    if (IN(9)) f[9] -= 2 * f[13] + 3 * f[15];
+    if (IN(8)) f[8] -= f[11] + f[14] + f[15];
+    if (IN(7)) f[7] -= f[9] + f[10] + 2 * f[13] + f[14] + 3 * f[15];
+    if (IN(6)) f[6] -= f[10] + 2 * f[11] + 2 * f[12] + 2 * f[13] + 4 * f[14] + 6 * f[15];
+    if (IN(5)) f[5] -= 2 * f[9] + f[10] + 2 * f[12] + 4 * f[13] + 2 * f[14] + 6 * f[15];
+    if (IN(3)) f[3] -= f[4];
+    if (IN(2)) f[2] -= 2 * f[4];
+#undef IN
 }
 
 }  // namespace fglt

@@ -403,38 +403,50 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
 
 // ------------------------------------------------------------ finalize / net
 
+// Table I for rank-space vertex r from its degree and the accumulators.
+// Orbits whose passes did not run read zeroed accumulators; a sub-dictionary
+// leaves them out of its conversion and its output.
+__device__ __forceinline__ void assemble_raw(i64 r, const i32* __restrict__ rdeg, const i64* __restrict__ sumd,
+                                             const i64* __restrict__ s7, const i64* __restrict__ c3x2,
+                                             const i64* __restrict__ ap2, const i64* __restrict__ ac3,
+                                             const i64* __restrict__ d10, const i64* __restrict__ d14,
+                                             const i64* __restrict__ d13, const i64* __restrict__ c4v,
+                                             const i64* __restrict__ k4v, i64* f) {
+    const i64 d = rdeg[r];
+    const i64 p2 = sumd[r] - d;
+    const i64 c3 = c3x2[r] >> 1;
+    f[0] = 1;
+    f[1] = d;
+    f[2] = p2;
+    f[3] = d * (d - 1) / 2;
+    f[4] = c3;
+    f[5] = ap2[r] - d * (d - 1) - 2 * c3;
+    f[6] = p2 * (d - 1) - 2 * c3;
+    f[7] = s7[r];
+    f[8] = d * (d - 1) * (d - 2) / 6;
+    f[9] = ac3[r] - 2 * c3;
+    f[10] = d10[r];
+    f[11] = (d - 2) * c3;
+    f[12] = c4v[r];
+    f[13] = d13[r];
+    f[14] = d14[r];
+    f[15] = k4v[r];
+    if (d < 2) {  // every term is 0 there, (d - 1) and (d - 2) factors included
+        f[3] = 0;
+        f[6] = 0;
+        f[8] = 0;
+        f[11] = 0;
+    }
+}
+
 __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
                            const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3x2,
                            const i64* __restrict__ ap2, const i64* __restrict__ ac3, const i64* __restrict__ d10,
                            const i64* __restrict__ d14, const i64* __restrict__ d13, const i64* __restrict__ c4v,
                            const i64* __restrict__ k4v, i64* __restrict__ out, int net) {
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
-        const i64 d = rdeg[r];
-        const i64 p2 = sumd[r] - d;
-        const i64 c3 = c3x2[r] >> 1;
         i64 f[16];
-        f[0] = 1;
-        f[1] = d;
-        f[2] = p2;
-        f[3] = d * (d - 1) / 2;
-        f[4] = c3;
-        f[5] = ap2[r] - d * (d - 1) - 2 * c3;
-        f[6] = p2 * (d - 1) - 2 * c3;
-        f[7] = s7[r];
-        f[8] = d * (d - 1) * (d - 2) / 6;
-        f[9] = ac3[r] - 2 * c3;
-        f[10] = d10[r];
-        f[11] = (d - 2) * c3;
-        f[12] = c4v[r];
-        f[13] = d13[r];
-        f[14] = d14[r];
-        f[15] = k4v[r];
-        if (d < 2) {  // every term is 0 there, (d - 1) and (d - 2) factors included
-            f[3] = 0;
-            f[6] = 0;
-            f[8] = 0;
-            f[11] = 0;
-        }
+        assemble_raw(r, rdeg, sumd, s7, c3x2, ap2, ac3, d10, d14, d13, c4v, k4v, f);
         if (net) raw_to_net16(f);
         i64* o = out + (i64)perm[r] * 16;
 #pragma unroll
@@ -444,27 +456,22 @@ __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __res
     }
 }
 
-// The transform with Sigma_5 (Theorem 1): the five tri-node orbits, raw
-// (Table I's first rows) or net (the leading 5x5 block of Table II, which no
-// quad-node orbit enters), scattered to caller order as [n][5].
-__global__ void k_finalize5(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
-                            const i64* __restrict__ sumd, const i64* __restrict__ c3x2, i64* __restrict__ out,
-                            int net) {
+// A sub-dictionary with index set `mask` (Section V): the orbits of the set,
+// raw or net by U16(s, s), scattered to caller order as [n][|s|].
+__global__ void k_finalize_sub(i64 n, const i32* __restrict__ rdeg, const i32* __restrict__ perm,
+                               const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3x2,
+                               const i64* __restrict__ ap2, const i64* __restrict__ ac3, const i64* __restrict__ d10,
+                               const i64* __restrict__ d14, const i64* __restrict__ d13, const i64* __restrict__ c4v,
+                               const i64* __restrict__ k4v, i64* __restrict__ out, int net, unsigned mask, int ncols) {
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
-        const i64 d = rdeg[r];
-        const i64 c3 = c3x2[r] >> 1;
-        i64 f2 = sumd[r] - d;                    // p2
-        i64 f3 = d * (d - 1) / 2;                // C(p1, 2)
-        if (net) {
-            f2 -= 2 * c3;  // a triangle closes two of the 2-paths that end at the vertex
-            f3 -= c3;      // and one pair of its neighbours
-        }
-        i64* o = out + (i64)perm[r] * 5;
-        o[0] = 1;
-        o[1] = d;
-        o[2] = f2;
-        o[3] = f3;
-        o[4] = c3;
+        i64 f[16];
+        assemble_raw(r, rdeg, sumd, s7, c3x2, ap2, ac3, d10, d14, d13, c4v, k4v, f);
+        if (net) raw_to_net_sub(f, mask);
+        i64* o = out + (i64)perm[r] * ncols;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if ((mask >> k) & 1u) o[c++] = f[k];
     }
 }
 
@@ -628,9 +635,10 @@ hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize5(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize5, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.c3x2,
-                       out, net ? 1 : 0);
+hipError_t launch_finalize_sub(i64 n, RawWs& w, i64* out, bool net, unsigned mask, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_sub, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7,
+                       w.c3x2, w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0, mask,
+                       __builtin_popcount(mask));
     return hipGetLastError();
 }
 

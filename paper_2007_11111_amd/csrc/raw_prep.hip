@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
 //   A diagonal entry gets rpos = -1 (the input check rejects it).
 __global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
                        i64 nnz, i32* __restrict__ rpos, i64* __restrict__ mir, i64* __restrict__ G,
-                       DevPlan* plan) {
+                       int with_c4, DevPlan* plan) {
     u32 err = 0;
     for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
         {
@@ -207,7 +207,7 @@ __global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ri
                     mir[p] = p;  // harmless: the run stops at the input check
                 }
                 rpos[p] = rp;
-                work = rp;
+                work = with_c4 ? rp : 0;  // no 4-cycle pass: no wedge work, no 4-cycle tiers
             } else {
                 if ((i64)v > u) work = rv.deg - rv.lo;  // mir[p] comes from the mirror's thread
                 rpos[p] = -1;
@@ -337,12 +337,12 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
     return t;
 }
 
-hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, hipStream_t s) {
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, bool with_c4, hipStream_t s) {
     hipError_t e;
     hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.vrec, w.plan);
     if (nnz > 0)
         hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.vrec, w.ridx, w.rrow, nnz,
-                           w.rpos, w.mir, w.G, w.plan);
+                           w.rpos, w.mir, w.G, with_c4 ? 1 : 0, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive_i64(w.G, w.G, nnz, w.partials, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tiers, dim3(grid_for(n, TT, 256)), dim3(TT), 0, s, w.roff, w.lo, w.rdeg, w.G, n, th,

@@ -72,6 +72,7 @@ class Outcome:
     host_net: object = None    # the result copied to the host (copying executors)
     t_done: float = 0.0        # perf_counter() when its kernels had completed
     t_host: float = 0.0        # perf_counter() when its host copy had completed
+    csr_base: tuple = (0, 0)   # (vertex, entry) offset of that CSR inside a batch's packed CSR
 
 
 @dataclass
@@ -82,9 +83,17 @@ class Result:
     queued_s: float          # arrival -> start of its launch
     batched_with: int        # number of requests in the same launch
     latency_host_s: float = 0.0  # arrival -> result on the host (copying executors), else 0
-    csr: object = None
+    csr: object = None       # resident device CSR (views into the launch's packed CSR for a batch)
     host_net: object = None
     _server: "Server" = None
+    csr_base: tuple = (0, 0)
+
+    def local_csr(self):
+        """The request's resident CSR in its own vertex numbering (a batched
+        request's views hold the packed batch's global ids and offsets)."""
+        off, idx = self.csr
+        v0, e0 = self.csr_base
+        return (off - e0, idx - v0) if (v0 or e0) else (off, idx)
 
     def release(self):
         """Returns the request's resident bytes to the budget."""
@@ -123,7 +132,7 @@ class GpuExecutor:
             work = self.fg.raw_workspace_bytes(n, nnz)
         return csr + out, work
 
-    def _finish(self, stream, nets, csrs):
+    def _finish(self, stream, nets, csrs, bases=None):
         stream.synchronize()
         t_done = time.perf_counter()
         hosts = [None] * len(nets)
@@ -134,8 +143,9 @@ class GpuExecutor:
             stream.synchronize()
             t_host = time.perf_counter()
             hosts = [h.numpy() if h is not None else None for h in hosts]
-        return [x if isinstance(x, Exception) else Outcome(x, c, h, t_done, t_host)
-                for x, c, h in zip(nets, csrs, hosts)]
+        bases = bases or [(0, 0)] * len(nets)
+        return [x if isinstance(x, Exception) else Outcome(x, c, h, t_done, t_host, bb)
+                for x, c, h, bb in zip(nets, csrs, hosts, bases)]
 
     def run_single(self, req, stream):
         torch = self.torch
@@ -170,7 +180,7 @@ class GpuExecutor:
         nets = [out[b[k]:b[k + 1]] for k in range(G)]
         e = off.tolist()
         csrs = [(off_d[b[k]:b[k + 1] + 1], idx_d[e[b[k]]:e[b[k + 1]]]) for k in range(G)]
-        return self._finish(stream, nets, csrs)
+        return self._finish(stream, nets, csrs, [(b[k], e[b[k]]) for k in range(G)])
 
 
 class Server:
@@ -317,7 +327,8 @@ class Server:
                 if isinstance(o, Outcome):
                     t_done = o.t_done or end
                     res = Result(r.rid, o.net, t_done - r.arrival, r.start - r.arrival, len(reqs),
-                                 (o.t_host - r.arrival) if o.t_host else 0.0, o.csr, o.host_net, self)
+                                 (o.t_host - r.arrival) if o.t_host else 0.0, o.csr, o.host_net, self,
+                                 o.csr_base)
                 else:
                     res = Result(r.rid, o, end - r.arrival, r.start - r.arrival, len(reqs), _server=self)
                 self.latencies.append(res.latency_s)

@@ -441,3 +441,64 @@ def test_sigma5_medium_and_stats(fg):
     seg = st["seg_ms"]
     for name in ("tri2_wave", "tri2_lds", "tri2_global", "l2", "c4_window"):
         assert seg[name] < 0.05, (name, seg[name])
+
+
+# ------------------------------------------------------------------ sub-dictionaries (Section V)
+
+# index sets that switch each pass on alone and together: degrees and row
+# pass 1 only; the triangle pass; row pass 2; the clique pass; the 4-cycle
+# pass alone; sets that are and are not closed under Table II
+SUBDICTS = [[0, 1, 2, 3, 7, 8], [0, 1, 2, 3, 4, 6, 11], [0, 1, 5, 9, 10, 14], [0, 1, 13, 15], [0, 1, 12],
+            [0, 1, 12, 13, 14, 15], [0, 1, 4, 9, 13, 15], [0, 1, 2, 3], [0, 1, 3, 12, 15], [0, 1, 6, 7, 14]]
+
+
+def gpu_subdict(fg, off, idx, s, plan=None, net=True):
+    o, i = to_dev(off, idx)
+    out = fg.raw(o, i, net=net, plan=plan, sigma=s)
+    torch.cuda.synchronize()
+    assert tuple(out.shape) == (off.size - 1, len(s))
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("plan", ["default", "wave", "block", "global"])
+def test_subdict(fg, plan):
+    """fglt_raw with a sub-dictionary mask against the oracle's U16(s, s)
+    conversion of its raw counts, raw-only and net, with every tier plan:
+    the small random graphs and K_80."""
+    graphs = _small_graphs()
+    k = graphgen.clique(80)
+    graphs.append((k.n, list(zip(k.src.tolist(), k.dst.tolist()))))
+    for gi, (n, edges) in enumerate(graphs):
+        off, idx = csr_arrays(n, edges)
+        raw = oracle.raw(off, idx)
+        for s in SUBDICTS:
+            say(f"subdict graph {gi} n={n} m={len(edges)} s={s} plan={plan}")
+            np.testing.assert_array_equal(gpu_subdict(fg, off, idx, s, PLANS[plan], net=False),
+                                          oracle.subdict(raw, s, net=False))
+            np.testing.assert_array_equal(gpu_subdict(fg, off, idx, s, PLANS[plan]), oracle.subdict(raw, s))
+
+
+def test_subdict_medium_and_skipped_passes(fg):
+    """A 20k-vertex power-law graph (window tier included) for every set, and
+    timing that shows the skipped passes: no 4-cycle work without orbit 12, no
+    clique pass without 13 and 15."""
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    raw = oracle.raw(off, idx)
+    o, i = to_dev(off, idx)
+    for s in SUBDICTS:
+        say(f"subdict medium s={s}")
+        out, st = fg.raw(o, i, net=True, sigma=s, stats=True, timing=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.subdict(raw, s))
+        seg = st["seg_ms"]
+        if 12 not in s:
+            assert st["wedge_items"] == 0 and sum(st["c4_tier_vertices"]) == 0
+            assert seg["c4_window"] < 0.05
+        if 13 not in s and 15 not in s:
+            for name in ("tri2_wave", "tri2_lds", "tri2_global"):
+                assert seg[name] < 0.05, (s, name, seg[name])
+    # the plan's own 4-cycle tiers for orbit 12 alone, window tier included
+    out = fg.raw(o, i, net=True, sigma=[0, 1, 12], plan={"c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": -1})
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), oracle.subdict(raw, [0, 1, 12]))

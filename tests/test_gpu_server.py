@@ -32,8 +32,9 @@ def test_server_mixed_requests():
     for k, ((o, i), r) in enumerate(zip(csrs, res)):
         got = r.net.cpu().numpy()
         # the request's CSR stays resident on the device with its result
-        np.testing.assert_array_equal(r.csr[0].cpu().numpy(), o)
-        np.testing.assert_array_equal(r.csr[1].cpu().numpy(), i)
+        lo, li = r.local_csr()
+        np.testing.assert_array_equal(lo.cpu().numpy(), o)
+        np.testing.assert_array_equal(li.cpu().numpy(), i)
         r.release()
         np.testing.assert_array_equal(got, oracle.net(o, i), err_msg=f"request {k} (n={o.size - 1})")
     assert srv.free == 8 << 30
