@@ -185,6 +185,27 @@ int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indi
              fglt_stats* stats, void* stream);
 
 /*
+ * fglt_raw without a workspace argument, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a device array of
+ * FGLT_NOALLOC_SCRATCH_BYTES inside the library, one per device, held from
+ * the library's load until the process ends; its device address is taken
+ * with hipGetSymbolAddress on the first call on each device.  The call
+ * itself allocates nothing (no hipMalloc, no stream or event creation; it
+ * runs every kernel on `stream`).
+ *   n, nnz, offsets, indices, out, flags, plan, stats   as for fglt_raw;
+ *                FGLT_TIMING is not offered (FGLT_EINVAL)
+ * Returns FGLT_EWORKSPACE when fglt_raw_workspace(n, nnz) exceeds
+ * FGLT_NOALLOC_SCRATCH_BYTES (about 1.6M directed entries fit).  Every call
+ * on a device shares that device's array and overwrites it, so calls that
+ * overlap on one device (different streams or threads) race: the caller
+ * serializes them.  Synchronizes with `stream` as fglt_raw does.
+ */
+#define FGLT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int fglt_raw_noalloc(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices,
+                     int64_t* out, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats, void* stream);
+
+/*
  * Net from raw frequencies: f = U16^{-1} \hat f per vertex (Section V,
  * Table II), by exact integer back-substitution.  `net` may equal `raw`.
  * Asynchronous; never synchronizes.
