@@ -142,8 +142,9 @@ typedef struct {
 /* Tier thresholds of fglt_raw (host struct); 0 selects a default.  A vertex u
  * with out-degree D (under the degree ordering) is counted by one wavefront if
  * D <= tri_wave_max (<= 64), by a workgroup with LDS bitmaps if
- * D <= tri_lds_max (<= 512), else by a workgroup with bitmaps in the
- * workspace.  The 4-cycle pass goes by the number W of rank-ordered wedges of
+ * D <= tri_lds_max (<= 512), by a 1024-thread workgroup with LDS position
+ * map and bitmap rows in the workspace if D <= tri_hub_max (<= 1024), else
+ * by a workgroup with bitmaps in the workspace.  The 4-cycle pass goes by the number W of rank-ordered wedges of
  * u: one wavefront if W <= c4_wave_max (<= 128), a workgroup with an LDS hash
  * if W <= c4_block_max (<= 2048), a large workgroup with a packed LDS hash if
  * W <= c4_hash_max (<= 16384) and the counts fit the packing, else dense LDS
@@ -158,6 +159,11 @@ typedef struct {
     int32_t c4_window_rows; /* window tier, how a middle's row is cut at the window
                                boundaries: 0 (default) a per-entry table where it fits the
                                workspace, else 1; 1 a per-vertex table; 2 binary searches */
+    int32_t tri_hub_max;    /* out-degree up to which a vertex beyond the LDS tier is counted
+                               by a 1024-thread workgroup with its position map (and, in the
+                               clique pass, its adjacency bitmaps) in LDS; default 1024,
+                               -1 disables the hub tier (every such vertex uses bitmaps in
+                               the workspace) */
 } fglt_raw_plan;
 
 /*

@@ -92,7 +92,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     sub-dictionary (Section V): a 16-bit mask or an iterable of orbit numbers
     that holds 0 and 1; the result is then [n, |s|], the orbits of s in
     ascending order, net by U16(s, s).  sigma5=True is sigma=0x1F (Theorem 1).  ``plan`` may set the tier
-    thresholds tri_wave_max, tri_lds_max, c4_wave_max, c4_block_max, c4_hash_max and the
+    thresholds tri_wave_max, tri_lds_max, tri_hub_max, c4_wave_max, c4_block_max, c4_hash_max and the
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events); with
     workmodel=True (and stats=True) they carry the byte model's work terms
@@ -119,7 +119,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     if plan:
         rp = RawPlan(int(plan.get("tri_wave_max", 0)), int(plan.get("tri_lds_max", 0)),
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
-                     int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)))
+                     int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)),
+                     int(plan.get("tri_hub_max", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
                      int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | FGLT_SIGMA(mask)
                      | (FGLT_WORKMODEL if workmodel else 0), ctypes.byref(rp) if rp is not None else None,

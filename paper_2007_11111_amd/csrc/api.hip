@@ -199,12 +199,12 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
     // 4-cycle work lists were built without the 4-cycle orbit, so its tiers
     // are empty and the second stream stays idle).
     const bool stored = sp.clique && bitmap_words <= w.bstore_cap;
-    if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, s, tm));
+    if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, tiers.tri_hub, s, tm));
     else
         for (int seg = FGLT_SEG_TRI1_WAVE; seg <= FGLT_SEG_TRI1_GLOBAL; ++seg) tm.mark(seg, s);
     tm.mark(FGLT_SEG_FILL, s);
     FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
-    if (sp.clique) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, s, tm));
+    if (sp.clique) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, tiers.tri_hub, s, tm));
     else
         for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_TRI2_GLOBAL; ++seg) tm.mark(seg, s);
     // the bitmaps are dead now: the window tier's per-entry table goes there,

@@ -891,24 +891,34 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 
 // ------------------------------------------------------------ launcher
 
-// The window tier's configuration, the same in both parts of the pass.
+// The window tier's configuration, the same in every part of the pass.  The
+// tier's vertices (ascending rank) split into those of degree below 65536 --
+// every count and every middle's row position fits 16 bits, since a middle
+// ranks below its vertex and so has no larger degree -- counted with 16-bit
+// counters over 65536-rank windows, and the rest (the last ranks), counted
+// with 32-bit counters over 32768-rank windows and binary searches of the
+// middles' rows.
 struct C4WinCfg {
-    bool pack16, use_tab, use_etab;
-    i64 WS, K1, TS;
+    u32 nl, nh;          // vertices with 16-bit and with 32-bit counters
+    bool use_tab, use_etab;
+    i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
 };
+
+static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
+static constexpr i64 C4W_WS32 = C4W_WORDS;      // ranks per window, 32-bit counters
 
 static C4WinCfg c4_win_cfg(i64 n, const RawWs& w, const DevPlan& hp, int rows_mode) {
     C4WinCfg c;
-    c.pack16 = hp.d_max < 65536;
-    c.WS = c.pack16 ? 2 * C4W_WORDS : C4W_WORDS;
-    c.K1 = (n + c.WS - 1) / c.WS + 1;
-    // the table's row stride: 32 bytes' worth of entries (16-bit entries with packed counts)
-    c.TS = c.pack16 ? (c.K1 + 15) & ~(i64)15 : (c.K1 + 7) & ~(i64)7;
-    c.use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * c.TS * (c.pack16 ? 2 : 4) <= w.c4_tab_cap * 4;
+    c.nh = std::min(hp.n_c4_heavy, hp.n_c4[3]);
+    c.nl = hp.n_c4[3] - c.nh;
+    c.K1 = (n + C4W_WS16 - 1) / C4W_WS16 + 1;
+    // the table's row stride: 32 bytes' worth of entries
+    c.TS = (c.K1 + 15) & ~(i64)15;
+    c.use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * c.TS <= w.c4_tab_cap;
     // the per-entry window table lives in the stored bitmaps' memory (16-bit
     // entries, four per word)
-    c.use_etab = rows_mode == 0 && c.pack16 && c.use_tab && hp.c4_etab <= 4 * w.bstore_cap;
-    static_assert(2 * C4W_WORDS == C4W_SPAN, "the tier assignment sizes the table with this window");
+    c.use_etab = rows_mode == 0 && c.use_tab && hp.c4_etab <= 4 * w.bstore_cap;
+    static_assert(C4W_WS16 == C4W_SPAN, "the tier assignment sizes the table with this window");
     return c;
 }
 
@@ -923,7 +933,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
     const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
     hipError_t e;
     if (c2 || c3)
-        if ((e = hipMemsetAsync(w.c4_jobctr, 0, 2 * sizeof(u32), s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(w.c4_jobctr, 0, 3 * sizeof(u32), s)) != hipSuccess) return e;
     if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
                                w.G, w.mir, w.c4_list, c0, w.c4v);
     if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
@@ -937,28 +947,32 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
     if (!c3) return hipSuccess;
     const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
     // window-tier vertices in ascending order (the sort's buffer: c4_ebase,
-    // not yet in use; the shared one is the clique pass's memory)
+    // not yet in use; the shared one is the clique pass's memory); the
+    // vertices of degree >= 65536 end the list
     i32* hs = w.c4_list + 3 * n;
     hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c3);
     SegSortWs ws = w.sort;
     ws.tmp = reinterpret_cast<i32*>(w.c4_ebase);
     if ((e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), ws, 1, s)) != hipSuccess) return e;
-    if (c.use_tab) {
-        if (c.pack16)
+    if (c.nl) {
+        if (c.use_tab)
             hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               n, c.K1, c.TS, c.WS, reinterpret_cast<u16*>(w.c4_tab));
-        else
-            hipLaunchKernelGGL(k_c4_table<i32>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               n, c.K1, c.TS, c.WS, w.c4_tab);
+                               n, c.K1, c.TS, C4W_WS16, w.c4_tab);
+        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nl, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c.nl, C4W_WS16,
+                           w.c4_jobcnt);
+        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.nl, w.partials, s)) != hipSuccess) return e;
+        if (c.use_etab) {
+            // c4_jobcnt is free again once the job prefix is built: the chunk counts
+            hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c.nl, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c.nl, C4W_WS16,
+                               w.c4_ebase, w.c4_jobcnt);
+            if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c.nl, w.partials, s)) != hipSuccess) return e;
+            if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.nl, w.partials, s)) != hipSuccess) return e;
+        }
     }
-    hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, c.WS, w.c4_jobcnt);
-    if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c3, w.partials, s)) != hipSuccess) return e;
-    if (c.use_etab) {
-        // c4_jobcnt is free again once the job prefix is built: the chunk counts
-        hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c3, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c3, c.WS,
-                           w.c4_ebase, w.c4_jobcnt);
-        if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c3, w.partials, s)) != hipSuccess) return e;
-        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c3, w.partials, s)) != hipSuccess) return e;
+    if (c.nh) {
+        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nh, PT, 4096)), dim3(PT), 0, s, hs + c.nl, w.lo, c.nh,
+                           C4W_WS32, w.c4_hjobcnt);
+        if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.nh, w.partials, s)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
@@ -966,40 +980,37 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
 // Part two: the per-entry window table, in the stored bitmaps' memory, so
 // after the clique pass (it may run on the second stream beside row pass 2).
 hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s) {
-    const u32 c3 = hp.n_c4[3];
-    if (!c3) return hipSuccess;
+    if (!hp.n_c4[3]) return hipSuccess;
     const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
-    if (c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
+    if (c.nl && c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
         hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
-                           w.rpos, reinterpret_cast<const u16*>(w.c4_tab), c.TS, w.c4_list + 3 * n, c3, w.c4_jobcnt,
-                           w.c4_ebase, c.WS, reinterpret_cast<u16*>(w.bstore));
+                           w.rpos, w.c4_tab, c.TS, w.c4_list + 3 * n, c.nl, w.c4_jobcnt, w.c4_ebase, C4W_WS16,
+                           reinterpret_cast<u16*>(w.bstore));
     return hipGetLastError();
 }
 
-// Part three: the window kernel.
+// Part three: the window kernels, 16-bit counters then 32-bit counters.
 hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
     (void)nnz;
-    const u32 c3 = hp.n_c4[3];
     tm.mark(FGLT_SEG_C4_WAVE, s);
     tm.mark(FGLT_SEG_C4_BLOCK, s);
     tm.mark(FGLT_SEG_C4_HASH, s);
-    if (!c3) {
-        tm.mark(FGLT_SEG_C4_WINDOW, s);
-        return hipSuccess;
-    }
+    tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernels alone
+    if (!hp.n_c4[3]) return hipSuccess;
     const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
     const i32* hs = w.c4_list + 3 * n;
     const u16* const etab = reinterpret_cast<const u16*>(w.bstore);
-    tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernel alone
+    const i32* const tab = reinterpret_cast<const i32*>(w.c4_tab);
     const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
-#define C4W_LAUNCH(P16, TM)                                                                                    \
-    hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, w.mir, \
-                       w.c4_tab, c.TS, etab, w.c4_ebase, hs, c3, w.c4_jobpre, w.c4_jobctr, w.c4_scr, w.c4_scr_cap, w.c4v)
-    if (c.use_etab) C4W_LAUNCH(true, 2);
-    else if (c.pack16 && c.use_tab) C4W_LAUNCH(true, 1);
-    else if (c.pack16) C4W_LAUNCH(true, 0);
-    else if (c.use_tab) C4W_LAUNCH(false, 1);
-    else C4W_LAUNCH(false, 0);
+#define C4W_LAUNCH(P16, TM, HS, NH, PRE, CTR)                                                                     \
+    hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
+                       w.mir, tab, c.TS, etab, w.c4_ebase, HS, NH, PRE, CTR, w.c4_scr, w.c4_scr_cap, w.c4v)
+    if (c.nl) {
+        if (c.use_etab) C4W_LAUNCH(true, 2, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
+        else if (c.use_tab) C4W_LAUNCH(true, 1, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
+        else C4W_LAUNCH(true, 0, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
+    }
+    if (c.nh) C4W_LAUNCH(false, 0, hs + c.nl, c.nh, w.c4_hjobpre, w.c4_jobctr + 2);
 #undef C4W_LAUNCH
     return hipGetLastError();
 }

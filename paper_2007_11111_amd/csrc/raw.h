@@ -14,11 +14,15 @@ namespace fglt {
 // Tier thresholds.
 constexpr int TRI_WAVE_MAX = 64;     // out-degree handled by one wavefront (one bitmap word)
 constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup's LDS
+constexpr int TRI_HUB_MAX = 1024;    // out-degree of the hub tier: position map in LDS, and in the
+                                     // clique pass A = B | B^T (128 KiB) in LDS
 // Clique-pass count of an N+ entry, packed as dv << EK_SHIFT | kv: kv (the
 // 4-cliques) is at most 2 (D - 1)^2 < 2^20 for D <= TRI_LDS_MAX, dv (the
 // diamonds) below D * 2^21 (degrees < 2^21), so the word stays below 2^50.
 constexpr int EK_SHIFT = 20;
+// (the hub tier stores kv = C(D - 1, 2) at most)
 static_assert(2 * (TRI_LDS_MAX - 1) * (TRI_LDS_MAX - 1) < (1 << EK_SHIFT), "kv must fit below EK_SHIFT");
+static_assert((TRI_HUB_MAX - 1) * (TRI_HUB_MAX - 2) / 2 < (1 << EK_SHIFT), "hub kv must fit below EK_SHIFT");
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
@@ -40,7 +44,9 @@ struct DevPlan {
     i64 tri_items_tier[3];
     i64 wedge_items_tier[4];
     i64 triangles;
-    i64 c4_etab;  // entries of the window tier's per-entry window table
+    i64 c4_etab;  // entries of the window tier's per-entry window table (16-bit part)
+    u32 n_c4_heavy; // window-tier vertices of degree >= 65536 (32-bit counters; the last ranks)
+    u32 pad1;
     i64 min_sum;  // byte model (FGLT_WORKMODEL): sum over edges of min(d_i, d_j)
     i64 k4_merge; // byte model: oriented 4-clique merge steps
 };
@@ -92,12 +98,14 @@ struct RawWs {
     i64* c4_jobcnt;     // [n+1] jobs per window-tier vertex, then the prefix of their middle counts
     i64* c4_jobpre;     // [n+1] their exclusive scan
     i64* c4_ebase;      // [n+1] start of each window-tier vertex's block of the per-entry window table
-    u32* c4_jobctr;     // [4] job queue heads: window tier, hash tier
+    i64* c4_hjobcnt;    // [nnz/65536 + 2] jobs per window-tier vertex of degree >= 65536
+    i64* c4_hjobpre;    // [nnz/65536 + 2] their exclusive scan
+    u32* c4_jobctr;     // [4] job queue heads: window tier (16-bit, 32-bit counters), hash tier
     i64* bcnt;          // [n] bitmap words per vertex (clique pass store)
     i64* boff;          // [n+1] their exclusive scan
     u64* bstore;        // stored N+ bitmaps of the wave and LDS tiers
     i64 bstore_cap;     // its capacity in words
-    i32* c4_tab;        // window table of the heavy 4-cycle tier (optional)
+    u16* c4_tab;        // vertex window table of the window tier, 16-bit entries (optional)
     i64 c4_tab_cap;     // its capacity in entries
     u32* c4_scr;        // [C4W_GRID * c4_scr_cap] per-workgroup copies of a window's wedge ends
     i64 c4_scr_cap;
@@ -121,7 +129,7 @@ hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, Ra
 hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
                                    hipStream_t s);
 struct Tiers {
-    i64 tri_wave, tri_lds, c4_wave, c4_block, c4_hash;
+    i64 tri_wave, tri_lds, tri_hub, c4_wave, c4_block, c4_hash;
     i64 c4_hash_lmax;  // largest |N-(u)| whose counts fit the packed hash words
     int c4_rows;       // window tier's row cuts: 0 per-entry table where it fits, 1 per-vertex table, 2 searches
 };
@@ -145,10 +153,11 @@ struct SegTimer {
 
 // tri.hip
 hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s);
-hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier);
-hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier);
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
-                      SegTimer& tm);
+hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier,
+                              i64 hub_max);
+hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier, i64 hub_max);
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, i64 hub_max,
+                      hipStream_t s, SegTimer& tm);
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s);
 hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);

@@ -256,8 +256,9 @@ template <int MODE, bool GLOBAL>
 __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                   const i64* __restrict__ G, const i32* __restrict__ list,
-                                                  u32 count, i32* __restrict__ C3, i64* __restrict__ k4v, i64* __restrict__ d13,
-                                                  u64* __restrict__ slots, i64 slot_words, DevPlan* plan) {
+                                                  u32 count, i64 dmin, i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                  i64* __restrict__ d13, u64* __restrict__ slots, i64 slot_words,
+                                                  DevPlan* plan) {
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     constexpr bool BITS = MODE == 2;
@@ -273,6 +274,7 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         const i64 u = list[it];
         const i64 bu = roff[u] + lo[u];
         const int D = (int)(roff[u + 1] - bu);
+        if (D <= dmin) continue;  // the hub tier takes it (uniform over the block)
         const int W = (D + 63) / 64;
         const i64 gb = G[bu];
         const i64 T = G[bu + D] - gb;
@@ -509,8 +511,8 @@ hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, hipStream_t s,
-                      SegTimer& tm) {
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, i64 hub_max,
+                      hipStream_t s, SegTimer& tm) {
     (void)nnz;
     const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const i32* l0 = w.tri_list;
@@ -518,36 +520,40 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
     const i32* l2 = w.tri_list + 2 * n;
     hipError_t e;
     if (mode == 1) {
-        // triangle pass; the wave and LDS tiers also store their N+ bitmaps
+        // triangle pass; the wave, LDS and hub tiers also store their N+ bitmaps
         tm.mark(FGLT_SEG_TRI1_WAVE, s);
-        if ((e = launch_tri1_stored(n, w, hp, stored, s, 0)) != hipSuccess) return e;
+        if ((e = launch_tri1_stored(n, w, hp, stored, s, 0, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_LDS, s);
-        if ((e = launch_tri1_stored(n, w, hp, stored, s, 1)) != hipSuccess) return e;
+        if ((e = launch_tri1_stored(n, w, hp, stored, s, 1, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
+        if ((e = launch_tri1_stored(n, w, hp, stored, s, 2, hub_max)) != hipSuccess) return e;
         if (c2) hipLaunchKernelGGL((k_tri_block<1, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words, w.plan);
+                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, hub_max, w.C3, w.k4v, w.d13,
+                                   w.tri_slots, w.tri_slot_words, w.plan);
     } else {
         // clique and diamond pass: from the stored bitmaps, or by scanning again
         tm.mark(FGLT_SEG_TRI2_WAVE, s);
         if (stored) {
-            if ((e = launch_tri2_stored(n, w, hp, s, 0)) != hipSuccess) return e;
+            if ((e = launch_tri2_stored(n, w, hp, s, 0, hub_max)) != hipSuccess) return e;
         } else if (c0) {
             hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
                                w.rdeg, w.G, l0, c0, w.C3, w.k4v, w.d13, w.plan);
         }
         tm.mark(FGLT_SEG_TRI2_LDS, s);
         if (stored) {
-            if ((e = launch_tri2_stored(n, w, hp, s, 1)) != hipSuccess) return e;
+            if ((e = launch_tri2_stored(n, w, hp, s, 1, hub_max)) != hipSuccess) return e;
         } else if (c1) {
             hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
-                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, w.C3, w.k4v, w.d13, w.tri_slots,
+                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, (i64)0, w.C3, w.k4v, w.d13, w.tri_slots,
                                w.tri_slot_words, w.plan);
         }
         tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
+        // the hub tier from its stored rows; the rest of the last tier (all of
+        // it when nothing is stored) with bitmaps in the workspace
+        if (stored && (e = launch_tri2_stored(n, w, hp, s, 2, hub_max)) != hipSuccess) return e;
         if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, w.C3, w.k4v, w.d13, w.tri_slots,
-                                   w.tri_slot_words, w.plan);
+                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, stored ? hub_max : (i64)0, w.C3,
+                                   w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan);
     }
     return hipGetLastError();
 }

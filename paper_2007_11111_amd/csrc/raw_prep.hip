@@ -259,6 +259,7 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
     i64 dpmax = 0;
     i64 titems[3] = {0, 0, 0}, witems[4] = {0, 0, 0, 0};
     i64 etab = 0;  // window tier: |N-(u)| x (windows + 1) entries of the per-entry window table
+    i64 heavy = 0; // window-tier vertices of degree >= 65536
     for (i64 u0 = (i64)blockIdx.x * TT; u0 < n; u0 += (i64)gridDim.x * TT) {
         const i64 u = u0 + threadIdx.x;
         int tcls = -1, ccls = -1;
@@ -277,7 +278,10 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
             }
             if (tcls >= 0) titems[tcls] += T;
             if (ccls >= 0) witems[ccls] += W;
-            if (ccls == 3) etab += (m - b) * ((u + C4W_SPAN - 1) / C4W_SPAN + 1);
+            if (ccls == 3) {
+                if (e - b < 65536) etab += (m - b) * ((u + C4W_SPAN - 1) / C4W_SPAN + 1);
+                else ++heavy;
+            }
         }
         block_append<TT, 3>(tcls, (i32)u, plan->n_tri, tri_list, n, wt, bt);
         block_append<TT, 4>(ccls, (i32)u, plan->n_c4, c4_list, n, wc, bc);
@@ -296,6 +300,8 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
     }
     etab = block_sum<TT>(etab, part);
     if (threadIdx.x == 0 && etab) atomicAdd((unsigned long long*)&plan->c4_etab, (unsigned long long)etab);
+    heavy = block_sum<TT>(heavy, part);
+    if (threadIdx.x == 0 && heavy) atomicAdd(&plan->n_c4_heavy, (u32)heavy);
 }
 
 __global__ void __launch_bounds__(PT) k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo,
@@ -315,10 +321,12 @@ int bits_for_n(i64 n) {
 }
 
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
-    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0, 0};
+    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, TRI_HUB_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0, 0};
     if (plan) {
         if (plan->tri_wave_max > 0) t.tri_wave = std::min<i64>(plan->tri_wave_max, TRI_WAVE_MAX);
         if (plan->tri_lds_max > 0) t.tri_lds = std::min<i64>(plan->tri_lds_max, TRI_LDS_MAX);
+        if (plan->tri_hub_max > 0) t.tri_hub = std::min<i64>(plan->tri_hub_max, TRI_HUB_MAX);
+        if (plan->tri_hub_max < 0) t.tri_hub = 0;
         if (plan->c4_wave_max > 0) t.c4_wave = std::min<i64>(plan->c4_wave_max, C4_WAVE_MAX);
         if (plan->c4_wave_max < 0) t.c4_wave = 0;
         if (plan->c4_block_max > 0) t.c4_block = std::min<i64>(plan->c4_block_max, C4_BLOCK_MAX);
@@ -349,7 +357,8 @@ hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, bool with
                        w.tri_list, w.c4_list, w.plan);
     hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_bitmap_offsets(n, w, th.tri_lds, s);
+    // bitmap rows of the wave, LDS and hub tiers (the clique pass reads them)
+    return launch_bitmap_offsets(n, w, std::max(th.tri_lds, th.tri_hub), s);
 }
 
 // ------------------------------------------------------------ workspace layout
@@ -397,19 +406,22 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.tri_slots = c.take<u64>(NUM_TRI_SLOTS * w.tri_slot_words);
     w.bcnt = c.take<i64>(nn);
     w.boff = c.take<i64>(nn + 1);
-    w.bstore_cap = std::max<i64>(2 * nnz, 64);
+    w.bstore_cap = std::max<i64>(3 * nnz, 64);
     w.bstore = c.take<u64>(w.bstore_cap);
     w.c4_segoff = c.take<i64>(2);
     w.c4_jobcnt = c.take<i64>(nn + 1);
     w.c4_jobpre = c.take<i64>(nn + 1);
     w.c4_ebase = c.take<i64>(nn + 1);
+    w.c4_hjobcnt = c.take<i64>((nnz >> 16) + 2);
+    w.c4_hjobpre = c.take<i64>((nnz >> 16) + 2);
     w.c4_jobctr = c.take<u32>(4);
-    // window table: n x (ceil(n / 32768) + 1) entries when that stays within 1 GiB
+    // vertex window table: n x (ceil(n / 65536) + 1) 16-bit entries, rows
+    // padded to 16 entries, when that stays within max(1 GiB, 8 bytes per entry)
     {
-        const i64 k1 = ((nn + 32767) / 32768 + 1 + 7) & ~(i64)7;  // rows padded to 8 entries
+        const i64 k1 = ((nn + C4W_SPAN - 1) / C4W_SPAN + 1 + 15) & ~(i64)15;
         const i64 entries = nn * k1;
-        w.c4_tab_cap = entries * 4 <= ((i64)1 << 30) ? entries : 0;
-        w.c4_tab = w.c4_tab_cap ? c.take<i32>(w.c4_tab_cap) : nullptr;
+        w.c4_tab_cap = entries * 2 <= std::max<i64>((i64)1 << 30, 8 * nnz) ? entries : 0;
+        w.c4_tab = w.c4_tab_cap ? c.take<u16>(w.c4_tab_cap) : nullptr;
         if (!c.base) w.c4_tab = nullptr;
     }
     // window-tier scratch: up to 2^20 words per workgroup, at most nnz / 16

@@ -252,6 +252,135 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
     }
 }
 
+// Hub tier of the triangle pass: TRI_LDS_MAX < D <= hub_max (at most
+// TRI_HUB_MAX), one vertex per 1024-thread workgroup.  The position map of
+// N+(u) and the run arrays stay in LDS; the bitmap B (up to 128 KiB) does not
+// fit beside them, so C3 of the edges (u, v_k) is counted in LDS (a hit at
+// (k, l) adds one to both), and the hits' bits of B (rows in the workspace,
+// read by the clique pass) and C3 increments of the far edges (v_k, v_l) are
+// queued per wavefront in LDS and issued in bursts, so that no device-scope
+// atomic sits between the walk's gathers.
+static constexpr int HT = 1024;        // hub-tier block: 16 wavefronts on one vertex
+static constexpr int HUB_QCAP = 256;   // hits queued per wavefront before a burst
+
+struct HubQueue {
+    u32* qe;   // entry index of the far edge (v_k, v_l)
+    u32* qkl;  // k << 16 | l
+    u32 n;     // wave-uniform fill
+};
+
+__device__ __forceinline__ void hub_flush(HubQueue& q, i32* __restrict__ C3, u64* __restrict__ Bg, int W) {
+    wave_lds_fence();
+    for (u32 i = lane_id(); i < q.n; i += WAVE) {
+        atomicAdd(&C3[q.qe[i]], 1);
+        if (Bg) {
+            const u32 kl = q.qkl[i];
+            const u32 k = kl >> 16, l = kl & 0xffffu;
+            atomicOr((unsigned long long*)&Bg[(i64)k * W + (l >> 6)], 1ull << (l & 63));
+        }
+    }
+    q.n = 0;
+    wave_lds_fence();
+}
+
+__device__ __forceinline__ void hub_push(bool hit, i64 e, u32 kl, HubQueue& q, i32* __restrict__ C3,
+                                         u64* __restrict__ Bg, int W, int defer) {
+    const u64 hm = __ballot(hit);
+    if (!hm) return;
+    if (!defer) {  // entry indices beyond 32 bits: issue at once
+        if (hit) {
+            atomicAdd(&C3[e], 1);
+            if (Bg) atomicOr((unsigned long long*)&Bg[(i64)(kl >> 16) * W + ((kl & 0xffffu) >> 6)], 1ull << (kl & 63));
+        }
+        return;
+    }
+    const u32 c = (u32)__popcll(hm);
+    if (q.n + c > (u32)HUB_QCAP) hub_flush(q, C3, Bg, W);
+    if (hit) {
+        const u32 pos = q.n + (u32)__popcll(hm & lanemask_lt());
+        q.qe[pos] = (u32)e;
+        q.qkl[pos] = kl;
+    }
+    q.n += c;
+}
+
+__global__ void __launch_bounds__(HT) k_tri1_hub(const i64* __restrict__ roff, const VRec* __restrict__ vrec,
+                                                 const i32* __restrict__ ridx, const i32* __restrict__ lo,
+                                                 const i64* __restrict__ G, const i32* __restrict__ list, u32 count,
+                                                 i32 hub_max, i32* __restrict__ C3, u64* __restrict__ bstore,
+                                                 const i64* __restrict__ boff, int store, int defer) {
+    constexpr int DM = TRI_HUB_MAX;
+    constexpr int NWV = HT / WAVE;
+    __shared__ i64 rbase[DM + 1];
+    __shared__ i32 rstart[DM + 1];
+    __shared__ i32 rk[DM + 1];
+    __shared__ BucketMap<10> pm;  // positions of N+(u): 1024 buckets of 4
+    __shared__ i32 flags[NWV][WAVE];
+    __shared__ i32 Cnt[DM];
+    __shared__ i32 wsum[NWV];
+    __shared__ i32 stot, sR;
+    __shared__ u32 sqe[NWV][HUB_QCAP];
+    __shared__ u32 sqkl[NWV][HUB_QCAP];
+    const int wv = threadIdx.x / WAVE;
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        if (D > hub_max) continue;  // the global-bitmap kernel takes it (uniform over the block)
+        const int W = (D + 63) >> 6;
+        const i64 gb = G[bu];
+        const i32 T = (i32)(G[bu + D] - gb);
+        u64* const Bg = store ? bstore + boff[u] : nullptr;
+        bmap_clear(pm, threadIdx.x, HT);
+        if (Bg)
+            for (int q = threadIdx.x; q < D * W; q += HT) Bg[q] = 0;
+        const int k = threadIdx.x;  // D <= DM == HT: one out-neighbour per thread
+        Cnt[k] = 0;
+        __threadfence();  // the cleared rows reach L2 before any wavefront's atomics
+        __syncthreads();
+        i32 len = 0, pre = 0;
+        i64 bv = 0;
+        if (k < D) {
+            const i32 v = ridx[bu + k];
+            bmap_insert(pm, v, k);
+            pre = (i32)(G[bu + k] - gb);
+            len = (i32)(G[bu + k + 1] - G[bu + k]);
+            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
+        }
+        const i32 cidx = block_scan<HT>(len > 0 ? 1 : 0, wsum, &stot);
+        if (k < D && len > 0) {
+            rbase[cidx] = bv - pre;
+            rstart[cidx] = pre;
+            rk[cidx] = k;
+        }
+        if (threadIdx.x == 0) {
+            sR = stot;
+            rstart[stot] = T;
+        }
+        __syncthreads();
+        const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
+        HubQueue q{sqe[wv], sqkl[wv], 0};
+        run_walk_keyed<4>(std::min(T, wv * per), std::min(T, (wv + 1) * per), rbase, rstart, rk, sR, flags[wv], ridx,
+                          [&](bool act, i32, i32 kr, i32 y, i64 e, u64, i32) {
+                              const i32 l = act ? bmap_find(pm, y) : -1;
+                              const bool hit = l >= 0;
+                              if (hit) {
+                                  atomicAdd(&Cnt[kr], 1);
+                                  atomicAdd(&Cnt[l], 1);
+                              }
+                              hub_push(hit, e, ((u32)kr << 16) | (u32)l, q, C3, Bg, W, defer);
+                          });
+        hub_flush(q, C3, Bg, W);
+        __syncthreads();
+        if (k < D) {
+            const i32 c = Cnt[k];
+            if (c) atomicAdd(&C3[bu + k], c);
+        }
+        __threadfence();
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ clique / diamond pass
 
 // C3(v, y) - 1 for y in N+(v): y is searched in N+(v) = ridx[from, end),
@@ -479,19 +608,99 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
     }
 }
 
+// Hub tier of the clique pass (D <= hub_max <= TRI_HUB_MAX): as the LDS tier,
+// with A = B | B^T (up to 1024 x 16 words) in LDS and B itself read from the
+// workspace rows the hub triangle pass wrote (each word once, when its edges
+// are taken, and once for the transpose).
+__global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, const i32* __restrict__ lo,
+                                                  const i64* __restrict__ mir, const i32* __restrict__ list,
+                                                  u32 count, i32 hub_max, const i32* __restrict__ C3,
+                                                  i64* __restrict__ k4v, i64* __restrict__ ek,
+                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff) {
+    constexpr int DM = TRI_HUB_MAX;
+    constexpr int WM = DM / 64;
+    __shared__ u64 A[DM * WM];
+    __shared__ i32 c3u[DM];
+    __shared__ u32 t2[DM];   // twice the triangles of H through k: below 2 * 1023 * 1022
+    __shared__ u32 dvs[DM];  // diamonds of v_k: below 1023 * 2^21
+    __shared__ i64 red[1];
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const int D = (int)(roff[u + 1] - bu);
+        if (D > hub_max) continue;  // uniform over the block
+        const int W = (D + 63) >> 6;
+        const u64* const B = bstore + boff[u];
+        if (threadIdx.x < D) {
+            c3u[threadIdx.x] = C3[bu + threadIdx.x];
+            t2[threadIdx.x] = 0;
+            dvs[threadIdx.x] = 0;
+        }
+        if (threadIdx.x == 0) red[0] = 0;
+        // A = B | B^T, 64 x 64 blocks: wavefront wv takes the blocks (bi, bj)
+        // with bi * W + bj = wv (mod HT / 64); lane = row in the block
+        for (int blk = threadIdx.x / WAVE; blk < W * W; blk += HT / WAVE) {
+            const int bi = blk / W, bj = blk % W;
+            const int row = bi * 64 + lane_id();
+            const u64 m = row < D ? B[(i64)row * W + bj] : 0ull;
+            const u64 t = wave_transpose64(m);  // column bj * 64 + lane of the block
+            const int col = bj * 64 + lane_id();
+            if (col < D) A[col * W + bi] = t | B[(i64)col * W + bi];
+        }
+        __syncthreads();
+        i64 R = 0;
+        for (int i = threadIdx.x; i < D * W; i += HT) {
+            const int k = i / W, wa = i - k * W;
+            u64 bits = B[i];
+            if (!bits) continue;
+            u64 Ak[WM];
+#pragma unroll
+            for (int z = 0; z < WM; ++z) Ak[z] = z < W ? A[k * W + z] : 0ull;
+            const u32 ck = (u32)(c3u[k] - 1);
+            u32 tk = 0, dk = 0;
+            FOR_BITS(bits, bb, {
+                const int l = wa * 64 + bb;
+                const u64* Al = A + l * W;
+                u32 c = 0;
+                for (int z = 0; z < W; ++z) c += (u32)__popcll(Ak[z] & Al[z]);
+                tk += c;
+                dk += (u32)(c3u[l] - 1);
+                if (c) atomicAdd(&t2[l], c);
+                if (ck) atomicAdd(&dvs[l], ck);
+                R += c;
+            });
+            if (tk) atomicAdd(&t2[k], tk);
+            if (dk) atomicAdd(&dvs[k], dk);
+        }
+        R = wave_sum(R);
+        if (lane_id() == 0 && R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < D) {
+            const i64 kv = t2[k] >> 1, dv = dvs[k];
+            if (kv | dv) ek[mir[bu + k]] = (dv << EK_SHIFT) | kv;
+        }
+        if (threadIdx.x == 0 && red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)(red[0] / 3));
+        __syncthreads();
+    }
+}
+
 // Diamond term of u for the LDS tier: over the triangles (u, v_k, v_l), the
 // number of other triangles on the opposite edge, C3(v_k, v_l) - 1.  The
 // out-lists N+(v_k) are walked again as in the triangle pass; a hit y = v_l
 // sits at the walked entry e, whose C3 is final now.
-__global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
+// NT threads take one vertex with D <= DM (NT == DM); MB: the position map's
+// bucket bits.  The hub instance skips the vertices above hub_max.
+template <int NT, int MB>
+__global__ void __launch_bounds__(NT) k_tri2_du_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                     const i32* __restrict__ lo, const i64* __restrict__ G,
-                                                    const i32* __restrict__ list, u32 count,
+                                                    const i32* __restrict__ list, u32 count, i32 hub_max,
                                                     const i32* __restrict__ C3, i64* __restrict__ d13) {
-    constexpr int DM = TRI_LDS_MAX;
-    constexpr int NWV = LT / WAVE;
+    constexpr int DM = NT;
+    constexpr int NWV = NT / WAVE;
     __shared__ i64 rbase[DM + 1];
     __shared__ i32 rstart[DM + 1];
-    __shared__ BucketMap<9> pm;
+    __shared__ BucketMap<MB> pm;
     __shared__ i32 flags[NWV][WAVE];
     __shared__ i32 wsum[NWV];
     __shared__ i32 stot, sR;
@@ -501,9 +710,10 @@ __global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff
         const i64 u = list[it];
         const i64 bu = roff[u] + lo[u];
         const int D = (int)(roff[u + 1] - bu);
+        if (D > hub_max) continue;  // uniform over the block
         const i64 gb = G[bu];
         const i32 T = (i32)(G[bu + D] - gb);
-        bmap_clear(pm, threadIdx.x, LT);
+        bmap_clear(pm, threadIdx.x, NT);
         __syncthreads();
         const int k = threadIdx.x;
         i32 len = 0, pre = 0;
@@ -515,7 +725,7 @@ __global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff
             len = (i32)(G[bu + k + 1] - G[bu + k]);
             { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
         }
-        const i32 cidx = block_scan<LT>(len > 0 ? 1 : 0, wsum, &stot);
+        const i32 cidx = block_scan<NT>(len > 0 ? 1 : 0, wsum, &stot);
         if (k < D && len > 0) {
             rbase[cidx] = bv - pre;
             rstart[cidx] = pre;
@@ -531,7 +741,7 @@ __global__ void __launch_bounds__(LT) k_tri2_du_lds(const i64* __restrict__ roff
                     [&](bool act, i32, i32, i32 y, i64 e, u64, i32) {
                         if (act && bmap_find(pm, y) >= 0) du += (i64)C3[e] - 1;
                     });
-        du = block_sum<LT>(du, part);
+        du = block_sum<NT>(du, part);
         if (threadIdx.x == 0 && du) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)du);
     }
 }
@@ -558,8 +768,9 @@ hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s) {
     return scan_exclusive_i64(w.bcnt, w.boff, n, w.partials, s);
 }
 
-hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier) {
-    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
+hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier,
+                              i64 hub_max) {
+    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
     if (tier == 0 && c0) {
         if (n <= ((i64)1 << 28))  // position-map keys (v, slot) fit 31 bits
@@ -572,19 +783,28 @@ hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hi
     if (tier == 1 && c1)
         hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
                            w.tri_list + n, c1, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+    if (tier == 2 && c2 && hub_max > 0)  // the hub tier's vertices of the last tier list
+        hipLaunchKernelGGL(k_tri1_hub, dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
+                           w.tri_list + 2 * n, c2, (i32)hub_max, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
     return hipGetLastError();
 }
 
-hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier) {
-    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1];
+hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier, i64 hub_max) {
+    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
     if (tier == 0 && c0)
         hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE * T2_TASK)), dim3(WT), 0, s, w.vrec, w.ridx,
                            w.mir, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
     if (tier == 1 && c1) {
         hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.mir,
                            w.tri_list + n, c1, w.C3, w.k4v, w.ek, w.bstore, w.boff);
-        hipLaunchKernelGGL(k_tri2_du_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
-                           w.tri_list + n, c1, w.C3, w.d13);
+        hipLaunchKernelGGL((k_tri2_du_lds<LT, 9>), dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo,
+                           w.G, w.tri_list + n, c1, (i32)TRI_LDS_MAX, w.C3, w.d13);
+    }
+    if (tier == 2 && c2 && hub_max > 0) {
+        hipLaunchKernelGGL(k_tri2s_hub, dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.lo, w.mir, w.tri_list + 2 * n,
+                           c2, (i32)hub_max, w.C3, w.k4v, w.ek, w.bstore, w.boff);
+        hipLaunchKernelGGL((k_tri2_du_lds<HT, 10>), dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.vrec, w.ridx, w.lo,
+                           w.G, w.tri_list + 2 * n, c2, (i32)hub_max, w.C3, w.d13);
     }
     return hipGetLastError();
 }

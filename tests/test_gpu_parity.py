@@ -20,13 +20,17 @@ C = math.comb
 
 # Tier plans: default; everything in the wave tiers where allowed; everything
 # in the LDS/workgroup tiers; the 4-cycle pass in the packed-hash tier where
-# it fits; everything in the global-memory / window tiers.
+# it fits; the triangle and clique passes in the hub tier (position map in
+# LDS, bitmap rows in the workspace) and the 4-cycle pass in the window tier;
+# the same with the hub tier off (bitmaps in the workspace).
 PLANS = {
     "default": None,
     "wave": {"tri_wave_max": 64, "tri_lds_max": 64, "c4_wave_max": 128, "c4_block_max": 128, "c4_hash_max": 128},
     "block": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": 2048, "c4_hash_max": -1},
     "hash": {"tri_wave_max": 1, "tri_lds_max": 512, "c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": 16384},
     "global": {"tri_wave_max": 1, "tri_lds_max": 1, "c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": -1},
+    "nohub": {"tri_wave_max": 1, "tri_lds_max": 1, "tri_hub_max": -1, "c4_wave_max": -1, "c4_block_max": -1,
+              "c4_hash_max": -1},
 }
 
 
@@ -119,10 +123,11 @@ def test_small_random_all_tiers(fg, plan):
 
 # ------------------------------------------------------------------ closed forms
 
-@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600, 1100])
 def test_clique(fg, n):
-    """K_n: out-degree n-1 of the lowest vertex (600 reaches the global-bitmap
-    tier, and the top vertex's (n-1)(n-2) wedges the heavy 4-cycle tier)."""
+    """K_n: out-degree n-1 of the lowest vertex (600 reaches the hub tier,
+    1100 the global-bitmap tier beyond it, and the top vertex's (n-1)(n-2)
+    wedges the heavy 4-cycle tier)."""
     g = graphgen.clique(n)
     say(f"clique n={n}")
     off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
@@ -502,3 +507,21 @@ def test_subdict_medium_and_skipped_passes(fg):
     out = fg.raw(o, i, net=True, sigma=[0, 1, 12], plan={"c4_wave_max": -1, "c4_block_max": -1, "c4_hash_max": -1})
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), oracle.subdict(raw, [0, 1, 12]))
+
+
+def test_k2b_32bit_window_counters(fg):
+    """K_{2,b} with b = 70000: the top hub has b middles and one wedge end
+    (the other hub) reached b times, a count beyond 16 bits, so its window job
+    takes the 32-bit counters; checked against the closed form (pinned by
+    brute force and the oracle on small b)."""
+    from tests.test_oracle_pins import k2b_net
+    b = 70000
+    edges = [(h, 2 + j) for h in (0, 1) for j in range(b)]
+    off, idx = csr_arrays(b + 2, edges)
+    say(f"K_2,{b}")
+    o, i = to_dev(off, idx)
+    out, st = fg.raw(o, i, net=True, stats=True)
+    torch.cuda.synchronize()
+    say(f"c4 tiers {st['c4_tier_vertices']}")
+    assert st["c4_tier_vertices"][3] >= 1
+    np.testing.assert_array_equal(out.cpu().numpy(), k2b_net(b))

@@ -473,3 +473,25 @@ def test_subdict_open_set_differs_from_full_columns():
     off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
     f = oracle.subdict(oracle.raw(off, idx), [0, 1, 2, 3])
     np.testing.assert_array_equal(f, np.tile([1, 4, 12, 6], (5, 1)))
+
+
+def k2b_net(b):
+    """Net frequencies of K_{2,b} (hubs 0, 1; leaves 2 .. b+1): a hub ends b
+    2-paths through a leaf to the other hub, centres C(b,2) 2-paths and C(b,3)
+    claws over its leaves, and lies on C(b,2) 4-cycles; a leaf centres the
+    hub-leaf-hub path, ends 2(b-1) paths, is a claw leaf 2 C(b-1,2) times and
+    lies on b-1 4-cycles.  No triangle, paw, diamond or 4-path is induced."""
+    hub = np.zeros(16, dtype=np.int64)
+    hub[[0, 1, 2, 3, 8, 12]] = [1, b, b, C(b, 2), C(b, 3), C(b, 2)]
+    leaf = np.zeros(16, dtype=np.int64)
+    leaf[[0, 1, 2, 3, 7, 12]] = [1, 2, 2 * (b - 1), 1, 2 * C(b - 1, 2), b - 1]
+    return np.vstack([hub, hub] + [leaf] * b)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 6])
+def test_k2b_closed_form(b):
+    edges = [(h, 2 + j) for h in (0, 1) for j in range(b)]
+    _, net = bruteforce.frequencies(b + 2, edges)
+    np.testing.assert_array_equal(net, k2b_net(b))
+    off, idx = csr_of(b + 2, edges)
+    np.testing.assert_array_equal(oracle.net(off, idx), k2b_net(b))
