@@ -237,11 +237,17 @@ int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream);
 int fglt_totals(int64_t num_graphs, const int64_t* vtx_offsets, int64_t n_total, const int64_t* net,
                 int64_t* totals, void* stream);
 
-/* Execution plan of fglt_batch (host struct); NULL selects the defaults. */
+/* Execution plan of fglt_batch (host struct); NULL or 0 fields select the
+ * defaults.  Any plan gives the same result; only the speed changes.
+ * fglt_batch_tune picks one for a given batch. */
 typedef struct {
     int32_t threads;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (default 256) */
-    int32_t small_n;        /* graphs with n <= small_n are packed several per workgroup (0 = off) */
-    int32_t lpt_order;      /* 1: largest graphs first through a device work queue (default 1) */
+    int32_t hub_degree;     /* vertices of at least this degree are taken by a whole wavefront in
+                               the last pass, the others by one thread each (default 24;
+                               -1: none) */
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit (256 of them) that take the
+                               graphs, largest first, from a device work queue (default 4, at
+                               most 64; never more workgroups than graphs) */
     int32_t use_graph;      /* 1: replay a captured hipGraph for this stream and shape (default 0) */
 } fglt_batch_plan;
 
@@ -269,6 +275,22 @@ size_t fglt_batch_workspace(int32_t num_graphs, int64_t n_total, int64_t nnz_tot
 int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const int64_t* vtx_offsets_host,
                int64_t n_total, int64_t nnz_total, const int64_t* offsets, const int32_t* indices,
                int64_t* net, const fglt_batch_plan* plan, void* ws, size_t ws_bytes, void* stream);
+/*
+ * Autotuner of fglt_batch: times candidate plans on the caller's batch (the
+ * same arguments as fglt_batch) and writes the fastest to *plan_out
+ * (use_graph 0).  The candidates are threads 128, 256, 512 x hub_degree 16,
+ * 32, 64, none x blocks_per_cu 2, 4, 8; each runs once untimed, then `reps`
+ * times (1..100) between HIP events on `stream`, and the median decides.  The
+ * choice is cached inside the library by (G, n_total, nnz_total, the
+ * histogram of graph sizes in 16 bins of 32 vertices): a later call with the
+ * same key returns it at once without timing.  Writes `net` as fglt_batch
+ * does.  Synchronizes with `stream`.  FGLT_EINVAL for bad arguments, else
+ * fglt_batch's status.
+ */
+int fglt_batch_tune(int32_t num_graphs, const int64_t* vtx_offsets, const int64_t* vtx_offsets_host,
+                    int64_t n_total, int64_t nnz_total, const int64_t* offsets, const int32_t* indices,
+                    int64_t* net, void* ws, size_t ws_bytes, int32_t reps, fglt_batch_plan* plan_out,
+                    void* stream);
 /* Reads the status word of the last fglt_batch on this workspace (synchronizes
  * with `stream`): FGLT_OK or FGLT_ENOTCANON. */
 int fglt_batch_status(const void* ws, void* stream);

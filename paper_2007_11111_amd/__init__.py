@@ -19,7 +19,7 @@ from ._lib import FGLT_NET, FGLT_SIGMA, FGLT_TIMING, FGLT_WORKMODEL, NORBITS, SE
 
 __all__ = [
     "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "sigma_mask", "FgltError", "Stats",
-    "BatchPlan", "check_host_csr", "batch_pack", "batch", "batch_release", "batch_status", "totals", "NORBITS",
+    "BatchPlan", "check_host_csr", "batch_pack", "batch", "batch_tune", "batch_release", "batch_status", "totals", "NORBITS",
 ]
 
 
@@ -233,12 +233,37 @@ def batch(vtx_offsets: torch.Tensor, offsets: torch.Tensor, indices: torch.Tenso
         workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     bp = None
     if plan is not None:
-        bp = BatchPlan(int(plan.get("threads", 256)), int(plan.get("small_n", 0)),
-                       int(plan.get("lpt_order", 1)), int(plan.get("use_graph", 0)))
+        bp = BatchPlan(int(plan.get("threads", 0)), int(plan.get("hub_degree", 0)),
+                       int(plan.get("blocks_per_cu", 0)), int(plan.get("use_graph", 0)))
     check(L.fglt_batch(G, _ptr(vtx_dev), ctypes.c_void_p(vtx_host.data_ptr()), n_total, nnz, _ptr(offsets),
                        _ptr(indices if nnz else None), _ptr(out), ctypes.byref(bp) if bp is not None else None,
                        _ptr(workspace), int(workspace.numel()), _stream(stream)), "fglt_batch")
     return out
+
+
+def batch_tune(vtx_offsets: torch.Tensor, offsets: torch.Tensor, indices: torch.Tensor, *, reps: int = 3,
+               out: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None) -> dict:
+    """Execution plan of ``fglt_batch`` for this batch -- ``fglt_batch_tune``
+    (times the candidate plans, or returns the plan cached for the same batch
+    shape and size histogram).  Returns the plan as a dict for ``batch``."""
+    L = lib()
+    vtx_host = vtx_offsets.to("cpu", torch.int64).contiguous()
+    dev = offsets.device
+    vtx_dev = vtx_host.to(dev)
+    G = int(vtx_host.numel()) - 1
+    n_total = int(vtx_host[-1])
+    nnz = int(indices.numel())
+    if out is None:
+        out = torch.empty((n_total, NORBITS), dtype=torch.int64, device=dev)
+    ws_bytes = int(L.fglt_batch_workspace(G, n_total, nnz))
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    bp = BatchPlan()
+    check(L.fglt_batch_tune(G, _ptr(vtx_dev), ctypes.c_void_p(vtx_host.data_ptr()), n_total, nnz, _ptr(offsets),
+                            _ptr(indices if nnz else None), _ptr(out), _ptr(workspace), int(workspace.numel()),
+                            int(reps), ctypes.byref(bp), _stream(stream)), "fglt_batch_tune")
+    return {"threads": bp.threads, "hub_degree": bp.hub_degree, "blocks_per_cu": bp.blocks_per_cu,
+            "use_graph": bp.use_graph}
 
 
 def batch_release(stream=None):

@@ -76,8 +76,8 @@ class RawPlan(ctypes.Structure):
 
 
 class BatchPlan(ctypes.Structure):
-    _fields_ = [("threads", ctypes.c_int32), ("small_n", ctypes.c_int32),
-                ("lpt_order", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+    _fields_ = [("threads", ctypes.c_int32), ("hub_degree", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -114,6 +114,9 @@ def lib():
                 L.fglt_batch_workspace.restype = sz
                 L.fglt_batch.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp, ctypes.POINTER(BatchPlan), vp, sz, vp]
                 L.fglt_batch.restype = ctypes.c_int
+                L.fglt_batch_tune.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp, vp, sz, i32,
+                                              ctypes.POINTER(BatchPlan), vp]
+                L.fglt_batch_tune.restype = ctypes.c_int
                 L.fglt_batch_status.argtypes = [vp, vp]
                 L.fglt_batch_status.restype = ctypes.c_int
                 L.fglt_batch_release.argtypes = [vp]

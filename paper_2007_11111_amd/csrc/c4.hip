@@ -500,7 +500,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const u16* __restrict__ etab, const i64* __restrict__ ebase,
                                                           const i32* __restrict__ hs, u32 nh,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
-                                                          u32* __restrict__ scr, i64 scr_cap, i64* __restrict__ c4v) {
+                                                          u32* __restrict__ scr, i64 scr_cap, i32 wlo,
+                                                          i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
     constexpr bool TAB = TABM > 0, ETAB = TABM == 2;
     using TabT = std::conditional_t<PACK16, u16, i32>;  // the vertex table's entries
@@ -554,8 +555,10 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 nwin = (i32)(((i64)u + WS - 1) / WS);
         const bool single = L <= CB_THREADS;
         const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
+        // windows below wlo hold only ranks of degree <= 1: every count there
+        // is at most 1 and adds nothing, so they are not visited
         const i32 wtop = single ? nwin - 1 : nwin - 1 - (i32)(j - jobpre[h]);
-        const i32 wbot = single ? 0 : wtop;
+        const i32 wbot = single ? wlo : wtop;
         const i64 eb = ETAB ? ebase[nh - 1 - h] : 0;  // this vertex's block of etab: [window][middle]
         // one chunk: thread k keeps middle k and the end of its not yet
         // visited run (windows go top-down, so each run ends where the
@@ -880,12 +883,15 @@ __global__ void k_set_pair(i64* p, i64 a, i64 b) {
     p[1] = b;
 }
 
-// Jobs per window-tier vertex, in descending vertex order.
-__global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS,
+// Jobs per window-tier vertex, in descending vertex order: one over windows
+// wlo .. ceil(u / WS) - 1 for a vertex whose middles fit one chunk, else one
+// per window (none when no window is left).
+__global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS, i64 wlo,
                           i64* __restrict__ jobcnt) {
     for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (i64)gridDim.x * blockDim.x) {
         const i64 u = hs[nh - 1 - h];
-        jobcnt[h] = lo[u] <= CB_THREADS ? 1 : (u + WS - 1) / WS;
+        const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
+        jobcnt[h] = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : nw;
     }
 }
 
@@ -900,6 +906,7 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 // middles' rows.
 struct C4WinCfg {
     u32 nl, nh;          // vertices with 16-bit and with 32-bit counters
+    i32 wlo16, wlo32;    // first window with a rank of degree >= 2, per window size
     bool use_tab, use_etab;
     i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
 };
@@ -911,6 +918,8 @@ static C4WinCfg c4_win_cfg(i64 n, const RawWs& w, const DevPlan& hp, int rows_mo
     C4WinCfg c;
     c.nh = std::min(hp.n_c4_heavy, hp.n_c4[3]);
     c.nl = hp.n_c4[3] - c.nh;
+    c.wlo16 = (i32)(hp.n_low / C4W_WS16);
+    c.wlo32 = (i32)(hp.n_low / C4W_WS32);
     c.K1 = (n + C4W_WS16 - 1) / C4W_WS16 + 1;
     // the table's row stride: 32 bytes' worth of entries
     c.TS = (c.K1 + 15) & ~(i64)15;
@@ -959,7 +968,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
             hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
                                n, c.K1, c.TS, C4W_WS16, w.c4_tab);
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nl, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c.nl, C4W_WS16,
-                           w.c4_jobcnt);
+                           (i64)c.wlo16, w.c4_jobcnt);
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.nl, w.partials, s)) != hipSuccess) return e;
         if (c.use_etab) {
             // c4_jobcnt is free again once the job prefix is built: the chunk counts
@@ -971,7 +980,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows
     }
     if (c.nh) {
         hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nh, PT, 4096)), dim3(PT), 0, s, hs + c.nl, w.lo, c.nh,
-                           C4W_WS32, w.c4_hjobcnt);
+                           C4W_WS32, (i64)c.wlo32, w.c4_hjobcnt);
         if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.nh, w.partials, s)) != hipSuccess) return e;
     }
     return hipGetLastError();
@@ -1002,15 +1011,15 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_
     const u16* const etab = reinterpret_cast<const u16*>(w.bstore);
     const i32* const tab = reinterpret_cast<const i32*>(w.c4_tab);
     const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
-#define C4W_LAUNCH(P16, TM, HS, NH, PRE, CTR)                                                                     \
+#define C4W_LAUNCH(P16, TM, HS, NH, PRE, CTR, WLO)                                                                \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.mir, tab, c.TS, etab, w.c4_ebase, HS, NH, PRE, CTR, w.c4_scr, w.c4_scr_cap, w.c4v)
+                       w.mir, tab, c.TS, etab, w.c4_ebase, HS, NH, PRE, CTR, w.c4_scr, w.c4_scr_cap, WLO, w.c4v)
     if (c.nl) {
-        if (c.use_etab) C4W_LAUNCH(true, 2, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
-        else if (c.use_tab) C4W_LAUNCH(true, 1, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
-        else C4W_LAUNCH(true, 0, hs, c.nl, w.c4_jobpre, w.c4_jobctr);
+        if (c.use_etab) C4W_LAUNCH(true, 2, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
+        else if (c.use_tab) C4W_LAUNCH(true, 1, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
+        else C4W_LAUNCH(true, 0, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
     }
-    if (c.nh) C4W_LAUNCH(false, 0, hs + c.nl, c.nh, w.c4_hjobpre, w.c4_jobctr + 2);
+    if (c.nh) C4W_LAUNCH(false, 0, hs + c.nl, c.nh, w.c4_hjobpre, w.c4_jobctr + 2, c.wlo32);
 #undef C4W_LAUNCH
     return hipGetLastError();
 }

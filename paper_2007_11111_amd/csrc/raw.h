@@ -47,6 +47,7 @@ struct DevPlan {
     i64 c4_etab;  // entries of the window tier's per-entry window table (16-bit part)
     u32 n_c4_heavy; // window-tier vertices of degree >= 65536 (32-bit counters; the last ranks)
     u32 pad1;
+    i64 n_low;      // vertices of degree <= 1 (the first ranks)
     i64 min_sum;  // byte model (FGLT_WORKMODEL): sum over edges of min(d_i, d_j)
     i64 k4_merge; // byte model: oriented 4-clique merge steps
 };

@@ -158,11 +158,12 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
 
 // ------------------------------------------------------------ structure
 
-// lo[u] = |N-(u)| (entries < u); self-loop check; sum of lo.
+// lo[u] = |N-(u)| (entries < u); self-loop check; sum of lo; the number of
+// vertices of degree <= 1.
 __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n,
                                            i32* __restrict__ lo, VRec* __restrict__ vrec, DevPlan* plan) {
     __shared__ i64 part[PT / WAVE];
-    i64 sum = 0;
+    i64 sum = 0, low = 0;
     u32 err = 0;
     for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
         const i64 b = roff[u], e = roff[u + 1];
@@ -171,9 +172,12 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
         lo[u] = (i32)(q - b);
         vrec[u] = VRec{b, (i32)(q - b), (i32)(e - b)};
         sum += q - b;
+        low += e - b <= 1;
     }
     sum = block_sum<PT>(sum, part);
     if (threadIdx.x == 0 && sum) atomicAdd((unsigned long long*)&plan->sum_lo, (unsigned long long)sum);
+    low = block_sum<PT>(low, part);
+    if (threadIdx.x == 0 && low) atomicAdd((unsigned long long*)&plan->n_low, (unsigned long long)low);
     if (err) atomicOr(&plan->err, err);
 }
 

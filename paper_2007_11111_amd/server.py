@@ -108,8 +108,8 @@ class GpuExecutor:
     """Runs requests on the GPU through the C ABI (one HIP stream per worker).
 
     The request's CSR is copied to the device and kept there with its result
-    until release; with copy_out=True the result is also copied to (pinned)
-    host memory and the time of that copy is recorded."""
+    until release; with copy_out=True the result is also copied to host
+    memory and the time of that copy is recorded."""
 
     def __init__(self, device=0, batch_plan=None, copy_out=False):
         import torch
@@ -138,9 +138,10 @@ class GpuExecutor:
         hosts = [None] * len(nets)
         t_host = 0.0
         if self.copy_out:
+            # into pageable memory: pinned buffers would stay pinned for as long
+            # as the client keeps the result
             with self.torch.cuda.stream(stream):
-                hosts = [x.to("cpu", non_blocking=True) if not isinstance(x, Exception) else None for x in nets]
-            stream.synchronize()
+                hosts = [x.to("cpu") if not isinstance(x, Exception) else None for x in nets]
             t_host = time.perf_counter()
             hosts = [h.numpy() if h is not None else None for h in hosts]
         bases = bases or [(0, 0)] * len(nets)

@@ -26,16 +26,51 @@ def _pack(fg, graphs):
     return vtx, off, idx, exp
 
 
-@pytest.mark.parametrize("threads", [64, 128, 256, 512, 1024])
-def test_batch_mixed(fg, threads):
+def _mixed():
     graphs = graphgen.batch_graphs(96, seed=21)
     graphs += [graphgen.clique(40), graphgen.star(300), graphgen.erdos_renyi(512, 0.3, seed=3),
-               graphgen.cycle(16), graphgen.path(2), graphgen.clique(1)]
-    vtx, off, idx, exp = _pack(fg, graphs)
-    say(f"batch mixed threads={threads} G={len(graphs)} n={int(vtx[-1])}")
-    out = fg.batch(vtx, off.cuda(), idx.cuda(), plan={"threads": threads})
+               graphgen.cycle(16), graphgen.path(2), graphgen.clique(1), graphgen.clique(64),
+               graphgen.clique(65)]
+    return graphs
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("hub,bpc", [(0, 0), (-1, 0), (1, 1), (8, 2), (64, 64)])
+def test_batch_mixed(fg, threads, hub, bpc):
+    """Every plan: thread-per-vertex only (hub -1), every vertex by a
+    wavefront (hub 1), mixed; the grid capped at 1, 2 or 64 workgroups per CU
+    (never more workgroups than graphs)."""
+    vtx, off, idx, exp = _pack(fg, _mixed())
+    say(f"batch mixed threads={threads} hub={hub} bpc={bpc} G={int(vtx.numel()) - 1} n={int(vtx[-1])}")
+    out = fg.batch(vtx, off.cuda(), idx.cuda(), plan={"threads": threads, "hub_degree": hub, "blocks_per_cu": bpc})
     torch.cuda.synchronize()
     np.testing.assert_array_equal(out.cpu().numpy(), exp)
+
+
+def test_batch_persistent_queue_and_tuner(fg):
+    """512 graphs through 256 persistent workgroups (two rounds of the queue
+    at least), and the autotuner: its plan gives the oracle's result, and a
+    second call on a batch of the same shape and size histogram returns the
+    cached plan."""
+    graphs = graphgen.batch_graphs(512, seed=23)
+    vtx, off, idx, exp = _pack(fg, graphs)
+    o, i = off.cuda(), idx.cuda()
+    say("batch 512 graphs, one workgroup per CU")
+    out = fg.batch(vtx, o, i, plan={"blocks_per_cu": 1})
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), exp)
+    say("batch tuner")
+    plan = fg.batch_tune(vtx, o, i, reps=2)
+    assert plan["threads"] in (128, 256, 512) and plan["blocks_per_cu"] in (2, 4, 8)
+    assert plan["hub_degree"] in (16, 32, 64, -1)
+    np.testing.assert_array_equal(fg.batch(vtx, o, i, plan=plan).cpu().numpy(), exp)
+    s = torch.cuda.Stream()  # graph capture needs a stream other than the legacy default one
+    with torch.cuda.stream(s):
+        got = fg.batch(vtx, o, i, plan=dict(plan, use_graph=1))
+        s.synchronize()
+    np.testing.assert_array_equal(got.cpu().numpy(), exp)
+    fg.batch_release(s)
+    assert fg.batch_tune(vtx, o, i, reps=2) == plan
 
 
 def test_batch_matches_single_graph_path(fg):
