@@ -70,13 +70,15 @@ typedef enum {
 #define FGLT_SIGMA(mask) ((unsigned)((mask) & 0xffffu) << 16)
 #define FGLT_SIGMA_MASK(flags) (((flags) >> 16) & 0xffffu)
 #define FGLT_SIGMA5 FGLT_SIGMA(0x001fu)  /* Theorem 1: orbits 0-4, [n][5] */
+#define FGLT_VALIDATE 16u    /* wait for the transform and return the device status word's
+                                verdict (FGLT_ENOTCANON, FGLT_EOVERFLOW) instead of FGLT_OK */
 #define FGLT_WORKMODEL 8u    /* also count the work terms of the byte model (statistics only,
                                 not part of the transform; needs `stats`): min_sum and
                                 k4_merge of fglt_stats                                    */
 
 /* Launch segments of fglt_raw, in execution order (indices into seg_ms). */
 enum {
-    FGLT_SEG_CHECK = 0,      /* input checks and the first synchronization      */
+    FGLT_SEG_CHECK = 0,      /* input checks                                     */
     FGLT_SEG_RELABEL,        /* degree ranking, relabelled and re-sorted rows    */
     FGLT_SEG_STRUCTURE,      /* N-/N+ split, mirror positions, work counts, tiers */
     FGLT_SEG_TRI1_WAVE,      /* triangle pass (C3), wavefront tier                */
@@ -175,20 +177,33 @@ typedef struct {
  *                self-loops, no repeated entry in a row (rows need not be sorted)
  *   out          out [n][16] int64, or [n][|s|] with a sub-dictionary FGLT_SIGMA(s)
  *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
- *   flags        FGLT_NET, FGLT_TIMING, FGLT_WORKMODEL and a sub-dictionary
- *                FGLT_SIGMA(s), or 0; a mask without orbits 0 and 1 is
- *                FGLT_EINVAL
+ *   flags        FGLT_NET, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL and a
+ *                sub-dictionary FGLT_SIGMA(s), or 0; a mask without orbits 0
+ *                and 1 is FGLT_EINVAL
  *   plan         (host) optional tier thresholds, NULL for the defaults
  *   stats        (host) optional, filled on success
- * Returns FGLT_ENOTCANON for a CSR that breaks the contract (checked on the
- * device), FGLT_EOVERFLOW for a degree >= 2^21.
- * Synchronizes with `stream` twice: after the input checks and after the
- * degree relabelling, to size the counting launches.
+ * The CSR is checked on the device (offsets, index range, self-loops,
+ * repeated entries, symmetry, degrees below 2^21); a failed check sets the
+ * workspace's status word and every later kernel that would index by the
+ * input leaves at once (the output is then undefined).
+ * Asynchronous: without FGLT_VALIDATE, FGLT_TIMING and `stats` it enqueues
+ * every launch on `stream` (tier sizes and choices are read on the device)
+ * and returns FGLT_OK without waiting, so it can be captured into a HIP graph;
+ * fglt_raw_status() reads the status word afterwards.  With FGLT_VALIDATE or
+ * `stats` it waits for the stream once, at the end, and returns
+ * FGLT_ENOTCANON for a CSR that breaks the contract, FGLT_EOVERFLOW for a
+ * degree >= 2^21.  FGLT_TIMING records events and is read at that wait.
+ * With a sub-dictionary beyond {0..11} the transform also uses a second
+ * stream of the calling thread, forked from and joined back into `stream`.
  */
 size_t fglt_raw_workspace(int64_t n, int64_t nnz);
 int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices,
              int64_t* out, void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan,
              fglt_stats* stats, void* stream);
+/* The status word of the last fglt_raw on this workspace (the same `ws`
+ * pointer): FGLT_OK, FGLT_ENOTCANON or FGLT_EOVERFLOW.  Synchronizes with
+ * `stream` (the stream that call used). */
+int fglt_raw_status(const void* ws, void* stream);
 
 /*
  * fglt_raw without a workspace argument, for callers that cannot allocate
@@ -200,12 +215,13 @@ int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indi
  * itself allocates nothing (no hipMalloc, no stream or event creation; it
  * runs every kernel on `stream`).
  *   n, nnz, offsets, indices, out, flags, plan, stats   as for fglt_raw;
- *                FGLT_TIMING is not offered (FGLT_EINVAL)
+ *                FGLT_TIMING is not offered (FGLT_EINVAL); FGLT_VALIDATE is
+ *                implied (the caller cannot reach the array's status word)
  * Returns FGLT_EWORKSPACE when fglt_raw_workspace(n, nnz) exceeds
  * FGLT_NOALLOC_SCRATCH_BYTES (about 1.6M directed entries fit).  Every call
  * on a device shares that device's array and overwrites it, so calls that
  * overlap on one device (different streams or threads) race: the caller
- * serializes them.  Synchronizes with `stream` as fglt_raw does.
+ * serializes them.  Waits for `stream` once, at the end (FGLT_VALIDATE).
  */
 #define FGLT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 int fglt_raw_noalloc(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices,
@@ -243,10 +259,10 @@ int fglt_totals(int64_t num_graphs, const int64_t* vtx_offsets, int64_t n_total,
 typedef struct {
     int32_t threads;        /* threads per workgroup: 64, 128, 256, 512 or 1024 (default 256) */
     int32_t hub_degree;     /* vertices of at least this degree are taken by a whole wavefront in
-                               the last pass, the others by one thread each (default 24;
-                               -1: none) */
+                               the last pass, the others by one thread each (default and -1:
+                               none) */
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit (256 of them) that take the
-                               graphs, largest first, from a device work queue (default 4, at
+                               graphs, largest first, from a device work queue (default 64, at
                                most 64; never more workgroups than graphs) */
     int32_t use_graph;      /* 1: replay a captured hipGraph for this stream and shape (default 0) */
 } fglt_batch_plan;
@@ -279,7 +295,7 @@ int fglt_batch(int32_t num_graphs, const int64_t* vtx_offsets, const int64_t* vt
  * Autotuner of fglt_batch: times candidate plans on the caller's batch (the
  * same arguments as fglt_batch) and writes the fastest to *plan_out
  * (use_graph 0).  The candidates are threads 128, 256, 512 x hub_degree 16,
- * 32, 64, none x blocks_per_cu 2, 4, 8; each runs once untimed, then `reps`
+ * 32, 64, none x blocks_per_cu 2, 4, 8, 64; each runs once untimed, then `reps`
  * times (1..100) between HIP events on `stream`, and the median decides.  The
  * choice is cached inside the library by (G, n_total, nnz_total, the
  * histogram of graph sizes in 16 bins of 32 vertices): a later call with the

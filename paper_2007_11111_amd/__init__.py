@@ -15,10 +15,10 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, FGLT_SIGMA, FGLT_TIMING, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_SIGMA, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
-    "build_csr", "raw", "net", "transform", "raw_workspace_bytes", "sigma_mask", "FgltError", "Stats",
+    "build_csr", "raw", "raw_status", "net", "transform", "raw_workspace_bytes", "sigma_mask", "FgltError", "Stats",
     "BatchPlan", "check_host_csr", "batch_pack", "batch", "batch_tune", "batch_release", "batch_status", "totals", "NORBITS",
 ]
 
@@ -85,13 +85,18 @@ def raw_workspace_bytes(n: int, nnz: int) -> int:
 
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
         workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
-        timing: bool = False, sigma=None, sigma5: bool = False, workmodel: bool = False, stream=None):
+        timing: bool = False, sigma=None, sigma5: bool = False, workmodel: bool = False, validate: bool = True,
+        stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
     (and a dict of plan statistics when stats=True).  ``sigma`` selects a
     sub-dictionary (Section V): a 16-bit mask or an iterable of orbit numbers
     that holds 0 and 1; the result is then [n, |s|], the orbits of s in
-    ascending order, net by U16(s, s).  sigma5=True is sigma=0x1F (Theorem 1).  ``plan`` may set the tier
+    ascending order, net by U16(s, s).  sigma5=True is sigma=0x1F (Theorem 1).
+    With validate=True (the default) the call waits for the stream and raises
+    FgltError for a CSR that breaks the contract; validate=False enqueues the
+    transform and returns at once (nothing waits: ``raw_status(workspace)``
+    reads the device status word later; capturable into a HIP graph).  ``plan`` may set the tier
     thresholds tri_wave_max, tri_lds_max, tri_hub_max, c4_wave_max, c4_block_max, c4_hash_max and the
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events); with
@@ -123,10 +128,17 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
                      int(plan.get("tri_hub_max", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
                      int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | FGLT_SIGMA(mask)
+                     | (FGLT_VALIDATE if validate else 0)
                      | (FGLT_WORKMODEL if workmodel else 0), ctypes.byref(rp) if rp is not None else None,
-                     ctypes.byref(st), _stream(stream)),
+                     ctypes.byref(st) if stats else None, _stream(stream)),
           "fglt_raw")
     return (out, st.as_dict()) if stats else out
+
+
+def raw_status(workspace: torch.Tensor, stream=None) -> int:
+    """Status word of the last ``fglt_raw`` on `workspace` -- ``fglt_raw_status``
+    (synchronizes with the stream): 0, FGLT_ENOTCANON (-2) or FGLT_EOVERFLOW (-4)."""
+    return int(lib().fglt_raw_status(_ptr(workspace), _stream(stream)))
 
 
 def net(raw_counts: torch.Tensor, out: torch.Tensor | None = None, stream=None):

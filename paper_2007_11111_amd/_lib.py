@@ -34,6 +34,7 @@ class FgltError(RuntimeError):
 
 FGLT_TIMING = 2
 FGLT_WORKMODEL = 8
+FGLT_VALIDATE = 16
 
 
 def FGLT_SIGMA(mask: int) -> int:
@@ -105,6 +106,8 @@ def lib():
             L.fglt_raw.argtypes = [i64, i64, vp, vp, vp, vp, sz, ctypes.c_uint, ctypes.POINTER(RawPlan),
                                    ctypes.POINTER(Stats), vp]
             L.fglt_raw.restype = ctypes.c_int
+            L.fglt_raw_status.argtypes = [vp, vp]
+            L.fglt_raw_status.restype = ctypes.c_int
             L.fglt_net.argtypes = [i64, vp, vp, vp]
             L.fglt_net.restype = ctypes.c_int
             L.fglt_totals.argtypes = [i64, vp, i64, vp, vp, vp]

@@ -64,40 +64,40 @@ static SubPasses sub_passes(unsigned s) {
     return p;
 }
 
-int read_plan(const RawWs& w, DevPlan& hp, hipStream_t s) {
-    if (hipMemcpyAsync(&hp, w.plan, sizeof(DevPlan), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return FGLT_EHIP;
-    return FGLT_OK;
-}
 
-// The last timing event, the triangle total and the statistics of fglt_raw.
-int finish(int64_t n, int64_t nnz, RawWs& w, const DevPlan& hp, SegTimer& tm, unsigned flags, fglt_stats* stats,
-           hipStream_t s) {
-    int st = FGLT_OK;
+// The last timing event; with statistics or FGLT_VALIDATE the one wait for
+// the stream: the device plan (status word, tier sizes, work totals) and, with
+// FGLT_TIMING, the segment times.  Without either, nothing is waited for and
+// the status stays on the device (fglt_raw_status).
+int finish(int64_t n, int64_t nnz, RawWs& w, SegTimer& tm, unsigned flags, fglt_stats* stats, hipStream_t s) {
     if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
-    i64 triangles = -1;
-    DevPlan fin{};
+    if (!stats && !(flags & FGLT_VALIDATE)) return FGLT_OK;
     if (stats) {
         FGLT_HIP_TRY(launch_count_triangles(n, w, s));
         if (flags & FGLT_WORKMODEL) FGLT_HIP_TRY(launch_work_model(nnz, w, s));
-        if ((st = read_plan(w, fin, s))) return st;
-        triangles = fin.triangles / 6;  // twice at each of its three vertices
     }
-
+    DevPlan fin{};
+    i64 g_total = 0;
+    if (hipMemcpyAsync(&fin, w.plan, sizeof(DevPlan), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
+    if (stats && hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return FGLT_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FGLT_EHIP;
+    const int st = status_from_err(fin.err);
+    if (st) return st;
     if (stats) {
-        stats->d_max = hp.d_max;
-        stats->dplus_max = hp.dplus_max;
-        stats->tri_items = hp.tri_items;
-        stats->wedge_items = hp.wedge_items;
+        stats->d_max = fin.d_max;
+        stats->dplus_max = fin.dplus_max;
+        stats->tri_items = g_total - fin.wedge_items;
+        stats->wedge_items = fin.wedge_items;
         for (int k = 0; k < 3; ++k) {
-            stats->tri_tier_vertices[k] = hp.n_tri[k];
-            stats->tri_items_tier[k] = hp.tri_items_tier[k];
+            stats->tri_tier_vertices[k] = fin.n_tri[k];
+            stats->tri_items_tier[k] = fin.tri_items_tier[k];
         }
         for (int k = 0; k < 4; ++k) {
-            stats->c4_tier_vertices[k] = hp.n_c4[k];
-            stats->wedge_items_tier[k] = hp.wedge_items_tier[k];
+            stats->c4_tier_vertices[k] = fin.n_c4[k];
+            stats->wedge_items_tier[k] = fin.wedge_items_tier[k];
         }
-        stats->triangles = triangles;
+        stats->triangles = fin.triangles / 6;  // twice at each of its three vertices
         stats->min_sum = fin.min_sum;
         stats->k4_merge = fin.k4_merge;
         if (tm.on) {
@@ -126,7 +126,7 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_WORKMODEL | FGLT_SIGMA(0xffffu))) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_WORKMODEL | FGLT_VALIDATE | FGLT_SIGMA(0xffffu))) return FGLT_EINVAL;
     // the sub-dictionary (Section V): every orbit by default; {0, 1} in any subset
     const unsigned smask = FGLT_SIGMA_MASK(flags) ? FGLT_SIGMA_MASK(flags) : 0xffffu;
     if ((smask & 3u) != 3u) return FGLT_EINVAL;
@@ -155,56 +155,42 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         tm.on = true;
     }
 
-    // 1. input checks (memory safety of everything below), degrees
+    // 1. input checks into the device status word; every later kernel that
+    // indexes by the input's values leaves at once if a check failed
     tm.mark(FGLT_SEG_CHECK, s);
     FGLT_HIP_TRY(launch_check_input(n, nnz, offsets, indices, w, s));
-    DevPlan hp{};
-    int st = read_plan(w, hp, s);
-    if (st) return st;
-    if ((st = status_from_err(hp.err))) return st;
 
-    // 2. degree ranking, relabelled CSR, work counts, tiers
+    // 2. degree ranking, relabelled CSR, work counts, tiers, and the decisions
+    // that depend on them, all on the device
     tm.mark(FGLT_SEG_RELABEL, s);
-    FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, hp.d_max, offsets, indices, w, s));
+    FGLT_HIP_TRY(launch_rank_and_relabel(n, nnz, offsets, indices, w, s));
     tm.mark(FGLT_SEG_STRUCTURE, s);
     const Tiers tiers = tiers_from_plan(plan, n);
-    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers, sp.c4, s));
-    i64 g_total = 0, bitmap_words = 0;
-    if (hipMemcpyAsync(&g_total, w.G + nnz, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess) return FGLT_EHIP;
-    if (hipMemcpyAsync(&bitmap_words, w.boff + n, sizeof(i64), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return FGLT_EHIP;
-    if ((st = read_plan(w, hp, s))) return st;
-    if ((st = status_from_err(hp.err))) return st;
-    if (2 * hp.sum_lo != nnz) return FGLT_ENOTCANON;  // every entry below the diagonal has its mirror
-    hp.tri_items = g_total - hp.wedge_items;
+    FGLT_HIP_TRY(launch_structure(n, nnz, w, tiers, sp.c4, sp.clique, tiers.c4_rows, s));
 
     // 3. counting
-    FGLT_HIP_TRY(hipMemsetAsync(w.acc, 0, sizeof(i64) * 10 * (size_t)n, s));
-    if (nnz > 0) FGLT_HIP_TRY(hipMemsetAsync(w.C3, 0, sizeof(i32) * (size_t)nnz, s));
+    FGLT_HIP_TRY(fill_u32(w.acc, 2 * 10 * n, 0u, s));
+    if (nnz > 0) FGLT_HIP_TRY(fill_u32(w.C3, nnz, 0u, s));
     const bool net = (flags & FGLT_NET) != 0;
     // the 4-cycle pass's hash tiers and window setup share no memory with the
     // triangle and clique passes: a second stream runs them alongside, and the
-    // window kernel (after the join) takes the whole GPU
+    // window kernels (after the join) take the whole GPU.  A sub-dictionary
+    // runs only the passes its orbits need.
     AuxStream* aux = nullptr;
     hipStream_t s4 = s;
-    if (!one_stream && (hp.n_c4[0] || hp.n_c4[1] || hp.n_c4[2] || hp.n_c4[3])) {
+    if (sp.c4 && !one_stream) {
         FGLT_HIP_TRY(aux_stream(aux));
         FGLT_HIP_TRY(hipEventRecord(aux->fork, s));
         FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
         s4 = aux->s;
     }
-    FGLT_HIP_TRY(launch_c4_early(n, nnz, w, hp, tiers.c4_rows, s4));
-    // the clique pass reuses the triangle pass's bitmaps when the workspace
-    // holds them.  A sub-dictionary runs only the passes its orbits need (no
-    // 4-cycle work lists were built without the 4-cycle orbit, so its tiers
-    // are empty and the second stream stays idle).
-    const bool stored = sp.clique && bitmap_words <= w.bstore_cap;
-    if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 1, stored, tiers.tri_hub, s, tm));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_early(n, nnz, w, tiers.c4_rows, s4));
+    if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, 1, tiers.tri_hub, s, tm));
     else
         for (int seg = FGLT_SEG_TRI1_WAVE; seg <= FGLT_SEG_TRI1_GLOBAL; ++seg) tm.mark(seg, s);
     tm.mark(FGLT_SEG_FILL, s);
-    FGLT_HIP_TRY(launch_fill_c3(nnz, w, stored, s));
-    if (sp.clique) FGLT_HIP_TRY(launch_tri(n, nnz, w, hp, 2, stored, tiers.tri_hub, s, tm));
+    FGLT_HIP_TRY(launch_fill_c3(nnz, w, s));
+    if (sp.clique) FGLT_HIP_TRY(launch_tri(n, nnz, w, 2, tiers.tri_hub, s, tm));
     else
         for (int seg = FGLT_SEG_TRI2_WAVE; seg <= FGLT_SEG_TRI2_GLOBAL; ++seg) tm.mark(seg, s);
     // the bitmaps are dead now: the window tier's per-entry table goes there,
@@ -213,22 +199,34 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         FGLT_HIP_TRY(hipEventRecord(aux->mid, s));
         FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->mid, 0));
     }
-    FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, hp, tiers.c4_rows, s4));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, tiers.c4_rows, s4));
     if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     tm.mark(FGLT_SEG_L2, s);
-    if (sp.l2) FGLT_HIP_TRY(launch_l2(n, nnz, w, stored, s));
+    if (sp.l2) FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
     if (aux) FGLT_HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
-    FGLT_HIP_TRY(launch_c4_late(n, nnz, w, hp, tiers.c4_rows, s, tm));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_late(n, nnz, w, tiers.c4_rows, s, tm));
+    else
+        for (int seg = FGLT_SEG_C4_WAVE; seg <= FGLT_SEG_C4_WINDOW; ++seg) tm.mark(seg, s);
     tm.mark(FGLT_SEG_FINALIZE, s);
     if (smask == 0xffffu) FGLT_HIP_TRY(launch_finalize(n, w, out, net, s));
     else FGLT_HIP_TRY(launch_finalize_sub(n, w, out, net, smask, s));
-    return finish(n, nnz, w, hp, tm, flags, stats, s);
+    return finish(n, nnz, w, tm, flags, stats, s);
 }
 
 extern "C" int fglt_raw(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indices, int64_t* out,
                         void* ws, size_t ws_bytes, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats,
                         void* stream) {
     return raw_run(n, nnz, offsets, indices, out, ws, ws_bytes, flags, plan, stats, stream, false);
+}
+
+extern "C" int fglt_raw_status(const void* ws, void* stream) {
+    if (!ws) return FGLT_EINVAL;
+    // the device plan is the workspace's first piece, at its first 256-byte boundary
+    const uintptr_t a = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
+    u32 err = 0;
+    FGLT_HIP_TRY(hipMemcpyAsync(&err, (const void*)a, sizeof(u32), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    FGLT_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return status_from_err(err);
 }
 
 extern "C" int fglt_net(int64_t n, const int64_t* raw, int64_t* net, void* stream) {

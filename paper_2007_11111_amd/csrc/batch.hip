@@ -374,8 +374,8 @@ struct BatchCfg {
 static constexpr int BATCH_CUS = 256;
 
 static BatchCfg batch_cfg(const fglt_batch_plan* plan, i64 G) {
-    BatchCfg c{256, 24, 0};
-    int bpc = 4;
+    BatchCfg c{256, BMAX + 1, 0};  // default: one thread per vertex, a workgroup per graph
+    int bpc = 64;
     if (plan) {
         if (plan->threads) c.threads = plan->threads;
         if (plan->hub_degree > 0) c.hub_deg = plan->hub_degree;
@@ -560,7 +560,7 @@ extern "C" int fglt_batch_tune(int32_t num_graphs, const int64_t* vtx_offsets, c
     FGLT_HIP_TRY(hipEventCreate(&e1));
     static const int kThreads[] = {128, 256, 512};
     static const int kHub[] = {16, 32, 64, -1};
-    static const int kBpc[] = {2, 4, 8};
+    static const int kBpc[] = {2, 4, 8, 64};
     fglt_batch_plan best{256, 0, 0, 0};
     float best_ms = -1.f;
     for (int th : kThreads)

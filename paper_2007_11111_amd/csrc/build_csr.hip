@@ -131,9 +131,9 @@ extern "C" int fglt_build_csr(int64_t n, int64_t num_edges, const int32_t* src, 
     if (!c.ok()) return FGLT_EWORKSPACE;
     const i64 E = num_edges;
     const i64 cap = 2 * E;
-    FGLT_HIP_TRY(hipMemsetAsync(w.cnt, 0, sizeof(i32) * (size_t)(n + 1), s));
-    FGLT_HIP_TRY(hipMemsetAsync(w.cursor, 0, sizeof(i32) * (size_t)(n + 1), s));
-    FGLT_HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(u32) * 4, s));
+    FGLT_HIP_TRY(fill_u32(w.cnt, n + 1, 0u, s));
+    FGLT_HIP_TRY(fill_u32(w.cursor, n + 1, 0u, s));
+    FGLT_HIP_TRY(fill_u32(w.err, 4, 0u, s));
     const unsigned ge = (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(E, 256), 65536));
     if (E > 0) hipLaunchKernelGGL(k_bc_count, dim3(ge), dim3(256), 0, s, src, dst, E, n, w.cnt, w.err);
     FGLT_LAUNCH_CHECK();

@@ -66,7 +66,8 @@ template <int WAVES_PER_U, int HSLOTS>
 __global__ void __launch_bounds__(PT) k_c4_hash(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                 const i32* __restrict__ lo, const i64* __restrict__ G,
                                                 const i64* __restrict__ mir,
-                                                const i32* __restrict__ list, u32 count, i64* __restrict__ c4v) {
+                                                const i32* __restrict__ list, const u32* __restrict__ countp, i64* __restrict__ c4v) {
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int NW = PT / WAVE;
     constexpr int GROUPS = NW / WAVES_PER_U;  // vertices per block
     constexpr int GT = WAVES_PER_U * WAVE;    // threads per vertex
@@ -325,8 +326,9 @@ __device__ __forceinline__ u32 c4h_get(const u32* tab, i32 w, int cb) {
 __global__ void __launch_bounds__(CB_THREADS) k_c4_hashbig(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                            const i32* __restrict__ lo, const i32* __restrict__ rpos,
                                                            const i64* __restrict__ mir,
-                                                           const i32* __restrict__ list, u32 count,
+                                                           const i32* __restrict__ list, const u32* __restrict__ countp,
                                                            u32* __restrict__ job_ctr, int cb, i64* __restrict__ c4v) {
+    const u32 count = *countp;  // the tier size, written on the device
     __shared__ u32 tab[C4H_SLOTS];
     __shared__ RunLds R;
     __shared__ i64 msum[CB_THREADS];
@@ -498,11 +500,22 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const i64* __restrict__ mir,
                                                           const i32* __restrict__ tab, i64 TS,
                                                           const u16* __restrict__ etab, const i64* __restrict__ ebase,
-                                                          const i32* __restrict__ hs, u32 nh,
+                                                          const i32* __restrict__ hs_all, const DevPlan* __restrict__ plan,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
-                                                          u32* __restrict__ scr, i64 scr_cap, i32 wlo,
+                                                          u32* __restrict__ scr, i64 scr_cap, int etab_mode,
                                                           i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
+    // the part of the window list this launch takes (16-bit counters: the
+    // first ranks, 32-bit: the last), and its first window, from the device plan
+    FGLT_GATE(&plan->err);
+    if (etab_mode == 2 && !plan->use_etab) return;
+    if (etab_mode == 1 && plan->use_etab) return;
+    const u32 c3 = plan->n_c4[3];
+    const u32 nheavy = plan->n_c4_heavy < c3 ? plan->n_c4_heavy : c3;
+    const u32 nh = PACK16 ? c3 - nheavy : nheavy;
+    const i32* const hs = PACK16 ? hs_all : hs_all + (c3 - nheavy);
+    const i32 wlo = (i32)(plan->n_low / WS);
+    if (nh == 0) return;
     constexpr bool TAB = TABM > 0, ETAB = TABM == 2;
     using TabT = std::conditional_t<PACK16, u16, i32>;  // the vertex table's entries
     const TabT* const tabt = reinterpret_cast<const TabT*>(tab);
@@ -800,12 +813,23 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     }
 }
 
+// The window list's part of one counter width (heavy: 32-bit counters, the
+// last nheavy entries of the ascending list), from the device plan.
+__device__ __forceinline__ void c4w_part(const DevPlan* plan, const i32* hs_all, bool heavy, const i32*& hs, u32& nh) {
+    const u32 c3 = plan->n_c4[3];
+    const u32 nheavy = plan->n_c4_heavy < c3 ? plan->n_c4_heavy : c3;
+    nh = heavy ? nheavy : c3 - nheavy;
+    hs = heavy ? hs_all + (c3 - nheavy) : hs_all;
+}
+
 // Window table: tab[v * TS + k] = number of neighbours of v with rank below
 // k * WS, for k < K1; rows of TS entries start on 32-byte boundaries.  T is
 // u16 where every degree is below 65536, else i32.
 template <class T>
 __global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 TS, i64 WS,
-                           T* __restrict__ tab) {
+                           T* __restrict__ tab, const DevPlan* __restrict__ plan) {
+    FGLT_GATE(&plan->err);
+    if (plan->n_c4[3] <= plan->n_c4_heavy) return;  // no window job with 16-bit counters
     const i64 total = n * K1;
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
         const i64 v = q / K1, k = q - v * K1;
@@ -821,12 +845,18 @@ __global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__
 // make ceil(L / ET_CHUNK) chunks of the build.
 static constexpr int ET_CHUNK = 256;
 
-__global__ void k_c4_ecount(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS,
-                            i64* __restrict__ ecnt, i64* __restrict__ ccnt) {
-    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < nh; i += (i64)gridDim.x * blockDim.x) {
-        const i64 u = hs[i];
-        ecnt[i] = (i64)lo[u] * ((u + WS - 1) / WS + 1);
-        ccnt[i] = ((i64)lo[u] + ET_CHUNK - 1) / ET_CHUNK;
+__global__ void k_c4_ecount(const i32* __restrict__ hs_all, const i32* __restrict__ lo,
+                            const DevPlan* __restrict__ plan, i64 WS, i64 bound, i64* __restrict__ ecnt,
+                            i64* __restrict__ ccnt) {
+    FGLT_GATE(&plan->err);
+    const i32* hs;
+    u32 nh;
+    c4w_part(plan, hs_all, false, hs, nh);
+    if (!plan->use_etab) nh = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < bound; i += (i64)gridDim.x * blockDim.x) {
+        const i64 u = i < (i64)nh ? hs[i] : 0;
+        ecnt[i] = i < (i64)nh ? (i64)lo[u] * ((u + WS - 1) / WS + 1) : 0;
+        ccnt[i] = i < (i64)nh ? ((i64)lo[u] + ET_CHUNK - 1) / ET_CHUNK : 0;
     }
 }
 
@@ -841,9 +871,14 @@ __global__ void k_c4_ecount(const i32* __restrict__ hs, const i32* __restrict__ 
 __global__ void __launch_bounds__(ET_CHUNK) k_c4_etab(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                       const i32* __restrict__ lo, const i32* __restrict__ rpos,
                                                       const u16* __restrict__ tab, i64 TS,
-                                                      const i32* __restrict__ hs, u32 nh,
+                                                      const i32* __restrict__ hs_all, const DevPlan* __restrict__ plan,
                                                       const i64* __restrict__ cpre, const i64* __restrict__ ebase,
                                                       i64 WS, u16* __restrict__ etab) {
+    FGLT_GATE(&plan->err);
+    if (!plan->use_etab) return;
+    const i32* hs;
+    u32 nh;
+    c4w_part(plan, hs_all, false, hs, nh);
     __shared__ i64 si;
     const i64 nchunks = cpre[nh];
     for (i64 c = blockIdx.x; c < nchunks; c += gridDim.x) {
@@ -878,20 +913,31 @@ __global__ void __launch_bounds__(ET_CHUNK) k_c4_etab(const i64* __restrict__ ro
     }
 }
 
-__global__ void k_set_pair(i64* p, i64 a, i64 b) {
-    p[0] = a;
-    p[1] = b;
+// The one segment of the window-tier list's sort: [0, its size).
+__global__ void k_c4_segment(i64* p, const DevPlan* __restrict__ plan) {
+    p[0] = 0;
+    p[1] = plan->err ? 0 : plan->n_c4[3];
 }
 
-// Jobs per window-tier vertex, in descending vertex order: one over windows
-// wlo .. ceil(u / WS) - 1 for a vertex whose middles fit one chunk, else one
-// per window (none when no window is left).
-__global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo, u32 nh, i64 WS, i64 wlo,
-                          i64* __restrict__ jobcnt) {
-    for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += (i64)gridDim.x * blockDim.x) {
-        const i64 u = hs[nh - 1 - h];
-        const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
-        jobcnt[h] = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : nw;
+// Jobs per window-tier vertex of one part, in descending vertex order: one
+// over windows wlo .. ceil(u / WS) - 1 for a vertex whose middles fit one
+// chunk, else one per window (none when no window is left); zero from the
+// part's size up to `bound`, so that the prefix over `bound` entries holds.
+__global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict__ lo, const DevPlan* __restrict__ plan,
+                          int heavy, i64 WS, i64 bound, i64* __restrict__ jobcnt) {
+    FGLT_GATE(&plan->err);
+    const i32* hs;
+    u32 nh;
+    c4w_part(plan, hs_all, heavy != 0, hs, nh);
+    const i64 wlo = plan->n_low / WS;
+    for (i64 h = (i64)blockIdx.x * blockDim.x + threadIdx.x; h < bound; h += (i64)gridDim.x * blockDim.x) {
+        i64 c = 0;
+        if (h < (i64)nh) {
+            const i64 u = hs[nh - 1 - h];
+            const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
+            c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : nw;
+        }
+        jobcnt[h] = c;
     }
 }
 
@@ -903,30 +949,29 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs, const i32* __restrict__ lo
 // ranks below its vertex and so has no larger degree -- counted with 16-bit
 // counters over 65536-rank windows, and the rest (the last ranks), counted
 // with 32-bit counters over 32768-rank windows and binary searches of the
-// middles' rows.
+// middles' rows.  The split, the first window (windows holding only ranks of
+// degree <= 1 are skipped) and whether the per-entry table fits are read on
+// the device from the plan; the host knows only the sizes.
 struct C4WinCfg {
-    u32 nl, nh;          // vertices with 16-bit and with 32-bit counters
-    i32 wlo16, wlo32;    // first window with a rank of degree >= 2, per window size
-    bool use_tab, use_etab;
+    bool use_tab, want_etab;
     i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
+    i64 bound_l, bound_h;  // entries of the job arrays of each part (at least its size)
 };
 
 static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
 static constexpr i64 C4W_WS32 = C4W_WORDS;      // ranks per window, 32-bit counters
 
-static C4WinCfg c4_win_cfg(i64 n, const RawWs& w, const DevPlan& hp, int rows_mode) {
+static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
     C4WinCfg c;
-    c.nh = std::min(hp.n_c4_heavy, hp.n_c4[3]);
-    c.nl = hp.n_c4[3] - c.nh;
-    c.wlo16 = (i32)(hp.n_low / C4W_WS16);
-    c.wlo32 = (i32)(hp.n_low / C4W_WS32);
     c.K1 = (n + C4W_WS16 - 1) / C4W_WS16 + 1;
     // the table's row stride: 32 bytes' worth of entries
     c.TS = (c.K1 + 15) & ~(i64)15;
     c.use_tab = rows_mode != 2 && w.c4_tab != nullptr && n * c.TS <= w.c4_tab_cap;
     // the per-entry window table lives in the stored bitmaps' memory (16-bit
-    // entries, four per word)
-    c.use_etab = rows_mode == 0 && c.use_tab && hp.c4_etab <= 4 * w.bstore_cap;
+    // entries, four per word); whether it fits is decided on the device
+    c.want_etab = rows_mode == 0 && c.use_tab;
+    c.bound_l = n;
+    c.bound_h = std::min<i64>(n, (nnz >> 16) + 1);  // vertices of degree >= 65536
     static_assert(C4W_WS16 == C4W_SPAN, "the tier assignment sizes the table with this window");
     return c;
 }
@@ -936,90 +981,80 @@ static C4WinCfg c4_win_cfg(i64 n, const RawWs& w, const DevPlan& hp, int rows_mo
 // per-entry table's offsets).  It reads only the structure and writes only
 // 4-cycle state (the sums, lists, tables, job arrays, and a sort buffer of its
 // own), so it may run on a second stream beside the triangle and clique
-// passes.
-hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s) {
-    (void)nnz;
-    const u32 c0 = hp.n_c4[0], c1 = hp.n_c4[1], c2 = hp.n_c4[2], c3 = hp.n_c4[3];
+// passes.  Tier sizes come from the device plan: the grids are bounds.
+hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s) {
     hipError_t e;
-    if (c2 || c3)
-        if ((e = hipMemsetAsync(w.c4_jobctr, 0, 3 * sizeof(u32), s)) != hipSuccess) return e;
-    if (c0) hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                               w.G, w.mir, w.c4_list, c0, w.c4v);
-    if (c1) hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               w.lo, w.G, w.mir, w.c4_list + n, c1, w.c4v);
-    if (c2) {
+    if ((e = fill_u32(w.c4_jobctr, 3, 0u, s)) != hipSuccess) return e;
+    const u32* const cnt = w.plan->n_c4;
+    hipLaunchKernelGGL((k_c4_hash<1, 256>), dim3(grid_for(n, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.G,
+                       w.mir, w.c4_list, cnt + 0, w.c4v);
+    hipLaunchKernelGGL((k_c4_hash<4, 4096>), dim3(grid_for(n, 1, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.G,
+                       w.mir, w.c4_list + n, cnt + 1, w.c4v);
+    {
         const int cb = 32 - std::max(1, bits_for_n(n));
-        hipLaunchKernelGGL(k_c4_hashbig, dim3(std::min<u32>(c2, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
-                           w.rpos, w.mir, w.c4_list + 2 * n, c2, w.c4_jobctr + 1, cb, w.c4v);
+        hipLaunchKernelGGL(k_c4_hashbig, dim3(grid_for(n, 1, 512)), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo,
+                           w.rpos, w.mir, w.c4_list + 2 * n, cnt + 2, w.c4_jobctr + 1, cb, w.c4v);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!c3) return hipSuccess;
-    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
     // window-tier vertices in ascending order (the sort's buffer: c4_ebase,
     // not yet in use; the shared one is the clique pass's memory); the
     // vertices of degree >= 65536 end the list
     i32* hs = w.c4_list + 3 * n;
-    hipLaunchKernelGGL(k_set_pair, dim3(1), dim3(1), 0, s, w.c4_segoff, (i64)0, (i64)c3);
+    hipLaunchKernelGGL(k_c4_segment, dim3(1), dim3(1), 0, s, w.c4_segoff, (const DevPlan*)w.plan);
     SegSortWs ws = w.sort;
     ws.tmp = reinterpret_cast<i32*>(w.c4_ebase);
     if ((e = seg_sort(hs, w.c4_segoff, 1, bits_for_n(n), ws, 1, s)) != hipSuccess) return e;
-    if (c.nl) {
-        if (c.use_tab)
-            hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx,
-                               n, c.K1, c.TS, C4W_WS16, w.c4_tab);
-        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nl, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c.nl, C4W_WS16,
-                           (i64)c.wlo16, w.c4_jobcnt);
-        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.nl, w.partials, s)) != hipSuccess) return e;
-        if (c.use_etab) {
-            // c4_jobcnt is free again once the job prefix is built: the chunk counts
-            hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c.nl, PT, 4096)), dim3(PT), 0, s, hs, w.lo, c.nl, C4W_WS16,
-                               w.c4_ebase, w.c4_jobcnt);
-            if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c.nl, w.partials, s)) != hipSuccess) return e;
-            if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.nl, w.partials, s)) != hipSuccess) return e;
-        }
+    if (c.use_tab)
+        hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n,
+                           c.K1, c.TS, C4W_WS16, w.c4_tab, (const DevPlan*)w.plan);
+    hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_l, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
+                       (const DevPlan*)w.plan, 0, C4W_WS16, c.bound_l, w.c4_jobcnt);
+    if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.bound_l, w.partials, s)) != hipSuccess) return e;
+    if (c.want_etab) {
+        // c4_jobcnt is free again once the job prefix is built: the chunk counts
+        hipLaunchKernelGGL(k_c4_ecount, dim3(grid_for(c.bound_l, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
+                           (const DevPlan*)w.plan, C4W_WS16, c.bound_l, w.c4_ebase, w.c4_jobcnt);
+        if ((e = scan_exclusive_i64(w.c4_ebase, w.c4_ebase, c.bound_l, w.partials, s)) != hipSuccess) return e;
+        if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.bound_l, w.partials, s)) != hipSuccess) return e;
     }
-    if (c.nh) {
-        hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.nh, PT, 4096)), dim3(PT), 0, s, hs + c.nl, w.lo, c.nh,
-                           C4W_WS32, (i64)c.wlo32, w.c4_hjobcnt);
-        if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.nh, w.partials, s)) != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_h, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
+                       (const DevPlan*)w.plan, 1, C4W_WS32, c.bound_h, w.c4_hjobcnt);
+    if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.bound_h, w.partials, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 // Part two: the per-entry window table, in the stored bitmaps' memory, so
 // after the clique pass (it may run on the second stream beside row pass 2).
-hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s) {
-    if (!hp.n_c4[3]) return hipSuccess;
-    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
-    if (c.nl && c.use_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s) {
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
+    if (c.want_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
         hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
-                           w.rpos, w.c4_tab, c.TS, w.c4_list + 3 * n, c.nl, w.c4_jobcnt, w.c4_ebase, C4W_WS16,
-                           reinterpret_cast<u16*>(w.bstore));
+                           w.rpos, w.c4_tab, c.TS, w.c4_list + 3 * n, (const DevPlan*)w.plan, w.c4_jobcnt, w.c4_ebase,
+                           C4W_WS16, reinterpret_cast<u16*>(w.bstore));
     return hipGetLastError();
 }
 
 // Part three: the window kernels, 16-bit counters then 32-bit counters.
-hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm) {
-    (void)nnz;
+hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s, SegTimer& tm) {
     tm.mark(FGLT_SEG_C4_WAVE, s);
     tm.mark(FGLT_SEG_C4_BLOCK, s);
     tm.mark(FGLT_SEG_C4_HASH, s);
     tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernels alone
-    if (!hp.n_c4[3]) return hipSuccess;
-    const C4WinCfg c = c4_win_cfg(n, w, hp, rows_mode);
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
     const i32* hs = w.c4_list + 3 * n;
     const u16* const etab = reinterpret_cast<const u16*>(w.bstore);
     const i32* const tab = reinterpret_cast<const i32*>(w.c4_tab);
+    const DevPlan* const plan = w.plan;
     const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
-#define C4W_LAUNCH(P16, TM, HS, NH, PRE, CTR, WLO)                                                                \
+#define C4W_LAUNCH(P16, TM, PRE, CTR, EM)                                                                          \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.mir, tab, c.TS, etab, w.c4_ebase, HS, NH, PRE, CTR, w.c4_scr, w.c4_scr_cap, WLO, w.c4v)
-    if (c.nl) {
-        if (c.use_etab) C4W_LAUNCH(true, 2, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
-        else if (c.use_tab) C4W_LAUNCH(true, 1, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
-        else C4W_LAUNCH(true, 0, hs, c.nl, w.c4_jobpre, w.c4_jobctr, c.wlo16);
-    }
-    if (c.nh) C4W_LAUNCH(false, 0, hs + c.nl, c.nh, w.c4_hjobpre, w.c4_jobctr + 2, c.wlo32);
+                       w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM, w.c4v)
+    // the per-entry table where it fits (decided on the device), else the vertex table
+    if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2);
+    if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0);
+    else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0);
+    C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
 #undef C4W_LAUNCH
     return hipGetLastError();
 }

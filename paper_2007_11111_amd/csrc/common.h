@@ -73,6 +73,21 @@ struct Carver {
     bool ok() const { return base != nullptr && used <= cap; }
 };
 
+// Kernels that follow the input checks of fglt_raw take the device error word
+// and leave at once when a check has failed, so that a malformed CSR never
+// drives an access (the host does not wait for the checks).  Uniform over the
+// workgroup; place it before any barrier.
+#define FGLT_GATE(errw)                    \
+    do {                                   \
+        if ((errw) && *(errw)) return;     \
+    } while (0)
+
+namespace fglt {
+// Fills `words` 32-bit words at p with v, with a kernel (a memset node would be
+// recorded into a captured HIP graph).  Defined in scan.hip.
+hipError_t fill_u32(void* p, i64 words, u32 v, hipStream_t s);
+}  // namespace fglt
+
 // ---------------------------------------------------------------- device helpers
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }

@@ -48,6 +48,7 @@ extern "C" int fglt_raw_noalloc(int64_t n, int64_t nnz, const int64_t* offsets, 
     void* ws = nullptr;
     if (n > 0) FGLT_HIP_TRY(scratch_address(&ws));
     // one stream: the transform's second stream would be created on first use
-    return raw_run(n, nnz, offsets, indices, out, ws, (size_t)FGLT_NOALLOC_SCRATCH_BYTES, flags, plan, stats, stream,
-                   true);
+    // the status word lives in the array: the call waits and returns it
+    return raw_run(n, nnz, offsets, indices, out, ws, (size_t)FGLT_NOALLOC_SCRATCH_BYTES, flags | FGLT_VALIDATE, plan,
+                   stats, stream, true);
 }

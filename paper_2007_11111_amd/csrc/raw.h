@@ -14,8 +14,8 @@ namespace fglt {
 // Tier thresholds.
 constexpr int TRI_WAVE_MAX = 64;     // out-degree handled by one wavefront (one bitmap word)
 constexpr int TRI_LDS_MAX = 512;     // out-degree whose bitmaps fit a workgroup's LDS
-constexpr int TRI_HUB_MAX = 1024;    // out-degree of the hub tier: position map in LDS, and in the
-                                     // clique pass A = B | B^T (128 KiB) in LDS
+constexpr int TRI_HUB_MAX = 1088;    // out-degree of the hub tier: position map in LDS, and in the
+                                     // clique pass A = B | B^T (1088 x 17 words, 145 KiB) in LDS
 // Clique-pass count of an N+ entry, packed as dv << EK_SHIFT | kv: kv (the
 // 4-cliques) is at most 2 (D - 1)^2 < 2^20 for D <= TRI_LDS_MAX, dv (the
 // diamonds) below D * 2^21 (degrees < 2^21), so the word stays below 2^50.
@@ -48,6 +48,8 @@ struct DevPlan {
     u32 n_c4_heavy; // window-tier vertices of degree >= 65536 (32-bit counters; the last ranks)
     u32 pad1;
     i64 n_low;      // vertices of degree <= 1 (the first ranks)
+    u32 stored;     // the wave, LDS and hub tiers' bitmaps fit the workspace (and the clique pass runs)
+    u32 use_etab;   // the window tier's per-entry table fits the workspace (and is wanted)
     i64 min_sum;  // byte model (FGLT_WORKMODEL): sum over edges of min(d_i, d_j)
     i64 k4_merge; // byte model: oriented 4-clique merge steps
 };
@@ -127,8 +129,7 @@ int raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t* indic
 
 // prep (raw_prep.hip)
 hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s);
-hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
-                                   hipStream_t s);
+hipError_t launch_rank_and_relabel(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s);
 struct Tiers {
     i64 tri_wave, tri_lds, tri_hub, c4_wave, c4_block, c4_hash;
     i64 c4_hash_lmax;  // largest |N-(u)| whose counts fit the packed hash words
@@ -136,7 +137,8 @@ struct Tiers {
 };
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n);
 int bits_for_n(i64 n);   // bits of the largest rank n - 1 (0 for n <= 1)
-hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, bool with_c4, hipStream_t s);
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, bool with_c4, bool want_store, int rows_mode,
+                            hipStream_t s);
 
 // counting (raw_count.hip)
 // Optional event marks between launches (FGLT_TIMING).
@@ -154,16 +156,14 @@ struct SegTimer {
 
 // tri.hip
 hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s);
-hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier,
-                              i64 hub_max);
-hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier, i64 hub_max);
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, i64 hub_max,
-                      hipStream_t s, SegTimer& tm);
-hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s);
-hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s);
-hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);
-hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s);
-hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int rows_mode, hipStream_t s, SegTimer& tm);
+hipError_t launch_tri1_stored(i64 n, i64 nnz, RawWs& w, hipStream_t s, int tier, i64 hub_max);
+hipError_t launch_tri2_stored(i64 n, i64 nnz, RawWs& w, hipStream_t s, int tier, i64 hub_max);
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream_t s, SegTimer& tm);
+hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
+hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s);
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s);
+hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_finalize_sub(i64 n, RawWs& w, i64* out, bool net, unsigned mask, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);

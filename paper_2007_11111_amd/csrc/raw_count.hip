@@ -60,7 +60,9 @@ __device__ __forceinline__ void add_run(i64* acc, i32 r, i64 v, const WaveRuns& 
 // (u, v) of its wave and LDS tiers, the 4-cliques and diamonds it attributes
 // to v, packed as dv << EK_SHIFT | kv, at the mirror (v, u).
 __global__ void k_l2_rec(i64 n, const i32* __restrict__ rdeg, const i64* __restrict__ sumd,
-                         const i64* __restrict__ c3x2, L2Rec* __restrict__ rec) {
+                         const i64* __restrict__ c3x2, L2Rec* __restrict__ rec,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
     for (i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (i64)gridDim.x * blockDim.x) {
         const i64 d = rdeg[v];
         rec[v] = L2Rec{sumd[v] - d, ((c3x2[v] >> 1) << 21) | d};
@@ -71,7 +73,10 @@ __global__ void __launch_bounds__(PT) k_l2(const i32* __restrict__ rrow, const i
                                            const L2Rec* __restrict__ rec, const i32* __restrict__ C3,
                                            const i64* __restrict__ ek, i64 nnz, i64* __restrict__ ap2,
                                            i64* __restrict__ ac3, i64* __restrict__ d10, i64* __restrict__ d14,
-                                           i64* __restrict__ k4v, i64* __restrict__ d13) {
+                                           i64* __restrict__ k4v, i64* __restrict__ d13,
+    const u32* __restrict__ storep, const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
+    if (!*storep) ek = nullptr;  // no per-entry clique counts without stored bitmaps
     row_chunks(nnz, [&](const i64* p) {
         i32 r[RP_CH], j[RP_CH], t[RP_CH];
         L2Rec g[RP_CH];
@@ -112,7 +117,11 @@ __global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ mir, con
                                                 const i32* __restrict__ rrow, const i32* __restrict__ rdeg,
                                                 i64 nnz, i32* __restrict__ C3, i64* __restrict__ c3x2,
                                                 i64* __restrict__ sumd, i64* __restrict__ s7,
-                                                i64* __restrict__ ek) {
+                                                i64* __restrict__ ek,
+    const u32* __restrict__ storep,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
+    if (!*storep) ek = nullptr;  // no per-entry clique counts without stored bitmaps
     row_chunks(nnz, [&](const i64* p) {
         i32 r[RP_CH], j[RP_CH], cv[RP_CH], dj[RP_CH];
         bool lower[RP_CH];
@@ -151,9 +160,12 @@ __global__ void __launch_bounds__(PT) k_fill_c3(const i64* __restrict__ mir, con
 template <int MODE>
 __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
-                                                 const i64* __restrict__ G, const i32* __restrict__ list, u32 count,
+                                                 const i64* __restrict__ G, const i32* __restrict__ list, const u32* __restrict__ countp,
                                                  i32* __restrict__ C3, i64* __restrict__ k4v,
-                                                 i64* __restrict__ d13, DevPlan* plan) {
+                                                 i64* __restrict__ d13, DevPlan* plan,
+    const u32* __restrict__ storep) {
+    if (MODE == 2 && storep && *storep) return;  // the stored-bitmap kernels count instead
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int NW = PT / WAVE;
     __shared__ i32 sL[NW][WAVE];
     __shared__ i32 sPre[NW][WAVE + 1];
@@ -256,9 +268,14 @@ template <int MODE, bool GLOBAL>
 __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                   const i64* __restrict__ G, const i32* __restrict__ list,
-                                                  u32 count, i64 dmin, i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                  const u32* __restrict__ countp, i64 dmin, i32* __restrict__ C3, i64* __restrict__ k4v,
                                                   i64* __restrict__ d13, u64* __restrict__ slots, i64 slot_words,
-                                                  DevPlan* plan) {
+                                                  DevPlan* plan,
+    const u32* __restrict__ storep) {
+    // the clique pass from stored bitmaps has counted instead (stored, device flag)
+    if (MODE == 2 && !GLOBAL && storep && *storep) return;
+    if (MODE == 2 && GLOBAL && storep && !*storep) dmin = 0;  // nothing stored: every vertex of the tier here
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     constexpr bool BITS = MODE == 2;
@@ -445,7 +462,9 @@ __global__ void k_finalize(i64 n, const i32* __restrict__ rdeg, const i32* __res
                            const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3x2,
                            const i64* __restrict__ ap2, const i64* __restrict__ ac3, const i64* __restrict__ d10,
                            const i64* __restrict__ d14, const i64* __restrict__ d13, const i64* __restrict__ c4v,
-                           const i64* __restrict__ k4v, i64* __restrict__ out, int net) {
+                           const i64* __restrict__ k4v, i64* __restrict__ out, int net,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
         i64 f[16];
         assemble_raw(r, rdeg, sumd, s7, c3x2, ap2, ac3, d10, d14, d13, c4v, k4v, f);
@@ -464,7 +483,9 @@ __global__ void k_finalize_sub(i64 n, const i32* __restrict__ rdeg, const i32* _
                                const i64* __restrict__ sumd, const i64* __restrict__ s7, const i64* __restrict__ c3x2,
                                const i64* __restrict__ ap2, const i64* __restrict__ ac3, const i64* __restrict__ d10,
                                const i64* __restrict__ d14, const i64* __restrict__ d13, const i64* __restrict__ c4v,
-                               const i64* __restrict__ k4v, i64* __restrict__ out, int net, unsigned mask, int ncols) {
+                               const i64* __restrict__ k4v, i64* __restrict__ out, int net, unsigned mask, int ncols,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
     for (i64 r = (i64)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (i64)gridDim.x * blockDim.x) {
         i64 f[16];
         assemble_raw(r, rdeg, sumd, s7, c3x2, ap2, ac3, d10, d14, d13, c4v, k4v, f);
@@ -496,64 +517,64 @@ __global__ void k_net(i64 n, const i64* __restrict__ raw, i64* __restrict__ net)
 
 // ------------------------------------------------------------ launchers
 
-hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, bool stored, hipStream_t s) {
+hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_l2_rec, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.sumd, w.c3x2, w.l2rec);
+    const u32* const errw = &w.plan->err;
+    hipLaunchKernelGGL(k_l2_rec, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.sumd, w.c3x2, w.l2rec,
+                       errw);
     hipLaunchKernelGGL(k_l2, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.rrow, w.ridx, w.l2rec, w.C3,
-                       stored ? w.ek : nullptr, nnz, w.ap2, w.ac3, w.d10, w.d14, w.k4v, w.d13);
+                       w.ek, nnz, w.ap2, w.ac3, w.d10, w.d14, w.k4v, w.d13, (const u32*)&w.plan->stored, errw);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_c3(i64 nnz, RawWs& w, bool stored, hipStream_t s) {
+hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_c3, dim3(grid_for(nnz, PT * RP_CH, 65536)), dim3(PT), 0, s, w.mir, w.ridx, w.rrow,
-                       w.rdeg, nnz, w.C3, w.c3x2, w.sumd, w.s7, stored ? w.ek : nullptr);
+                       w.rdeg, nnz, w.C3, w.c3x2, w.sumd, w.s7, w.ek, (const u32*)&w.plan->stored,
+                       (const u32*)&w.plan->err);
     return hipGetLastError();
 }
 
-hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, bool stored, i64 hub_max,
-                      hipStream_t s, SegTimer& tm) {
-    (void)nnz;
-    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
+hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream_t s, SegTimer& tm) {
+    const u32* const cnt = w.plan->n_tri;
+    const u32* const stp = &w.plan->stored;
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
+    // the last tier's bound: vertices of out-degree above the LDS tier's
+    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>({n, nnz / (2 * TRI_LDS_MAX) + 1, NUM_TRI_SLOTS}));
     hipError_t e;
     if (mode == 1) {
         // triangle pass; the wave, LDS and hub tiers also store their N+ bitmaps
         tm.mark(FGLT_SEG_TRI1_WAVE, s);
-        if ((e = launch_tri1_stored(n, w, hp, stored, s, 0, hub_max)) != hipSuccess) return e;
+        if ((e = launch_tri1_stored(n, nnz, w, s, 0, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_LDS, s);
-        if ((e = launch_tri1_stored(n, w, hp, stored, s, 1, hub_max)) != hipSuccess) return e;
+        if ((e = launch_tri1_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
-        if ((e = launch_tri1_stored(n, w, hp, stored, s, 2, hub_max)) != hipSuccess) return e;
-        if (c2) hipLaunchKernelGGL((k_tri_block<1, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, hub_max, w.C3, w.k4v, w.d13,
-                                   w.tri_slots, w.tri_slot_words, w.plan);
+        if ((e = launch_tri1_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tri_block<1, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l2,
+                           cnt + 2, hub_max, w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan,
+                           (const u32*)nullptr);
     } else {
-        // clique and diamond pass: from the stored bitmaps, or by scanning again
+        // clique and diamond pass: from the stored bitmaps, or by scanning
+        // again (the stored flag is read on the device; each kernel of the
+        // other way leaves at once)
         tm.mark(FGLT_SEG_TRI2_WAVE, s);
-        if (stored) {
-            if ((e = launch_tri2_stored(n, w, hp, s, 0, hub_max)) != hipSuccess) return e;
-        } else if (c0) {
-            hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(c0, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo,
-                               w.rdeg, w.G, l0, c0, w.C3, w.k4v, w.d13, w.plan);
-        }
+        if ((e = launch_tri2_stored(n, nnz, w, s, 0, hub_max)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tri_wave<2>), dim3(grid_for(n, 4, 65536)), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg,
+                           w.G, l0, cnt + 0, w.C3, w.k4v, w.d13, w.plan, stp);
         tm.mark(FGLT_SEG_TRI2_LDS, s);
-        if (stored) {
-            if ((e = launch_tri2_stored(n, w, hp, s, 1, hub_max)) != hipSuccess) return e;
-        } else if (c1) {
-            hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(c1, 1, 65536)), dim3(PT), 0, s, w.roff,
-                               w.ridx, w.lo, w.rdeg, w.G, l1, c1, (i64)0, w.C3, w.k4v, w.d13, w.tri_slots,
-                               w.tri_slot_words, w.plan);
-        }
+        if ((e = launch_tri2_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(std::min<i64>(n, nnz / (2 * TRI_WAVE_MAX) + 1), 1,
+                                                                   65536)),
+                           dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l1, cnt + 1, (i64)0, w.C3, w.k4v, w.d13,
+                           w.tri_slots, w.tri_slot_words, w.plan, stp);
         tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
         // the hub tier from its stored rows; the rest of the last tier (all of
         // it when nothing is stored) with bitmaps in the workspace
-        if (stored && (e = launch_tri2_stored(n, w, hp, s, 2, hub_max)) != hipSuccess) return e;
-        if (c2) hipLaunchKernelGGL((k_tri_block<2, true>), dim3(std::min<u32>(c2, NUM_TRI_SLOTS)), dim3(PT), 0, s,
-                                   w.roff, w.ridx, w.lo, w.rdeg, w.G, l2, c2, stored ? hub_max : (i64)0, w.C3,
-                                   w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan);
+        if ((e = launch_tri2_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_tri_block<2, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l2,
+                           cnt + 2, hub_max, w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
     }
     return hipGetLastError();
 }
@@ -561,6 +582,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, const DevPlan& hp, int mode, boo
 // Six times the triangles of the graph (the sum over vertices of 2 c3) into
 // plan->triangles (statistics only: one atomic per workgroup).
 __global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __restrict__ c3x2, DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     __shared__ i64 part[PT / WAVE];
     i64 sum = 0;
     for (i64 r = (i64)blockIdx.x * PT + threadIdx.x; r < n; r += (i64)gridDim.x * PT) sum += c3x2[r];
@@ -584,6 +606,7 @@ __global__ void __launch_bounds__(PT) k_count_triangles(i64 n, const i64* __rest
 // T is found by walking the shorter out-list and searching the longer one.
 __global__ void __launch_bounds__(PT) k_work_model(const i32* __restrict__ rrow, const i32* __restrict__ ridx,
                                                    const VRec* __restrict__ vrec, i64 nnz, DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     __shared__ i64 part[PT / WAVE];
     i64 ms = 0, ko = 0;
     for (i64 p = (i64)blockIdx.x * PT + threadIdx.x; p < nnz; p += (i64)gridDim.x * PT) {
@@ -629,7 +652,7 @@ hipError_t launch_work_model(i64 nnz, RawWs& w, hipStream_t s) {
 }
 
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
-    const hipError_t e = hipMemsetAsync(&w.plan->triangles, 0, sizeof(i64), s);
+    const hipError_t e = fill_u32(&w.plan->triangles, 2, 0u, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_count_triangles, dim3(grid_for(n, PT, 256)), dim3(PT), 0, s, n, w.c3x2, w.plan);
     return hipGetLastError();
@@ -637,14 +660,14 @@ hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s) {
 
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7, w.c3x2,
-                       w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0);
+                       w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0, (const u32*)&w.plan->err);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_sub(i64 n, RawWs& w, i64* out, bool net, unsigned mask, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize_sub, dim3(grid_for(n, PT, 65536)), dim3(PT), 0, s, n, w.rdeg, w.perm, w.sumd, w.s7,
                        w.c3x2, w.ap2, w.ac3, w.d10, w.d14, w.d13, w.c4v, w.k4v, out, net ? 1 : 0, mask,
-                       __builtin_popcount(mask));
+                       __builtin_popcount(mask), (const u32*)&w.plan->err);
     return hipGetLastError();
 }
 

@@ -54,7 +54,8 @@ __global__ void k_check_indices(const i32* __restrict__ idx, i64 nnz, i64 n, Dev
 }
 
 hipError_t launch_check_input(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(w.plan, 0, sizeof(DevPlan), s);
+    static_assert(sizeof(DevPlan) % 4 == 0, "the plan is cleared in 32-bit words");
+    hipError_t e = fill_u32(w.plan, sizeof(DevPlan) / 4, 0u, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, off, n, nnz, w.deg, w.plan);
     if (nnz > 0) hipLaunchKernelGGL(k_check_indices, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, idx, nnz, n, w.plan);
@@ -114,7 +115,9 @@ __global__ void __launch_bounds__(PT) k_rowfill(const i64* __restrict__ roff, i6
 __global__ void __launch_bounds__(PT) k_relabel_copy(const i64* __restrict__ off, const i32* __restrict__ idx,
                                                      const i32* __restrict__ perm, const i32* __restrict__ rank,
                                                      const i64* __restrict__ roff, const i32* __restrict__ rrow,
-                                                     i64 nnz, u32* __restrict__ key) {
+                                                     i64 nnz, u32* __restrict__ key,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (i64)gridDim.x * blockDim.x) {
         const i64 r = rrow[q];
         const i64 src = off[perm[r]] + (q - roff[r]);
@@ -127,13 +130,14 @@ __global__ void __launch_bounds__(PT) k_relabel_copy(const i64* __restrict__ off
 // Rows: the entries of rank space (r, t) taken row by row are pairs (t, r);
 // a stable radix sort by t gathers row t with its columns r in ascending
 // order, and the row ids of the sorted pairs are rrow itself.
-hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, const i32* idx, RawWs& w,
-                                   hipStream_t s) {
+hipError_t launch_rank_and_relabel(i64 n, i64 nnz, const i64* off, const i32* idx, RawWs& w, hipStream_t s) {
     hipError_t e;
     const i64 nn = std::max<i64>(n, 1);
+    // degrees are below min(n, nnz + 1, 2^21) (the checks clamp a larger one to 0)
+    const i64 d_bound = std::min<i64>({n - 1, nnz, FGLT_MAX_DEGREE - 1});
     // pass buffers: ek holds 2 max(nnz, n) and cntd 2 (n + 2) 32-bit words, G 2 (nnz + 1)
     u32* ek_k = reinterpret_cast<u32*>(w.ek);
-    if ((e = radix_sort_pairs(n, bits_for(d_max), reinterpret_cast<const u32*>(w.deg), nullptr,
+    if ((e = radix_sort_pairs(n, bits_for(d_bound), reinterpret_cast<const u32*>(w.deg), nullptr,
                               reinterpret_cast<u32*>(w.rdeg), w.perm, ek_k, reinterpret_cast<i32*>(ek_k + nn),
                               reinterpret_cast<u32*>(w.cntd), reinterpret_cast<i32*>(w.cntd) + nn, w.rx_hist,
                               w.partials, s)) != hipSuccess)
@@ -145,7 +149,7 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
                            nnz, w.rrow);
         u32* g_k = reinterpret_cast<u32*>(w.G);
         hipLaunchKernelGGL(k_relabel_copy, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, off, idx, w.perm, w.rank,
-                           w.roff, w.rrow, nnz, g_k);
+                           w.roff, w.rrow, nnz, g_k, (const u32*)&w.plan->err);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // pass 1 reads (G, rrow); later passes alternate between ek and G
         if ((e = radix_sort_pairs(nnz, bits_for(n - 1), g_k, w.rrow, nullptr, w.ridx, ek_k,
@@ -162,6 +166,7 @@ hipError_t launch_rank_and_relabel(i64 n, i64 nnz, i64 d_max, const i64* off, co
 // vertices of degree <= 1.
 __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n,
                                            i32* __restrict__ lo, VRec* __restrict__ vrec, DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     __shared__ i64 part[PT / WAVE];
     i64 sum = 0, low = 0;
     u32 err = 0;
@@ -190,6 +195,7 @@ __global__ void __launch_bounds__(PT) k_lo(const i64* __restrict__ roff, const i
 __global__ void k_rpos(const VRec* __restrict__ vrec, const i32* __restrict__ ridx, const i32* __restrict__ rrow,
                        i64 nnz, i32* __restrict__ rpos, i64* __restrict__ mir, i64* __restrict__ G,
                        int with_c4, DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     u32 err = 0;
     for (i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (i64)gridDim.x * blockDim.x) {
         {
@@ -257,6 +263,7 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
                                               const i32* __restrict__ rdeg, const i64* __restrict__ G, i64 n,
                                               Tiers th, i32* __restrict__ tri_list, i32* __restrict__ c4_list,
                                               DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     __shared__ u32 wt[TT / WAVE][3], wc[TT / WAVE][4];
     __shared__ u32 bt[3], bc[4];
     __shared__ i64 part[TT / WAVE];
@@ -310,6 +317,7 @@ __global__ void __launch_bounds__(TT) k_tiers(const i64* __restrict__ roff, cons
 
 __global__ void __launch_bounds__(PT) k_totals(const i64* __restrict__ roff, const i32* __restrict__ lo,
                                                const i64* __restrict__ G, i64 n, i64 nnz, DevPlan* plan) {
+    FGLT_GATE(&plan->err);
     __shared__ i64 part[PT / WAVE];
     i64 wedges = 0;
     for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x)
@@ -349,9 +357,26 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
     return t;
 }
 
-hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, bool with_c4, hipStream_t s) {
+// Every entry below the diagonal has its mirror (k_rpos) and half the entries
+// lie below it: the CSR is symmetric.  One thread.
+__global__ void k_check_half(DevPlan* plan, i64 nnz) {
+    if (2 * plan->sum_lo != nnz) atomicOr(&plan->err, ERR_ASYM);
+}
+
+// What the host no longer waits for: whether the bitmaps of the wave, LDS and
+// hub tiers fit the workspace (the clique pass then reads them), and whether
+// the window tier's per-entry table does.  One thread.
+__global__ void k_plan_decide(DevPlan* plan, const i64* __restrict__ bitmap_words, i64 bstore_cap, int want_store,
+                              int want_etab) {
+    plan->stored = want_store && !plan->err && *bitmap_words <= bstore_cap;
+    plan->use_etab = want_etab && !plan->err && plan->c4_etab <= 4 * bstore_cap;
+}
+
+hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, bool with_c4, bool want_store, int rows_mode,
+                            hipStream_t s) {
     hipError_t e;
     hipLaunchKernelGGL(k_lo, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.ridx, n, w.lo, w.vrec, w.plan);
+    hipLaunchKernelGGL(k_check_half, dim3(1), dim3(1), 0, s, w.plan, nnz);
     if (nnz > 0)
         hipLaunchKernelGGL(k_rpos, dim3(grid_for(nnz, PT, 65536)), dim3(PT), 0, s, w.vrec, w.ridx, w.rrow, nnz,
                            w.rpos, w.mir, w.G, with_c4 ? 1 : 0, w.plan);
@@ -362,7 +387,13 @@ hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& th, bool with
     hipLaunchKernelGGL(k_totals, dim3(grid_for(n, PT, 1024)), dim3(PT), 0, s, w.roff, w.lo, w.G, n, nnz, w.plan);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // bitmap rows of the wave, LDS and hub tiers (the clique pass reads them)
-    return launch_bitmap_offsets(n, w, std::max(th.tri_lds, th.tri_hub), s);
+    if ((e = launch_bitmap_offsets(n, w, std::max(th.tri_lds, th.tri_hub), s)) != hipSuccess) return e;
+    // the per-entry window table needs the 16-bit vertex table (its capacity is known here)
+    const i64 k1 = (n + C4W_SPAN - 1) / C4W_SPAN + 1, ts = (k1 + 15) & ~(i64)15;
+    const bool want_etab = rows_mode == 0 && w.c4_tab != nullptr && n * ts <= w.c4_tab_cap;
+    hipLaunchKernelGGL(k_plan_decide, dim3(1), dim3(1), 0, s, w.plan, (const i64*)(w.boff + n), w.bstore_cap,
+                       want_store ? 1 : 0, want_etab ? 1 : 0);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ workspace layout

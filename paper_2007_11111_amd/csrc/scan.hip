@@ -124,11 +124,19 @@ __global__ void __launch_bounds__(SCAN_THREADS) k_tile_scan(const T* __restrict_
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[count] = partials[gridDim.x];
 }
 
+__global__ void k_fill_u32(u32* __restrict__ p, i64 words, u32 v) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (i64)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t fill_u32(void* p, i64 words, u32 v, hipStream_t s) {
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(words, 256, 16384)), dim3(256), 0, s, (u32*)p, words, v);
+    return hipGetLastError();
+}
+
 template <class T>
 static hipError_t scan_impl(const T* in, i64* out, i64 count, i64* partials, hipStream_t s) {
-    if (count <= 0) {
-        return hipMemsetAsync(out, 0, sizeof(i64), s);
-    }
+    if (count <= 0) return fill_u32(out, 2, 0u, s);
     const i64 nb = ceil_div(count, SCAN_TILE);
     hipLaunchKernelGGL(k_tile_sums<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, s, in, count, partials);
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, partials, nb);

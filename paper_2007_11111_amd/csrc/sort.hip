@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(RADIX_THREADS) k_sort_large(i32* __restrict__ 
 hipError_t seg_sort(i32* keys, const i64* seg_off, i64 nseg, int key_bits, SegSortWs ws, i64 max_seg_grid,
                     hipStream_t s) {
     if (nseg <= 0) return hipSuccess;
-    hipError_t e = hipMemsetAsync(ws.counters, 0, 4 * sizeof(u32), s);
+    hipError_t e = fill_u32(ws.counters, 4, 0u, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_classify, dim3((unsigned)ceil_div(nseg, 256)), dim3(256), 0, s, seg_off, nseg,
                        ws.lists, nseg, ws.counters);

@@ -64,9 +64,11 @@ __device__ __forceinline__ void flush_c3(const u32* q, u32 nq, i32* __restrict__
 // the list first, where the vertices of high out-degree sit.
 template <bool PACK>
 __global__ void __launch_bounds__(WT) k_tri1_wave(const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
-                                                  const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
-                                                  u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
+                                                  const i32* __restrict__ list, const u32* __restrict__ countp, i32* __restrict__ C3,
+                                                  u64* __restrict__ bstore, const i64* __restrict__ boff, const u32* __restrict__ storep,
                                                   int defer) {
+    const int store = (int)*storep;  // the bitmaps are stored (decided on the device)
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int NW = WT / WAVE;
     constexpr int TASK = PACK ? 8 : 1;
     __shared__ i64 rbase[NW][WAVE + 1];
@@ -170,9 +172,11 @@ __global__ void __launch_bounds__(WT) k_tri1_wave(const VRec* __restrict__ vrec,
 
 __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                  const i32* __restrict__ lo, const i64* __restrict__ G,
-                                                 const i32* __restrict__ list, u32 count, i32* __restrict__ C3,
-                                                 u64* __restrict__ bstore, const i64* __restrict__ boff, int store,
+                                                 const i32* __restrict__ list, const u32* __restrict__ countp, i32* __restrict__ C3,
+                                                 u64* __restrict__ bstore, const i64* __restrict__ boff, const u32* __restrict__ storep,
                                                  int defer) {
+    const int store = (int)*storep;  // the bitmaps are stored (decided on the device)
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     constexpr int NWV = LT / WAVE;
@@ -263,9 +267,15 @@ __global__ void __launch_bounds__(LT) k_tri1_lds(const i64* __restrict__ roff, c
 static constexpr int HT = 1024;        // hub-tier block: 16 wavefronts on one vertex
 static constexpr int HUB_QCAP = 256;   // hits queued per wavefront before a burst
 
+// The first rows of B that fit HUB_BWORDS words of LDS are set there (most
+// hits: row k holds the bits l > k); the rest go to the workspace rows
+// through the queue, marked by HUB_GLOBAL_ROW.
+static constexpr int HUB_BWORDS = 9792;         // 576 rows of 17 words
+static constexpr u32 HUB_GLOBAL_ROW = 1u << 31;  // queued hit whose bit goes to the workspace row
+
 struct HubQueue {
     u32* qe;   // entry index of the far edge (v_k, v_l)
-    u32* qkl;  // k << 16 | l
+    u32* qkl;  // k << 16 | l, with HUB_GLOBAL_ROW when row k is not in LDS
     u32 n;     // wave-uniform fill
 };
 
@@ -273,9 +283,9 @@ __device__ __forceinline__ void hub_flush(HubQueue& q, i32* __restrict__ C3, u64
     wave_lds_fence();
     for (u32 i = lane_id(); i < q.n; i += WAVE) {
         atomicAdd(&C3[q.qe[i]], 1);
-        if (Bg) {
-            const u32 kl = q.qkl[i];
-            const u32 k = kl >> 16, l = kl & 0xffffu;
+        const u32 kl = q.qkl[i];
+        if (Bg && (kl & HUB_GLOBAL_ROW)) {
+            const u32 k = (kl >> 16) & 0x7fffu, l = kl & 0xffffu;
             atomicOr((unsigned long long*)&Bg[(i64)k * W + (l >> 6)], 1ull << (l & 63));
         }
     }
@@ -290,7 +300,9 @@ __device__ __forceinline__ void hub_push(bool hit, i64 e, u32 kl, HubQueue& q, i
     if (!defer) {  // entry indices beyond 32 bits: issue at once
         if (hit) {
             atomicAdd(&C3[e], 1);
-            if (Bg) atomicOr((unsigned long long*)&Bg[(i64)(kl >> 16) * W + ((kl & 0xffffu) >> 6)], 1ull << (kl & 63));
+            if (Bg && (kl & HUB_GLOBAL_ROW))
+                atomicOr((unsigned long long*)&Bg[(i64)((kl >> 16) & 0x7fffu) * W + ((kl & 0xffffu) >> 6)],
+                         1ull << (kl & 63));
         }
         return;
     }
@@ -304,11 +316,44 @@ __device__ __forceinline__ void hub_push(bool hit, i64 e, u32 kl, HubQueue& q, i
     q.n += c;
 }
 
+// The out-lists N+(v_k) of a vertex with D <= 2 NT out-neighbours as runs of
+// the walk, in k order: thread t takes k = t, then k = NT + t; each v_k goes
+// into the position map.  Returns the number of runs (block-uniform).
+template <int NT, int MB>
+__device__ __forceinline__ i32 hub_runs(int D, i64 bu, i64 gb, const i32* __restrict__ ridx, const i64* __restrict__ G,
+                                        const VRec* __restrict__ vrec, BucketMap<MB>& pm, i64* rbase, i32* rstart,
+                                        i32* rk, i32* wsum, i32* stot) {
+    i32 runs = 0;
+    for (int k0 = 0; k0 < D; k0 += NT) {  // uniform over the block
+        const int k = k0 + (int)threadIdx.x;
+        i32 len = 0, pre = 0;
+        i64 bv = 0;
+        if (k < D) {
+            const i32 v = ridx[bu + k];
+            bmap_insert(pm, v, k);
+            pre = (i32)(G[bu + k] - gb);
+            len = (i32)(G[bu + k + 1] - G[bu + k]);
+            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
+        }
+        const i32 cidx = runs + block_scan<NT>(len > 0 ? 1 : 0, wsum, stot);
+        if (k < D && len > 0) {
+            rbase[cidx] = bv - pre;
+            rstart[cidx] = pre;
+            if (rk) rk[cidx] = k;
+        }
+        runs += *stot;
+        __syncthreads();  // wsum and the total are reused by the next round
+    }
+    return runs;
+}
+
 __global__ void __launch_bounds__(HT) k_tri1_hub(const i64* __restrict__ roff, const VRec* __restrict__ vrec,
                                                  const i32* __restrict__ ridx, const i32* __restrict__ lo,
-                                                 const i64* __restrict__ G, const i32* __restrict__ list, u32 count,
+                                                 const i64* __restrict__ G, const i32* __restrict__ list, const u32* __restrict__ countp,
                                                  i32 hub_max, i32* __restrict__ C3, u64* __restrict__ bstore,
-                                                 const i64* __restrict__ boff, int store, int defer) {
+                                                 const i64* __restrict__ boff, const u32* __restrict__ storep, int defer) {
+    const int store = (int)*storep;  // the bitmaps are stored (decided on the device)
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_HUB_MAX;
     constexpr int NWV = HT / WAVE;
     __shared__ i64 rbase[DM + 1];
@@ -321,6 +366,7 @@ __global__ void __launch_bounds__(HT) k_tri1_hub(const i64* __restrict__ roff, c
     __shared__ i32 stot, sR;
     __shared__ u32 sqe[NWV][HUB_QCAP];
     __shared__ u32 sqkl[NWV][HUB_QCAP];
+    __shared__ u64 Bl[HUB_BWORDS];  // rows 0 .. RL-1 of B
     const int wv = threadIdx.x / WAVE;
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
         const i64 u = list[it];
@@ -328,34 +374,22 @@ __global__ void __launch_bounds__(HT) k_tri1_hub(const i64* __restrict__ roff, c
         const int D = (int)(roff[u + 1] - bu);
         if (D > hub_max) continue;  // the global-bitmap kernel takes it (uniform over the block)
         const int W = (D + 63) >> 6;
+        const int RL = std::min(D, HUB_BWORDS / W);  // rows of B kept in LDS
         const i64 gb = G[bu];
         const i32 T = (i32)(G[bu + D] - gb);
         u64* const Bg = store ? bstore + boff[u] : nullptr;
         bmap_clear(pm, threadIdx.x, HT);
+        for (int q = threadIdx.x; q < RL * W; q += HT) Bl[q] = 0;
         if (Bg)
-            for (int q = threadIdx.x; q < D * W; q += HT) Bg[q] = 0;
-        const int k = threadIdx.x;  // D <= DM == HT: one out-neighbour per thread
-        Cnt[k] = 0;
+            for (int q = RL * W + threadIdx.x; q < D * W; q += HT) Bg[q] = 0;
+        for (int k = threadIdx.x; k < DM; k += HT) Cnt[k] = 0;
         __threadfence();  // the cleared rows reach L2 before any wavefront's atomics
         __syncthreads();
-        i32 len = 0, pre = 0;
-        i64 bv = 0;
-        if (k < D) {
-            const i32 v = ridx[bu + k];
-            bmap_insert(pm, v, k);
-            pre = (i32)(G[bu + k] - gb);
-            len = (i32)(G[bu + k + 1] - G[bu + k]);
-            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
-        }
-        const i32 cidx = block_scan<HT>(len > 0 ? 1 : 0, wsum, &stot);
-        if (k < D && len > 0) {
-            rbase[cidx] = bv - pre;
-            rstart[cidx] = pre;
-            rk[cidx] = k;
-        }
+        // out-neighbour k on thread k mod HT (two rounds when D > HT), runs in k order
+        const i32 R = hub_runs<HT>(D, bu, gb, ridx, G, vrec, pm, rbase, rstart, rk, wsum, &stot);
         if (threadIdx.x == 0) {
-            sR = stot;
-            rstart[stot] = T;
+            sR = R;
+            rstart[R] = T;
         }
         __syncthreads();
         const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
@@ -367,15 +401,19 @@ __global__ void __launch_bounds__(HT) k_tri1_hub(const i64* __restrict__ roff, c
                               if (hit) {
                                   atomicAdd(&Cnt[kr], 1);
                                   atomicAdd(&Cnt[l], 1);
+                                  if (kr < RL) atomicOr((unsigned long long*)&Bl[kr * W + (l >> 6)], 1ull << (l & 63));
                               }
-                              hub_push(hit, e, ((u32)kr << 16) | (u32)l, q, C3, Bg, W, defer);
+                              hub_push(hit, e, ((u32)kr << 16) | (u32)l | (kr < RL ? 0u : HUB_GLOBAL_ROW), q, C3,
+                                       Bg, W, defer);
                           });
         hub_flush(q, C3, Bg, W);
         __syncthreads();
-        if (k < D) {
+        for (int k = threadIdx.x; k < D; k += HT) {
             const i32 c = Cnt[k];
             if (c) atomicAdd(&C3[bu + k], c);
         }
+        if (Bg)
+            for (int q = threadIdx.x; q < RL * W; q += HT) Bg[q] = Bl[q];
         __threadfence();
         __syncthreads();
     }
@@ -405,9 +443,12 @@ static constexpr int T2_TASK = 8;  // vertices a wavefront takes at a time
 
 __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                    const i64* __restrict__ mir, const i32* __restrict__ list,
-                                                   u32 count, const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                   const u32* __restrict__ countp, const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                    i64* __restrict__ d13, i64* __restrict__ ek,
-                                                   const u64* __restrict__ bstore, const i64* __restrict__ boff) {
+                                                   const u64* __restrict__ bstore, const i64* __restrict__ boff,
+    const u32* __restrict__ storep) {
+    if (!*storep) return;  // the bitmaps were not stored: the fallback kernels count
+    const u32 count = *countp;  // the tier size, written on the device
     // Each wavefront works alone, on T2_TASK consecutive vertices at a time,
     // packed into rounds: consecutive vertices whose out-degrees sum to at
     // most 64 share the 64 lanes, vertex g's rows k on lanes off_g + k, its
@@ -532,10 +573,13 @@ __global__ void __launch_bounds__(WT) k_tri2s_wave(const VRec* __restrict__ vrec
 // the out-lists again).
 __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i64* __restrict__ mir,
-                                                  const i32* __restrict__ list, u32 count,
+                                                  const i32* __restrict__ list, const u32* __restrict__ countp,
                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
                                                   i64* __restrict__ ek,
-                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff) {
+                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff,
+    const u32* __restrict__ storep) {
+    if (!*storep) return;  // the bitmaps were not stored: the fallback kernels count
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
     __shared__ u64 B[DM * WM];
@@ -614,15 +658,18 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
 // are taken, and once for the transpose).
 __global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, const i32* __restrict__ lo,
                                                   const i64* __restrict__ mir, const i32* __restrict__ list,
-                                                  u32 count, i32 hub_max, const i32* __restrict__ C3,
+                                                  const u32* __restrict__ countp, i32 hub_max, const i32* __restrict__ C3,
                                                   i64* __restrict__ k4v, i64* __restrict__ ek,
-                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff) {
+                                                  const u64* __restrict__ bstore, const i64* __restrict__ boff,
+    const u32* __restrict__ storep) {
+    if (!*storep) return;  // the bitmaps were not stored: the fallback kernels count
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_HUB_MAX;
     constexpr int WM = DM / 64;
     __shared__ u64 A[DM * WM];
     __shared__ i32 c3u[DM];
-    __shared__ u32 t2[DM];   // twice the triangles of H through k: below 2 * 1023 * 1022
-    __shared__ u32 dvs[DM];  // diamonds of v_k: below 1023 * 2^21
+    __shared__ u32 t2[DM];   // twice the triangles of H through k: below 2 * 1087 * 1086
+    __shared__ u32 dvs[DM];  // diamonds of v_k: below 1087 * 2^21
     __shared__ i64 red[1];
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
         const i64 u = list[it];
@@ -631,10 +678,10 @@ __global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, 
         if (D > hub_max) continue;  // uniform over the block
         const int W = (D + 63) >> 6;
         const u64* const B = bstore + boff[u];
-        if (threadIdx.x < D) {
-            c3u[threadIdx.x] = C3[bu + threadIdx.x];
-            t2[threadIdx.x] = 0;
-            dvs[threadIdx.x] = 0;
+        for (int k = threadIdx.x; k < D; k += HT) {
+            c3u[k] = C3[bu + k];
+            t2[k] = 0;
+            dvs[k] = 0;
         }
         if (threadIdx.x == 0) red[0] = 0;
         // A = B | B^T, 64 x 64 blocks: wavefront wv takes the blocks (bi, bj)
@@ -675,8 +722,7 @@ __global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, 
         R = wave_sum(R);
         if (lane_id() == 0 && R) atomicAdd((unsigned long long*)&red[0], (unsigned long long)R);
         __syncthreads();
-        const int k = threadIdx.x;
-        if (k < D) {
+        for (int k = threadIdx.x; k < D; k += HT) {
             const i64 kv = t2[k] >> 1, dv = dvs[k];
             if (kv | dv) ek[mir[bu + k]] = (dv << EK_SHIFT) | kv;
         }
@@ -689,14 +735,16 @@ __global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, 
 // number of other triangles on the opposite edge, C3(v_k, v_l) - 1.  The
 // out-lists N+(v_k) are walked again as in the triangle pass; a hit y = v_l
 // sits at the walked entry e, whose C3 is final now.
-// NT threads take one vertex with D <= DM (NT == DM); MB: the position map's
+// NT threads take one vertex with D <= DM <= 2 NT; MB: the position map's
 // bucket bits.  The hub instance skips the vertices above hub_max.
-template <int NT, int MB>
+template <int NT, int DM, int MB>
 __global__ void __launch_bounds__(NT) k_tri2_du_lds(const i64* __restrict__ roff, const VRec* __restrict__ vrec, const i32* __restrict__ ridx,
                                                     const i32* __restrict__ lo, const i64* __restrict__ G,
-                                                    const i32* __restrict__ list, u32 count, i32 hub_max,
-                                                    const i32* __restrict__ C3, i64* __restrict__ d13) {
-    constexpr int DM = NT;
+                                                    const i32* __restrict__ list, const u32* __restrict__ countp, i32 hub_max,
+                                                    const i32* __restrict__ C3, i64* __restrict__ d13,
+    const u32* __restrict__ storep) {
+    if (!*storep) return;  // the bitmaps were not stored: the fallback kernels count
+    const u32 count = *countp;  // the tier size, written on the device
     constexpr int NWV = NT / WAVE;
     __shared__ i64 rbase[DM + 1];
     __shared__ i32 rstart[DM + 1];
@@ -715,24 +763,10 @@ __global__ void __launch_bounds__(NT) k_tri2_du_lds(const i64* __restrict__ roff
         const i32 T = (i32)(G[bu + D] - gb);
         bmap_clear(pm, threadIdx.x, NT);
         __syncthreads();
-        const int k = threadIdx.x;
-        i32 len = 0, pre = 0;
-        i64 bv = 0;
-        if (k < D) {
-            const i32 v = ridx[bu + k];
-            bmap_insert(pm, v, k);
-            pre = (i32)(G[bu + k] - gb);
-            len = (i32)(G[bu + k + 1] - G[bu + k]);
-            { const VRec rv = vrec[v]; bv = rv.off + rv.lo; }
-        }
-        const i32 cidx = block_scan<NT>(len > 0 ? 1 : 0, wsum, &stot);
-        if (k < D && len > 0) {
-            rbase[cidx] = bv - pre;
-            rstart[cidx] = pre;
-        }
+        const i32 R = hub_runs<NT>(D, bu, gb, ridx, G, vrec, pm, rbase, rstart, (i32*)nullptr, wsum, &stot);
         if (threadIdx.x == 0) {
-            sR = stot;
-            rstart[stot] = T;
+            sR = R;
+            rstart[R] = T;
         }
         __syncthreads();
         const i32 per = ((T + NWV * WAVE - 1) / (NWV * WAVE)) * WAVE;
@@ -748,7 +782,9 @@ __global__ void __launch_bounds__(NT) k_tri2_du_lds(const i64* __restrict__ roff
 
 // Bitmap words of every vertex of the wave and LDS tiers (D x ceil(D/64)).
 __global__ void k_bitmap_words(const i64* __restrict__ roff, const i32* __restrict__ lo, i64 n, i64 lds_max,
-                               i64* __restrict__ words) {
+                               i64* __restrict__ words,
+    const u32* __restrict__ errw) {
+    FGLT_GATE(errw);
     for (i64 u = (i64)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (i64)gridDim.x * blockDim.x) {
         const i64 D = roff[u + 1] - roff[u] - lo[u];
         words[u] = (D >= 2 && D <= lds_max) ? D * ((D + 63) / 64) : 0;
@@ -762,49 +798,59 @@ static inline unsigned tgrid(i64 work, i64 per_block) {
 }
 
 hipError_t launch_bitmap_offsets(i64 n, RawWs& w, i64 lds_max, hipStream_t s) {
-    hipLaunchKernelGGL(k_bitmap_words, dim3(tgrid(n, 256)), dim3(256), 0, s, w.roff, w.lo, n, lds_max, w.bcnt);
+    hipLaunchKernelGGL(k_bitmap_words, dim3(tgrid(n, 256)), dim3(256), 0, s, w.roff, w.lo, n, lds_max, w.bcnt,
+                       (const u32*)&w.plan->err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan_exclusive_i64(w.bcnt, w.boff, n, w.partials, s);
 }
 
-hipError_t launch_tri1_stored(i64 n, RawWs& w, const DevPlan& hp, bool store, hipStream_t s, int tier,
-                              i64 hub_max) {
-    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
-    const int defer = 2 * hp.sum_lo <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
-    if (tier == 0 && c0) {
+// Grids of the tier launches, from bounds on the tier sizes (the sizes
+// themselves are on the device): a vertex of out-degree above D has more
+// than D of the nnz / 2 oriented edges.
+static inline unsigned tier_grid(i64 n, i64 nnz, int tier, i64 per_block, i64 cap) {
+    const i64 bound = tier == 0 ? n : std::min<i64>(n, nnz / (tier == 1 ? 2 * TRI_WAVE_MAX : 2 * TRI_LDS_MAX) + 1);
+    return (unsigned)std::max<i64>(1, std::min<i64>(ceil_div(std::max<i64>(bound, 1), per_block), cap));
+}
+
+hipError_t launch_tri1_stored(i64 n, i64 nnz, RawWs& w, hipStream_t s, int tier, i64 hub_max) {
+    const u32* const cnt = w.plan->n_tri;
+    const u32* const stp = &w.plan->stored;
+    const int defer = nnz <= (i64)0xffffffffLL;  // entry indices fit the 32-bit queue
+    if (tier == 0) {
         if (n <= ((i64)1 << 28))  // position-map keys (v, slot) fit 31 bits
-            hipLaunchKernelGGL(k_tri1_wave<true>, dim3(tgrid(c0, WT / WAVE * 8)), dim3(WT), 0, s, w.vrec, w.ridx,
-                               w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+            hipLaunchKernelGGL(k_tri1_wave<true>, dim3(tier_grid(n, nnz, 0, WT / WAVE * 8, 65536)), dim3(WT), 0, s,
+                               w.vrec, w.ridx, w.tri_list, cnt + 0, w.C3, w.bstore, w.boff, stp, defer);
         else
-            hipLaunchKernelGGL(k_tri1_wave<false>, dim3(tgrid(c0, WT / WAVE)), dim3(WT), 0, s, w.vrec, w.ridx,
-                               w.tri_list, c0, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+            hipLaunchKernelGGL(k_tri1_wave<false>, dim3(tier_grid(n, nnz, 0, WT / WAVE, 65536)), dim3(WT), 0, s,
+                               w.vrec, w.ridx, w.tri_list, cnt + 0, w.C3, w.bstore, w.boff, stp, defer);
     }
-    if (tier == 1 && c1)
-        hipLaunchKernelGGL(k_tri1_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
-                           w.tri_list + n, c1, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
-    if (tier == 2 && c2 && hub_max > 0)  // the hub tier's vertices of the last tier list
-        hipLaunchKernelGGL(k_tri1_hub, dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.vrec, w.ridx, w.lo, w.G,
-                           w.tri_list + 2 * n, c2, (i32)hub_max, w.C3, w.bstore, w.boff, store ? 1 : 0, defer);
+    if (tier == 1)
+        hipLaunchKernelGGL(k_tri1_lds, dim3(tier_grid(n, nnz, 1, 1, 65536)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx,
+                           w.lo, w.G, w.tri_list + n, cnt + 1, w.C3, w.bstore, w.boff, stp, defer);
+    if (tier == 2 && hub_max > 0)  // the hub tier's vertices of the last tier list
+        hipLaunchKernelGGL(k_tri1_hub, dim3(tier_grid(n, nnz, 2, 1, 4096)), dim3(HT), 0, s, w.roff, w.vrec, w.ridx,
+                           w.lo, w.G, w.tri_list + 2 * n, cnt + 2, (i32)hub_max, w.C3, w.bstore, w.boff, stp, defer);
     return hipGetLastError();
 }
 
-hipError_t launch_tri2_stored(i64 n, RawWs& w, const DevPlan& hp, hipStream_t s, int tier, i64 hub_max) {
-    const u32 c0 = hp.n_tri[0], c1 = hp.n_tri[1], c2 = hp.n_tri[2];
-    if (tier == 0 && c0)
-        hipLaunchKernelGGL(k_tri2s_wave, dim3(tgrid(c0, WT / WAVE * T2_TASK)), dim3(WT), 0, s, w.vrec, w.ridx,
-                           w.mir, w.tri_list, c0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff);
-    if (tier == 1 && c1) {
-        hipLaunchKernelGGL(k_tri2s_lds, dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.ridx, w.lo, w.mir,
-                           w.tri_list + n, c1, w.C3, w.k4v, w.ek, w.bstore, w.boff);
-        hipLaunchKernelGGL((k_tri2_du_lds<LT, 9>), dim3(tgrid(c1, 1)), dim3(LT), 0, s, w.roff, w.vrec, w.ridx, w.lo,
-                           w.G, w.tri_list + n, c1, (i32)TRI_LDS_MAX, w.C3, w.d13);
+hipError_t launch_tri2_stored(i64 n, i64 nnz, RawWs& w, hipStream_t s, int tier, i64 hub_max) {
+    const u32* const cnt = w.plan->n_tri;
+    const u32* const stp = &w.plan->stored;
+    if (tier == 0)
+        hipLaunchKernelGGL(k_tri2s_wave, dim3(tier_grid(n, nnz, 0, WT / WAVE * T2_TASK, 65536)), dim3(WT), 0, s,
+                           w.vrec, w.ridx, w.mir, w.tri_list, cnt + 0, w.C3, w.k4v, w.d13, w.ek, w.bstore, w.boff, stp);
+    if (tier == 1) {
+        hipLaunchKernelGGL(k_tri2s_lds, dim3(tier_grid(n, nnz, 1, 1, 65536)), dim3(LT), 0, s, w.roff, w.ridx, w.lo,
+                           w.mir, w.tri_list + n, cnt + 1, w.C3, w.k4v, w.ek, w.bstore, w.boff, stp);
+        hipLaunchKernelGGL((k_tri2_du_lds<LT, TRI_LDS_MAX, 9>), dim3(tier_grid(n, nnz, 1, 1, 65536)), dim3(LT), 0, s, w.roff,
+                           w.vrec, w.ridx, w.lo, w.G, w.tri_list + n, cnt + 1, (i32)TRI_LDS_MAX, w.C3, w.d13, stp);
     }
-    if (tier == 2 && c2 && hub_max > 0) {
-        hipLaunchKernelGGL(k_tri2s_hub, dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.lo, w.mir, w.tri_list + 2 * n,
-                           c2, (i32)hub_max, w.C3, w.k4v, w.ek, w.bstore, w.boff);
-        hipLaunchKernelGGL((k_tri2_du_lds<HT, 10>), dim3(tgrid(c2, 1)), dim3(HT), 0, s, w.roff, w.vrec, w.ridx, w.lo,
-                           w.G, w.tri_list + 2 * n, c2, (i32)hub_max, w.C3, w.d13);
+    if (tier == 2 && hub_max > 0) {
+        hipLaunchKernelGGL(k_tri2s_hub, dim3(tier_grid(n, nnz, 2, 1, 4096)), dim3(HT), 0, s, w.roff, w.lo, w.mir,
+                           w.tri_list + 2 * n, cnt + 2, (i32)hub_max, w.C3, w.k4v, w.ek, w.bstore, w.boff, stp);
+        hipLaunchKernelGGL((k_tri2_du_lds<HT, TRI_HUB_MAX, 10>), dim3(tier_grid(n, nnz, 2, 1, 4096)), dim3(HT), 0, s, w.roff,
+                           w.vrec, w.ridx, w.lo, w.G, w.tri_list + 2 * n, cnt + 2, (i32)hub_max, w.C3, w.d13, stp);
     }
     return hipGetLastError();
 }

@@ -153,11 +153,17 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             off = torch.from_numpy(req.offsets).to(self.device, non_blocking=True)
             idx = torch.from_numpy(req.indices).to(self.device, non_blocking=True)
+            n, nnz = int(off.numel()) - 1, int(idx.numel())
+            ws = torch.empty(max(self.fg.raw_workspace_bytes(n, nnz), 1), dtype=torch.uint8, device=self.device)
             try:
-                out = self.fg.transform(off, idx, stream=stream)
+                # enqueued without waiting; the status word is read once the stream is done
+                out = self.fg.transform(off, idx, workspace=ws, validate=False, stream=stream)
             except self.fg.FgltError as e:
                 stream.synchronize()
                 return [e]
+        st = self.fg.raw_status(ws, stream=stream)
+        if st != 0:
+            return [self.fg.FgltError(st, "fglt_raw", "the request's CSR breaks the contract")]
         return self._finish(stream, [out], [(off, idx)])
 
     def run_batch(self, reqs, stream):

@@ -61,7 +61,7 @@ def test_batch_persistent_queue_and_tuner(fg):
     np.testing.assert_array_equal(out.cpu().numpy(), exp)
     say("batch tuner")
     plan = fg.batch_tune(vtx, o, i, reps=2)
-    assert plan["threads"] in (128, 256, 512) and plan["blocks_per_cu"] in (2, 4, 8)
+    assert plan["threads"] in (128, 256, 512) and plan["blocks_per_cu"] in (2, 4, 8, 64)
     assert plan["hub_degree"] in (16, 32, 64, -1)
     np.testing.assert_array_equal(fg.batch(vtx, o, i, plan=plan).cpu().numpy(), exp)
     s = torch.cuda.Stream()  # graph capture needs a stream other than the legacy default one

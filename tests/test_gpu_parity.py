@@ -123,11 +123,12 @@ def test_small_random_all_tiers(fg, plan):
 
 # ------------------------------------------------------------------ closed forms
 
-@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600, 1100])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600, 1070, 1100])
 def test_clique(fg, n):
     """K_n: out-degree n-1 of the lowest vertex (600 reaches the hub tier,
-    1100 the global-bitmap tier beyond it, and the top vertex's (n-1)(n-2)
-    wedges the heavy 4-cycle tier)."""
+    1070 its second round of out-neighbours per thread, 1100 the
+    global-bitmap tier beyond it, and the top vertex's (n-1)(n-2) wedges the
+    heavy 4-cycle tier)."""
     g = graphgen.clique(n)
     say(f"clique n={n}")
     off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
@@ -525,3 +526,76 @@ def test_k2b_32bit_window_counters(fg):
     say(f"c4 tiers {st['c4_tier_vertices']}")
     assert st["c4_tier_vertices"][3] >= 1
     np.testing.assert_array_equal(out.cpu().numpy(), k2b_net(b))
+
+
+# ------------------------------------------------------------------ asynchronous calls
+
+def test_raw_async_graph_capture(fg):
+    """fglt_raw without FGLT_VALIDATE or statistics waits for nothing, so it
+    can be captured into a HIP graph on a non-default stream (the second
+    stream of the 4-cycle pass forks and joins inside the capture); every
+    replay, with eager work and synchronizations between, equals the oracle.
+    Chung-Lu 20k (window tier included) and the ER workload."""
+    cases = []
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    cases.append(oracle.canonical_csr(g.n, g.src, g.dst))
+    g = graphgen.erdos_renyi(2000, 0.005, seed=1)
+    cases.append(oracle.canonical_csr(g.n, g.src, g.dst))
+    for off, idx in cases:
+        n = off.size - 1
+        say(f"graph capture of fglt_raw n={n} nnz={idx.size}")
+        exp = oracle.net(off, idx)
+        o, i = to_dev(off, idx)
+        out = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+        ws = torch.empty(fg.raw_workspace_bytes(n, idx.size), dtype=torch.uint8, device="cuda")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            fg.raw(o, i, net=True, out=out, workspace=ws, validate=False)  # warm-up: the second stream exists
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            fg.raw(o, i, net=True, out=out, workspace=ws, validate=False)
+        for rep in range(3):
+            out.fill_(-1)
+            graph.replay()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(), exp, err_msg=f"replay {rep}")
+            assert fg.raw_status(ws) == 0
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        del graph
+
+
+def test_raw_async_status_word(fg):
+    """Without FGLT_VALIDATE a malformed CSR returns FGLT_OK at once and the
+    device status word tells: an asymmetric graph, an index out of range (no
+    kernel reads beyond the arrays), a degree at 2^21; then a good graph on
+    the same workspace clears it."""
+    L = fg._lib.lib()
+    cases = [
+        ("asymmetric", np.array([0, 1, 1], np.int64), np.array([1], np.int32), -2),
+        ("index out of range", np.array([0, 1, 2], np.int64), np.array([1, 7], np.int32), -2),
+        ("offsets beyond the indices", np.array([0, 1, 5], np.int64), np.array([1, 0], np.int32), -2),
+    ]
+    k = 1 << 21
+    g = graphgen.star(k)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    cases.append(("degree 2^21", off, idx, -4))
+    ws = torch.empty(fg.raw_workspace_bytes(k + 1, idx.size), dtype=torch.uint8, device="cuda")
+    for name, off, idx, want in cases:
+        say(f"async status: {name}")
+        n = off.size - 1
+        o, i = to_dev(off, idx)
+        out = torch.empty((n, 16), dtype=torch.int64, device="cuda")
+        st = L.fglt_raw(n, idx.size, o.data_ptr(), i.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), 1,
+                        None, None, torch.cuda.current_stream().cuda_stream)
+        assert st == 0, name
+        assert fg.raw_status(ws) == want, name
+        with pytest.raises(fg.FgltError) as e:
+            fg.raw(o, i, net=True, workspace=ws)  # validated
+        assert e.value.status == want, name
+    g = graphgen.erdos_renyi(200, 0.05, seed=2)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    o, i = to_dev(off, idx)
+    out = fg.raw(o, i, net=True, workspace=ws, validate=False)
+    assert fg.raw_status(ws) == 0
+    np.testing.assert_array_equal(out.cpu().numpy(), oracle.net(off, idx))
