@@ -281,7 +281,9 @@ def serving_leg(fg, torch, pool=24, total=2000, warm=200, seed=5, budget=64 << 3
       (GpuExecutor on `streams` streams, continuous admission); graphs/s;
     * Poisson arrivals at 0.5, 0.8 and 0.95 x the saturated rate: latency from
       arrival to the completion of the request's kernels (counts resident),
-      p50/p99, and the same with the result copied to the host.
+      p50/p99, and the same with the result copied to the host; and the
+      0.5 x arrivals through a server with one stream (plain launches one
+      after another, no overlap).
     Every result is released by the client as it completes."""
     import graphgen
     from paper_2007_11111_amd.server import GpuExecutor, Server
@@ -306,8 +308,8 @@ def serving_leg(fg, torch, pool=24, total=2000, warm=200, seed=5, budget=64 << 3
             del out
         return np.array(lat)
 
-    def stream(qps, copy_out):
-        srv = Server(GpuExecutor(copy_out=copy_out), budget_bytes=budget, streams=streams)
+    def stream(qps, copy_out, nstreams=streams):
+        srv = Server(GpuExecutor(copy_out=copy_out), budget_bytes=budget, streams=nstreams)
         lat, lat_host = [], []
         lock = __import__("threading").Lock()
 
@@ -357,6 +359,8 @@ def serving_leg(fg, torch, pool=24, total=2000, warm=200, seed=5, budget=64 << 3
     res["saturated"] = sat
     rate = sat["graphs_per_s"]
     res["poisson"] = [stream(f * rate, True) for f in (0.5, 0.8, 0.95)]
+    # the same arrivals at 0.5 x through one stream: launches one after another
+    res["poisson_one_stream"] = stream(0.5 * rate, True, 1)
     res["speedup_vs_one_at_a_time"] = round(rate / res["one_at_a_time"]["graphs_per_s"], 2)
     return res
 

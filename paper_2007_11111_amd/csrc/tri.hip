@@ -652,6 +652,18 @@ __global__ void __launch_bounds__(LT) k_tri2s_lds(const i64* __restrict__ roff, 
     }
 }
 
+// |Ak & Al| over the first W words of two rows, unrolled with constant
+// indices so that Ak stays in registers (a loop bounded by W alone indexes Ak
+// at run time and moves it to scratch memory).
+template <int WM>
+__device__ __forceinline__ u32 popc_and_row(const u64 (&Ak)[WM], const u64* Al, int W) {
+    u32 c = 0;
+#pragma unroll
+    for (int z = 0; z < WM; ++z)
+        if (z < W) c += (u32)__popcll(Ak[z] & Al[z]);
+    return c;
+}
+
 // Hub tier of the clique pass (D <= hub_max <= TRI_HUB_MAX): as the LDS tier,
 // with A = B | B^T (up to 1024 x 16 words) in LDS and B itself read from the
 // workspace rows the hub triangle pass wrote (each word once, when its edges
@@ -708,8 +720,7 @@ __global__ void __launch_bounds__(HT) k_tri2s_hub(const i64* __restrict__ roff, 
             FOR_BITS(bits, bb, {
                 const int l = wa * 64 + bb;
                 const u64* Al = A + l * W;
-                u32 c = 0;
-                for (int z = 0; z < W; ++z) c += (u32)__popcll(Ak[z] & Al[z]);
+                const u32 c = popc_and_row<WM>(Ak, Al, W);
                 tk += c;
                 dk += (u32)(c3u[l] - 1);
                 if (c) atomicAdd(&t2[l], c);
