@@ -19,7 +19,8 @@ are not available here; these synthetic families stand in for them):
   scale calibrated so that the mean weight equals ``mean_degree``;
   round(sum(w) / 2) endpoint pairs drawn with probability proportional to w.
 * R-MAT: ``edge_factor * 2**scale`` pairs, one quadrant draw per bit with
-  probabilities (a, b, c, d) and no noise, then a random relabelling.
+  probabilities (a, b, c, d) and no noise, then a random relabelling (for
+  the largest sizes in independently seeded chunks, filled in parallel).
 * Barabasi-Albert: grown from a star K_{1,m}; each new vertex links to m
   distinct existing vertices chosen with probability proportional to degree.
 """
@@ -31,7 +32,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "rng_for", "EdgeList", "erdos_renyi", "chung_lu", "rmat", "barabasi_albert",
+    "rng_for", "EdgeList", "erdos_renyi", "chung_lu", "rmat", "rmat_chunked", "barabasi_albert",
     "batch_graphs", "serving_requests", "star", "clique", "cycle", "path",
 ]
 
@@ -169,6 +170,66 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
     return _el(n, src, dst, f"rmat({scale},{edge_factor})")
 
 
+_RMAT_CHUNK = 1 << 24  # pairs per independently seeded chunk of rmat_chunked
+
+
+def _rmat_chunk(args):
+    """Pairs [k * _RMAT_CHUNK, ...) of rmat_chunked into the shared arrays."""
+    from multiprocessing import shared_memory
+    k, m_pairs, scale, a, b, c, seed, shm_name, chunk = args
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        both = np.ndarray((2, m_pairs), dtype=np.int32, buffer=shm.buf)
+        s = k * chunk
+        e = min(m_pairs, s + chunk)
+        rng = rng_for(seed, 10_000 + k)
+        ss = np.zeros(e - s, dtype=np.int32)
+        dd = np.zeros(e - s, dtype=np.int32)
+        t_ab, t_abc = a + b, a + b + c
+        for bit in range(scale):
+            u = rng.random(e - s, dtype=np.float32)
+            ss |= (u >= t_ab).astype(np.int32) << bit
+            dd |= ((((u >= a) & (u < t_ab)) | (u >= t_abc)).astype(np.int32)) << bit
+        both[0, s:e] = ss
+        both[1, s:e] = dd
+    finally:
+        shm.close()
+    return k
+
+
+def rmat_chunked(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+                 workers: int = 16, chunk: int = _RMAT_CHUNK) -> EdgeList:
+    """R-MAT pairs as in ``rmat`` (the same quadrant draws, no noise), for
+    sizes where one generator stream is too slow: pair chunk k (``chunk``
+    pairs, 2^24 by default) draws from stream (seed, 10000 + k), so the result does not depend on
+    ``workers`` (processes that fill the chunks side by side); the ids are
+    then relabelled by a uniform random permutation from stream (seed, 9999).
+    """
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    n = 1 << scale
+    m_pairs = edge_factor * n
+    shm = shared_memory.SharedMemory(create=True, size=2 * 4 * m_pairs)
+    try:
+        both = np.ndarray((2, m_pairs), dtype=np.int32, buffer=shm.buf)
+        jobs = [(k, m_pairs, scale, a, b, c, seed, shm.name, chunk) for k in range((m_pairs + chunk - 1) // chunk)]
+        if workers > 1:
+            with mp.get_context("fork").Pool(workers) as pool:
+                for _ in pool.imap_unordered(_rmat_chunk, jobs):
+                    pass
+        else:
+            for j in jobs:
+                _rmat_chunk(j)
+        perm = rng_for(seed, 9_999).permutation(n).astype(np.int32)
+        src = perm[both[0]]
+        dst = perm[both[1]]
+        del both
+    finally:
+        shm.close()
+        shm.unlink()
+    return _el(n, src, dst, f"rmat_chunked({scale},{edge_factor})")
+
+
 def barabasi_albert(n: int, m: int, seed: int, stream: int = 0) -> EdgeList:
     """Barabasi-Albert graph grown from the star K_{1,m} (vertices 0..m).
 
@@ -286,6 +347,9 @@ def make(name: str):
     rmat18   the same recipe at scale 18 (a size the oracle finishes in minutes)
     cl_small Chung-Lu, n = 100,000, exponent 2.1, mean 20, cap 5,000
     batch    4096 graphs, n ~ U{16..512}, half ER (mean degree U[2,12]), half BA (m U{1..5})
+    rmat26   R-MAT scale 26, edge factor 27, (0.57, 0.19, 0.19, 0.05), ids permuted, chunked
+             streams: about 1.8e9 pairs on 67M vertices, the size of the paper's Friendster run
+    rmat20c  the chunked recipe at scale 20 (tests of the chunked generator)
     """
     if name == "er":
         return erdos_renyi(2000, 0.005, seed=1)
@@ -299,4 +363,8 @@ def make(name: str):
         return rmat(18, 16, 0.57, 0.19, 0.19, seed=3, stream=1)
     if name == "batch":
         return batch_graphs(4096, seed=4)
+    if name == "rmat26":
+        return rmat_chunked(26, 27, 0.57, 0.19, 0.19, seed=6)
+    if name == "rmat20c":
+        return rmat_chunked(20, 27, 0.57, 0.19, 0.19, seed=6)
     raise KeyError(name)

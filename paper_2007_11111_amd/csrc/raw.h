@@ -26,7 +26,7 @@ static_assert((TRI_HUB_MAX - 1) * (TRI_HUB_MAX - 2) / 2 < (1 << EK_SHIFT), "hub 
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
-constexpr int NUM_TRI_SLOTS = 64;    // workgroups of the global-bitmap clique tier
+constexpr int NUM_TRI_SLOTS = 64;    // at most this many workgroups in the global-bitmap clique tier
 constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
 
@@ -95,8 +95,9 @@ struct RawWs {
     i32* tri_list;  // [3][n]
     i32* c4_list;   // [4][n]
     // heavy-tier scratch
-    u64* tri_slots;     // NUM_TRI_SLOTS * tri_slot_words
+    u64* tri_slots;     // tri_nslots * tri_slot_words
     i64 tri_slot_words;
+    int tri_nslots;     // slots (and workgroups) of the global-bitmap tier, 1..NUM_TRI_SLOTS
     i64* c4_segoff;     // [2] one segment over the window-tier list
     i64* c4_jobcnt;     // [n+1] jobs per window-tier vertex, then the prefix of their middle counts
     i64* c4_jobpre;     // [n+1] their exclusive scan

@@ -542,7 +542,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
     // the last tier's bound: vertices of out-degree above the LDS tier's
-    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>({n, nnz / (2 * TRI_LDS_MAX) + 1, NUM_TRI_SLOTS}));
+    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>({n, nnz / (2 * TRI_LDS_MAX) + 1, (i64)w.tri_nslots}));
     hipError_t e;
     if (mode == 1) {
         // triangle pass; the wave, LDS and hub tiers also store their N+ bitmaps

@@ -433,16 +433,18 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.tri_list = c.take<i32>(3 * nn);
     w.c4_list = c.take<i32>(4 * nn);
     // out-degree under the degree ordering is at most sqrt(nnz): two bitmaps
-    // of D x ceil(D/64) words plus per-row lists fit in tri_slot_words.
+    // of D x ceil(D/64) words plus per-row lists fit in tri_slot_words.  The
+    // global-bitmap tier (out-degree above the hub tier's) has as many slots,
+    // and workgroups, as fit max(1 GiB, 2 bytes per entry), from 1 to 64.
     i64 dmax_plus = 1;
     while (dmax_plus * dmax_plus <= nnz) ++dmax_plus;
     const i64 words_per_row = ceil_div(dmax_plus, 64);
     w.tri_slot_words = 2 * dmax_plus * words_per_row + 4 * dmax_plus + 64;
-    w.tri_slots = c.take<u64>(NUM_TRI_SLOTS * w.tri_slot_words);
+    w.tri_nslots = (int)std::max<i64>(
+        1, std::min<i64>(NUM_TRI_SLOTS, std::max<i64>((i64)1 << 30, 2 * nnz) / (8 * w.tri_slot_words)));
+    w.tri_slots = c.take<u64>(w.tri_nslots * w.tri_slot_words);
     w.bcnt = c.take<i64>(nn);
     w.boff = c.take<i64>(nn + 1);
-    w.bstore_cap = std::max<i64>(3 * nnz, 64);
-    w.bstore = c.take<u64>(w.bstore_cap);
     w.c4_segoff = c.take<i64>(2);
     w.c4_jobcnt = c.take<i64>(nn + 1);
     w.c4_jobpre = c.take<i64>(nn + 1);
@@ -470,6 +472,16 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.sort.lists = c.take<i32>(3 * (nn + 2));
     w.sort.counters = c.take<u32>(4);
     w.rx_hist = c.take<i64>(radix_hist_size(std::max(nnz, nn)));
+    // the stored bitmaps last: at least 3 words per entry (1 beyond 2^31
+    // entries), and whatever a larger workspace holds beyond the rest (the
+    // clique pass reads stored bitmaps only when all of them fit)
+    {
+        const i64 min_words = std::max<i64>(nnz < ((i64)1 << 31) ? 3 * nnz : nnz, 64);
+        i64 words = min_words;
+        if (c.base && c.cap > c.used + 512) words = std::max<i64>(min_words, (i64)((c.cap - c.used - 512) / 8));
+        w.bstore_cap = words;
+        w.bstore = c.take<u64>(words);
+    }
     return w;
 }
 
