@@ -349,7 +349,8 @@ def make(name: str):
     batch    4096 graphs, n ~ U{16..512}, half ER (mean degree U[2,12]), half BA (m U{1..5})
     rmat26   R-MAT scale 26, edge factor 27, (0.57, 0.19, 0.19, 0.05), ids permuted, chunked
              streams: about 1.8e9 pairs on 67M vertices, the size of the paper's Friendster run
-    rmat20c  the chunked recipe at scale 20 (tests of the chunked generator)
+    rmatSc   the chunked recipe at scale S (edge factor 27), e.g. rmat22c .. rmat25c: the
+             steps up to the scale-26 run
     """
     if name == "er":
         return erdos_renyi(2000, 0.005, seed=1)
@@ -365,6 +366,6 @@ def make(name: str):
         return batch_graphs(4096, seed=4)
     if name == "rmat26":
         return rmat_chunked(26, 27, 0.57, 0.19, 0.19, seed=6)
-    if name == "rmat20c":
-        return rmat_chunked(20, 27, 0.57, 0.19, 0.19, seed=6)
+    if name.startswith("rmat") and name.endswith("c") and name[4:-1].isdigit():
+        return rmat_chunked(int(name[4:-1]), 27, 0.57, 0.19, 0.19, seed=6)
     raise KeyError(name)

@@ -7,7 +7,8 @@ binding never import, link or call it, and it shares no code with them.
 Contents
 --------
 * ``canonical_csr`` -- the plain definition of a simple undirected graph's
-  adjacency (symmetrise, drop self-loops, drop duplicates, sort rows), in numpy.
+  adjacency (symmetrise, drop self-loops, drop duplicates, sort rows), in numpy;
+  ``canonical_csr_large`` the same in C with OpenMP, for billions of pairs.
 * ``raw`` / ``net`` / ``raw_to_net`` -- ctypes front end of ``fglt_oracle.c``,
   the per-vertex evaluation of Table I and the back-substitution with Table II.
 * ``bruteforce`` (module) -- enumeration of every vertex subset of size <= 4,
@@ -61,6 +62,8 @@ def _load():
             lib.oracle_raw_to_net.restype = None
             lib.oracle_u16.argtypes = [p64]
             lib.oracle_u16.restype = None
+            lib.oracle_canonical_csr.argtypes = [ctypes.c_int64, ctypes.c_int64, p32, p32, p64, p32, ctypes.c_int]
+            lib.oracle_canonical_csr.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -94,6 +97,28 @@ def canonical_csr(n: int, src, dst):
     if n:
         np.cumsum(np.bincount(rows, minlength=n), out=offsets[1:])
     return offsets, cols.astype(np.int32)
+
+
+def canonical_csr_large(n: int, src, dst, threads: int = 0):
+    """``canonical_csr`` for graphs of billions of pairs: the same definition
+    by the C routine (rows filled in parallel, then sorted and deduplicated
+    row by row), with int32 ids.  Returns (offsets int64[n+1], indices
+    int32[nnz]); the indices are a view of a 2m-entry buffer."""
+    n = int(n)
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    if s.shape != d.shape:
+        raise ValueError("src and dst differ in length")
+    off = np.zeros(n + 1, dtype=np.int64)
+    idx = np.empty(max(2 * s.size, 1), dtype=np.int32)
+    st = _load().oracle_canonical_csr(n, s.size, _p32(s) if s.size else _p32(np.zeros(1, np.int32)),
+                                      _p32(d) if d.size else _p32(np.zeros(1, np.int32)), _p64(off), _p32(idx),
+                                      int(threads))
+    if st == -3:
+        raise ValueError("vertex id out of range")
+    if st != 0:
+        raise RuntimeError(f"oracle_canonical_csr failed with status {st}")
+    return off, idx[:off[-1]]
 
 
 def max_threads() -> int:

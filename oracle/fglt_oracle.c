@@ -354,6 +354,85 @@ int oracle_net(i64 n, const i64* off, const i32* idx, i64 nsel, const i64* sel,
     return st;
 }
 
+/* ------------------------------------------------------------------ graph */
+
+static int cmp_i32(const void* a, const void* b) {
+    const i32 x = *(const i32*)a, y = *(const i32*)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * The adjacency of the simple undirected graph on n vertices spanned by the
+ * m pairs (src[t], dst[t]) (Section I's graph model): both directions of each
+ * pair, self-loops and duplicates dropped, rows sorted.  The definition, in
+ * three plain steps for sizes where the numpy route is too slow: every entry
+ * is placed in its row, each row is sorted and its repeats are dropped, then
+ * the rows are packed.  off (n + 1 entries) and idx (2 m entries, of which
+ * off[n] are used) are the caller's.  Returns 0, or -3 for an id outside
+ * [0, n), -1 on memory exhaustion.
+ */
+int oracle_canonical_csr(i64 n, i64 m, const i32* src, const i32* dst, i64* off, i32* idx, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int status = 0;
+#pragma omp parallel for schedule(static)
+    for (i64 t = 0; t < m; ++t)
+        if (src[t] < 0 || src[t] >= n || dst[t] < 0 || dst[t] >= n) {
+#pragma omp atomic write
+            status = -3;
+        }
+    if (status) return status;
+    i64* fill = (i64*)calloc((size_t)(n + 1), sizeof(i64));
+    if (!fill) return -1;
+    /* entries per row, both directions, no self-loops */
+#pragma omp parallel for schedule(static)
+    for (i64 t = 0; t < m; ++t) {
+        if (src[t] == dst[t]) continue;
+#pragma omp atomic
+        fill[src[t]] += 1;
+#pragma omp atomic
+        fill[dst[t]] += 1;
+    }
+    off[0] = 0;
+    for (i64 i = 0; i < n; ++i) off[i + 1] = off[i] + fill[i];
+    for (i64 i = 0; i < n; ++i) fill[i] = off[i];
+    /* every entry into its row (in no particular order within the row) */
+#pragma omp parallel for schedule(static)
+    for (i64 t = 0; t < m; ++t) {
+        if (src[t] == dst[t]) continue;
+        i64 a, b;
+#pragma omp atomic capture
+        a = fill[src[t]]++;
+#pragma omp atomic capture
+        b = fill[dst[t]]++;
+        idx[a] = dst[t];
+        idx[b] = src[t];
+    }
+    /* sort each row and drop its repeats; fill[i] = the row's distinct count */
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (i64 i = 0; i < n; ++i) {
+        i32* r = idx + off[i];
+        const i64 len = off[i + 1] - off[i];
+        qsort(r, (size_t)len, sizeof(i32), cmp_i32);
+        i64 k = 0;
+        for (i64 q = 0; q < len; ++q)
+            if (k == 0 || r[q] != r[k - 1]) r[k++] = r[q];
+        fill[i] = k;
+    }
+    /* pack the rows to the front, in row order */
+    i64 pos = 0;
+    for (i64 i = 0; i < n; ++i) {
+        const i64 b = off[i], k = fill[i];
+        off[i] = pos;
+        if (pos != b) memmove(idx + pos, idx + b, sizeof(i32) * (size_t)k);
+        pos += k;
+    }
+    off[n] = pos;
+    free(fill);
+    return 0;
+}
+
 /* Number of threads OpenMP will use by default. */
 int oracle_max_threads(void) {
 #ifdef _OPENMP

@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const i32* __restrict__ hs_all, const DevPlan* __restrict__ plan,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
                                                           u32* __restrict__ scr, i64 scr_cap, int etab_mode,
-                                                          i64* __restrict__ c4v) {
+                                                          i64* __restrict__ esum, i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
     // the part of the window list this launch takes (16-bit counters: the
     // first ranks, 32-bit: the last), and its first window, from the device plan
@@ -702,8 +702,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             prefetched = false;
             for (i32 ch = 0; ch < nch; ++ch) {
                 MS* const ms = msum + (ch % NMS) * CB_THREADS;
-                i32 fv = 0;  // the flush's middle, loaded before the chunk's wedges
-                if (!single && ch * CB_THREADS + (i32)threadIdx.x < L) fv = ridx[b + ch * CB_THREADS + threadIdx.x];
                 bool streamed = false;
                 if constexpr (PACK16) {  // only 16-bit counters keep a scratch copy
                     if ((stored >> ch) & 1ull) {
@@ -717,11 +715,15 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                               [&](i32 w) { return c4w_get<PACK16>(cnt, w - W0); });
                 }
                 if (!single) {
+                    // the chunk's middle sums go to their N- entries of u:
+                    // consecutive words, so a wavefront's atomics share a few
+                    // cache lines; every window of u adds to the same entries,
+                    // and k_c4_esum_flush moves them to the middles at the end
                     __syncthreads();
                     const i32 k = ch * CB_THREADS + (i32)threadIdx.x;
                     if (k < L) {
                         const i64 m = ms[threadIdx.x];
-                        if (m) atomicAdd((unsigned long long*)&c4v[fv], (unsigned long long)m);
+                        if (m) atomicAdd((unsigned long long*)&esum[b + k], (unsigned long long)m);
                         ms[threadIdx.x] = 0;
                     }
                 }
@@ -810,6 +812,19 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             }
         }
         __syncthreads();
+    }
+}
+
+// The middle sums that the window kernels left per N- entry (vertices whose
+// middles span several chunks, one job per window) go to the middles: one
+// streaming pass over the entries, an atomic for each non-zero sum.
+__global__ void k_c4_esum_flush(const i32* __restrict__ ridx, const i64* __restrict__ esum, i64 nnz,
+                                i64* __restrict__ c4v, const DevPlan* __restrict__ plan) {
+    FGLT_GATE(&plan->err);
+    if (plan->n_c4[3] == 0) return;
+    for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (i64)gridDim.x * blockDim.x) {
+        const i64 m = esum[q];
+        if (m) atomicAdd((unsigned long long*)&c4v[ridx[q]], (unsigned long long)m);
     }
 }
 
@@ -1047,15 +1062,25 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
     const i32* const tab = reinterpret_cast<const i32*>(w.c4_tab);
     const DevPlan* const plan = w.plan;
     const unsigned grid = C4W_GRID;  // one workgroup per CU; each owns a scratch slice
+    // per-entry middle sums of the multi-chunk jobs (the clique pass's
+    // per-entry counts are dead once the row pass has read them)
+    if (nnz > 0) {
+        hipError_t e = fill_u32(reinterpret_cast<u32*>(w.ek), 2 * nnz, 0u, s);
+        if (e != hipSuccess) return e;
+    }
 #define C4W_LAUNCH(P16, TM, PRE, CTR, EM)                                                                          \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM, w.c4v)
+                       w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM, w.ek,   \
+                       w.c4v)
     // the per-entry table where it fits (decided on the device), else the vertex table
     if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2);
     if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0);
     else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0);
     C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
 #undef C4W_LAUNCH
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_c4_esum_flush, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, w.ridx,
+                           (const i64*)w.ek, nnz, w.c4v, plan);
     return hipGetLastError();
 }
 

@@ -474,9 +474,14 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.rx_hist = c.take<i64>(radix_hist_size(std::max(nnz, nn)));
     // the stored bitmaps last: at least 3 words per entry (1 beyond 2^31
     // entries), and whatever a larger workspace holds beyond the rest (the
-    // clique pass reads stored bitmaps only when all of them fit)
+    // clique pass reads stored bitmaps only when all of them fit).  The
+    // window tier's per-entry table reuses this memory: when the vertex table
+    // is there and a bound on the per-entry table, (nnz / 2) (n / 65536 + 2)
+    // 16-bit entries, stays within 80 bytes per entry, the memory holds it.
     {
-        const i64 min_words = std::max<i64>(nnz < ((i64)1 << 31) ? 3 * nnz : nnz, 64);
+        i64 min_words = std::max<i64>(nnz < ((i64)1 << 31) ? 3 * nnz : nnz, 64);
+        const i64 etab_bound = (nnz / 2) * ((nn + C4W_SPAN - 1) / C4W_SPAN + 2);
+        if (w.c4_tab_cap && 2 * etab_bound <= 80 * nnz) min_words = std::max(min_words, ceil_div(etab_bound, 4));
         i64 words = min_words;
         if (c.base && c.cap > c.used + 512) words = std::max<i64>(min_words, (i64)((c.cap - c.used - 512) / 8));
         w.bstore_cap = words;

@@ -291,6 +291,24 @@ def test_canonical_csr_definition():
     np.testing.assert_array_equal(idx, [1, 3, 0, 3, 0, 2])
     with pytest.raises(ValueError):
         oracle.canonical_csr(3, np.array([0]), np.array([3]))
+    off2, idx2 = oracle.canonical_csr_large(5, src, dst)
+    np.testing.assert_array_equal(off2, [0, 2, 3, 4, 6, 6])
+    np.testing.assert_array_equal(idx2, [1, 3, 0, 3, 0, 2])
+    with pytest.raises(ValueError):
+        oracle.canonical_csr_large(3, np.array([0]), np.array([3]))
+
+
+@pytest.mark.parametrize("n,m", [(1, 0), (7, 0), (10, 60), (2000, 30000), (50000, 200000)])
+def test_canonical_csr_large_matches_numpy(n, m):
+    """The C route for billion-pair graphs against the numpy definition, with
+    self-loops and repeated pairs in the input."""
+    rng = np.random.default_rng(n + m)
+    src = rng.integers(0, n, m)
+    dst = np.where(rng.random(m) < 0.05, src, rng.integers(0, n, m))
+    a = oracle.canonical_csr(n, src, dst)
+    b = oracle.canonical_csr_large(n, src, dst, threads=4)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
 
 
 # ---------------------------------------------------------------- graph-level totals
