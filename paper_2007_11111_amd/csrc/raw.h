@@ -26,6 +26,7 @@ static_assert((TRI_HUB_MAX - 1) * (TRI_HUB_MAX - 2) / 2 < (1 << EK_SHIFT), "hub 
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
+constexpr int TRI_MID_D = 4096;      // global-bitmap clique tier: out-degree of its many-slot launch
 constexpr int NUM_TRI_SLOTS = 64;    // at most this many workgroups in the global-bitmap clique tier
 constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)

@@ -14,6 +14,7 @@
 //   FINALIZE:       Table I assembled per vertex, Table II back-substitution,
 //                   rows scattered back to the caller's vertex order
 #include <algorithm>
+#include <climits>
 
 #include "walk.h"
 
@@ -263,18 +264,22 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
 
 // Workgroup tiers: out-degree D > 64.  GLOBAL = false keeps bitmaps and lists
 // in LDS (D <= TRI_LDS_MAX); GLOBAL = true keeps them in a per-block slot of
-// device memory (any D up to sqrt(nnz)).
+// device memory (any D up to sqrt(nnz)) of slot_words words: 4 D + 64 for the
+// lists alone (MODE 1), 2 D ceil(D / 64) more for the bitmaps (MODE 2).  A
+// launch takes the list's vertices with dmin < D <= dmax (dmin_nostore in
+// place of dmin for the clique pass when the hub tier stored no bitmaps).
 template <int MODE, bool GLOBAL>
 __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                   const i32* __restrict__ lo, const i32* __restrict__ rdeg,
                                                   const i64* __restrict__ G, const i32* __restrict__ list,
-                                                  const u32* __restrict__ countp, i64 dmin, i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                  const u32* __restrict__ countp, i64 dmin, i64 dmax, i64 dmin_nostore,
+                                                  i32* __restrict__ C3, i64* __restrict__ k4v,
                                                   i64* __restrict__ d13, u64* __restrict__ slots, i64 slot_words,
                                                   DevPlan* plan,
     const u32* __restrict__ storep) {
     // the clique pass from stored bitmaps has counted instead (stored, device flag)
     if (MODE == 2 && !GLOBAL && storep && *storep) return;
-    if (MODE == 2 && GLOBAL && storep && !*storep) dmin = 0;  // nothing stored: every vertex of the tier here
+    if (MODE == 2 && GLOBAL && storep && !*storep) dmin = dmin_nostore;  // nothing stored: the hub tier's vertices too
     const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
@@ -291,7 +296,7 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         const i64 u = list[it];
         const i64 bu = roff[u] + lo[u];
         const int D = (int)(roff[u + 1] - bu);
-        if (D <= dmin) continue;  // the hub tier takes it (uniform over the block)
+        if (D <= dmin || D > dmax) continue;  // another tier or launch takes it (uniform over the block)
         const int W = (D + 63) / 64;
         const i64 gb = G[bu];
         const i64 T = G[bu + D] - gb;
@@ -299,10 +304,11 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
         i64* Bv;
         u64 *B, *C;
         if (GLOBAL) {
+            // the triangle pass needs no bitmaps: its slot holds the lists alone
             u64* sl = slots + (i64)blockIdx.x * slot_words;
             B = sl;
-            C = sl + (i64)D * W;
-            u64* rest = C + (i64)D * W;
+            C = sl + (BITS ? (i64)D * W : 0);
+            u64* rest = BITS ? C + (i64)D * W : sl;
             Bv = (i64*)rest;
             L = (i32*)(rest + D);
             Pre = L + D;               // D + 1 entries
@@ -541,8 +547,22 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
     const i32* l0 = w.tri_list;
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
-    // the last tier's bound: vertices of out-degree above the LDS tier's
-    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>({n, nnz / (2 * TRI_LDS_MAX) + 1, (i64)w.tri_nslots}));
+    // the last tier's bound: vertices of out-degree above the LDS tier's.  The
+    // global-bitmap slots' memory is shared out by the largest out-degree a
+    // launch takes: the triangle pass's lists alone (up to 2048 workgroups),
+    // and for the clique pass the bitmaps of out-degree up to TRI_MID_D
+    // (many slots), then the rest (slots for the largest out-degree)
+    const i64 region = (i64)w.tri_nslots * w.tri_slot_words;
+    i64 dplus = 1;  // above every out-degree (the degree order keeps them below sqrt(nnz))
+    while (dplus * dplus <= nnz) ++dplus;
+    const i64 tier_bound = std::min<i64>(n, nnz / (2 * TRI_LDS_MAX) + 1);
+    auto slots_for = [&](i64 words, i64 cap) {
+        return (unsigned)std::max<i64>(1, std::min<i64>({tier_bound, region / words, cap}));
+    };
+    const i64 w_list = 4 * dplus + 64;
+    const i64 d_mid = std::min<i64>(TRI_MID_D, dplus);
+    const i64 w_mid = 2 * d_mid * ceil_div(d_mid, 64) + 4 * d_mid + 64;
+    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>(tier_bound, (i64)w.tri_nslots));
     hipError_t e;
     if (mode == 1) {
         // triangle pass; the wave, LDS and hub tiers also store their N+ bitmaps
@@ -552,9 +572,9 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         if ((e = launch_tri1_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
         if ((e = launch_tri1_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tri_block<1, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l2,
-                           cnt + 2, hub_max, w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan,
-                           (const u32*)nullptr);
+        hipLaunchKernelGGL((k_tri_block<1, true>), dim3(slots_for(w_list, 2048)), dim3(PT), 0, s, w.roff, w.ridx,
+                           w.lo, w.rdeg, w.G, l2, cnt + 2, hub_max, (i64)INT_MAX, hub_max, w.C3, w.k4v, w.d13,
+                           w.tri_slots, w_list, w.plan, (const u32*)nullptr);
     } else {
         // clique and diamond pass: from the stored bitmaps, or by scanning
         // again (the stored flag is read on the device; each kernel of the
@@ -567,14 +587,19 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         if ((e = launch_tri2_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
         hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(std::min<i64>(n, nnz / (2 * TRI_WAVE_MAX) + 1), 1,
                                                                    65536)),
-                           dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l1, cnt + 1, (i64)0, w.C3, w.k4v, w.d13,
-                           w.tri_slots, w.tri_slot_words, w.plan, stp);
+                           dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l1, cnt + 1, (i64)0, (i64)INT_MAX, (i64)0,
+                           w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
         tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
         // the hub tier from its stored rows; the rest of the last tier (all of
         // it when nothing is stored) with bitmaps in the workspace
         if ((e = launch_tri2_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tri_block<2, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l2,
-                           cnt + 2, hub_max, w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
+        hipLaunchKernelGGL((k_tri_block<2, true>), dim3(slots_for(w_mid, 1024)), dim3(PT), 0, s, w.roff, w.ridx,
+                           w.lo, w.rdeg, w.G, l2, cnt + 2, hub_max, d_mid, (i64)0, w.C3, w.k4v, w.d13, w.tri_slots,
+                           w_mid, w.plan, stp);
+        if (dplus > d_mid)
+            hipLaunchKernelGGL((k_tri_block<2, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G,
+                               l2, cnt + 2, std::max<i64>(hub_max, d_mid), (i64)INT_MAX, std::max<i64>(hub_max, d_mid),
+                               w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
     }
     return hipGetLastError();
 }

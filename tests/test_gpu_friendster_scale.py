@@ -7,7 +7,8 @@ the chunked R-MAT recipe at scale S (26 for the full size; smaller scales are
 the steps up to it), and FGLT_FRIENDSTER_SIGMAS lists the sub-dictionary masks
 to run (default 0x1f, Theorem 1's Sigma_5).  For each mask: fglt_build_csr on
 the device against the oracle's canonical CSR (C route, every entry), the
-transform timed with HIP events, whole-graph invariants of the net counts, and
+transform timed with HIP events (one call, with per-segment events),
+whole-graph invariants of the net counts, and
 a degree-stratified vertex sample recomputed by the oracle (vertices whose
 two-hop oracle cost stays bounded).  FGLT_FRIENDSTER_OUT names a JSON file for
 the measured figures.
@@ -99,31 +100,37 @@ def test_friendster_scale_sigma(fg):
     for mask in masks:
         cols = oracle.subdict_columns(mask)
         out = torch.empty((n, len(cols)), dtype=torch.int64, device="cuda")
-        say(f"friendster-scale: transform sigma={hex(mask)} (validated)")
-        fg.raw(off, idx, net=True, out=out, workspace=ws, sigma=mask)
-        torch.cuda.synchronize()
-        say(f"friendster-scale: transform sigma={hex(mask)} timed")
+        say(f"friendster-scale: transform sigma={hex(mask)}")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        fg.raw(off, idx, net=True, out=out, workspace=ws, sigma=mask, validate=False)
+        _, st = fg.raw(off, idx, net=True, out=out, workspace=ws, sigma=mask, stats=True, timing=True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         assert fg.raw_status(ws) == 0
         f = out.cpu().numpy()
-        say(f"friendster-scale: sigma={hex(mask)} {ms:.1f} ms; checks")
+        say(f"friendster-scale: sigma={hex(mask)} {ms:.1f} ms; segments "
+            + json.dumps({k: round(v, 1) for k, v in st["seg_ms"].items() if v >= 0.05}))
+        say(f"friendster-scale: tiers tri {list(st['tri_tier_vertices'])} c4 {list(st['c4_tier_vertices'])}; checks")
         # the oracle's sample, through the same sub-dictionary
         np.testing.assert_array_equal(f[sel], oracle.subdict(raw_o, mask))
-        # whole-graph invariants of the net counts that every run has
+        # whole-graph invariants of the net counts that every run has; a
+        # column is an induced count (so never negative) when its row of
+        # U16^-1 stays inside s
         S = f.sum(0)
         c = {k: i for i, k in enumerate(cols)}
-        assert (f[:, c[0]] == 1).all() and (f >= 0).all()
+        uinv = np.rint(np.linalg.inv(oracle.U16().astype(np.float64))).astype(np.int64)
+        closed = [c[k] for k in cols if set(np.nonzero(uinv[k])[0]) <= set(cols)]
+        assert (f[:, c[0]] == 1).all() and (f[:, closed] >= 0).all()
         np.testing.assert_array_equal(f[:, c[1]], deg)
         if 2 in c and 3 in c:
             assert S[c[2]] == 2 * S[c[3]]
         if 4 in c:
             assert S[c[4]] % 3 == 0
         report["sigmas"][hex(mask)] = {"ms": round(ms, 1), "edges_per_s": round((nnz // 2) / (ms / 1e3), 1),
+                                       "seg_ms": {k: round(v, 2) for k, v in st["seg_ms"].items()},
+                                       "tri_tier_vertices": st["tri_tier_vertices"],
+                                       "c4_tier_vertices": st["c4_tier_vertices"],
                                        "column_sums": [int(x) for x in S]}
         del out
     path = os.environ.get("FGLT_FRIENDSTER_OUT")
