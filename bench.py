@@ -131,6 +131,111 @@ def load_traffic(seg, workload):
     return max(v["bytes_per_launch"] for v in hits) if hits else None
 
 
+# rocprofv3 counter passes behind profiles/traffic.json (one --pmc run each;
+# the TCC block collects at most four counters per pass).
+PMC_PASSES = {
+    "A": ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum"],
+    "B": ["TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_RDREQ_DRAM_32B_sum", "TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum"],
+    "C": ["TCC_EA0_WRREQ_DRAM_sum", "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", "TCC_EA0_WRREQ_ATOMIC_DRAM_sum",
+          "TCC_EA0_WRREQ_ATOMIC_DRAM_32B_sum"],
+    "D": ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_INSTS_VALU", "SQ_INSTS_LDS",
+          "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE"],
+}
+
+
+def _pmc_db(path):
+    """Per-kernel counter sums and dispatch counts from one rocprofv3 database."""
+    import re
+    import sqlite3
+    sums, disp = {}, {}
+    db = sqlite3.connect(path)
+    for name, ctr, val, did in db.execute(
+            "select kernel_name, counter_name, value, dispatch_id from counters_collection"):
+        k = re.sub(r"\(.*", "", name).replace("void ", "").replace("fglt::", "")
+        sums.setdefault(k, {})
+        sums[k][ctr] = sums[k].get(ctr, 0.0) + float(val)
+        disp.setdefault(k, set()).add(did)
+    db.close()
+    return sums, {k: len(v) for k, v in disp.items()}
+
+
+def write_traffic(prof_dir, command):
+    """profiles/traffic.json (and a markdown summary per workload) from the
+    counter passes under prof_dir: <part>_<pass>/run_results.db for the parts
+    copy (a plain 1 GiB device copy), rmat22, cl and batch.  HBM bytes: the
+    DRAM-side read and write request counters (TCC_EA0_RDREQ_DRAM_32B,
+    TCC_EA0_WRREQ_WRITE_DRAM_32B), each scaled by what the same counter reads
+    for the copy of known size; DRAM atomics are reported apart (32-byte
+    units).  L2-miss (EA) read bytes by request size from pass A."""
+    copy_bytes = 1 << 30
+    cal = {}
+    for p in ("A", "B", "C"):
+        sums, _ = _pmc_db(os.path.join(prof_dir, f"copy_{p}", "run_results.db"))
+        cp = [v for k, v in sums.items() if "copyBuffer" in k or "copy" in k.lower()]
+        if cp:
+            cal.update(cp[0])
+    scale_rd = copy_bytes / cal["TCC_EA0_RDREQ_DRAM_32B_sum"]
+    scale_wr = copy_bytes / cal["TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]
+    out = {"source_sha256": source_hash(), "command": command, "counters": PMC_PASSES,
+           "calibration": {"copy_bytes": copy_bytes,
+                           "copy_counters": {k: cal[k] for k in sorted(cal)},
+                           "dram_read_bytes_per_unit": scale_rd, "dram_write_bytes_per_unit": scale_wr},
+           "workloads": {}}
+    names = {"rmat22": "R-MAT scale 22 (edge factor 16)", "cl": "Chung-Lu n = 10^6",
+             "batch": "batch of 4096 small graphs"}
+    for wl in ("rmat22", "cl", "batch"):
+        if not os.path.exists(os.path.join(prof_dir, f"{wl}_A", "run_results.db")):
+            continue
+        ks, launches = {}, {}
+        for p in ("A", "B", "C", "D"):
+            sums, disp = _pmc_db(os.path.join(prof_dir, f"{wl}_{p}", "run_results.db"))
+            for k, v in sums.items():
+                ks.setdefault(k, {}).update(v)
+                launches[k] = max(launches.get(k, 0), disp[k])
+        kern = {}
+        for k, v in ks.items():
+            nl = launches[k]
+            g = lambda c: v.get(c, 0.0) / nl
+            rd = g("TCC_EA0_RDREQ_DRAM_32B_sum") * scale_rd
+            wr = g("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum") * scale_wr
+            ea_rd = 32 * g("TCC_EA0_RDREQ_32B_sum") + 64 * g("TCC_EA0_RDREQ_64B_sum") + 128 * g("TCC_EA0_RDREQ_128B_sum")
+            e = {"launches": nl, "dram_read_bytes": round(rd), "dram_write_bytes": round(wr),
+                 "dram_atomic_bytes": round(32 * g("TCC_EA0_WRREQ_ATOMIC_DRAM_32B_sum")),
+                 "dram_atomics": round(g("TCC_EA0_WRREQ_ATOMIC_DRAM_sum")),
+                 "ea_read_bytes": round(ea_rd), "bytes_per_launch": round(rd + wr)}
+            sq = {c: g(c) for c in PMC_PASSES["D"] if c in v}
+            if sq.get("SQ_WAVE_CYCLES"):
+                e["wait_any_frac"] = round(sq["SQ_WAIT_ANY"] / sq["SQ_WAVE_CYCLES"], 3)
+            if sq.get("SQ_LDS_IDX_ACTIVE"):
+                e["lds_conflict_frac"] = round(sq["SQ_LDS_BANK_CONFLICT"] / sq["SQ_LDS_IDX_ACTIVE"], 3)
+            e["valu_insts"] = round(sq.get("SQ_INSTS_VALU", 0.0))
+            kern[k] = e
+        out["workloads"][wl] = {"name": names[wl], "kernels": kern}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    for wl, d in out["workloads"].items():
+        rows = sorted(d["kernels"].items(), key=lambda kv: -kv[1]["bytes_per_launch"])
+        lines = [f"# HBM traffic and SQ counters per kernel: {d['name']}, one MI355X", "",
+                 "Counter passes (rocprofv3 --pmc, one pass per run; commands below), values per launch",
+                 "(the mean over the launches of the run).  HBM bytes are the DRAM-side request counters",
+                 "TCC_EA0_RDREQ_DRAM_32B and TCC_EA0_WRREQ_WRITE_DRAM_32B, each scaled by what it reads for a",
+                 f"plain 1 GiB device copy ({scale_rd:.3f} and {scale_wr:.3f} bytes per unit); atomics executed",
+                 "at the memory side are listed apart.  EA read bytes: L2-miss reads by request size (32, 64,",
+                 "128 B), which also count reads served by the memory-side cache.", "",
+                 "Commands (from /tmp with TMPDIR=/tmp):", "", f"    {command}", "",
+                 "| kernel | launches | HBM read B | HBM write B | atomics at DRAM | EA read B | wait / wave cycles | LDS conflict / busy |",
+                 "|---|---:|---:|---:|---:|---:|---:|---:|"]
+        for k, e in rows[:24]:
+            lines.append(f"| `{k}` | {e['launches']} | {e['dram_read_bytes']:,} | {e['dram_write_bytes']:,} | "
+                         f"{e['dram_atomics']:,} | {e['ea_read_bytes']:,} | {e.get('wait_any_frac', '')} | "
+                         f"{e.get('lds_conflict_frac', '')} |")
+        fname = {"rmat22": "rmat22_counters.md", "cl": "cl1m_counters.md", "batch": "batch_counters.md"}[wl]
+        with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
@@ -206,13 +311,10 @@ def transform_leg(fg, torch, off, idx, steps, warmup):
     return s
 
 
-def batch_leg(fg, torch, steps):
-    """The batched workload: 4096 graphs, n ~ U{16..512}, half ER, half BA,
-    as one block-diagonal CSR built on the device with fglt_build_csr (the
-    union of the graphs' edge lists; no edge crosses two graphs).  Timed with
-    the default plan and with the autotuner's plan (fglt_batch_tune), one
-    launch at a time (eager) and by HIP-graph replay, against a loop of
-    per-graph fglt_raw calls on one stream."""
+def batch_inputs(fg, torch):
+    """The batched workload's block-diagonal CSR, built on the device with
+    fglt_build_csr from the union of the graphs' edge lists (no edge crosses
+    two graphs): (sizes, vertex offsets on the host, offsets, indices)."""
     import graphgen
     graphs = graphgen.make("batch")
     sizes = np.array([g.n for g in graphs], dtype=np.int64)
@@ -220,10 +322,21 @@ def batch_leg(fg, torch, steps):
     base = np.repeat(vtx[:-1].numpy(), [g.src.size for g in graphs])
     src = np.concatenate([g.src for g in graphs]).astype(np.int64) + base
     dst = np.concatenate([g.dst for g in graphs]).astype(np.int64) + base
-    n_total = int(vtx[-1])
-    off_d, idx_d = fg.build_csr(n_total, torch.from_numpy(src.astype(np.int32)).cuda(),
+    off_d, idx_d = fg.build_csr(int(vtx[-1]), torch.from_numpy(src.astype(np.int32)).cuda(),
                                 torch.from_numpy(dst.astype(np.int32)).cuda())
-    G = len(graphs)
+    return sizes, vtx, off_d, idx_d
+
+
+def batch_leg(fg, torch, steps):
+    """The batched workload: 4096 graphs, n ~ U{16..512}, half ER, half BA,
+    as one block-diagonal CSR built on the device with fglt_build_csr (the
+    union of the graphs' edge lists; no edge crosses two graphs).  Timed with
+    the default plan and with the autotuner's plan (fglt_batch_tune), one
+    launch at a time (eager) and by HIP-graph replay, against a loop of
+    per-graph fglt_raw calls on one stream."""
+    sizes, vtx, off_d, idx_d = batch_inputs(fg, torch)
+    n_total = int(vtx[-1])
+    G = int(sizes.size)
     out = torch.empty((n_total, 16), dtype=torch.int64, device="cuda")
     res = {"graphs": G, "n_total": n_total, "nnz_total": int(idx_d.numel())}
     s = torch.cuda.Stream()
@@ -381,7 +494,26 @@ def main():
                     help="skip the sub-dictionary legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter check) and exit")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="only write profiles/traffic.json and the counter summaries from rocprofv3 counter runs "
+                         "under DIR, and exit")
+    ap.add_argument("--traffic-command", default="", help="the command recorded with --traffic-from")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched workload with the default plan, K launches (for profiling), and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        out = write_traffic(args.traffic_from, args.traffic_command)
+        print(json.dumps({wl: len(d["kernels"]) for wl, d in out["workloads"].items()}))
+        return
+    if args.batch_only:
+        import torch
+        import paper_2007_11111_amd as fg
+        sizes, vtx, off_d, idx_d = batch_inputs(fg, torch)
+        out = torch.empty((int(vtx[-1]), 16), dtype=torch.int64, device="cuda")
+        ms, _ = time_steps(torch, lambda: fg.batch(vtx, off_d, idx_d, out=out), args.steps, args.warmup)
+        st = step_summary(ms)
+        print(json.dumps({"graphs": int(sizes.size), "ms": st, "graphs_per_s": round(sizes.size / (st["median"] / 1e3), 1)}))
+        return
     if args.copy_calibration:
         import torch
         nbytes = args.copy_calibration << 20

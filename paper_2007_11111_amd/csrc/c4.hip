@@ -471,22 +471,6 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
     }
 }
 
-// Last index h in [0, cnt) with a[h] <= key, for a non-decreasing a with
-// a[0] <= key.  The whole wavefront searches, 64 probes per round, so a list
-// of N entries takes about log64(N) dependent loads.
-__device__ __forceinline__ i64 wave_last_le(const i64* __restrict__ a, i64 cnt, i64 key) {
-    i64 lo_ = 0, hi_ = cnt;  // the answer lies in [lo_, hi_)
-    while (hi_ - lo_ > 1) {
-        const i64 step = (hi_ - lo_ + WAVE - 1) / WAVE;
-        const i64 p = lo_ + (i64)lane_id() * step;
-        const bool ok = p < hi_ && a[p] <= key;
-        const int c = __popcll(__ballot(ok));  // lanes 0 .. c-1 hold probes <= key
-        lo_ += (i64)(c - 1) * step;
-        hi_ = min(hi_, lo_ + step);
-    }
-    return lo_;
-}
-
 // Jobs: window-tier vertices in descending rank order (hs holds them in
 // ascending order); a vertex whose middles fit one chunk is one job over all
 // its windows, top window first; a larger one is one job per window.

@@ -99,6 +99,8 @@ struct RawWs {
     u64* tri_slots;     // tri_nslots * tri_slot_words
     i64 tri_slot_words;
     int tri_nslots;     // slots (and workgroups) of the global-bitmap tier, 1..NUM_TRI_SLOTS
+    i64* tri_jobpre;    // [n+2] job counts, then their prefix, of the split triangle tier
+    i64* tri_partials;  // scan partials of the triangle pass (the second stream scans with `partials`)
     i64* c4_segoff;     // [2] one segment over the window-tier list
     i64* c4_jobcnt;     // [n+1] jobs per window-tier vertex, then the prefix of their middle counts
     i64* c4_jobpre;     // [n+1] their exclusive scan

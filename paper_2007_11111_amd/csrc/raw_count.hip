@@ -262,6 +262,122 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
     }
 }
 
+// Triangle pass, out-degree above the hub tier's (the list's vertices with
+// D > dmin): every vertex's items are cut into chunks of TRI_SPLIT_CH (jobs,
+// numbered through the prefix jobpre over the list), which the workgroups take
+// by grid stride, so that one vertex with many items keeps every workgroup
+// busy.  An item (u, v_k, y), y in N+(v_k), is a triangle when y is in N+(u).
+// N+(u) lies in the ranks above u: when they fit, a bitmap of them in LDS
+// answers with one read; otherwise every TRI_SAMP-th entry of N+(u) in LDS
+// narrows a search to one short stretch of the row.  Counts go straight to C3
+// with global atomics (the entries (u, v_k), (u, y) and (v_k, y)).
+static constexpr i64 TRI_SPLIT_CH = 262144;
+static constexpr int TRI_SPLIT_T = 1024;  // threads per workgroup
+static constexpr int TRI_SAMP = 4096;     // LDS sample entries
+static constexpr int TRI_BITW = 24576;    // LDS bitmap words: ranks u + 1 .. u + 786432
+
+// Jobs per list entry (zero beyond the list and for out-degrees <= dmin).
+__global__ void k_tri1_jobs(const i64* __restrict__ roff, const i32* __restrict__ lo, const i64* __restrict__ G,
+                            const i32* __restrict__ list, const u32* __restrict__ countp, i64 dmin, i64 bound,
+                            i64* __restrict__ jobcnt, const DevPlan* __restrict__ plan) {
+    FGLT_GATE(&plan->err);
+    const u32 count = *countp;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < bound; i += (i64)gridDim.x * blockDim.x) {
+        i64 c = 0;
+        if (i < (i64)count) {
+            const i64 u = list[i];
+            const i64 bu = roff[u] + lo[u];
+            const i64 D = roff[u + 1] - bu;
+            if (D > dmin) c = (G[bu + D] - G[bu] + TRI_SPLIT_CH - 1) / TRI_SPLIT_CH;
+        }
+        jobcnt[i] = c;
+    }
+}
+
+__global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                            const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                            const i32* __restrict__ list, const u32* __restrict__ countp,
+                                                            const i64* __restrict__ jobpre, i64 n,
+                                                            i32* __restrict__ C3, const DevPlan* __restrict__ plan) {
+    FGLT_GATE(&plan->err);
+    const u32 count = *countp;
+    __shared__ u32 bits[TRI_BITW];
+    __shared__ i32 samp[TRI_SAMP];
+    __shared__ i64 s_vi;
+    const i64 total = jobpre[count];
+    i64 have = -1;  // the list entry whose lookup structure is in LDS
+    for (i64 j = blockIdx.x; j < total; j += gridDim.x) {
+        if (threadIdx.x < WAVE) {
+            const i64 vi = wave_last_le(jobpre, (i64)count, j);
+            if (threadIdx.x == 0) s_vi = vi;
+        }
+        __syncthreads();
+        const i64 vi = s_vi;
+        const i64 u = list[vi];
+        const i64 bu = roff[u] + lo[u];
+        const i32 D = (i32)(roff[u + 1] - bu);
+        const i64 span = n - 1 - u;  // ranks above u
+        const bool bm = span <= 32 * (i64)TRI_BITW;
+        const i32 step = 64 * ((D + 64 * TRI_SAMP - 1) / (64 * TRI_SAMP));
+        const i32 ns = (D + step - 1) / step;
+        if (vi != have) {
+            if (bm) {
+                const i32 nw = (i32)((span + 31) >> 5);
+                for (i32 q = threadIdx.x; q < nw; q += TRI_SPLIT_T) bits[q] = 0;
+                __syncthreads();
+                for (i32 k = threadIdx.x; k < D; k += TRI_SPLIT_T) {
+                    const u32 r = (u32)(ridx[bu + k] - u - 1);
+                    atomicOr(&bits[r >> 5], 1u << (r & 31));
+                }
+            } else {
+                for (i32 q = threadIdx.x; q < ns; q += TRI_SPLIT_T) samp[q] = ridx[bu + (i64)q * step];
+            }
+            have = vi;
+        }
+        __syncthreads();
+        const i64 gb = G[bu];
+        const i64 T = G[bu + D] - gb;
+        const i64 c = j - jobpre[vi];
+        const i64 t0 = c * TRI_SPLIT_CH, t1 = std::min<i64>(T, t0 + TRI_SPLIT_CH);
+        // items t0 + tid, t0 + tid + 1024, ...: entry q of u holds items
+        // [G[q] - gb, G[q+1] - gb); one search for the first, then forward
+        i64 q = -1, qe = 0, eb = 0;
+        for (i64 t = t0 + threadIdx.x; t < t1; t += TRI_SPLIT_T) {
+            if (q < 0 || gb + t >= qe) {
+                q = q < 0 ? last_le_dev(G, bu, bu + D - 1, gb + t) : q + 1;
+                while (G[q + 1] <= gb + t) ++q;
+                qe = G[q + 1];
+                const i32 v = ridx[q];
+                eb = roff[v] + lo[v] - (G[q] - gb);  // item t of entry q at ridx[eb + t]
+            }
+            const i64 e = eb + t;
+            const i32 y = ridx[e];
+            i64 p = -1;
+            if (bm) {
+                const u32 r = (u32)(y - u - 1);  // y follows v_k, so u, in rank
+                if ((bits[r >> 5] >> (r & 31)) & 1u) p = lower_bound_dev(ridx, bu, bu + D, y);
+            } else {
+                // last sample entry <= y (entry 0 is below y)
+                i32 a = 0, b2 = ns;
+                while (b2 - a > 1) {
+                    const i32 mid = (a + b2) >> 1;
+                    if (samp[mid] <= y) a = mid;
+                    else b2 = mid;
+                }
+                const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
+                const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
+                if (pp < hi_ && ridx[pp] == y) p = pp;
+            }
+            if (p >= 0) {
+                atomicAdd(&C3[q], 1);
+                atomicAdd(&C3[p], 1);
+                atomicAdd(&C3[e], 1);
+            }
+        }
+        __syncthreads();  // the next job may rebuild the lookup structure
+    }
+}
+
 // Workgroup tiers: out-degree D > 64.  GLOBAL = false keeps bitmaps and lists
 // in LDS (D <= TRI_LDS_MAX); GLOBAL = true keeps them in a per-block slot of
 // device memory (any D up to sqrt(nnz)) of slot_words words: 4 D + 64 for the
@@ -548,9 +664,8 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
     const i32* l1 = w.tri_list + n;
     const i32* l2 = w.tri_list + 2 * n;
     // the last tier's bound: vertices of out-degree above the LDS tier's.  The
-    // global-bitmap slots' memory is shared out by the largest out-degree a
-    // launch takes: the triangle pass's lists alone (up to 2048 workgroups),
-    // and for the clique pass the bitmaps of out-degree up to TRI_MID_D
+    // clique pass shares out the global-bitmap slots' memory by the largest
+    // out-degree a launch takes: the bitmaps of out-degree up to TRI_MID_D
     // (many slots), then the rest (slots for the largest out-degree)
     const i64 region = (i64)w.tri_nslots * w.tri_slot_words;
     i64 dplus = 1;  // above every out-degree (the degree order keeps them below sqrt(nnz))
@@ -559,7 +674,6 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
     auto slots_for = [&](i64 words, i64 cap) {
         return (unsigned)std::max<i64>(1, std::min<i64>({tier_bound, region / words, cap}));
     };
-    const i64 w_list = 4 * dplus + 64;
     const i64 d_mid = std::min<i64>(TRI_MID_D, dplus);
     const i64 w_mid = 2 * d_mid * ceil_div(d_mid, 64) + 4 * d_mid + 64;
     const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>(tier_bound, (i64)w.tri_nslots));
@@ -572,9 +686,15 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         if ((e = launch_tri1_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
         tm.mark(FGLT_SEG_TRI1_GLOBAL, s);
         if ((e = launch_tri1_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tri_block<1, true>), dim3(slots_for(w_list, 2048)), dim3(PT), 0, s, w.roff, w.ridx,
-                           w.lo, w.rdeg, w.G, l2, cnt + 2, hub_max, (i64)INT_MAX, hub_max, w.C3, w.k4v, w.d13,
-                           w.tri_slots, w_list, w.plan, (const u32*)nullptr);
+        // the rest of the last tier, split into chunks of items (the job
+        // prefix over the list's n entries at most -- a plan with lower tier
+        // bounds may put any vertex there -- with scan partials of its own:
+        // the 4-cycle setup may scan on the second stream meanwhile)
+        hipLaunchKernelGGL(k_tri1_jobs, dim3(grid_for(n + 1, PT, 4096)), dim3(PT), 0, s, w.roff, w.lo, w.G, l2,
+                           cnt + 2, hub_max, n + 1, w.tri_jobpre, (const DevPlan*)w.plan);
+        if ((e = scan_exclusive_i64(w.tri_jobpre, w.tri_jobpre, n + 1, w.tri_partials, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tri1_split, dim3(4 * 256), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx, w.lo, w.G, l2,
+                           cnt + 2, (const i64*)w.tri_jobpre, n, w.C3, (const DevPlan*)w.plan);
     } else {
         // clique and diamond pass: from the stored bitmaps, or by scanning
         // again (the stored flag is read on the device; each kernel of the

@@ -443,6 +443,8 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.tri_nslots = (int)std::max<i64>(
         1, std::min<i64>(NUM_TRI_SLOTS, std::max<i64>((i64)1 << 30, 2 * nnz) / (8 * w.tri_slot_words)));
     w.tri_slots = c.take<u64>(w.tri_nslots * w.tri_slot_words);
+    w.tri_jobpre = c.take<i64>(nn + 2);
+    w.tri_partials = c.take<i64>(scan_partials_size(nn + 2));
     w.bcnt = c.take<i64>(nn);
     w.boff = c.take<i64>(nn + 1);
     w.c4_segoff = c.take<i64>(2);

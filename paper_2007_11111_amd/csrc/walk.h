@@ -116,6 +116,22 @@ __device__ __forceinline__ i32 wave_last_le_lds(const i32* a, i32 R, i32 key) {
     return lo_;
 }
 
+// Last index h in [0, cnt) with a[h] <= key, for a non-decreasing a with
+// a[0] <= key.  The whole wavefront searches, 64 probes per round, so a list
+// of N entries takes about log64(N) dependent loads.
+__device__ __forceinline__ i64 wave_last_le(const i64* __restrict__ a, i64 cnt, i64 key) {
+    i64 lo_ = 0, hi_ = cnt;  // the answer lies in [lo_, hi_)
+    while (hi_ - lo_ > 1) {
+        const i64 step = (hi_ - lo_ + WAVE - 1) / WAVE;
+        const i64 p = lo_ + (i64)lane_id() * step;
+        const bool ok = p < hi_ && a[p] <= key;
+        const int c = __popcll(__ballot(ok));  // lanes 0 .. c-1 hold probes <= key
+        lo_ += (i64)(c - 1) * step;
+        hi_ = min(hi_, lo_ + step);
+    }
+    return lo_;
+}
+
 // The run walk, in groups of up to U steps of 64 items.  A group reads the
 // starts of the next 64 runs once (one per lane); it ends before the last of
 // them, so every item in it has a known run.  The run starts inside the group
