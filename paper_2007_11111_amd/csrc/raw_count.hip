@@ -268,8 +268,10 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
 // by grid stride, so that one vertex with many items keeps every workgroup
 // busy.  An item (u, v_k, y), y in N+(v_k), is a triangle when y is in N+(u).
 // N+(u) lies in the ranks above u: when they fit, a bitmap of them in LDS
-// answers with one read; otherwise every TRI_SAMP-th entry of N+(u) in LDS
-// narrows a search to one short stretch of the row.  Counts go straight to C3
+// answers with one read, and a hit's position in N+(u) is its rank among the
+// set bits (prefix counts per 8 words, then at most 8 word popcounts);
+// otherwise every TRI_SAMP-th entry of N+(u) in LDS narrows a search to one
+// short stretch of the row.  Counts go straight to C3
 // with global atomics (the entries (u, v_k), (u, y) and (v_k, y)).
 static constexpr i64 TRI_SPLIT_CH = 262144;
 static constexpr int TRI_SPLIT_T = 1024;  // threads per workgroup
@@ -302,7 +304,10 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
     FGLT_GATE(&plan->err);
     const u32 count = *countp;
     __shared__ u32 bits[TRI_BITW];
+    __shared__ i32 bpre[TRI_BITW / 8];  // set bits before each group of 8 words
     __shared__ i32 samp[TRI_SAMP];
+    __shared__ i32 wsum[TRI_SPLIT_T / WAVE];
+    __shared__ i32 btot;
     __shared__ i64 s_vi;
     const i64 total = jobpre[count];
     i64 have = -1;  // the list entry whose lookup structure is in LDS
@@ -328,6 +333,28 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
                 for (i32 k = threadIdx.x; k < D; k += TRI_SPLIT_T) {
                     const u32 r = (u32)(ridx[bu + k] - u - 1);
                     atomicOr(&bits[r >> 5], 1u << (r & 31));
+                }
+                __syncthreads();
+                // the position of a set bit in N+(u) is its rank among the set
+                // bits: prefix counts per group of 8 words (3 groups a thread)
+                constexpr int GPT = TRI_BITW / 8 / TRI_SPLIT_T;
+                const i32 ng = (nw + 7) >> 3;
+                i32 gc[GPT], tsum = 0;
+#pragma unroll
+                for (int g = 0; g < GPT; ++g) {
+                    const i32 grp = (i32)threadIdx.x * GPT + g;
+                    i32 cg = 0;
+                    if (grp < ng)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) cg += grp * 8 + q < nw ? __popc(bits[grp * 8 + q]) : 0;
+                    gc[g] = cg;
+                    tsum += cg;
+                }
+                i32 run = block_scan<TRI_SPLIT_T>(tsum, wsum, &btot);
+#pragma unroll
+                for (int g = 0; g < GPT; ++g) {
+                    bpre[threadIdx.x * GPT + g] = run;
+                    run += gc[g];
                 }
             } else {
                 for (i32 q = threadIdx.x; q < ns; q += TRI_SPLIT_T) samp[q] = ridx[bu + (i64)q * step];
@@ -355,7 +382,12 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
             i64 p = -1;
             if (bm) {
                 const u32 r = (u32)(y - u - 1);  // y follows v_k, so u, in rank
-                if ((bits[r >> 5] >> (r & 31)) & 1u) p = lower_bound_dev(ridx, bu, bu + D, y);
+                const u32 wd = bits[r >> 5];
+                if ((wd >> (r & 31)) & 1u) {
+                    i32 pos = bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
+                    for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(bits[q]);
+                    p = bu + pos;
+                }
             } else {
                 // last sample entry <= y (entry 0 is below y)
                 i32 a = 0, b2 = ns;
