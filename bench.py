@@ -69,12 +69,15 @@ SEG_UNITS = {
     "finalize": ("vertex", 128),  # the n x 16 int64 output row
 }
 
-# The kernel behind each timed segment whose traffic the counters give.
+# The kernels behind each timed segment whose traffic the counters give (a
+# name covers its template instances; the segment's traffic is their sum).
 SEG_KERNEL = {
-    "c4_window": "k_c4_window", "c4_hash": "k_c4_hashbig", "c4_block": "k_c4_hash<4, 4096>",
-    "c4_wave": "k_c4_hash<1, 256>", "tri1_wave": "k_tri1_wave", "tri1_lds": "k_tri1_lds",
-    "tri1_global": "k_tri_block<1, true>", "tri2_wave": "k_tri2s_wave", "tri2_lds": "k_tri2s_lds",
-    "tri2_global": "k_tri_block<2, true>", "l2": "k_l2", "fill": "k_fill_c3", "finalize": "k_finalize",
+    "c4_window": ["k_c4_window", "k_c4_esum_flush"], "c4_hash": ["k_c4_hashbig"],
+    "c4_block": ["k_c4_hash<4, 4096>"], "c4_wave": ["k_c4_hash<1, 256>"], "tri1_wave": ["k_tri1_wave"],
+    "tri1_lds": ["k_tri1_lds"], "tri1_global": ["k_tri1_hub", "k_tri1_jobs", "k_tri1_split"],
+    "tri2_wave": ["k_tri2s_wave", "k_tri_wave"], "tri2_lds": ["k_tri2s_lds", "k_tri2_du_lds<512, 512, 9>"],
+    "tri2_global": ["k_tri2s_hub", "k_tri2_du_lds<1024, 1088, 10>", "k_tri_block<2, true>"],
+    "l2": ["k_l2", "k_l2_rec"], "fill": ["k_fill_c3"], "finalize": ["k_finalize"],
 }
 
 
@@ -113,9 +116,10 @@ def source_hash():
 
 
 def load_traffic(seg, workload):
-    """DRAM-side bytes per launch of the kernel behind `seg` on `workload` from
-    the committed rocprofv3 counters (profiles/traffic.json), or None if absent
-    or taken on a different kernel source."""
+    """HBM bytes per transform of the kernels behind `seg` on `workload` (the
+    sum of their bytes per launch) from the committed rocprofv3 counters
+    (profiles/traffic.json), or None if absent or taken on a different kernel
+    source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path) or seg not in SEG_KERNEL:
         return None
@@ -125,10 +129,10 @@ def load_traffic(seg, workload):
         return None
     if t.get("source_sha256") != source_hash():
         return None
-    k = SEG_KERNEL[seg]
     ks = t.get("workloads", {}).get(workload, {}).get("kernels", {})
-    hits = [v for name, v in ks.items() if name == k or name.startswith(k + "<")]
-    return max(v["bytes_per_launch"] for v in hits) if hits else None
+    hits = [v for name, v in ks.items()
+            if any(name == k or (not k.endswith(">") and name.startswith(k + "<")) for k in SEG_KERNEL[seg])]
+    return sum(v["bytes_per_launch"] for v in hits) if hits else None
 
 
 # rocprofv3 counter passes behind profiles/traffic.json (one --pmc run each;
