@@ -477,7 +477,9 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
 // TABM: how a middle's run in a window is found -- 0: binary searches of its
 // row, 1: the window table of its vertex (tab), 2: the per-entry window table
 // (etab, 16-bit counts only: entries below 65536), whose reads for consecutive
-// middles are consecutive.
+// middles are consecutive, 3 (32-bit counts): the 16-bit window table's
+// entries on each side of a 32768-rank boundary, then a search between them
+// (searches of the whole row for a middle whose cut is 65536 or more).
 template <bool PACK16, int TABM>
 __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                           const i32* __restrict__ lo, const i32* __restrict__ rpos,
@@ -500,7 +502,8 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     const i32* const hs = PACK16 ? hs_all : hs_all + (c3 - nheavy);
     const i32 wlo = (i32)(plan->n_low / WS);
     if (nh == 0) return;
-    constexpr bool TAB = TABM > 0, ETAB = TABM == 2;
+    constexpr bool TAB = TABM == 1 || TABM == 2, ETAB = TABM == 2;
+    static_assert(TABM != 3 || !PACK16, "table brackets serve the 32-bit counters' windows");
     using TabT = std::conditional_t<PACK16, u16, i32>;  // the vertex table's entries
     const TabT* const tabt = reinterpret_cast<const TabT*>(tab);
     static_assert(!ETAB || PACK16, "the per-entry table holds 16-bit entries");
@@ -604,6 +607,23 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         const i32 a1 = std::min((i32)tabt[vrow + win + 1], cut);
                         s0 = rs + a0;
                         len = a1 - a0;
+                    } else if (TABM == 3 && cut < 65536) {
+                        // the 16-bit vertex table brackets a 32768-rank window
+                        // boundary between two 65536-rank ones: below u every
+                        // count is at most the cut, so the entries hold
+                        const i64 re = rs + cut;
+                        const u16* const t16 =
+                            reinterpret_cast<const u16*>(tab) + (i64)(prefetched ? pc_v : ridx[b + k]) * TS;
+                        auto pos_of = [&](i32 W) -> i64 {  // first entry of the row at rank >= W
+                            if (W >= u) return re;
+                            const i32 q = W >> 16;
+                            const i64 p0 = rs + t16[q];
+                            if ((W & 0xffff) == 0) return p0;
+                            const i64 p1 = ((i64)(q + 1) << 16) >= u ? re : rs + t16[q + 1];
+                            return lower_bound_dev(ridx, p0, p1, W);
+                        };
+                        s0 = pos_of(W0);
+                        len = (i32)(pos_of(W1) - s0);
                     } else {
                         const i64 re = rs + cut;
                         s0 = lower_bound_dev(ridx, rs, re, W0);
@@ -828,7 +848,7 @@ template <class T>
 __global__ void k_c4_table(const i64* __restrict__ roff, const i32* __restrict__ ridx, i64 n, i64 K1, i64 TS, i64 WS,
                            T* __restrict__ tab, const DevPlan* __restrict__ plan) {
     FGLT_GATE(&plan->err);
-    if (plan->n_c4[3] <= plan->n_c4_heavy) return;  // no window job with 16-bit counters
+    if (plan->n_c4[3] == 0) return;  // no window job
     const i64 total = n * K1;
     for (i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (i64)gridDim.x * blockDim.x) {
         const i64 v = q / K1, k = q - v * K1;
@@ -1060,7 +1080,8 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
     if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2);
     if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0);
     else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0);
-    C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
+    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0);
+    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
 #undef C4W_LAUNCH
     if (nnz > 0)
         hipLaunchKernelGGL(k_c4_esum_flush, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, w.ridx,
