@@ -615,7 +615,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a vertex sample)")
-        sample = args.cpu_sample or {"rmat22": 300, "cl": 20000}.get(args.workload, 20000)
+        sample = args.cpu_sample or {"rmat22": 2000, "cl": 20000}.get(args.workload, 20000)
         cpu = cpu_baseline(off.cpu().numpy(), idx.cpu().numpy(), m, sample)
     del ws, out
     torch.cuda.empty_cache()
