@@ -218,7 +218,7 @@ int fglt_raw_status(const void* ws, void* stream);
  *                FGLT_TIMING is not offered (FGLT_EINVAL); FGLT_VALIDATE is
  *                implied (the caller cannot reach the array's status word)
  * Returns FGLT_EWORKSPACE when fglt_raw_workspace(n, nnz) exceeds
- * FGLT_NOALLOC_SCRATCH_BYTES (about 1.6M directed entries fit).  Every call
+ * FGLT_NOALLOC_SCRATCH_BYTES (1.2M to 1.6M directed entries fit).  Every call
  * on a device shares that device's array and overwrites it, so calls that
  * overlap on one device (different streams or threads) race: the caller
  * serializes them.  Waits for `stream` once, at the end (FGLT_VALIDATE).

@@ -73,6 +73,22 @@ def test_batch_persistent_queue_and_tuner(fg):
     assert fg.batch_tune(vtx, o, i, reps=2) == plan
 
 
+def test_batch_unsorted_rows(fg):
+    """Rows in any order (the contract of fglt_raw, which the batch shares):
+    the batch's rows shuffled per vertex give the oracle's counts."""
+    vtx, off, idx, exp = _pack(fg, _mixed())
+    rng = np.random.default_rng(12)
+    o, ix = off.numpy(), idx.numpy().copy()
+    for v in range(o.size - 1):
+        a, b = int(o[v]), int(o[v + 1])
+        if b - a > 1:
+            ix[a:b] = ix[a:b][rng.permutation(b - a)]
+    say("batch with shuffled rows")
+    out = fg.batch(vtx, off.cuda(), torch.from_numpy(ix).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), exp)
+
+
 def test_batch_matches_single_graph_path(fg):
     graphs = graphgen.batch_graphs(64, seed=22)
     vtx, off, idx, exp = _pack(fg, graphs)

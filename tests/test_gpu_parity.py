@@ -190,6 +190,31 @@ def test_chung_lu_medium(fg, plan):
     np.testing.assert_array_equal(gpu_raw(fg, off, idx, PLANS[plan], net=True), exp)
 
 
+def _shuffle_rows(off, idx, seed):
+    """The same graph with every row's entries in a seeded random order."""
+    rng = np.random.default_rng(seed)
+    out = idx.copy()
+    for v in range(off.size - 1):
+        a, b = int(off[v]), int(off[v + 1])
+        if b - a > 1:
+            out[a:b] = out[a:b][rng.permutation(b - a)]
+    return out
+
+
+@pytest.mark.parametrize("plan", ["default", "global"])
+def test_unsorted_rows(fg, plan):
+    """The contract admits rows in any order (fglt_raw relabels and re-sorts
+    them): rows shuffled per vertex give the oracle's counts of the sorted
+    CSR, a power-law graph with a window tier and a dense graph."""
+    for name, g in (("chung-lu 20k", graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)),
+                    ("er dense", graphgen.erdos_renyi(300, 0.2, seed=8))):
+        off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+        shuffled = _shuffle_rows(off, idx, seed=9)
+        assert not np.array_equal(shuffled, idx)
+        say(f"unsorted rows: {name} plan={plan}")
+        np.testing.assert_array_equal(gpu_raw(fg, off, shuffled, PLANS[plan], net=True), oracle.net(off, idx))
+
+
 @pytest.mark.parametrize("plan", ["default", "hash", "global"])
 @pytest.mark.parametrize("a,b", [(2, 1500), (3, 2600), (40, 300)])
 def test_complete_bipartite(fg, plan, a, b):
