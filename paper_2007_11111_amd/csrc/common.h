@@ -186,6 +186,25 @@ __device__ __forceinline__ bool wave_seg_tail(i64 key, bool active) {
     return active && (l == WAVE - 1 || !next_active || next != key);
 }
 
+// One atomic per run of equal keys instead of one per lane: for lanes whose
+// keys are non-decreasing across the wavefront and whose active lanes form a
+// prefix of it, the first lane of each run adds the number of the run's lanes
+// with `hit` set to a[key].  Call with every active lane.
+template <class T>
+__device__ __forceinline__ void wave_run_add(T* a, i64 key, bool hit) {
+    const int l = lane_id();
+    const u64 hm = __ballot(hit);
+    const i64 prev = __shfl_up(key, 1, WAVE);
+    const bool head = l == 0 || prev != key;
+    const u64 hd = __ballot(head);
+    if (head) {
+        const u64 later = l == WAVE - 1 ? 0ull : hd & (~0ull << (l + 1));  // heads after this lane
+        const u64 upto = later ? (later & (0ull - later)) - 1ull : ~0ull;  // lanes below the next head
+        const int c = __popcll(hm & upto & (~0ull << l));
+        if (c) atomicAdd(&a[key], (T)c);
+    }
+}
+
 // ---------------------------------------------------------------- host launch helpers
 
 namespace fglt {

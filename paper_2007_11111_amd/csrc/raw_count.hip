@@ -277,6 +277,7 @@ static constexpr i64 TRI_SPLIT_CH = 262144;
 static constexpr int TRI_SPLIT_T = 1024;  // threads per workgroup
 static constexpr int TRI_SAMP = 4096;     // LDS sample entries
 static constexpr int TRI_BITW = 24576;    // LDS bitmap words: ranks u + 1 .. u + 786432
+static constexpr int TRI_ECAP = 4096;     // entries of a chunk held in LDS at a time
 
 // Jobs per list entry (zero beyond the list and for out-degrees <= dmin).
 __global__ void k_tri1_jobs(const i64* __restrict__ roff, const i32* __restrict__ lo, const i64* __restrict__ G,
@@ -303,12 +304,15 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
                                                             i32* __restrict__ C3, const DevPlan* __restrict__ plan) {
     FGLT_GATE(&plan->err);
     const u32 count = *countp;
-    __shared__ u32 bits[TRI_BITW];
+    static_assert(TRI_SAMP <= TRI_BITW, "the sample shares the bitmap's memory");
+    __shared__ u32 bits[TRI_BITW];  // the bitmap, or the sample (never both)
+    i32* const samp = reinterpret_cast<i32*>(bits);
     __shared__ i32 bpre[TRI_BITW / 8];  // set bits before each group of 8 words
-    __shared__ i32 samp[TRI_SAMP];
+    __shared__ i32 eS[TRI_ECAP + 1];    // a block of the chunk's entries: their first items (from t0)
+    __shared__ i64 eB[TRI_ECAP];        // and the position of item t (from 0) at ridx[eB + t]
     __shared__ i32 wsum[TRI_SPLIT_T / WAVE];
     __shared__ i32 btot;
-    __shared__ i64 s_vi;
+    __shared__ i64 s_vi, s_qa, s_qb;
     const i64 total = jobpre[count];
     i64 have = -1;  // the list entry whose lookup structure is in LDS
     for (i64 j = blockIdx.x; j < total; j += gridDim.x) {
@@ -361,52 +365,79 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
             }
             have = vi;
         }
-        __syncthreads();
         const i64 gb = G[bu];
         const i64 T = G[bu + D] - gb;
         const i64 c = j - jobpre[vi];
         const i64 t0 = c * TRI_SPLIT_CH, t1 = std::min<i64>(T, t0 + TRI_SPLIT_CH);
-        // items t0 + tid, t0 + tid + 1024, ...: entry q of u holds items
-        // [G[q] - gb, G[q+1] - gb); one search for the first, then forward
-        i64 q = -1, qe = 0, eb = 0;
-        for (i64 t = t0 + threadIdx.x; t < t1; t += TRI_SPLIT_T) {
-            if (q < 0 || gb + t >= qe) {
-                q = q < 0 ? last_le_dev(G, bu, bu + D - 1, gb + t) : q + 1;
-                while (G[q + 1] <= gb + t) ++q;
-                qe = G[q + 1];
-                const i32 v = ridx[q];
-                eb = roff[v] + lo[v] - (G[q] - gb);  // item t of entry q at ridx[eb + t]
-            }
-            const i64 e = eb + t;
-            const i32 y = ridx[e];
-            i64 p = -1;
-            if (bm) {
-                const u32 r = (u32)(y - u - 1);  // y follows v_k, so u, in rank
-                const u32 wd = bits[r >> 5];
-                if ((wd >> (r & 31)) & 1u) {
-                    i32 pos = bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
-                    for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(bits[q]);
-                    p = bu + pos;
-                }
-            } else {
-                // last sample entry <= y (entry 0 is below y)
-                i32 a = 0, b2 = ns;
-                while (b2 - a > 1) {
-                    const i32 mid = (a + b2) >> 1;
-                    if (samp[mid] <= y) a = mid;
-                    else b2 = mid;
-                }
-                const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
-                const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
-                if (pp < hi_ && ridx[pp] == y) p = pp;
-            }
-            if (p >= 0) {
-                atomicAdd(&C3[q], 1);
-                atomicAdd(&C3[p], 1);
-                atomicAdd(&C3[e], 1);
+        // the entries of u holding the chunk's first and last items (entry q
+        // holds items [G[q] - gb, G[q+1] - gb))
+        if (threadIdx.x < WAVE) {
+            const i64 qa = wave_last_le(G + bu, D, gb + t0);
+            const i64 qb = wave_last_le(G + bu, D, gb + t1 - 1);
+            if (threadIdx.x == 0) {
+                s_qa = qa;
+                s_qb = qb;
             }
         }
-        __syncthreads();  // the next job may rebuild the lookup structure
+        __syncthreads();
+        const i64 qa = s_qa, qb = s_qb;
+        // blocks of up to TRI_ECAP entries: their item starts and row
+        // positions in LDS, loaded side by side; then items tid, tid + 1024,
+        // ... of the block, each entry found by a search of the starts
+        for (i64 sa = qa; sa <= qb; sa += TRI_ECAP) {
+            const i32 ne = (i32)std::min<i64>(TRI_ECAP, qb - sa + 1);
+            for (i32 i = threadIdx.x; i < ne; i += TRI_SPLIT_T) {
+                const i64 q = bu + sa + i;
+                const i64 gs = G[q] - gb;
+                const i32 v = ridx[q];
+                eB[i] = roff[v] + lo[v] - gs;
+                eS[i] = (i32)(std::max(gs, t0) - t0);
+            }
+            if (threadIdx.x == 0) eS[ne] = (i32)(std::min(G[bu + sa + ne] - gb, t1) - t0);
+            __syncthreads();
+            const i32 ia = eS[0], ib = eS[ne];
+            i32 cur = 0;
+            for (i32 tr = ia + (i32)threadIdx.x; tr < ib; tr += TRI_SPLIT_T) {
+                i32 ka = cur, kb = ne;  // eS[ka] <= tr < eS[kb] (ne: the end)
+                while (kb - ka > 1) {
+                    const i32 mid = (ka + kb) >> 1;
+                    if (eS[mid] <= tr) ka = mid;
+                    else kb = mid;
+                }
+                cur = ka;
+                const i64 q = bu + sa + ka;
+                const i64 e = eB[ka] + t0 + tr;
+                const i32 y = ridx[e];
+                i64 p = -1;
+                if (bm) {
+                    const u32 r = (u32)(y - u - 1);  // y follows v_k, so u, in rank
+                    const u32 wd = bits[r >> 5];
+                    if ((wd >> (r & 31)) & 1u) {
+                        i32 pos = bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
+                        for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(bits[q]);
+                        p = bu + pos;
+                    }
+                } else {
+                    // last sample entry <= y (entry 0 is below y)
+                    i32 a = 0, b2 = ns;
+                    while (b2 - a > 1) {
+                        const i32 mid = (a + b2) >> 1;
+                        if (samp[mid] <= y) a = mid;
+                        else b2 = mid;
+                    }
+                    const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
+                    const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
+                    if (pp < hi_ && ridx[pp] == y) p = pp;
+                }
+                if (p >= 0) {
+                    atomicAdd(&C3[p], 1);
+                    atomicAdd(&C3[e], 1);
+                }
+                // lanes hold consecutive items, so runs of one entry q: one add per run
+                wave_run_add(C3, q, p >= 0);
+            }
+            __syncthreads();  // the next block of entries, or the next job's lookup structure
+        }
     }
 }
 
@@ -508,9 +539,11 @@ __global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, 
             const i64 e = Bv[k] + o;
             const i32 y = ridx[e];
             const int l = (int)lower_bound_dev(L, (i64)k + 1, (i64)D, y);
-            if (l < D && L[l] == y) {
+            const bool hit = l < D && L[l] == y;
+            // lanes hold consecutive items, so runs of one entry k: one add per run
+            if (MODE == 1) wave_run_add(Cnt, (i64)k, hit);
+            if (hit) {
                 if (MODE == 1) {
-                    atomicAdd(&Cnt[k], 1);
                     atomicAdd(&Cnt[l], 1);
                     atomicAdd(&C3[e], 1);
                 } else {
