@@ -297,6 +297,142 @@ __global__ void k_tri1_jobs(const i64* __restrict__ roff, const i32* __restrict_
     }
 }
 
+// LDS of the out-neighbourhood lookup and of the staged entries, shared by
+// the split triangle kernel and the clique kernel above the LDS tier.
+struct NbrLds {
+    u32 bits[TRI_BITW];      // bitmap of the ranks above u, or the sample (never both)
+    i32 bpre[TRI_BITW / 8];  // set bits before each group of 8 words
+    i32 eS[TRI_ECAP + 1];    // a block of a chunk's entries: their first items (from the chunk's start)
+    i64 eB[TRI_ECAP];        // and where item t (from 0) of each sits: ridx[eB + t]
+    i32 wsum[TRI_SPLIT_T / WAVE];
+    i32 btot;
+    i64 sq[2];
+};
+static_assert(TRI_SAMP <= TRI_BITW, "the sample shares the bitmap's memory");
+
+// Positions in N+(u) = ridx[bu .. bu + D) (ascending ranks, all above u).
+// When the ranks above u fit in the bitmap, a rank's position is its rank
+// among the set bits: prefix counts per group of 8 words, then at most 8 word
+// popcounts; otherwise every step-th entry of the row, in LDS, narrows a
+// search to one stretch of at most step entries.
+struct NbrLookup {
+    i64 u, bu;
+    i32 D;
+    bool bm;
+    i32 step, ns;
+    __device__ NbrLookup(i64 u_, i64 bu_, i32 D_, i64 n) : u(u_), bu(bu_), D(D_) {
+        bm = n - 1 - u <= 32 * (i64)TRI_BITW;
+        step = 64 * ((D + 64 * TRI_SAMP - 1) / (64 * TRI_SAMP));
+        ns = (D + step - 1) / step;
+    }
+    // Every thread of the (TRI_SPLIT_T-thread) workgroup; the caller
+    // synchronises before the first find.
+    __device__ void build(NbrLds& sm, const i32* __restrict__ ridx, i64 n) const {
+        if (bm) {
+            const i32 nw = (i32)((n - 1 - u + 31) >> 5);
+            for (i32 q = threadIdx.x; q < nw; q += TRI_SPLIT_T) sm.bits[q] = 0;
+            __syncthreads();
+            for (i32 k = threadIdx.x; k < D; k += TRI_SPLIT_T) {
+                const u32 r = (u32)(ridx[bu + k] - u - 1);
+                atomicOr(&sm.bits[r >> 5], 1u << (r & 31));
+            }
+            __syncthreads();
+            constexpr int GPT = TRI_BITW / 8 / TRI_SPLIT_T;  // groups of 8 words a thread
+            const i32 ng = (nw + 7) >> 3;
+            i32 gc[GPT], tsum = 0;
+#pragma unroll
+            for (int g = 0; g < GPT; ++g) {
+                const i32 grp = (i32)threadIdx.x * GPT + g;
+                i32 cg = 0;
+                if (grp < ng)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) cg += grp * 8 + q < nw ? __popc(sm.bits[grp * 8 + q]) : 0;
+                gc[g] = cg;
+                tsum += cg;
+            }
+            i32 run = block_scan<TRI_SPLIT_T>(tsum, sm.wsum, &sm.btot);
+#pragma unroll
+            for (int g = 0; g < GPT; ++g) {
+                sm.bpre[threadIdx.x * GPT + g] = run;
+                run += gc[g];
+            }
+        } else {
+            i32* const samp = reinterpret_cast<i32*>(sm.bits);
+            for (i32 q = threadIdx.x; q < ns; q += TRI_SPLIT_T) samp[q] = ridx[bu + (i64)q * step];
+        }
+    }
+    // Position of y (a rank above u) in N+(u), or -1.
+    __device__ __forceinline__ i32 find(const NbrLds& sm, const i32* __restrict__ ridx, i32 y) const {
+        if (bm) {
+            const u32 r = (u32)(y - u - 1);
+            const u32 wd = sm.bits[r >> 5];
+            if (!((wd >> (r & 31)) & 1u)) return -1;
+            i32 pos = sm.bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
+            for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(sm.bits[q]);
+            return pos;
+        }
+        const i32* const samp = reinterpret_cast<const i32*>(sm.bits);
+        i32 a = 0, b = ns;  // the last sample entry <= y (entry 0 is below y)
+        while (b - a > 1) {
+            const i32 mid = (a + b) >> 1;
+            if (samp[mid] <= y) a = mid;
+            else b = mid;
+        }
+        const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
+        const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
+        return pp < hi_ && ridx[pp] == y ? (i32)(pp - bu) : -1;
+    }
+};
+
+// Items [t0, t1) of vertex u (t0 < t1 <= t0 + 2^31): entry q of u holds items
+// [G[q] - gb, G[q+1] - gb), item t of it at ridx[roff[v] + lo[v] + t - (G[q] -
+// gb)] with v = ridx[q].  Blocks of up to TRI_ECAP entries are staged in LDS
+// side by side; the threads then take items tid, tid + 1024, ... of the
+// block, each finding its entry by a search of the staged starts, and call
+// f(q, e) with q the item's entry and e its position in ridx.  Lanes hold
+// consecutive items, so a wavefront's entries are non-decreasing.  Every
+// thread of the workgroup calls it.
+template <class F>
+__device__ __forceinline__ void walk_items(NbrLds& sm, const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                           const i32* __restrict__ lo, const i64* __restrict__ G, i64 bu, i32 D,
+                                           i64 gb, i64 t0, i64 t1, F&& f) {
+    if (threadIdx.x < WAVE) {  // the entries holding the first and the last item
+        const i64 qa = wave_last_le(G + bu, D, gb + t0);
+        const i64 qb = wave_last_le(G + bu, D, gb + t1 - 1);
+        if (threadIdx.x == 0) {
+            sm.sq[0] = qa;
+            sm.sq[1] = qb;
+        }
+    }
+    __syncthreads();
+    const i64 qa = sm.sq[0], qb = sm.sq[1];
+    for (i64 sa = qa; sa <= qb; sa += TRI_ECAP) {
+        const i32 ne = (i32)std::min<i64>(TRI_ECAP, qb - sa + 1);
+        for (i32 i = threadIdx.x; i < ne; i += TRI_SPLIT_T) {
+            const i64 q = bu + sa + i;
+            const i64 gs = G[q] - gb;
+            const i32 v = ridx[q];
+            sm.eB[i] = roff[v] + lo[v] - gs;
+            sm.eS[i] = (i32)(std::max(gs, t0) - t0);
+        }
+        if (threadIdx.x == 0) sm.eS[ne] = (i32)(std::min(G[bu + sa + ne] - gb, t1) - t0);
+        __syncthreads();
+        const i32 ia = sm.eS[0], ib = sm.eS[ne];
+        i32 cur = 0;
+        for (i32 tr = ia + (i32)threadIdx.x; tr < ib; tr += TRI_SPLIT_T) {
+            i32 ka = cur, kb = ne;  // eS[ka] <= tr < eS[kb] (ne: the end)
+            while (kb - ka > 1) {
+                const i32 mid = (ka + kb) >> 1;
+                if (sm.eS[mid] <= tr) ka = mid;
+                else kb = mid;
+            }
+            cur = ka;
+            f(bu + sa + ka, sm.eB[ka] + t0 + tr);
+        }
+        __syncthreads();  // the next block of entries, or what follows the walk
+    }
+}
+
 __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                                             const i32* __restrict__ lo, const i64* __restrict__ G,
                                                             const i32* __restrict__ list, const u32* __restrict__ countp,
@@ -304,15 +440,8 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
                                                             i32* __restrict__ C3, const DevPlan* __restrict__ plan) {
     FGLT_GATE(&plan->err);
     const u32 count = *countp;
-    static_assert(TRI_SAMP <= TRI_BITW, "the sample shares the bitmap's memory");
-    __shared__ u32 bits[TRI_BITW];  // the bitmap, or the sample (never both)
-    i32* const samp = reinterpret_cast<i32*>(bits);
-    __shared__ i32 bpre[TRI_BITW / 8];  // set bits before each group of 8 words
-    __shared__ i32 eS[TRI_ECAP + 1];    // a block of the chunk's entries: their first items (from t0)
-    __shared__ i64 eB[TRI_ECAP];        // and the position of item t (from 0) at ridx[eB + t]
-    __shared__ i32 wsum[TRI_SPLIT_T / WAVE];
-    __shared__ i32 btot;
-    __shared__ i64 s_vi, s_qa, s_qb;
+    __shared__ NbrLds sm;
+    __shared__ i64 s_vi;
     const i64 total = jobpre[count];
     i64 have = -1;  // the list entry whose lookup structure is in LDS
     for (i64 j = blockIdx.x; j < total; j += gridDim.x) {
@@ -325,119 +454,177 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
         const i64 u = list[vi];
         const i64 bu = roff[u] + lo[u];
         const i32 D = (i32)(roff[u + 1] - bu);
-        const i64 span = n - 1 - u;  // ranks above u
-        const bool bm = span <= 32 * (i64)TRI_BITW;
-        const i32 step = 64 * ((D + 64 * TRI_SAMP - 1) / (64 * TRI_SAMP));
-        const i32 ns = (D + step - 1) / step;
+        const NbrLookup nb(u, bu, D, n);
         if (vi != have) {
-            if (bm) {
-                const i32 nw = (i32)((span + 31) >> 5);
-                for (i32 q = threadIdx.x; q < nw; q += TRI_SPLIT_T) bits[q] = 0;
-                __syncthreads();
-                for (i32 k = threadIdx.x; k < D; k += TRI_SPLIT_T) {
-                    const u32 r = (u32)(ridx[bu + k] - u - 1);
-                    atomicOr(&bits[r >> 5], 1u << (r & 31));
-                }
-                __syncthreads();
-                // the position of a set bit in N+(u) is its rank among the set
-                // bits: prefix counts per group of 8 words (3 groups a thread)
-                constexpr int GPT = TRI_BITW / 8 / TRI_SPLIT_T;
-                const i32 ng = (nw + 7) >> 3;
-                i32 gc[GPT], tsum = 0;
-#pragma unroll
-                for (int g = 0; g < GPT; ++g) {
-                    const i32 grp = (i32)threadIdx.x * GPT + g;
-                    i32 cg = 0;
-                    if (grp < ng)
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) cg += grp * 8 + q < nw ? __popc(bits[grp * 8 + q]) : 0;
-                    gc[g] = cg;
-                    tsum += cg;
-                }
-                i32 run = block_scan<TRI_SPLIT_T>(tsum, wsum, &btot);
-#pragma unroll
-                for (int g = 0; g < GPT; ++g) {
-                    bpre[threadIdx.x * GPT + g] = run;
-                    run += gc[g];
-                }
-            } else {
-                for (i32 q = threadIdx.x; q < ns; q += TRI_SPLIT_T) samp[q] = ridx[bu + (i64)q * step];
-            }
+            nb.build(sm, ridx, n);
             have = vi;
         }
         const i64 gb = G[bu];
         const i64 T = G[bu + D] - gb;
-        const i64 c = j - jobpre[vi];
-        const i64 t0 = c * TRI_SPLIT_CH, t1 = std::min<i64>(T, t0 + TRI_SPLIT_CH);
-        // the entries of u holding the chunk's first and last items (entry q
-        // holds items [G[q] - gb, G[q+1] - gb))
-        if (threadIdx.x < WAVE) {
-            const i64 qa = wave_last_le(G + bu, D, gb + t0);
-            const i64 qb = wave_last_le(G + bu, D, gb + t1 - 1);
-            if (threadIdx.x == 0) {
-                s_qa = qa;
-                s_qb = qb;
+        const i64 t0 = (j - jobpre[vi]) * TRI_SPLIT_CH, t1 = std::min<i64>(T, t0 + TRI_SPLIT_CH);
+        walk_items(sm, roff, ridx, lo, G, bu, D, gb, t0, t1, [&](i64 q, i64 e) {
+            const i32 l = nb.find(sm, ridx, ridx[e]);
+            if (l >= 0) {
+                atomicAdd(&C3[bu + l], 1);
+                atomicAdd(&C3[e], 1);
             }
+            wave_run_add(C3, q, l >= 0);  // one add per run of lanes on entry q
+        });
+    }
+}
+
+__device__ __forceinline__ u64 readlane_u64(u64 v, int lane) {
+    const u32 a = (u32)__builtin_amdgcn_readlane((int)(u32)v, lane);
+    const u32 b = (u32)__builtin_amdgcn_readlane((int)(u32)(v >> 32), lane);
+    return (u64)b << 32 | a;
+}
+
+// Calls f(p) for the set bits p of a row of words spread over the lanes
+// (lane z holds word z0 + z: p = 64 (z0 + z) + bit), four at a time -- f gets
+// up to 4 positions and their count -- so that the gathers f issues for them
+// are in flight together.  Wave-uniform.
+template <class F>
+__device__ __forceinline__ void row_bits4(u64 word, i32 z0, F&& f) {
+    u64 nz = __ballot(word != 0);
+    u64 wd = 0;
+    i32 base = 0;
+    for (;;) {
+        i32 p[4];
+        int c = 0;
+        while (c < 4) {
+            if (!wd) {
+                if (!nz) break;
+                const int z = __ffsll((long long)nz) - 1;
+                nz &= nz - 1;
+                wd = readlane_u64(word, z);
+                base = (z0 + z) * 64;
+            }
+            p[c++] = base + __ffsll((long long)wd) - 1;
+            wd &= wd - 1;
+        }
+        if (c) f(p, c);
+        if (c < 4) return;
+    }
+}
+
+// Clique / diamond pass above the LDS tier with the bitmaps in device memory:
+// the list's vertices with dmin < D <= dmax (dmin_nostore in place of dmin
+// when the hub tier stored no bitmaps), one TRI_SPLIT_T-thread workgroup at a
+// time, each with a slot of slot_words >= 2 D ceil(D / 64) words for B (row
+// k: the positions l > k of N+(u) adjacent to v_k, the subgraph H that N+(u)
+// induces) and C = B^T.  The items (u, v_k, y) are walked in chunks as in the
+// split triangle kernel, with y's position l from the same LDS lookup; a hit
+// sets B(k, l) and C(l, k) and adds C3(v_k, y) - 1 to u's diamonds.  Then one
+// wavefront per row k, one word of the row per lane: the triangles of H
+// through k number R + M + X with R = sum over l in B_k of |B_k & B_l| and
+// M + X = sum over j in C_k of |B_j & (B_k | C_k)| (each a 4-clique with u
+// and v_k; R summed over k counts u's own once), and v_k's diamonds add
+// C3(u, v_x) - 1 for every x in B_k | C_k.  A lane reads B_l or B_j only
+// where its own word of the row is non-zero and at or past the word of
+// position l + 1 (j + 1), the first that B_l (B_j) can hold.
+__global__ void __launch_bounds__(TRI_SPLIT_T) k_tri2_big(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                          const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                          const i32* __restrict__ list, const u32* __restrict__ countp,
+                                                          i64 dmin, i64 dmax, i64 dmin_nostore, i64 n,
+                                                          const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                          i64* __restrict__ d13, u64* __restrict__ slots,
+                                                          i64 slot_words, const DevPlan* __restrict__ plan,
+                                                          const u32* __restrict__ storep) {
+    FGLT_GATE(&plan->err);
+    if (storep && !*storep) dmin = dmin_nostore;  // nothing stored: the hub tier's vertices too
+    const u32 count = *countp;
+    constexpr int NWV = TRI_SPLIT_T / WAVE;
+    __shared__ NbrLds sm;
+    __shared__ i64 red[2];
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    u64* const B = slots + (i64)blockIdx.x * slot_words;
+    for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
+        const i64 u = list[it];
+        const i64 bu = roff[u] + lo[u];
+        const i32 D = (i32)(roff[u + 1] - bu);
+        if (D <= dmin || D > dmax) continue;  // another launch takes it (uniform over the workgroup)
+        const i32 W = (D + 63) >> 6;
+        u64* const C = B + (i64)D * W;
+        for (i64 q = threadIdx.x; q < 2 * (i64)D * W; q += TRI_SPLIT_T) B[q] = 0;
+        if (threadIdx.x == 0) red[0] = red[1] = 0;
+        const NbrLookup nb(u, bu, D, n);
+        nb.build(sm, ridx, n);
+        fence_agent();
+        __syncthreads();
+        fence_agent();
+        const i64 gb = G[bu];
+        const i64 T = G[bu + D] - gb;
+        i64 d13u = 0;
+        for (i64 t0 = 0; t0 < T; t0 += TRI_SPLIT_CH)
+            walk_items(sm, roff, ridx, lo, G, bu, D, gb, t0, std::min<i64>(T, t0 + TRI_SPLIT_CH), [&](i64 q, i64 e) {
+                const i32 l = nb.find(sm, ridx, ridx[e]);
+                if (l >= 0) {
+                    const i32 k = (i32)(q - bu);  // l > k: y follows v_k in rank
+                    atomicOr((unsigned long long*)&B[(i64)k * W + (l >> 6)], 1ull << (l & 63));
+                    atomicOr((unsigned long long*)&C[(i64)l * W + (k >> 6)], 1ull << (k & 63));
+                    d13u += (i64)C3[e] - 1;
+                }
+            });
+        fence_agent();
+        __syncthreads();
+        fence_agent();
+        i64 Rsum = 0;
+        for (i32 k = wv; k < D; k += NWV) {
+            const u64* Bk = B + (i64)k * W;
+            const u64* Ck = C + (i64)k * W;
+            i64 R = 0, MX = 0, dv = 0;
+            for (i32 z0 = 0; z0 < W; z0 += WAVE) {
+                const i32 z = z0 + lane;  // this lane's word
+                const u64 bk = z < W ? Bk[z] : 0ull, ck = z < W ? Ck[z] : 0ull;
+                const u64 ak = bk | ck;
+                FOR_BITS(ak, b, dv += (i64)C3[bu + z * 64 + b] - 1);
+                if (!__ballot(ak != 0)) continue;
+                // every set bit of the row (all its words) against this lane's word
+                for (i32 y0 = 0; y0 < W; y0 += WAVE) {
+                    const i32 y = y0 + lane;
+                    const u64 rb = y0 == z0 ? bk : (y < W ? Bk[y] : 0ull);
+                    const u64 rc = y0 == z0 ? ck : (y < W ? Ck[y] : 0ull);
+                    row_bits4(rb, y0, [&](const i32* p, int c) {
+                        u64 x[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            x[i] = i < c && bk && z >= ((p[i] + 1) >> 6) ? B[(i64)p[i] * W + z] : 0ull;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) R += __popcll(bk & x[i]);
+                    });
+                    row_bits4(rc, y0, [&](const i32* p, int c) {
+                        u64 x[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            x[i] = i < c && ak && z >= ((p[i] + 1) >> 6) ? B[(i64)p[i] * W + z] : 0ull;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) MX += __popcll(ak & x[i]);
+                    });
+                }
+            }
+            R = wave_sum(R);
+            MX = wave_sum(MX);
+            dv = wave_sum(dv);
+            if (lane == 0) {
+                const i32 vk = ridx[bu + k];
+                if (R + MX) atomicAdd((unsigned long long*)&k4v[vk], (unsigned long long)(R + MX));
+                if (dv) atomicAdd((unsigned long long*)&d13[vk], (unsigned long long)dv);
+                Rsum += R;
+            }
+        }
+        d13u = wave_sum(d13u);
+        if (lane == 0) {
+            if (Rsum) atomicAdd((unsigned long long*)&red[0], (unsigned long long)Rsum);
+            if (d13u) atomicAdd((unsigned long long*)&red[1], (unsigned long long)d13u);
         }
         __syncthreads();
-        const i64 qa = s_qa, qb = s_qb;
-        // blocks of up to TRI_ECAP entries: their item starts and row
-        // positions in LDS, loaded side by side; then items tid, tid + 1024,
-        // ... of the block, each entry found by a search of the starts
-        for (i64 sa = qa; sa <= qb; sa += TRI_ECAP) {
-            const i32 ne = (i32)std::min<i64>(TRI_ECAP, qb - sa + 1);
-            for (i32 i = threadIdx.x; i < ne; i += TRI_SPLIT_T) {
-                const i64 q = bu + sa + i;
-                const i64 gs = G[q] - gb;
-                const i32 v = ridx[q];
-                eB[i] = roff[v] + lo[v] - gs;
-                eS[i] = (i32)(std::max(gs, t0) - t0);
-            }
-            if (threadIdx.x == 0) eS[ne] = (i32)(std::min(G[bu + sa + ne] - gb, t1) - t0);
-            __syncthreads();
-            const i32 ia = eS[0], ib = eS[ne];
-            i32 cur = 0;
-            for (i32 tr = ia + (i32)threadIdx.x; tr < ib; tr += TRI_SPLIT_T) {
-                i32 ka = cur, kb = ne;  // eS[ka] <= tr < eS[kb] (ne: the end)
-                while (kb - ka > 1) {
-                    const i32 mid = (ka + kb) >> 1;
-                    if (eS[mid] <= tr) ka = mid;
-                    else kb = mid;
-                }
-                cur = ka;
-                const i64 q = bu + sa + ka;
-                const i64 e = eB[ka] + t0 + tr;
-                const i32 y = ridx[e];
-                i64 p = -1;
-                if (bm) {
-                    const u32 r = (u32)(y - u - 1);  // y follows v_k, so u, in rank
-                    const u32 wd = bits[r >> 5];
-                    if ((wd >> (r & 31)) & 1u) {
-                        i32 pos = bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
-                        for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(bits[q]);
-                        p = bu + pos;
-                    }
-                } else {
-                    // last sample entry <= y (entry 0 is below y)
-                    i32 a = 0, b2 = ns;
-                    while (b2 - a > 1) {
-                        const i32 mid = (a + b2) >> 1;
-                        if (samp[mid] <= y) a = mid;
-                        else b2 = mid;
-                    }
-                    const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
-                    const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
-                    if (pp < hi_ && ridx[pp] == y) p = pp;
-                }
-                if (p >= 0) {
-                    atomicAdd(&C3[p], 1);
-                    atomicAdd(&C3[e], 1);
-                }
-                // lanes hold consecutive items, so runs of one entry q: one add per run
-                wave_run_add(C3, q, p >= 0);
-            }
-            __syncthreads();  // the next block of entries, or the next job's lookup structure
+        if (threadIdx.x == 0) {
+            if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
+            if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
         }
+        fence_agent();
+        __syncthreads();  // the slot and the LDS are reused by the next vertex
+        fence_agent();
     }
 }
 
@@ -778,13 +965,13 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         // the hub tier from its stored rows; the rest of the last tier (all of
         // it when nothing is stored) with bitmaps in the workspace
         if ((e = launch_tri2_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tri_block<2, true>), dim3(slots_for(w_mid, 1024)), dim3(PT), 0, s, w.roff, w.ridx,
-                           w.lo, w.rdeg, w.G, l2, cnt + 2, hub_max, d_mid, (i64)0, w.C3, w.k4v, w.d13, w.tri_slots,
-                           w_mid, w.plan, stp);
+        hipLaunchKernelGGL(k_tri2_big, dim3(slots_for(w_mid, 256)), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx, w.lo,
+                           w.G, l2, cnt + 2, hub_max, d_mid, (i64)0, n, w.C3, w.k4v, w.d13, w.tri_slots, w_mid,
+                           (const DevPlan*)w.plan, stp);
         if (dplus > d_mid)
-            hipLaunchKernelGGL((k_tri_block<2, true>), dim3(g2), dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G,
-                               l2, cnt + 2, std::max<i64>(hub_max, d_mid), (i64)INT_MAX, std::max<i64>(hub_max, d_mid),
-                               w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
+            hipLaunchKernelGGL(k_tri2_big, dim3(g2), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx, w.lo, w.G, l2, cnt + 2,
+                               std::max<i64>(hub_max, d_mid), (i64)INT_MAX, std::max<i64>(hub_max, d_mid), n, w.C3,
+                               w.k4v, w.d13, w.tri_slots, w.tri_slot_words, (const DevPlan*)w.plan, stp);
     }
     return hipGetLastError();
 }
