@@ -25,9 +25,6 @@ static constexpr int PT = 256;
 
 __device__ __forceinline__ void fence_agent() { __threadfence(); }
 
-__device__ __forceinline__ i32 load_relaxed(const i32* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ------------------------------------------------------------ row passes
 //
@@ -361,15 +358,15 @@ struct NbrLookup {
             for (i32 q = threadIdx.x; q < ns; q += TRI_SPLIT_T) samp[q] = ridx[bu + (i64)q * step];
         }
     }
-    // Position of y (a rank above u) in N+(u), or -1.
-    __device__ __forceinline__ i32 find(const NbrLds& sm, const i32* __restrict__ ridx, i32 y) const {
+    // Whether y (a rank above u) is in N+(u); pos = the entries of N+(u)
+    // below y (its position there when it is), ascending with y.
+    __device__ __forceinline__ bool locate(const NbrLds& sm, const i32* __restrict__ ridx, i32 y, i32& pos) const {
         if (bm) {
             const u32 r = (u32)(y - u - 1);
             const u32 wd = sm.bits[r >> 5];
-            if (!((wd >> (r & 31)) & 1u)) return -1;
-            i32 pos = sm.bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
+            pos = sm.bpre[r >> 8] + __popc(wd & ((1u << (r & 31)) - 1u));
             for (u32 q = (r >> 8) << 3; q < (r >> 5); ++q) pos += __popc(sm.bits[q]);
-            return pos;
+            return (wd >> (r & 31)) & 1u;
         }
         const i32* const samp = reinterpret_cast<const i32*>(sm.bits);
         i32 a = 0, b = ns;  // the last sample entry <= y (entry 0 is below y)
@@ -380,7 +377,8 @@ struct NbrLookup {
         }
         const i64 lo_ = bu + (i64)a * step, hi_ = std::min<i64>(bu + D, lo_ + step);
         const i64 pp = lower_bound_dev(ridx, lo_, hi_, y);
-        return pp < hi_ && ridx[pp] == y ? (i32)(pp - bu) : -1;
+        pos = (i32)(pp - bu);
+        return pp < hi_ && ridx[pp] == y;
     }
 };
 
@@ -393,7 +391,7 @@ struct NbrLookup {
 // consecutive items, so a wavefront's entries are non-decreasing.  Every
 // thread of the workgroup calls it.
 template <class F>
-__device__ __forceinline__ void walk_items(NbrLds& sm, const i64* __restrict__ roff, const i32* __restrict__ ridx,
+__device__ __forceinline__ void walk_chunk(NbrLds& sm, const i64* __restrict__ roff, const i32* __restrict__ ridx,
                                            const i32* __restrict__ lo, const i64* __restrict__ G, i64 bu, i32 D,
                                            i64 gb, i64 t0, i64 t1, F&& f) {
     if (threadIdx.x < WAVE) {  // the entries holding the first and the last item
@@ -462,13 +460,14 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri1_split(const i64* __restric
         const i64 gb = G[bu];
         const i64 T = G[bu + D] - gb;
         const i64 t0 = (j - jobpre[vi]) * TRI_SPLIT_CH, t1 = std::min<i64>(T, t0 + TRI_SPLIT_CH);
-        walk_items(sm, roff, ridx, lo, G, bu, D, gb, t0, t1, [&](i64 q, i64 e) {
-            const i32 l = nb.find(sm, ridx, ridx[e]);
-            if (l >= 0) {
+        walk_chunk(sm, roff, ridx, lo, G, bu, D, gb, t0, t1, [&](i64 q, i64 e) {
+            i32 l;
+            const bool hit = nb.locate(sm, ridx, ridx[e], l);
+            if (hit) {
                 atomicAdd(&C3[bu + l], 1);
                 atomicAdd(&C3[e], 1);
             }
-            wave_run_add(C3, q, l >= 0);  // one add per run of lanes on entry q
+            wave_run_add(C3, q, hit);  // one add per run of lanes on entry q
         });
     }
 }
@@ -514,7 +513,8 @@ __device__ __forceinline__ void row_bits4(u64 word, i32 z0, F&& f) {
 // k: the positions l > k of N+(u) adjacent to v_k, the subgraph H that N+(u)
 // induces) and C = B^T.  The items (u, v_k, y) are walked in chunks as in the
 // split triangle kernel, with y's position l from the same LDS lookup; a hit
-// sets B(k, l) and C(l, k) and adds C3(v_k, y) - 1 to u's diamonds.  Then one
+// sets B(k, l) (one atomic per word and run of lanes) and adds C3(v_k, y) - 1
+// to u's diamonds, and C follows by 64 x 64 bit transposes.  Then one
 // wavefront per row k, one word of the row per lane: the triangles of H
 // through k number R + M + X with R = sum over l in B_k of |B_k & B_l| and
 // M + X = sum over j in C_k of |B_j & (B_k | C_k)| (each a 4-clique with u
@@ -556,15 +556,33 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri2_big(const i64* __restrict_
         const i64 T = G[bu + D] - gb;
         i64 d13u = 0;
         for (i64 t0 = 0; t0 < T; t0 += TRI_SPLIT_CH)
-            walk_items(sm, roff, ridx, lo, G, bu, D, gb, t0, std::min<i64>(T, t0 + TRI_SPLIT_CH), [&](i64 q, i64 e) {
-                const i32 l = nb.find(sm, ridx, ridx[e]);
-                if (l >= 0) {
+            walk_chunk(sm, roff, ridx, lo, G, bu, D, gb, t0, std::min<i64>(T, t0 + TRI_SPLIT_CH), [&](i64 q, i64 e) {
+                i32 l;
+                const bool hit = nb.locate(sm, ridx, ridx[e], l);
+                if (hit) d13u += (i64)C3[e] - 1;
+                if (__ballot(hit)) {
+                    // lanes hold consecutive items: within one entry k the
+                    // positions l ascend, so the hits bound for one word of
+                    // row k sit in one run of lanes, whose bits (distinct,
+                    // so their sum is their union) go in with one atomic
                     const i32 k = (i32)(q - bu);  // l > k: y follows v_k in rank
-                    atomicOr((unsigned long long*)&B[(i64)k * W + (l >> 6)], 1ull << (l & 63));
-                    atomicOr((unsigned long long*)&C[(i64)l * W + (k >> 6)], 1ull << (k & 63));
-                    d13u += (i64)C3[e] - 1;
+                    const WaveRuns wr = wave_runs(k * (W + 1) + (l >> 6), true);
+                    const u64 bitsum = (u64)run_total(hit ? (i64)(1ull << (l & 63)) : 0, wr);
+                    if (wr.tail && bitsum) atomicOr((unsigned long long*)&B[(i64)k * W + (l >> 6)], bitsum);
                 }
             });
+        fence_agent();
+        __syncthreads();
+        fence_agent();
+        // C = B^T by 64 x 64 blocks (B holds bits l > k only: blocks on and
+        // above the diagonal)
+        for (i32 p = wv; p < W * W; p += NWV) {
+            const i32 bi = p / W, bj = p - bi * W;
+            if (bj < bi) continue;
+            const i32 r = bi * 64 + lane, c = bj * 64 + lane;
+            const u64 t = wave_transpose64(r < D ? B[(i64)r * W + bj] : 0ull);
+            if (c < D) C[(i64)c * W + bi] = t;
+        }
         fence_agent();
         __syncthreads();
         fence_agent();
@@ -628,168 +646,105 @@ __global__ void __launch_bounds__(TRI_SPLIT_T) k_tri2_big(const i64* __restrict_
     }
 }
 
-// Workgroup tiers: out-degree D > 64.  GLOBAL = false keeps bitmaps and lists
-// in LDS (D <= TRI_LDS_MAX); GLOBAL = true keeps them in a per-block slot of
-// device memory (any D up to sqrt(nnz)) of slot_words words: 4 D + 64 for the
-// lists alone (MODE 1), 2 D ceil(D / 64) more for the bitmaps (MODE 2).  A
-// launch takes the list's vertices with dmin < D <= dmax (dmin_nostore in
-// place of dmin for the clique pass when the hub tier stored no bitmaps).
-template <int MODE, bool GLOBAL>
-__global__ void __launch_bounds__(PT) k_tri_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
-                                                  const i32* __restrict__ lo, const i32* __restrict__ rdeg,
-                                                  const i64* __restrict__ G, const i32* __restrict__ list,
-                                                  const u32* __restrict__ countp, i64 dmin, i64 dmax, i64 dmin_nostore,
-                                                  i32* __restrict__ C3, i64* __restrict__ k4v,
-                                                  i64* __restrict__ d13, u64* __restrict__ slots, i64 slot_words,
-                                                  DevPlan* plan,
-    const u32* __restrict__ storep) {
-    // the clique pass from stored bitmaps has counted instead (stored, device flag)
-    if (MODE == 2 && !GLOBAL && storep && *storep) return;
-    if (MODE == 2 && GLOBAL && storep && !*storep) dmin = dmin_nostore;  // nothing stored: the hub tier's vertices too
+// Clique / diamond pass, LDS tier (64 < D <= TRI_LDS_MAX) when the triangle
+// pass stored no bitmaps: one workgroup per vertex rebuilds B (and C = B^T)
+// in LDS from the items (u, v_k, y), y's position in N+(u) by a search of
+// the LDS copy of N+(u) past k, then counts as the kernel above the LDS tier
+// does, one thread per row.
+__global__ void __launch_bounds__(PT) k_tri2_block(const i64* __restrict__ roff, const i32* __restrict__ ridx,
+                                                   const i32* __restrict__ lo, const i64* __restrict__ G,
+                                                   const i32* __restrict__ list, const u32* __restrict__ countp,
+                                                   const i32* __restrict__ C3, i64* __restrict__ k4v,
+                                                   i64* __restrict__ d13, const u32* __restrict__ storep) {
+    if (*storep) return;  // the clique pass from stored bitmaps has counted instead (device flag)
     const u32 count = *countp;  // the tier size, written on the device
     constexpr int DM = TRI_LDS_MAX;
     constexpr int WM = DM / 64;
-    constexpr bool BITS = MODE == 2;
-    __shared__ i32 lL[GLOBAL ? 1 : DM];
-    __shared__ i32 lPre[GLOBAL ? 1 : DM + 1];
-    __shared__ i64 lBv[GLOBAL ? 1 : DM];
-    __shared__ i32 lCnt[GLOBAL ? 1 : DM];
-    __shared__ u64 lB[(GLOBAL || !BITS) ? 1 : DM * WM];
-    __shared__ u64 lC[(GLOBAL || !BITS) ? 1 : DM * WM];
+    __shared__ i32 L[DM];
+    __shared__ i32 Pre[DM + 1];
+    __shared__ i64 Bv[DM];
+    __shared__ i32 Cnt[DM];
+    __shared__ u64 B[DM * WM];
+    __shared__ u64 C[DM * WM];
     __shared__ i64 red[2];
 
     for (i64 it = blockIdx.x; it < (i64)count; it += gridDim.x) {
         const i64 u = list[it];
         const i64 bu = roff[u] + lo[u];
         const int D = (int)(roff[u + 1] - bu);
-        if (D <= dmin || D > dmax) continue;  // another tier or launch takes it (uniform over the block)
         const int W = (D + 63) / 64;
         const i64 gb = G[bu];
-        const i64 T = G[bu + D] - gb;
-        i32 *L, *Pre, *Cnt;
-        i64* Bv;
-        u64 *B, *C;
-        if (GLOBAL) {
-            // the triangle pass needs no bitmaps: its slot holds the lists alone
-            u64* sl = slots + (i64)blockIdx.x * slot_words;
-            B = sl;
-            C = sl + (BITS ? (i64)D * W : 0);
-            u64* rest = BITS ? C + (i64)D * W : sl;
-            Bv = (i64*)rest;
-            L = (i32*)(rest + D);
-            Pre = L + D;               // D + 1 entries
-            Cnt = Pre + D + 2;         // D entries
-        } else {
-            L = lL;
-            Pre = lPre;
-            Bv = lBv;
-            Cnt = lCnt;
-            B = lB;
-            C = lC;
-        }
-        // Pre holds offsets relative to gb; T may exceed 2^31 only for D beyond the LDS tier,
-        // where Pre is read from G directly instead.
+        const i32 T = (i32)(G[bu + D] - gb);  // at most D * TRI_LDS_MAX in this tier
         for (int k = threadIdx.x; k < D; k += blockDim.x) {
             const i32 v = ridx[bu + k];
             L[k] = v;
             Bv[k] = roff[v] + lo[v];
-            if (!GLOBAL) Pre[k] = (i32)(G[bu + k] - gb);
-            Cnt[k] = MODE == 1 ? 0 : C3[bu + k];
+            Pre[k] = (i32)(G[bu + k] - gb);
+            Cnt[k] = C3[bu + k];
         }
-        if (BITS) {
-            for (i64 q = threadIdx.x; q < (i64)D * W; q += blockDim.x) {
-                B[q] = 0;
-                C[q] = 0;
-            }
+        for (int q = threadIdx.x; q < D * W; q += blockDim.x) {
+            B[q] = 0;
+            C[q] = 0;
         }
         if (threadIdx.x == 0) {
-            if (!GLOBAL) Pre[D] = (i32)T;
+            Pre[D] = T;
             red[0] = 0;
             red[1] = 0;
         }
-        if (GLOBAL) fence_agent();
         __syncthreads();
-        if (GLOBAL) fence_agent();
 
         i64 d13u = 0;
-        for (i64 t = threadIdx.x; t < T; t += blockDim.x) {
-            int k;
-            i64 o;
-            if (GLOBAL) {
-                const i64 q = last_le_dev(G, bu, bu + D - 1, gb + t);
-                k = (int)(q - bu);
-                o = gb + t - G[q];
-            } else {
-                k = (int)last_le_dev(Pre, 0, D - 1, (i32)t);
-                o = t - Pre[k];
-            }
-            const i64 e = Bv[k] + o;
+        for (i32 t = threadIdx.x; t < T; t += blockDim.x) {
+            const int k = (int)last_le_dev(Pre, 0, D - 1, t);
+            const i64 e = Bv[k] + (t - Pre[k]);
             const i32 y = ridx[e];
             const int l = (int)lower_bound_dev(L, (i64)k + 1, (i64)D, y);
-            const bool hit = l < D && L[l] == y;
-            // lanes hold consecutive items, so runs of one entry k: one add per run
-            if (MODE == 1) wave_run_add(Cnt, (i64)k, hit);
-            if (hit) {
-                if (MODE == 1) {
-                    atomicAdd(&Cnt[l], 1);
-                    atomicAdd(&C3[e], 1);
-                } else {
-                    atomicOr((unsigned long long*)&B[(i64)k * W + (l >> 6)], 1ull << (l & 63));
-                    atomicOr((unsigned long long*)&C[(i64)l * W + (k >> 6)], 1ull << (k & 63));
-                    d13u += (i64)C3[e] - 1;
-                }
+            if (l < D && L[l] == y) {
+                atomicOr((unsigned long long*)&B[k * W + (l >> 6)], 1ull << (l & 63));
+                atomicOr((unsigned long long*)&C[l * W + (k >> 6)], 1ull << (k & 63));
+                d13u += (i64)C3[e] - 1;
             }
         }
-        if (GLOBAL) fence_agent();
         __syncthreads();
-        if (GLOBAL) fence_agent();
 
-        if (MODE == 1) {
-            for (int k = threadIdx.x; k < D; k += blockDim.x) {
-                const i32 ck = GLOBAL ? load_relaxed(&Cnt[k]) : Cnt[k];
-                if (ck) atomicAdd(&C3[bu + k], ck);
+        i64 Rsum = 0;
+        for (int k = threadIdx.x; k < D; k += blockDim.x) {
+            const u64* Bk = B + k * W;
+            const u64* Ck = C + k * W;
+            i64 R = 0, M = 0, X = 0, dv = 0;
+            for (int wa = 0; wa < W; ++wa) {
+                FOR_BITS(Bk[wa], bb, {
+                    const int l = wa * 64 + bb;
+                    const u64* Bl = B + l * W;
+                    for (int z = 0; z < W; ++z) R += __popcll(Bk[z] & Bl[z]);
+                    dv += Cnt[l] - 1;
+                });
+                FOR_BITS(Ck[wa], bb, {
+                    const int j = wa * 64 + bb;
+                    const u64* Bj = B + j * W;
+                    for (int z = 0; z < W; ++z) {
+                        M += __popcll(Bj[z] & Bk[z]);
+                        X += __popcll(Bj[z] & Ck[z]);
+                    }
+                    dv += Cnt[j] - 1;
+                });
             }
-        } else {
-            i64 Rsum = 0;
-            for (int k = threadIdx.x; k < D; k += blockDim.x) {
-                const u64* Bk = B + (i64)k * W;
-                const u64* Ck = C + (i64)k * W;
-                i64 R = 0, M = 0, X = 0, dv = 0;
-                for (int wa = 0; wa < W; ++wa) {
-                    FOR_BITS(Bk[wa], bb, {
-                        const int l = wa * 64 + bb;
-                        const u64* Bl = B + (i64)l * W;
-                        for (int z = 0; z < W; ++z) R += __popcll(Bk[z] & Bl[z]);
-                        dv += Cnt[l] - 1;
-                    });
-                    FOR_BITS(Ck[wa], bb, {
-                        const int j = wa * 64 + bb;
-                        const u64* Bj = B + (i64)j * W;
-                        for (int z = 0; z < W; ++z) {
-                            M += __popcll(Bj[z] & Bk[z]);
-                            X += __popcll(Bj[z] & Ck[z]);
-                        }
-                        dv += Cnt[j] - 1;
-                    });
-                }
-                const i64 kv = R + M + X;
-                if (kv) atomicAdd((unsigned long long*)&k4v[L[k]], (unsigned long long)kv);
-                if (dv) atomicAdd((unsigned long long*)&d13[L[k]], (unsigned long long)dv);
-                Rsum += R;
-            }
-            Rsum = wave_sum(Rsum);
-            d13u = wave_sum(d13u);
-            if (lane_id() == 0) {
-                if (Rsum) atomicAdd((unsigned long long*)&red[0], (unsigned long long)Rsum);
-                if (d13u) atomicAdd((unsigned long long*)&red[1], (unsigned long long)d13u);
-            }
+            const i64 kv = R + M + X;
+            if (kv) atomicAdd((unsigned long long*)&k4v[L[k]], (unsigned long long)kv);
+            if (dv) atomicAdd((unsigned long long*)&d13[L[k]], (unsigned long long)dv);
+            Rsum += R;
+        }
+        Rsum = wave_sum(Rsum);
+        d13u = wave_sum(d13u);
+        if (lane_id() == 0) {
+            if (Rsum) atomicAdd((unsigned long long*)&red[0], (unsigned long long)Rsum);
+            if (d13u) atomicAdd((unsigned long long*)&red[1], (unsigned long long)d13u);
         }
         __syncthreads();
-        if (MODE == 2 && threadIdx.x == 0) {
+        if (threadIdx.x == 0) {
             if (red[0]) atomicAdd((unsigned long long*)&k4v[u], (unsigned long long)red[0]);
             if (red[1]) atomicAdd((unsigned long long*)&d13[u], (unsigned long long)red[1]);
         }
-        if (GLOBAL) fence_agent();
         __syncthreads();
     }
 }
@@ -927,7 +882,7 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         return (unsigned)std::max<i64>(1, std::min<i64>({tier_bound, region / words, cap}));
     };
     const i64 d_mid = std::min<i64>(TRI_MID_D, dplus);
-    const i64 w_mid = 2 * d_mid * ceil_div(d_mid, 64) + 4 * d_mid + 64;
+    const i64 w_mid = 2 * d_mid * ceil_div(d_mid, 64);
     const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>(tier_bound, (i64)w.tri_nslots));
     hipError_t e;
     if (mode == 1) {
@@ -957,10 +912,8 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
                            w.G, l0, cnt + 0, w.C3, w.k4v, w.d13, w.plan, stp);
         tm.mark(FGLT_SEG_TRI2_LDS, s);
         if ((e = launch_tri2_stored(n, nnz, w, s, 1, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_tri_block<2, false>), dim3(grid_for(std::min<i64>(n, nnz / (2 * TRI_WAVE_MAX) + 1), 1,
-                                                                   65536)),
-                           dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.rdeg, w.G, l1, cnt + 1, (i64)0, (i64)INT_MAX, (i64)0,
-                           w.C3, w.k4v, w.d13, w.tri_slots, w.tri_slot_words, w.plan, stp);
+        hipLaunchKernelGGL(k_tri2_block, dim3(grid_for(std::min<i64>(n, nnz / (2 * TRI_WAVE_MAX) + 1), 1, 65536)),
+                           dim3(PT), 0, s, w.roff, w.ridx, w.lo, w.G, l1, cnt + 1, w.C3, w.k4v, w.d13, stp);
         tm.mark(FGLT_SEG_TRI2_GLOBAL, s);
         // the hub tier from its stored rows; the rest of the last tier (all of
         // it when nothing is stored) with bitmaps in the workspace

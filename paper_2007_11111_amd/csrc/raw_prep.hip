@@ -433,13 +433,14 @@ RawWs carve_raw(Carver& c, i64 n, i64 nnz) {
     w.tri_list = c.take<i32>(3 * nn);
     w.c4_list = c.take<i32>(4 * nn);
     // out-degree under the degree ordering is at most sqrt(nnz): two bitmaps
-    // of D x ceil(D/64) words plus per-row lists fit in tri_slot_words.  The
-    // global-bitmap tier (out-degree above the hub tier's) has as many slots,
-    // and workgroups, as fit max(1 GiB, 2 bytes per entry), from 1 to 64.
+    // of D x ceil(D/64) words fit in tri_slot_words.  The clique pass above
+    // the hub tier has as many slots of that size as fit max(1 GiB, 2 bytes
+    // per entry), from 1 to 64 (its launch for out-degrees up to TRI_MID_D
+    // cuts the same memory into smaller slots).
     i64 dmax_plus = 1;
     while (dmax_plus * dmax_plus <= nnz) ++dmax_plus;
     const i64 words_per_row = ceil_div(dmax_plus, 64);
-    w.tri_slot_words = 2 * dmax_plus * words_per_row + 4 * dmax_plus + 64;
+    w.tri_slot_words = 2 * dmax_plus * words_per_row;
     w.tri_nslots = (int)std::max<i64>(
         1, std::min<i64>(NUM_TRI_SLOTS, std::max<i64>((i64)1 << 30, 2 * nnz) / (8 * w.tri_slot_words)));
     w.tri_slots = c.take<u64>(w.tri_nslots * w.tri_slot_words);
