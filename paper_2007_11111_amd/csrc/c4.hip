@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             const i32 W1 = (i32)std::min<i64>((i64)W0 + WS, u);
             auto run_of = [&](i32 k, i64& s0, i32& len) {
                 if (single) {
-                    const i64 a0 = TAB ? mrs + (ETAB ? tcur : std::min(tcur, mcut)) : lower_bound_dev(ridx, mrs, mhi, W0);
+                    const i64 a0 = TAB ? mrs + (ETAB ? tcur : std::min(tcur, mcut)) : lower_bound_back(ridx, mrs, mhi, W0);
                     s0 = a0;
                     len = (i32)(mhi - a0);
                     mhi = a0;
@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                     } else {
                         const i64 re = rs + cut;
                         s0 = lower_bound_dev(ridx, rs, re, W0);
-                        len = (i32)(lower_bound_dev(ridx, s0, re, W1) - s0);
+                        len = (i32)(lower_bound_fwd(ridx, s0, re, W1) - s0);
                     }
                 }
             };

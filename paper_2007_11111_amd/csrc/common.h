@@ -148,6 +148,35 @@ __device__ __forceinline__ i64 lower_bound_dev(const T* a, i64 lo, i64 hi, K key
     return lo;
 }
 
+// lower_bound_dev for an answer expected near hi: probes hi - 1, hi - 2,
+// hi - 4, ... (one read when the answer is hi), then a binary search of the
+// last gap, so O(log(hi - answer)) reads.
+template <class T, class K>
+__device__ __forceinline__ i64 lower_bound_back(const T* a, i64 lo, i64 hi, K key) {
+    i64 p = hi, step = 1;  // a[p .. hi) >= key
+    while (p > lo) {
+        const i64 q = p - step > lo ? p - step : lo;
+        if (a[q] < key) return lower_bound_dev(a, q + 1, p, key);
+        p = q;
+        step <<= 1;
+    }
+    return lo;
+}
+
+// lower_bound_dev for an answer expected near lo: probes lo, lo + 1, lo + 3,
+// lo + 7, ..., then a binary search of the last gap.
+template <class T, class K>
+__device__ __forceinline__ i64 lower_bound_fwd(const T* a, i64 lo, i64 hi, K key) {
+    i64 p = lo, step = 1;  // a[lo .. p) < key
+    while (p < hi) {
+        const i64 q = p + step - 1 < hi ? p + step - 1 : hi - 1;
+        if (!(a[q] < key)) return lower_bound_dev(a, p, q, key);
+        p = q + 1;
+        step <<= 1;
+    }
+    return hi;
+}
+
 // Last index r in [lo, hi] with a[r] <= key (lo - 1 if none).
 template <class T, class K>
 __device__ __forceinline__ i64 last_le_dev(const T* a, i64 lo, i64 hi, K key) {
