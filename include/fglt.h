@@ -72,6 +72,10 @@ typedef enum {
 #define FGLT_SIGMA5 FGLT_SIGMA(0x001fu)  /* Theorem 1: orbits 0-4, [n][5] */
 #define FGLT_VALIDATE 16u    /* wait for the transform and return the device status word's
                                 verdict (FGLT_ENOTCANON, FGLT_EOVERFLOW) instead of FGLT_OK */
+#define FGLT_PROGRESS 32u    /* report each launch segment's end on stderr as the stream
+                                reaches it (a host function enqueued on `stream`; the 4-cycle
+                                window kernels report one by one): a line per step of a
+                                transform that runs for minutes                            */
 #define FGLT_WORKMODEL 8u    /* also count the work terms of the byte model (statistics only,
                                 not part of the transform; needs `stats`): min_sum and
                                 k4_merge of fglt_stats                                    */
@@ -177,7 +181,7 @@ typedef struct {
  *                self-loops, no repeated entry in a row (rows need not be sorted)
  *   out          out [n][16] int64, or [n][|s|] with a sub-dictionary FGLT_SIGMA(s)
  *   ws, ws_bytes device workspace of at least fglt_raw_workspace(n, nnz) bytes
- *   flags        FGLT_NET, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL and a
+ *   flags        FGLT_NET, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL, FGLT_PROGRESS and a
  *                sub-dictionary FGLT_SIGMA(s), or 0; a mask without orbits 0
  *                and 1 is FGLT_EINVAL
  *   plan         (host) optional tier thresholds, NULL for the defaults
@@ -215,7 +219,7 @@ int fglt_raw_status(const void* ws, void* stream);
  * itself allocates nothing (no hipMalloc, no stream or event creation; it
  * runs every kernel on `stream`).
  *   n, nnz, offsets, indices, out, flags, plan, stats   as for fglt_raw;
- *                FGLT_TIMING is not offered (FGLT_EINVAL); FGLT_VALIDATE is
+ *                FGLT_TIMING and FGLT_PROGRESS are not offered (FGLT_EINVAL); FGLT_VALIDATE is
  *                implied (the caller cannot reach the array's status word)
  * Returns FGLT_EWORKSPACE when fglt_raw_workspace(n, nnz) exceeds
  * FGLT_NOALLOC_SCRATCH_BYTES (1.2M to 1.6M directed entries fit).  Every call

@@ -15,7 +15,7 @@ import ctypes
 
 import torch
 
-from ._lib import FGLT_NET, FGLT_SIGMA, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
+from ._lib import FGLT_NET, FGLT_PROGRESS, FGLT_SIGMA, FGLT_TIMING, FGLT_VALIDATE, FGLT_WORKMODEL, NORBITS, SEGMENTS, BatchPlan, FgltError, RawPlan, Stats, check, lib
 
 __all__ = [
     "build_csr", "raw", "raw_status", "net", "transform", "raw_workspace_bytes", "sigma_mask", "FgltError", "Stats",
@@ -86,7 +86,7 @@ def raw_workspace_bytes(n: int, nnz: int) -> int:
 def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out: torch.Tensor | None = None,
         workspace: torch.Tensor | None = None, stats: bool = False, plan: dict | None = None,
         timing: bool = False, sigma=None, sigma5: bool = False, workmodel: bool = False, validate: bool = True,
-        stream=None):
+        progress: bool = False, stream=None):
     """Raw frequencies (Table I) per vertex -- ``fglt_raw``; with net=True the
     net frequencies (Table I then Table II).  Returns an int64 [n, 16] tensor
     (and a dict of plan statistics when stats=True).  ``sigma`` selects a
@@ -101,7 +101,9 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
     timing=True the statistics carry per-segment milliseconds (HIP events); with
     workmodel=True (and stats=True) they carry the byte model's work terms
-    min_sum and k4_merge (a statistics pass after the transform)."""
+    min_sum and k4_merge (a statistics pass after the transform); with
+    progress=True each launch segment's end is printed on stderr as the stream
+    reaches it."""
     L = lib()
     assert offsets.dtype == torch.int64 and indices.dtype == torch.int32
     assert offsets.is_cuda and indices.is_cuda
@@ -129,7 +131,8 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
                      int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | FGLT_SIGMA(mask)
                      | (FGLT_VALIDATE if validate else 0)
-                     | (FGLT_WORKMODEL if workmodel else 0), ctypes.byref(rp) if rp is not None else None,
+                     | (FGLT_WORKMODEL if workmodel else 0) | (FGLT_PROGRESS if progress else 0),
+                     ctypes.byref(rp) if rp is not None else None,
                      ctypes.byref(st) if stats else None, _stream(stream)),
           "fglt_raw")
     return (out, st.as_dict()) if stats else out

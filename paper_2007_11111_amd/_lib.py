@@ -35,6 +35,7 @@ class FgltError(RuntimeError):
 FGLT_TIMING = 2
 FGLT_WORKMODEL = 8
 FGLT_VALIDATE = 16
+FGLT_PROGRESS = 32
 
 
 def FGLT_SIGMA(mask: int) -> int:

@@ -1,11 +1,26 @@
 // api.hip -- C ABI entry points of the single-graph transform (fglt_raw,
 // fglt_net) and the status helpers.  See include/fglt.h.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <initializer_list>
 
 #include "raw.h"
 
 using namespace fglt;
+
+const char* const fglt::kSegNames[FGLT_NSEG] = {
+    "check", "relabel", "structure", "tri1_wave", "tri1_lds", "tri1_global", "fill", "tri2_wave",
+    "tri2_lds", "tri2_global", "l2", "c4_wave", "c4_block", "c4_hash", "c4_window", "finalize"};
+
+// Runs on the runtime's callback thread when the stream reaches it; makes no HIP call.
+void fglt::progress_line(void* what) {
+    using clk = std::chrono::steady_clock;
+    static const clk::time_point t0 = clk::now();
+    const double sec = std::chrono::duration<double>(clk::now() - t0).count();
+    std::fprintf(stderr, "fglt: %s done (%.1f s)\n", static_cast<const char*>(what), sec);
+    std::fflush(stderr);
+}
 
 namespace {
 
@@ -71,6 +86,7 @@ static SubPasses sub_passes(unsigned s) {
 // the status stays on the device (fglt_raw_status).
 int finish(int64_t n, int64_t nnz, RawWs& w, SegTimer& tm, unsigned flags, fglt_stats* stats, hipStream_t s) {
     if (tm.on) FGLT_HIP_TRY(hipEventRecord(tm.ev[FGLT_NSEG], s));
+    if (tm.last >= 0) tm.note(kSegNames[tm.last], s);
     if (!stats && !(flags & FGLT_VALIDATE)) return FGLT_OK;
     if (stats) {
         FGLT_HIP_TRY(launch_count_triangles(n, w, s));
@@ -126,7 +142,8 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
     if (n < 0 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (n > 0 && (!offsets || !out || !ws)) return FGLT_EINVAL;
     if (nnz > 0 && !indices) return FGLT_EINVAL;
-    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_WORKMODEL | FGLT_VALIDATE | FGLT_SIGMA(0xffffu))) return FGLT_EINVAL;
+    if (flags & ~(FGLT_NET | FGLT_TIMING | FGLT_WORKMODEL | FGLT_VALIDATE | FGLT_PROGRESS | FGLT_SIGMA(0xffffu)))
+        return FGLT_EINVAL;
     // the sub-dictionary (Section V): every orbit by default; {0, 1} in any subset
     const unsigned smask = FGLT_SIGMA_MASK(flags) ? FGLT_SIGMA_MASK(flags) : 0xffffu;
     if ((smask & 3u) != 3u) return FGLT_EINVAL;
@@ -154,6 +171,7 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         for (auto& e : tm.ev) FGLT_HIP_TRY(hipEventCreate(&e));
         tm.on = true;
     }
+    tm.progress = (flags & FGLT_PROGRESS) != 0;
 
     // 1. input checks into the device status word; every later kernel that
     // indexes by the input's values leaves at once if a check failed

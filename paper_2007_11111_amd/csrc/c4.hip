@@ -1080,6 +1080,7 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
     if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2);
     if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0);
     else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0);
+    tm.note("c4_window (16-bit counters)", s);
     if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0);
     else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
 #undef C4W_LAUNCH

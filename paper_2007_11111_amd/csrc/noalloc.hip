@@ -41,7 +41,7 @@ extern "C" int fglt_raw_noalloc(int64_t n, int64_t nnz, const int64_t* offsets, 
                                 int64_t* out, unsigned flags, const fglt_raw_plan* plan, fglt_stats* stats,
                                 void* stream) {
     // timing creates HIP events: not offered here
-    if (flags & FGLT_TIMING) return FGLT_EINVAL;
+    if (flags & (FGLT_TIMING | FGLT_PROGRESS)) return FGLT_EINVAL;
     if (n < 0 || nnz < 0) return FGLT_EINVAL;
     if (n >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 40)) return FGLT_EINVAL;
     if (fglt_raw_workspace(n, nnz) > (size_t)FGLT_NOALLOC_SCRATCH_BYTES) return FGLT_EWORKSPACE;

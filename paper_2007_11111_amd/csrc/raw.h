@@ -26,7 +26,7 @@ static_assert((TRI_HUB_MAX - 1) * (TRI_HUB_MAX - 2) / 2 < (1 << EK_SHIFT), "hub 
 constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slot LDS hash)
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
-constexpr int TRI_MID_D = 4096;      // global-bitmap clique tier: out-degree of its many-slot launch
+constexpr int TRI_MID_D = 4096;      // clique tier above the hub tier: out-degree bound of its first launch (then doubling)
 constexpr int NUM_TRI_SLOTS = 64;    // at most this many workgroups in the global-bitmap clique tier
 constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
@@ -145,16 +145,24 @@ hipError_t launch_structure(i64 n, i64 nnz, RawWs& w, const Tiers& t, bool with_
                             hipStream_t s);
 
 // counting (raw_count.hip)
-// Optional event marks between launches (FGLT_TIMING).
+// Optional event marks between launches (FGLT_TIMING) and progress lines
+// (FGLT_PROGRESS: a host function on the stream prints a step's end on
+// stderr when the stream gets there).
+void progress_line(void* what);  // what: a static C string
+extern const char* const kSegNames[FGLT_NSEG];
 struct SegTimer {
     hipEvent_t ev[FGLT_NSEG + 1] = {};
     bool on = false;
+    bool progress = false;
     int last = -1;
     // records the start of segment `seg` (and thereby the end of the previous one)
     void mark(int seg, hipStream_t s) {
-        if (!on) return;
-        (void)hipEventRecord(ev[seg], s);
+        if (progress && last >= 0) note(kSegNames[last], s);
+        if (on) (void)hipEventRecord(ev[seg], s);
         last = seg;
+    }
+    void note(const char* what, hipStream_t s) const {
+        if (progress) (void)hipLaunchHostFunc(s, progress_line, const_cast<char*>(what));
     }
 };
 

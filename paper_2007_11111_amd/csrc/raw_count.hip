@@ -872,8 +872,8 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
     const i32* l2 = w.tri_list + 2 * n;
     // the last tier's bound: vertices of out-degree above the LDS tier's.  The
     // clique pass shares out the global-bitmap slots' memory by the largest
-    // out-degree a launch takes: the bitmaps of out-degree up to TRI_MID_D
-    // (many slots), then the rest (slots for the largest out-degree)
+    // out-degree a launch takes: out-degree up to TRI_MID_D, then ranges of
+    // doubling out-degree, each launch with slots for its own largest bitmaps
     const i64 region = (i64)w.tri_nslots * w.tri_slot_words;
     i64 dplus = 1;  // above every out-degree (the degree order keeps them below sqrt(nnz))
     while (dplus * dplus <= nnz) ++dplus;
@@ -882,8 +882,6 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         return (unsigned)std::max<i64>(1, std::min<i64>({tier_bound, region / words, cap}));
     };
     const i64 d_mid = std::min<i64>(TRI_MID_D, dplus);
-    const i64 w_mid = 2 * d_mid * ceil_div(d_mid, 64);
-    const unsigned g2 = (unsigned)std::max<i64>(1, std::min<i64>(tier_bound, (i64)w.tri_nslots));
     hipError_t e;
     if (mode == 1) {
         // triangle pass; the wave, LDS and hub tiers also store their N+ bitmaps
@@ -918,13 +916,18 @@ hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream
         // the hub tier from its stored rows; the rest of the last tier (all of
         // it when nothing is stored) with bitmaps in the workspace
         if ((e = launch_tri2_stored(n, nnz, w, s, 2, hub_max)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tri2_big, dim3(slots_for(w_mid, 256)), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx, w.lo,
-                           w.G, l2, cnt + 2, hub_max, d_mid, (i64)0, n, w.C3, w.k4v, w.d13, w.tri_slots, w_mid,
-                           (const DevPlan*)w.plan, stp);
-        if (dplus > d_mid)
-            hipLaunchKernelGGL(k_tri2_big, dim3(g2), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx, w.lo, w.G, l2, cnt + 2,
-                               std::max<i64>(hub_max, d_mid), (i64)INT_MAX, std::max<i64>(hub_max, d_mid), n, w.C3,
-                               w.k4v, w.d13, w.tri_slots, w.tri_slot_words, (const DevPlan*)w.plan, stp);
+        // out-degree ranges (hub_max, d_mid], (d_mid, 2 d_mid], (2 d_mid, 4 d_mid], ...,
+        // each with as many slots for its largest bitmaps as the memory holds
+        // (up to 256 workgroups: one per CU, the kernel's LDS allows no more)
+        for (i64 a = hub_max, b = d_mid, first = 1;; a = b, b *= 2, first = 0) {
+            const i64 top = std::min(b, dplus);
+            const i64 words = 2 * top * ceil_div(top, 64);
+            hipLaunchKernelGGL(k_tri2_big, dim3(slots_for(words, 256)), dim3(TRI_SPLIT_T), 0, s, w.roff, w.ridx,
+                               w.lo, w.G, l2, cnt + 2, a, b >= dplus ? (i64)INT_MAX : b, first ? (i64)0 : a, n,
+                               w.C3, w.k4v, w.d13, w.tri_slots, words, (const DevPlan*)w.plan, stp);
+            if (b >= dplus) break;
+            tm.note("tri2_global (an out-degree range)", s);
+        }
     }
     return hipGetLastError();
 }

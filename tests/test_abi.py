@@ -65,11 +65,12 @@ def test_host_argument_checks_need_no_device(lib):
     # unknown flag bits
     assert lib.fglt_raw(0, 0, None, None, None, None, 0, 0x80, None, None, None) == -1
     # the empty graph is a no-op, with every defined flag (FGLT_NET 1, FGLT_TIMING 2,
-    # FGLT_WORKMODEL 8, FGLT_VALIDATE 16, sub-dictionary masks in bits 16..31 that
-    # hold orbits 0 and 1)
-    for flags in (0, 1, 2, 3, 8, 11, 16, 27, 0x1F << 16, (0x1F << 16) | 1, (0x8003 << 16) | 3, 0xFFFF << 16):
+    # FGLT_WORKMODEL 8, FGLT_VALIDATE 16, FGLT_PROGRESS 32, sub-dictionary masks in
+    # bits 16..31 that hold orbits 0 and 1)
+    for flags in (0, 1, 2, 3, 8, 11, 16, 27, 32, 59, 0x1F << 16, (0x1F << 16) | 1, (0x8003 << 16) | 3,
+                  0xFFFF << 16):
         assert lib.fglt_raw(0, 0, None, None, None, None, 0, flags, None, None, None) == 0
-    for flags in (4, 32, 0x80, 0x1E << 16, 0x1D << 16, 0x8000 << 16):
+    for flags in (4, 64, 0x80, 0x1E << 16, 0x1D << 16, 0x8000 << 16):
         assert lib.fglt_raw(0, 0, None, None, None, None, 0, flags, None, None, None) == -1
     lib.fglt_net.restype = ctypes.c_int
     lib.fglt_net.argtypes = [ctypes.c_int64, vp, vp, vp]
@@ -86,9 +87,9 @@ def test_binding_flags_match_header():
     import re
     from paper_2007_11111_amd import _lib
     hdr = open(os.path.join(ROOT, "include", "fglt.h")).read()
-    defs = {k: int(v) for k, v in re.findall(r"#define FGLT_(NET|TIMING|WORKMODEL|VALIDATE) (\d+)u", hdr)}
+    defs = {k: int(v) for k, v in re.findall(r"#define FGLT_(NET|TIMING|WORKMODEL|VALIDATE|PROGRESS) (\d+)u", hdr)}
     assert defs == {"NET": _lib.FGLT_NET, "TIMING": _lib.FGLT_TIMING, "WORKMODEL": _lib.FGLT_WORKMODEL,
-                    "VALIDATE": _lib.FGLT_VALIDATE}
+                    "VALIDATE": _lib.FGLT_VALIDATE, "PROGRESS": _lib.FGLT_PROGRESS}
     # the sub-dictionary field: FGLT_SIGMA(mask) puts the 16-bit mask in bits 16..31
     assert re.search(r"#define FGLT_SIGMA\(mask\) \(\(unsigned\)\(\(mask\) & 0xffffu\) << 16\)", hdr)
     assert re.search(r"#define FGLT_SIGMA5 FGLT_SIGMA\(0x001fu\)", hdr)

@@ -11,7 +11,10 @@ transform timed with HIP events (one call, with per-segment events),
 whole-graph invariants of the net counts, and
 a degree-stratified vertex sample recomputed by the oracle (vertices whose
 two-hop oracle cost stays bounded).  FGLT_FRIENDSTER_OUT names a JSON file for
-the measured figures.
+the measured figures.  FGLT_FRIENDSTER_WS_EXTRA_GB gives the transform that
+many GiB of workspace beyond fglt_raw_workspace's minimum (default 0): the
+library keeps the triangle pass's neighbourhood bitmaps there for the clique
+pass when all of them fit, instead of forming them again.
 """
 import json
 import os
@@ -91,7 +94,8 @@ def test_friendster_scale_sigma(fg):
     oracle_s = time.perf_counter() - t
     say(f"friendster-scale: oracle sample in {oracle_s:.1f} s")
     nnz = int(idx.numel())
-    ws = torch.empty(fg.raw_workspace_bytes(n, nnz), dtype=torch.uint8, device="cuda")
+    extra = int(float(os.environ.get("FGLT_FRIENDSTER_WS_EXTRA_GB", "0")) * 2 ** 30)
+    ws = torch.empty(fg.raw_workspace_bytes(n, nnz) + extra, dtype=torch.uint8, device="cuda")
     report = {"workload": f"rmat_scale{scale}_ef27_abcd0.57-0.19-0.19-0.05_permuted_chunked", "n": n,
               "m": nnz // 2, "d_max": int(deg.max()), "isolated": int((deg == 0).sum()),
               "generate_s": round(gen_s, 1), "build_csr_ms": round(build_ms, 1),
@@ -103,7 +107,8 @@ def test_friendster_scale_sigma(fg):
         say(f"friendster-scale: transform sigma={hex(mask)}")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        _, st = fg.raw(off, idx, net=True, out=out, workspace=ws, sigma=mask, stats=True, timing=True)
+        _, st = fg.raw(off, idx, net=True, out=out, workspace=ws, sigma=mask, stats=True, timing=True,
+                       progress=True)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)

@@ -5,6 +5,7 @@ through each kernel tier on small graphs, so each tier is checked against the
 oracle, not only the tiers a graph would pick by itself.
 """
 import math
+import re
 
 import numpy as np
 import pytest
@@ -123,12 +124,13 @@ def test_small_random_all_tiers(fg, plan):
 
 # ------------------------------------------------------------------ closed forms
 
-@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600, 1070, 1100])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 30, 70, 600, 1070, 1100, 4200])
 def test_clique(fg, n):
     """K_n: out-degree n-1 of the lowest vertex (600 reaches the hub tier,
     1070 its second round of out-neighbours per thread, 1100 the
-    global-bitmap tier beyond it, and the top vertex's (n-1)(n-2) wedges the
-    heavy 4-cycle tier)."""
+    global-bitmap tier beyond it, 4200 the clique launch for out-degrees
+    above 4096, and the top vertex's (n-1)(n-2) wedges the heavy 4-cycle
+    tier)."""
     g = graphgen.clique(n)
     say(f"clique n={n}")
     off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
@@ -301,6 +303,23 @@ def test_stats(fg):
     # vertices with one out-neighbour have merge items but no triangle: no tier takes them
     assert sum(st["tri_items_tier"]) <= st["tri_items"]
     assert st["d_max"] == int(np.diff(off).max())
+
+
+def test_progress_lines(fg, capfd):
+    """FGLT_PROGRESS: each launch segment's end on stderr, in order, the
+    finalize last; the counts are those of a call without it."""
+    g = graphgen.chung_lu(20_000, 2.1, 16.0, 2000.0, seed=7)
+    off, idx = oracle.canonical_csr(g.n, g.src, g.dst)
+    o, i = to_dev(off, idx)
+    want = fg.raw(o, i, net=True).cpu().numpy()
+    capfd.readouterr()
+    got = fg.raw(o, i, net=True, progress=True)
+    torch.cuda.synchronize()
+    lines = [ln for ln in capfd.readouterr().err.splitlines() if ln.startswith("fglt: ")]
+    np.testing.assert_array_equal(got.cpu().numpy(), want)
+    names = [m.group(1) for m in (re.match(r"fglt: (\w+) done \(", ln) for ln in lines) if m]
+    assert names[0] == "check" and names[-1] == "finalize", lines
+    assert names == [s for s in fg._lib.SEGMENTS if s in names], lines  # each once, in launch order
 
 
 def test_barabasi_albert_and_rmat_small(fg):
