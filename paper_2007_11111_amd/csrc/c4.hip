@@ -489,6 +489,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const i32* __restrict__ hs_all, const DevPlan* __restrict__ plan,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
                                                           u32* __restrict__ scr, i64 scr_cap, int etab_mode,
+                                                          i32 group, i64 cur_n,
                                                           i64* __restrict__ esum, i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
     // the part of the window list this launch takes (16-bit counters: the
@@ -524,9 +525,14 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ MS msum[NMS * CB_THREADS];
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
-    // the last 64 words of the slice are a sink that nobody reads
-    const i64 scr_use = scr_cap - WAVE;
-    const u32 sink = (u32)(scr_use + lane_id());
+    // the last 64 words of the slice are a sink that nobody reads; with
+    // grouped windows (searched runs, 16-bit counts) the cur_n words before
+    // them hold each middle's run in the current window: start (from the
+    // middle's row cut back) | length << 16, both below 2^16
+    const bool grouped = PACK16 && TABM == 0 && group > 1;
+    const i64 scr_use = scr_cap - WAVE - (grouped ? cur_n : 0);
+    const u32 sink = (u32)(scr_cap - WAVE + lane_id());
+    u32* const runw = sc + scr_use;
     __shared__ i64 sj, sh, red;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
@@ -557,8 +563,9 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
         // windows below wlo hold only ranks of degree <= 1: every count there
         // is at most 1 and adds nothing, so they are not visited
-        const i32 wtop = single ? nwin - 1 : nwin - 1 - (i32)(j - jobpre[h]);
-        const i32 wbot = single ? wlo : wtop;
+        // a larger vertex: `group` windows per job (one unless grouped)
+        const i32 wtop = single ? nwin - 1 : nwin - 1 - group * (i32)(j - jobpre[h]);
+        const i32 wbot = single ? wlo : (wtop - group + 1 > wlo ? wtop - group + 1 : wlo);
         const i64 eb = ETAB ? ebase[nh - 1 - h] : 0;  // this vertex's block of etab: [window][middle]
         // one chunk: thread k keeps middle k and the end of its not yet
         // visited run (windows go top-down, so each run ends where the
@@ -624,6 +631,23 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         };
                         s0 = pos_of(W0);
                         len = (i32)(pos_of(W1) - s0);
+                    } else if (grouped) {
+                        // pass A (the loaded values): the run ends where the
+                        // previous window's run began (a search of the row for
+                        // the job's top window), and its start comes by
+                        // galloping back from there; pass C reads what pass A
+                        // stored (same thread, same k)
+                        const i64 re = rs + cut;
+                        if (!prefetched) {
+                            const u32 rw = runw[k];
+                            s0 = re - (i64)(rw & 0xffffu);
+                            len = (i32)(rw >> 16);
+                        } else {
+                            const i64 e = win == wtop ? lower_bound_dev(ridx, rs, re, W1) : re - (i64)(runw[k] & 0xffffu);
+                            s0 = lower_bound_back(ridx, rs, e, W0);
+                            len = (i32)(e - s0);
+                            runw[k] = (u32)(re - s0) | ((u32)len << 16);
+                        }
                     } else {
                         const i64 re = rs + cut;
                         s0 = lower_bound_dev(ridx, rs, re, W0);
@@ -943,7 +967,7 @@ __global__ void k_c4_segment(i64* p, const DevPlan* __restrict__ plan) {
 // chunk, else one per window (none when no window is left); zero from the
 // part's size up to `bound`, so that the prefix over `bound` entries holds.
 __global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict__ lo, const DevPlan* __restrict__ plan,
-                          int heavy, i64 WS, i64 bound, i64* __restrict__ jobcnt) {
+                          int heavy, i64 WS, i64 group, i64 bound, i64* __restrict__ jobcnt) {
     FGLT_GATE(&plan->err);
     const i32* hs;
     u32 nh;
@@ -954,7 +978,7 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict_
         if (h < (i64)nh) {
             const i64 u = hs[nh - 1 - h];
             const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
-            c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : nw;
+            c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : (nw + group - 1) / group;
         }
         jobcnt[h] = c;
     }
@@ -975,6 +999,11 @@ struct C4WinCfg {
     bool use_tab, want_etab;
     i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
     i64 bound_l, bound_h;  // entries of the job arrays of each part (at least its size)
+    // searched runs (no table), 16-bit counters: windows per job of a vertex
+    // with more than one chunk of middles, when the scratch slice also holds
+    // a run word for each middle (cur_n = min(65536, n) of them) and still
+    // keeps three quarters for the wedge ends
+    i64 group, cur_n;
 };
 
 static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
@@ -991,6 +1020,8 @@ static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
     c.want_etab = rows_mode == 0 && c.use_tab;
     c.bound_l = n;
     c.bound_h = std::min<i64>(n, (nnz >> 16) + 1);  // vertices of degree >= 65536
+    c.cur_n = std::min<i64>(65536, std::max<i64>(n, 1));
+    c.group = !c.use_tab && w.c4_scr_cap >= 4 * c.cur_n + WAVE ? C4W_GROUP : 1;
     static_assert(C4W_WS16 == C4W_SPAN, "the tier assignment sizes the table with this window");
     return c;
 }
@@ -1028,7 +1059,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
         hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n,
                            c.K1, c.TS, C4W_WS16, w.c4_tab, (const DevPlan*)w.plan);
     hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_l, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
-                       (const DevPlan*)w.plan, 0, C4W_WS16, c.bound_l, w.c4_jobcnt);
+                       (const DevPlan*)w.plan, 0, C4W_WS16, c.group, c.bound_l, w.c4_jobcnt);
     if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.bound_l, w.partials, s)) != hipSuccess) return e;
     if (c.want_etab) {
         // c4_jobcnt is free again once the job prefix is built: the chunk counts
@@ -1038,7 +1069,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.bound_l, w.partials, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_h, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
-                       (const DevPlan*)w.plan, 1, C4W_WS32, c.bound_h, w.c4_hjobcnt);
+                       (const DevPlan*)w.plan, 1, C4W_WS32, (i64)1, c.bound_h, w.c4_hjobcnt);
     if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.bound_h, w.partials, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1072,17 +1103,17 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
         hipError_t e = fill_u32(reinterpret_cast<u32*>(w.ek), 2 * nnz, 0u, s);
         if (e != hipSuccess) return e;
     }
-#define C4W_LAUNCH(P16, TM, PRE, CTR, EM)                                                                          \
+#define C4W_LAUNCH(P16, TM, PRE, CTR, EM, GRP)                                                                     \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
-                       w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM, w.ek,   \
-                       w.c4v)
+                       w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM,         \
+                       (i32)(GRP), c.cur_n, w.ek, w.c4v)
     // the per-entry table where it fits (decided on the device), else the vertex table
-    if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2);
-    if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0);
-    else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0);
+    if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2, 1);
+    if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0, 1);
+    else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0, c.group);
     tm.note("c4_window (16-bit counters)", s);
-    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0);
-    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0);
+    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1);
+    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1);
 #undef C4W_LAUNCH
     if (nnz > 0)
         hipLaunchKernelGGL(k_c4_esum_flush, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, w.ridx,
