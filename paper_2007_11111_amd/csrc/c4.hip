@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                                           const i32* __restrict__ hs_all, const DevPlan* __restrict__ plan,
                                                           const i64* __restrict__ jobpre, u32* __restrict__ job_ctr,
                                                           u32* __restrict__ scr, i64 scr_cap, int etab_mode,
-                                                          i32 group, i64 cur_n,
+                                                          i32 group, i64 lmax,
                                                           i64* __restrict__ esum, i64* __restrict__ c4v) {
     constexpr i32 WS = PACK16 ? 2 * C4W_WORDS : C4W_WORDS;
     // the part of the window list this launch takes (16-bit counters: the
@@ -525,14 +525,16 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ MS msum[NMS * CB_THREADS];
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
-    // the last 64 words of the slice are a sink that nobody reads; with
-    // grouped windows (searched runs, 16-bit counts) the cur_n words before
-    // them hold each middle's run in the current window: start (from the
-    // middle's row cut back) | length << 16, both below 2^16
-    const bool grouped = PACK16 && TABM == 0 && group > 1;
-    const i64 scr_use = scr_cap - WAVE - (grouped ? cur_n : 0);
+    // the last 64 words of the slice are a sink that nobody reads.  Grouped
+    // windows (searched runs, vertices of at most lmax middles) keep each
+    // middle's run in the current window in the slice: with 16-bit counts one
+    // word per middle before the sink, start (back from the middle's row
+    // cut) | length << 16, both below 2^16; with 32-bit counts (no copy of
+    // the ends) two words per middle from the slice's start
+    const bool grouped = TABM == 0 && group > 1;
+    const i64 scr_use = scr_cap - WAVE - (grouped && PACK16 ? lmax : 0);
     const u32 sink = (u32)(scr_cap - WAVE + lane_id());
-    u32* const runw = sc + scr_use;
+    u32* const runw = PACK16 ? sc + scr_use : sc;
     __shared__ i64 sj, sh, red;
     const int wv = threadIdx.x / WAVE, l = lane_id();
     const i64 njobs = jobpre[nh];
@@ -563,9 +565,12 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
         // windows below wlo hold only ranks of degree <= 1: every count there
         // is at most 1 and adds nothing, so they are not visited
-        // a larger vertex: `group` windows per job (one unless grouped)
-        const i32 wtop = single ? nwin - 1 : nwin - 1 - group * (i32)(j - jobpre[h]);
-        const i32 wbot = single ? wlo : (wtop - group + 1 > wlo ? wtop - group + 1 : wlo);
+        // a larger vertex: `group` windows per job when grouped and its
+        // middles' run words fit, else one
+        const bool grp = grouped && !single && (i64)L <= lmax;
+        const i32 gsz = grp ? group : 1;
+        const i32 wtop = single ? nwin - 1 : nwin - 1 - gsz * (i32)(j - jobpre[h]);
+        const i32 wbot = single ? wlo : (wtop - gsz + 1 > wlo ? wtop - gsz + 1 : wlo);
         const i64 eb = ETAB ? ebase[nh - 1 - h] : 0;  // this vertex's block of etab: [window][middle]
         // one chunk: thread k keeps middle k and the end of its not yet
         // visited run (windows go top-down, so each run ends where the
@@ -631,7 +636,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         };
                         s0 = pos_of(W0);
                         len = (i32)(pos_of(W1) - s0);
-                    } else if (grouped) {
+                    } else if (grp) {
                         // pass A (the loaded values): the run ends where the
                         // previous window's run began (a search of the row for
                         // the job's top window), and its start comes by
@@ -639,14 +644,25 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         // stored (same thread, same k)
                         const i64 re = rs + cut;
                         if (!prefetched) {
-                            const u32 rw = runw[k];
-                            s0 = re - (i64)(rw & 0xffffu);
-                            len = (i32)(rw >> 16);
+                            if (PACK16) {
+                                const u32 rw = runw[k];
+                                s0 = re - (i64)(rw & 0xffffu);
+                                len = (i32)(rw >> 16);
+                            } else {
+                                s0 = re - (i64)runw[2 * k];
+                                len = (i32)runw[2 * k + 1];
+                            }
                         } else {
-                            const i64 e = win == wtop ? lower_bound_dev(ridx, rs, re, W1) : re - (i64)(runw[k] & 0xffffu);
+                            const i64 back = win == wtop ? 0 : PACK16 ? (i64)(runw[k] & 0xffffu) : (i64)runw[2 * k];
+                            const i64 e = win == wtop ? lower_bound_dev(ridx, rs, re, W1) : re - back;
                             s0 = lower_bound_back(ridx, rs, e, W0);
                             len = (i32)(e - s0);
-                            runw[k] = (u32)(re - s0) | ((u32)len << 16);
+                            if (PACK16) {
+                                runw[k] = (u32)(re - s0) | ((u32)len << 16);
+                            } else {
+                                runw[2 * k] = (u32)(re - s0);
+                                runw[2 * k + 1] = (u32)len;
+                            }
                         }
                     } else {
                         const i64 re = rs + cut;
@@ -967,7 +983,7 @@ __global__ void k_c4_segment(i64* p, const DevPlan* __restrict__ plan) {
 // chunk, else one per window (none when no window is left); zero from the
 // part's size up to `bound`, so that the prefix over `bound` entries holds.
 __global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict__ lo, const DevPlan* __restrict__ plan,
-                          int heavy, i64 WS, i64 group, i64 bound, i64* __restrict__ jobcnt) {
+                          int heavy, i64 WS, i64 group, i64 lmax, i64 bound, i64* __restrict__ jobcnt) {
     FGLT_GATE(&plan->err);
     const i32* hs;
     u32 nh;
@@ -978,7 +994,8 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict_
         if (h < (i64)nh) {
             const i64 u = hs[nh - 1 - h];
             const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
-            c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : (nw + group - 1) / group;
+            const i64 g = lo[u] <= lmax ? group : 1;  // as the window kernel groups them
+            c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : (nw + g - 1) / g;
         }
         jobcnt[h] = c;
     }
@@ -999,11 +1016,12 @@ struct C4WinCfg {
     bool use_tab, want_etab;
     i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
     i64 bound_l, bound_h;  // entries of the job arrays of each part (at least its size)
-    // searched runs (no table), 16-bit counters: windows per job of a vertex
-    // with more than one chunk of middles, when the scratch slice also holds
-    // a run word for each middle (cur_n = min(65536, n) of them) and still
-    // keeps three quarters for the wedge ends
-    i64 group, cur_n;
+    // searched runs (no table): windows per job of a vertex with more than
+    // one chunk of middles and at most lmax of them, whose run words the
+    // scratch slice holds -- 16-bit counters: one word per middle for up to
+    // min(65536, n) middles, when three quarters of the slice stay for the
+    // wedge ends; 32-bit counters (no copy of the ends): two words per middle
+    i64 group, lmax16, lmax32;
 };
 
 static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
@@ -1020,8 +1038,10 @@ static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
     c.want_etab = rows_mode == 0 && c.use_tab;
     c.bound_l = n;
     c.bound_h = std::min<i64>(n, (nnz >> 16) + 1);  // vertices of degree >= 65536
-    c.cur_n = std::min<i64>(65536, std::max<i64>(n, 1));
-    c.group = !c.use_tab && w.c4_scr_cap >= 4 * c.cur_n + WAVE ? C4W_GROUP : 1;
+    c.group = c.use_tab ? 1 : C4W_GROUP;
+    const i64 m16 = std::min<i64>(65536, std::max<i64>(n, 1));
+    c.lmax16 = w.c4_scr_cap >= 4 * m16 + WAVE ? m16 : 0;
+    c.lmax32 = (w.c4_scr_cap - WAVE) / 2;
     static_assert(C4W_WS16 == C4W_SPAN, "the tier assignment sizes the table with this window");
     return c;
 }
@@ -1059,7 +1079,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
         hipLaunchKernelGGL(k_c4_table<u16>, dim3(grid_for(n * c.K1, PT, 65536)), dim3(PT), 0, s, w.roff, w.ridx, n,
                            c.K1, c.TS, C4W_WS16, w.c4_tab, (const DevPlan*)w.plan);
     hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_l, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
-                       (const DevPlan*)w.plan, 0, C4W_WS16, c.group, c.bound_l, w.c4_jobcnt);
+                       (const DevPlan*)w.plan, 0, C4W_WS16, c.group, c.lmax16, c.bound_l, w.c4_jobcnt);
     if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobpre, c.bound_l, w.partials, s)) != hipSuccess) return e;
     if (c.want_etab) {
         // c4_jobcnt is free again once the job prefix is built: the chunk counts
@@ -1069,7 +1089,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.bound_l, w.partials, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_h, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
-                       (const DevPlan*)w.plan, 1, C4W_WS32, (i64)1, c.bound_h, w.c4_hjobcnt);
+                       (const DevPlan*)w.plan, 1, C4W_WS32, c.group, c.lmax32, c.bound_h, w.c4_hjobcnt);
     if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.bound_h, w.partials, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1103,17 +1123,17 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
         hipError_t e = fill_u32(reinterpret_cast<u32*>(w.ek), 2 * nnz, 0u, s);
         if (e != hipSuccess) return e;
     }
-#define C4W_LAUNCH(P16, TM, PRE, CTR, EM, GRP)                                                                     \
+#define C4W_LAUNCH(P16, TM, PRE, CTR, EM, GRP, LMAX)                                                               \
     hipLaunchKernelGGL((k_c4_window<P16, TM>), dim3(grid), dim3(CB_THREADS), 0, s, w.roff, w.ridx, w.lo, w.rpos, \
                        w.mir, tab, c.TS, etab, w.c4_ebase, hs, plan, PRE, CTR, w.c4_scr, w.c4_scr_cap, EM,         \
-                       (i32)(GRP), c.cur_n, w.ek, w.c4v)
+                       (i32)(GRP), (i64)(LMAX), w.ek, w.c4v)
     // the per-entry table where it fits (decided on the device), else the vertex table
-    if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2, 1);
-    if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0, 1);
-    else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0, c.group);
+    if (c.want_etab) C4W_LAUNCH(true, 2, w.c4_jobpre, w.c4_jobctr, 2, 1, 0);
+    if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0, 1, 0);
+    else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0, c.group, c.lmax16);
     tm.note("c4_window (16-bit counters)", s);
-    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1);
-    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1);
+    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1, 0);
+    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0, c.group, c.lmax32);
 #undef C4W_LAUNCH
     if (nnz > 0)
         hipLaunchKernelGGL(k_c4_esum_flush, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, w.ridx,
