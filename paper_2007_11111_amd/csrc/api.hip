@@ -164,7 +164,7 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         SegTimer& t;
         ~EvGuard() {
             for (auto& e : t.ev)
-                if (e) hipEventDestroy(e);
+                if (e) (void)hipEventDestroy(e);
         }
     } guard{tm};
     if (flags & FGLT_TIMING) {

@@ -552,8 +552,8 @@ extern "C" int fglt_batch_tune(int32_t num_graphs, const int64_t* vtx_offsets, c
         hipEvent_t& a;
         hipEvent_t& b;
         ~EvGuard() {
-            if (a) hipEventDestroy(a);
-            if (b) hipEventDestroy(b);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
         }
     } guard{e0, e1};
     FGLT_HIP_TRY(hipEventCreate(&e0));
@@ -610,8 +610,8 @@ extern "C" int fglt_batch_release(void* stream) {
     std::lock_guard<std::mutex> lock(g_cache_mu);
     for (auto it = g_cache.begin(); it != g_cache.end();) {
         if (stream == nullptr || it->first.stream == (hipStream_t)stream) {
-            if (it->second.exec) hipGraphExecDestroy(it->second.exec);
-            if (it->second.graph) hipGraphDestroy(it->second.graph);
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
             it = g_cache.erase(it);
         } else {
             ++it;

@@ -30,7 +30,7 @@ constexpr int TRI_MID_D = 4096;      // clique tier above the hub tier: out-degr
 constexpr int NUM_TRI_SLOTS = 64;    // at most this many workgroups in the global-bitmap clique tier
 constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
-constexpr int C4W_GROUP = 8;         // windows per job of a many-middle vertex when runs are searched
+constexpr int C4W_GROUP = 16;        // windows per job of a many-middle vertex when runs are searched
 
 // Device statistics / plan words (one small block of device memory).
 struct DevPlan {
