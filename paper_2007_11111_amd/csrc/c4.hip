@@ -471,6 +471,16 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
     }
 }
 
+// Windows per job of a vertex with more than one chunk of middles and nw
+// windows, in a part of nh vertices: `group` when the middles' run words fit
+// (L <= lmax) and the part's windows leave every workgroup several jobs,
+// fewer when they do not (a few heavy vertices keep a job per window).
+__device__ __forceinline__ i64 c4w_gsz(i64 group, i64 L, i64 lmax, i64 nw, i64 nh) {
+    if (group <= 1 || L > lmax) return 1;
+    const i64 g = nw * nh / (8 * C4W_GRID);
+    return g < 1 ? 1 : g > group ? group : g;
+}
+
 // Jobs: window-tier vertices in descending rank order (hs holds them in
 // ascending order); a vertex whose middles fit one chunk is one job over all
 // its windows, top window first; a larger one is one job per window.
@@ -526,12 +536,13 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     __shared__ i32 cst[MAXCH + 1];  // scratch offset of each chunk's ends (pass A order)
     u32* const sc = scr + (i64)blockIdx.x * scr_cap;
     // the last 64 words of the slice are a sink that nobody reads.  Grouped
-    // windows (searched runs, vertices of at most lmax middles) keep each
+    // windows (runs searched or bracketed by the 16-bit table, vertices of at
+    // most lmax middles) keep each
     // middle's run in the current window in the slice: with 16-bit counts one
     // word per middle before the sink, start (back from the middle's row
     // cut) | length << 16, both below 2^16; with 32-bit counts (no copy of
     // the ends) two words per middle from the slice's start
-    const bool grouped = TABM == 0 && group > 1;
+    const bool grouped = (TABM == 0 || TABM == 3) && group > 1;
     const i64 scr_use = scr_cap - WAVE - (grouped && PACK16 ? lmax : 0);
     const u32 sink = (u32)(scr_cap - WAVE + lane_id());
     u32* const runw = PACK16 ? sc + scr_use : sc;
@@ -565,10 +576,10 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         const i32 nch = single ? 1 : (L + CB_THREADS - 1) / CB_THREADS;
         // windows below wlo hold only ranks of degree <= 1: every count there
         // is at most 1 and adds nothing, so they are not visited
-        // a larger vertex: `group` windows per job when grouped and its
-        // middles' run words fit, else one
-        const bool grp = grouped && !single && (i64)L <= lmax;
-        const i32 gsz = grp ? group : 1;
+        // a larger vertex: several windows per job when grouped (c4w_gsz),
+        // with its middles' run words kept between them
+        const i32 gsz = grouped && !single ? (i32)c4w_gsz(group, L, lmax, nwin - wlo, nh) : 1;
+        const bool grp = gsz > 1;
         const i32 wtop = single ? nwin - 1 : nwin - 1 - gsz * (i32)(j - jobpre[h]);
         const i32 wbot = single ? wlo : (wtop - gsz + 1 > wlo ? wtop - gsz + 1 : wlo);
         const i64 eb = ETAB ? ebase[nh - 1 - h] : 0;  // this vertex's block of etab: [window][middle]
@@ -619,23 +630,6 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                         const i32 a1 = std::min((i32)tabt[vrow + win + 1], cut);
                         s0 = rs + a0;
                         len = a1 - a0;
-                    } else if (TABM == 3 && cut < 65536) {
-                        // the 16-bit vertex table brackets a 32768-rank window
-                        // boundary between two 65536-rank ones: below u every
-                        // count is at most the cut, so the entries hold
-                        const i64 re = rs + cut;
-                        const u16* const t16 =
-                            reinterpret_cast<const u16*>(tab) + (i64)(prefetched ? pc_v : ridx[b + k]) * TS;
-                        auto pos_of = [&](i32 W) -> i64 {  // first entry of the row at rank >= W
-                            if (W >= u) return re;
-                            const i32 q = W >> 16;
-                            const i64 p0 = rs + t16[q];
-                            if ((W & 0xffff) == 0) return p0;
-                            const i64 p1 = ((i64)(q + 1) << 16) >= u ? re : rs + t16[q + 1];
-                            return lower_bound_dev(ridx, p0, p1, W);
-                        };
-                        s0 = pos_of(W0);
-                        len = (i32)(pos_of(W1) - s0);
                     } else if (grp) {
                         // pass A (the loaded values): the run ends where the
                         // previous window's run began (a search of the row for
@@ -664,6 +658,23 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
                                 runw[2 * k + 1] = (u32)len;
                             }
                         }
+                    } else if (TABM == 3 && cut < 65536) {
+                        // the 16-bit vertex table brackets a 32768-rank window
+                        // boundary between two 65536-rank ones: below u every
+                        // count is at most the cut, so the entries hold
+                        const i64 re = rs + cut;
+                        const u16* const t16 =
+                            reinterpret_cast<const u16*>(tab) + (i64)(prefetched ? pc_v : ridx[b + k]) * TS;
+                        auto pos_of = [&](i32 W) -> i64 {  // first entry of the row at rank >= W
+                            if (W >= u) return re;
+                            const i32 q = W >> 16;
+                            const i64 p0 = rs + t16[q];
+                            if ((W & 0xffff) == 0) return p0;
+                            const i64 p1 = ((i64)(q + 1) << 16) >= u ? re : rs + t16[q + 1];
+                            return lower_bound_dev(ridx, p0, p1, W);
+                        };
+                        s0 = pos_of(W0);
+                        len = (i32)(pos_of(W1) - s0);
                     } else {
                         const i64 re = rs + cut;
                         s0 = lower_bound_dev(ridx, rs, re, W0);
@@ -994,7 +1005,7 @@ __global__ void k_c4_jobs(const i32* __restrict__ hs_all, const i32* __restrict_
         if (h < (i64)nh) {
             const i64 u = hs[nh - 1 - h];
             const i64 nw = std::max<i64>(0, (u + WS - 1) / WS - wlo);
-            const i64 g = lo[u] <= lmax ? group : 1;  // as the window kernel groups them
+            const i64 g = c4w_gsz(group, lo[u], lmax, nw, nh);  // as the window kernel groups them
             c = lo[u] <= CB_THREADS ? std::min<i64>(nw, 1) : (nw + g - 1) / g;
         }
         jobcnt[h] = c;
@@ -1016,12 +1027,13 @@ struct C4WinCfg {
     bool use_tab, want_etab;
     i64 K1, TS;          // the 16-bit vertex table: entries per row, row stride
     i64 bound_l, bound_h;  // entries of the job arrays of each part (at least its size)
-    // searched runs (no table): windows per job of a vertex with more than
-    // one chunk of middles and at most lmax of them, whose run words the
-    // scratch slice holds -- 16-bit counters: one word per middle for up to
+    // windows per job of a vertex with more than one chunk of middles and at
+    // most lmax of them, whose run words the scratch slice holds: 16-bit
+    // counters with searched runs (no table), one word per middle for up to
     // min(65536, n) middles, when three quarters of the slice stay for the
-    // wedge ends; 32-bit counters (no copy of the ends): two words per middle
-    i64 group, lmax16, lmax32;
+    // wedge ends; 32-bit counters (searched or bracketed runs, no copy of the
+    // ends), two words per middle
+    i64 group, hgroup, lmax16, lmax32;
 };
 
 static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
@@ -1039,6 +1051,7 @@ static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
     c.bound_l = n;
     c.bound_h = std::min<i64>(n, (nnz >> 16) + 1);  // vertices of degree >= 65536
     c.group = c.use_tab ? 1 : C4W_GROUP;
+    c.hgroup = C4W_GROUP;  // 32-bit counters: runs searched or bracketed, grouped either way
     const i64 m16 = std::min<i64>(65536, std::max<i64>(n, 1));
     c.lmax16 = w.c4_scr_cap >= 4 * m16 + WAVE ? m16 : 0;
     c.lmax32 = (w.c4_scr_cap - WAVE) / 2;
@@ -1089,7 +1102,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
         if ((e = scan_exclusive_i64(w.c4_jobcnt, w.c4_jobcnt, c.bound_l, w.partials, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_c4_jobs, dim3(grid_for(c.bound_h, PT, 4096)), dim3(PT), 0, s, hs, w.lo,
-                       (const DevPlan*)w.plan, 1, C4W_WS32, c.group, c.lmax32, c.bound_h, w.c4_hjobcnt);
+                       (const DevPlan*)w.plan, 1, C4W_WS32, c.hgroup, c.lmax32, c.bound_h, w.c4_hjobcnt);
     if ((e = scan_exclusive_i64(w.c4_hjobcnt, w.c4_hjobpre, c.bound_h, w.partials, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1132,8 +1145,8 @@ hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
     if (c.use_tab) C4W_LAUNCH(true, 1, w.c4_jobpre, w.c4_jobctr, c.want_etab ? 1 : 0, 1, 0);
     else C4W_LAUNCH(true, 0, w.c4_jobpre, w.c4_jobctr, 0, c.group, c.lmax16);
     tm.note("c4_window (16-bit counters)", s);
-    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0, 1, 0);
-    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0, c.group, c.lmax32);
+    if (c.use_tab) C4W_LAUNCH(false, 3, w.c4_hjobpre, w.c4_jobctr + 2, 0, c.hgroup, c.lmax32);
+    else C4W_LAUNCH(false, 0, w.c4_hjobpre, w.c4_jobctr + 2, 0, c.hgroup, c.lmax32);
 #undef C4W_LAUNCH
     if (nnz > 0)
         hipLaunchKernelGGL(k_c4_esum_flush, dim3(grid_for(nnz, PT, 8192)), dim3(PT), 0, s, w.ridx,
