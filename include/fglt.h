@@ -170,6 +170,11 @@ typedef struct {
                                clique pass, its adjacency bitmaps) in LDS; default 1024,
                                -1 disables the hub tier (every such vertex uses bitmaps in
                                the workspace) */
+    int32_t c4_window_group; /* window tier, windows per job of a vertex with more than 1024
+                               middles whose runs are searched (or, with 32-bit counters,
+                               bracketed by the vertex table), each middle's run kept
+                               between them: 0 (default) up to 16 as the tier's size allows,
+                               k >= 1 exactly k (at most 1024) */
 } fglt_raw_plan;
 
 /*

@@ -97,8 +97,9 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
     FgltError for a CSR that breaks the contract; validate=False enqueues the
     transform and returns at once (nothing waits: ``raw_status(workspace)``
     reads the device status word later; capturable into a HIP graph).  ``plan`` may set the tier
-    thresholds tri_wave_max, tri_lds_max, tri_hub_max, c4_wave_max, c4_block_max, c4_hash_max and the
-    window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches); with
+    thresholds tri_wave_max, tri_lds_max, tri_hub_max, c4_wave_max, c4_block_max, c4_hash_max, the
+    window tier's row cuts c4_window_rows (0 default, 1 per-vertex table, 2 searches) and its
+    windows per many-middle job c4_window_group (0 default, k exactly k); with
     timing=True the statistics carry per-segment milliseconds (HIP events); with
     workmodel=True (and stats=True) they carry the byte model's work terms
     min_sum and k4_merge (a statistics pass after the transform); with
@@ -127,7 +128,7 @@ def raw(offsets: torch.Tensor, indices: torch.Tensor, *, net: bool = False, out:
         rp = RawPlan(int(plan.get("tri_wave_max", 0)), int(plan.get("tri_lds_max", 0)),
                      int(plan.get("c4_wave_max", 0)), int(plan.get("c4_block_max", 0)),
                      int(plan.get("c4_hash_max", 0)), int(plan.get("c4_window_rows", 0)),
-                     int(plan.get("tri_hub_max", 0)))
+                     int(plan.get("tri_hub_max", 0)), int(plan.get("c4_window_group", 0)))
     check(L.fglt_raw(n, nnz, _ptr(offsets), _ptr(indices if nnz else None), _ptr(out), _ptr(workspace),
                      int(workspace.numel()), (FGLT_NET if net else 0) | (FGLT_TIMING if timing else 0) | FGLT_SIGMA(mask)
                      | (FGLT_VALIDATE if validate else 0)

@@ -74,7 +74,7 @@ class RawPlan(ctypes.Structure):
     _fields_ = [("tri_wave_max", ctypes.c_int32), ("tri_lds_max", ctypes.c_int32),
                 ("c4_wave_max", ctypes.c_int32), ("c4_block_max", ctypes.c_int32),
                 ("c4_hash_max", ctypes.c_int32), ("c4_window_rows", ctypes.c_int32),
-                ("tri_hub_max", ctypes.c_int32)]
+                ("tri_hub_max", ctypes.c_int32), ("c4_window_group", ctypes.c_int32)]
 
 
 class BatchPlan(ctypes.Structure):

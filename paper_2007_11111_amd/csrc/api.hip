@@ -202,7 +202,7 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->fork, 0));
         s4 = aux->s;
     }
-    if (sp.c4) FGLT_HIP_TRY(launch_c4_early(n, nnz, w, tiers.c4_rows, s4));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_early(n, nnz, w, tiers.c4_rows, tiers.c4_group, s4));
     if (sp.tri) FGLT_HIP_TRY(launch_tri(n, nnz, w, 1, tiers.tri_hub, s, tm));
     else
         for (int seg = FGLT_SEG_TRI1_WAVE; seg <= FGLT_SEG_TRI1_GLOBAL; ++seg) tm.mark(seg, s);
@@ -217,12 +217,12 @@ int fglt::raw_run(int64_t n, int64_t nnz, const int64_t* offsets, const int32_t*
         FGLT_HIP_TRY(hipEventRecord(aux->mid, s));
         FGLT_HIP_TRY(hipStreamWaitEvent(aux->s, aux->mid, 0));
     }
-    if (sp.c4) FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, tiers.c4_rows, s4));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_etab(n, nnz, w, tiers.c4_rows, tiers.c4_group, s4));
     if (aux) FGLT_HIP_TRY(hipEventRecord(aux->join, s4));
     tm.mark(FGLT_SEG_L2, s);
     if (sp.l2) FGLT_HIP_TRY(launch_l2(n, nnz, w, s));
     if (aux) FGLT_HIP_TRY(hipStreamWaitEvent(s, aux->join, 0));
-    if (sp.c4) FGLT_HIP_TRY(launch_c4_late(n, nnz, w, tiers.c4_rows, s, tm));
+    if (sp.c4) FGLT_HIP_TRY(launch_c4_late(n, nnz, w, tiers.c4_rows, tiers.c4_group, s, tm));
     else
         for (int seg = FGLT_SEG_C4_WAVE; seg <= FGLT_SEG_C4_WINDOW; ++seg) tm.mark(seg, s);
     tm.mark(FGLT_SEG_FINALIZE, s);

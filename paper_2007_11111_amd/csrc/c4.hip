@@ -474,9 +474,11 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
 // Windows per job of a vertex with more than one chunk of middles and nw
 // windows, in a part of nh vertices: `group` when the middles' run words fit
 // (L <= lmax) and the part's windows leave every workgroup several jobs,
-// fewer when they do not (a few heavy vertices keep a job per window).
+// fewer when they do not (a few heavy vertices keep a job per window); a
+// negative group is a plan's setting, taken as it is (-group windows).
 __device__ __forceinline__ i64 c4w_gsz(i64 group, i64 L, i64 lmax, i64 nw, i64 nh) {
-    if (group <= 1 || L > lmax) return 1;
+    if ((group <= 1 && group >= -1) || L > lmax) return 1;
+    if (group < 0) return -group;  // as the plan sets it
     const i64 g = nw * nh / (8 * C4W_GRID);
     return g < 1 ? 1 : g > group ? group : g;
 }
@@ -542,7 +544,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
     // word per middle before the sink, start (back from the middle's row
     // cut) | length << 16, both below 2^16; with 32-bit counts (no copy of
     // the ends) two words per middle from the slice's start
-    const bool grouped = (TABM == 0 || TABM == 3) && group > 1;
+    const bool grouped = (TABM == 0 || TABM == 3) && (group > 1 || group < -1);
     const i64 scr_use = scr_cap - WAVE - (grouped && PACK16 ? lmax : 0);
     const u32 sink = (u32)(scr_cap - WAVE + lane_id());
     u32* const runw = PACK16 ? sc + scr_use : sc;
@@ -1039,7 +1041,7 @@ struct C4WinCfg {
 static constexpr i64 C4W_WS16 = 2 * C4W_WORDS;  // ranks per window, 16-bit counters
 static constexpr i64 C4W_WS32 = C4W_WORDS;      // ranks per window, 32-bit counters
 
-static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
+static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode, int win_group) {
     C4WinCfg c;
     c.K1 = (n + C4W_WS16 - 1) / C4W_WS16 + 1;
     // the table's row stride: 32 bytes' worth of entries
@@ -1050,8 +1052,11 @@ static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
     c.want_etab = rows_mode == 0 && c.use_tab;
     c.bound_l = n;
     c.bound_h = std::min<i64>(n, (nnz >> 16) + 1);  // vertices of degree >= 65536
-    c.group = c.use_tab ? 1 : C4W_GROUP;
-    c.hgroup = C4W_GROUP;  // 32-bit counters: runs searched or bracketed, grouped either way
+    // a plan's group is taken as it is (negative: exactly that many), the
+    // default adapts to the part's size (c4w_gsz)
+    const i64 g = win_group > 0 ? -(i64)win_group : C4W_GROUP;
+    c.group = c.use_tab ? 1 : g;
+    c.hgroup = g;  // 32-bit counters: runs searched or bracketed, grouped either way
     const i64 m16 = std::min<i64>(65536, std::max<i64>(n, 1));
     c.lmax16 = w.c4_scr_cap >= 4 * m16 + WAVE ? m16 : 0;
     c.lmax32 = (w.c4_scr_cap - WAVE) / 2;
@@ -1065,7 +1070,7 @@ static C4WinCfg c4_win_cfg(i64 n, i64 nnz, const RawWs& w, int rows_mode) {
 // 4-cycle state (the sums, lists, tables, job arrays, and a sort buffer of its
 // own), so it may run on a second stream beside the triangle and clique
 // passes.  Tier sizes come from the device plan: the grids are bounds.
-hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s) {
+hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s) {
     hipError_t e;
     if ((e = fill_u32(w.c4_jobctr, 3, 0u, s)) != hipSuccess) return e;
     const u32* const cnt = w.plan->n_c4;
@@ -1079,7 +1084,7 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
                            w.rpos, w.mir, w.c4_list + 2 * n, cnt + 2, w.c4_jobctr + 1, cb, w.c4v);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode, win_group);
     // window-tier vertices in ascending order (the sort's buffer: c4_ebase,
     // not yet in use; the shared one is the clique pass's memory); the
     // vertices of degree >= 65536 end the list
@@ -1109,8 +1114,8 @@ hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t 
 
 // Part two: the per-entry window table, in the stored bitmaps' memory, so
 // after the clique pass (it may run on the second stream beside row pass 2).
-hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s) {
-    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s) {
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode, win_group);
     if (c.want_etab)  // 16 workgroups per CU stride over the chunks (their count is on the device)
         hipLaunchKernelGGL(k_c4_etab, dim3(grid_for(nnz, ET_CHUNK, 4096)), dim3(ET_CHUNK), 0, s, w.roff, w.ridx, w.lo,
                            w.rpos, w.c4_tab, c.TS, w.c4_list + 3 * n, (const DevPlan*)w.plan, w.c4_jobcnt, w.c4_ebase,
@@ -1119,12 +1124,12 @@ hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s
 }
 
 // Part three: the window kernels, 16-bit counters then 32-bit counters.
-hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s, SegTimer& tm) {
+hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s, SegTimer& tm) {
     tm.mark(FGLT_SEG_C4_WAVE, s);
     tm.mark(FGLT_SEG_C4_BLOCK, s);
     tm.mark(FGLT_SEG_C4_HASH, s);
     tm.mark(FGLT_SEG_C4_WINDOW, s);  // the segment times the window kernels alone
-    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode);
+    const C4WinCfg c = c4_win_cfg(n, nnz, w, rows_mode, win_group);
     const i32* hs = w.c4_list + 3 * n;
     const u16* const etab = reinterpret_cast<const u16*>(w.bstore);
     const i32* const tab = reinterpret_cast<const i32*>(w.c4_tab);

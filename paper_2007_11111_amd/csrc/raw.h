@@ -139,6 +139,7 @@ struct Tiers {
     i64 tri_wave, tri_lds, tri_hub, c4_wave, c4_block, c4_hash;
     i64 c4_hash_lmax;  // largest |N-(u)| whose counts fit the packed hash words
     int c4_rows;       // window tier's row cuts: 0 per-entry table where it fits, 1 per-vertex table, 2 searches
+    int c4_group;      // window tier's windows per job of a many-middle vertex: 0 by the tier's size, else exactly
 };
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n);
 int bits_for_n(i64 n);   // bits of the largest rank n - 1 (0 for n <= 1)
@@ -174,9 +175,9 @@ hipError_t launch_tri2_stored(i64 n, i64 nnz, RawWs& w, hipStream_t s, int tier,
 hipError_t launch_tri(i64 n, i64 nnz, RawWs& w, int mode, i64 hub_max, hipStream_t s, SegTimer& tm);
 hipError_t launch_fill_c3(i64 nnz, RawWs& w, hipStream_t s);
 hipError_t launch_l2(i64 n, i64 nnz, RawWs& w, hipStream_t s);
-hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s);
-hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s);
-hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, hipStream_t s, SegTimer& tm);
+hipError_t launch_c4_early(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s);
+hipError_t launch_c4_etab(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s);
+hipError_t launch_c4_late(i64 n, i64 nnz, RawWs& w, int rows_mode, int win_group, hipStream_t s, SegTimer& tm);
 hipError_t launch_finalize(i64 n, RawWs& w, i64* out, bool net, hipStream_t s);
 hipError_t launch_finalize_sub(i64 n, RawWs& w, i64* out, bool net, unsigned mask, hipStream_t s);
 hipError_t launch_count_triangles(i64 n, RawWs& w, hipStream_t s);

@@ -333,7 +333,7 @@ int bits_for_n(i64 n) {
 }
 
 Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
-    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, TRI_HUB_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0, 0};
+    Tiers t{TRI_WAVE_MAX, TRI_LDS_MAX, TRI_HUB_MAX, C4_WAVE_MAX, C4_BLOCK_MAX, C4_HASH_MAX, 0, 0, 0};
     if (plan) {
         if (plan->tri_wave_max > 0) t.tri_wave = std::min<i64>(plan->tri_wave_max, TRI_WAVE_MAX);
         if (plan->tri_lds_max > 0) t.tri_lds = std::min<i64>(plan->tri_lds_max, TRI_LDS_MAX);
@@ -346,6 +346,7 @@ Tiers tiers_from_plan(const fglt_raw_plan* plan, i64 n) {
         if (plan->c4_hash_max > 0) t.c4_hash = std::min<i64>(plan->c4_hash_max, C4_HASH_MAX);
         if (plan->c4_hash_max < 0) t.c4_hash = 0;
         if (plan->c4_window_rows == 1 || plan->c4_window_rows == 2) t.c4_rows = plan->c4_window_rows;
+        if (plan->c4_window_group > 0) t.c4_group = std::min<int>(plan->c4_window_group, 1024);
     }
     t.tri_lds = std::max(t.tri_lds, t.tri_wave);
     t.c4_block = std::max(t.c4_block, t.c4_wave);

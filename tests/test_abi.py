@@ -83,6 +83,17 @@ def test_host_argument_checks_need_no_device(lib):
     assert lib.fglt_totals(2, None, 10, None, None, None) == -1
 
 
+def test_binding_plan_matches_header():
+    """The ctypes plan structure lists the header's fields in its order."""
+    import re
+    from paper_2007_11111_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "fglt.h")).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} fglt_raw_plan;", hdr).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"int32_t (\w+);", body)
+    assert fields == [f for f, _ in _lib.RawPlan._fields_]
+
+
 def test_binding_flags_match_header():
     import re
     from paper_2007_11111_amd import _lib

@@ -90,6 +90,14 @@ def test_workload_digest(fg, name):
         f2 = fg.net(fg.raw(off, idx, plan={"c4_window_rows": rows}))
         torch.cuda.synchronize()
         assert sha(f2.cpu().numpy()) == d["net_sha256"], f"net digest mismatch with c4_window_rows={rows}"
+    # 16 windows per job of every many-middle vertex whatever the tier's size
+    # (R-MAT 22's 23 vertices of degree >= 65536 keep one per window by
+    # default): bracketed runs with the default row cuts, searched ones with 2
+    for rows in (0, 2):
+        say(f"workload {name}: c4_window_group=16 c4_window_rows={rows}")
+        f2 = fg.net(fg.raw(off, idx, plan={"c4_window_rows": rows, "c4_window_group": 16}))
+        torch.cuda.synchronize()
+        assert sha(f2.cpu().numpy()) == d["net_sha256"], f"net digest mismatch with grouped windows, rows={rows}"
     # the transform with Sigma_5 gives the first five columns (raw and net)
     say(f"workload {name}: sigma5")
     s5n = fg.raw(off, idx, net=True, sigma5=True)
