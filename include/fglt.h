@@ -87,12 +87,13 @@ enum {
     FGLT_SEG_STRUCTURE,      /* N-/N+ split, mirror positions, work counts, tiers */
     FGLT_SEG_TRI1_WAVE,      /* triangle pass (C3), wavefront tier                */
     FGLT_SEG_TRI1_LDS,       /* triangle pass, workgroup/LDS tier                 */
-    FGLT_SEG_TRI1_GLOBAL,    /* triangle pass, workgroup/global-bitmap tier       */
+    FGLT_SEG_TRI1_GLOBAL,    /* triangle pass, hub tier and the chunked tier above */
     FGLT_SEG_FILL,           /* C3 mirrored to the lower entries, c3 by row sums,
                                 row pass 1: A p1, A (p1-1)(p1-2)/2               */
     FGLT_SEG_TRI2_WAVE,      /* clique/diamond pass, wavefront tier               */
     FGLT_SEG_TRI2_LDS,       /* clique/diamond pass, LDS-bitmap tier              */
-    FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, global-bitmap tier           */
+    FGLT_SEG_TRI2_GLOBAL,    /* clique/diamond pass, hub tier and the tier above it
+                                with bitmaps in workspace slots                   */
     FGLT_SEG_L2,             /* row pass 2: A p2, A c3, C3 (p1-2), C(C3, 2), and the
                                 clique/diamond counts stored per entry            */
     FGLT_SEG_C4_WAVE,        /* empty: the 4-cycle pass's wavefront, workgroup and
@@ -150,7 +151,8 @@ typedef struct {
  * D <= tri_wave_max (<= 64), by a workgroup with LDS bitmaps if
  * D <= tri_lds_max (<= 512), by a 1024-thread workgroup with LDS position
  * map and bitmap rows in the workspace if D <= tri_hub_max (<= 1024), else
- * by a workgroup with bitmaps in the workspace.  The 4-cycle pass goes by the number W of rank-ordered wedges of
+ * by chunks of its items spread over all workgroups (triangle pass) or a
+ * 1024-thread workgroup with bitmaps in the workspace (clique pass).  The 4-cycle pass goes by the number W of rank-ordered wedges of
  * u: one wavefront if W <= c4_wave_max (<= 128), a workgroup with an LDS hash
  * if W <= c4_block_max (<= 2048), a large workgroup with a packed LDS hash if
  * W <= c4_hash_max (<= 16384) and the counts fit the packing, else dense LDS
