@@ -126,6 +126,25 @@ def _batch_union_on_device(fg, graphs):
     return torch.from_numpy(vtx), off, idx
 
 
+@pytest.mark.parametrize("name", ["rmat18", "cl"])
+def test_workload_digest_last_tier(fg, name):
+    """Every vertex of out-degree above 1 in the last triangle and clique tiers
+    (the chunked triangle kernel and the clique kernel with bitmaps in the
+    workspace), against the oracle's digest.  With 10^6 vertices (Chung-Lu),
+    N+(u) of most vertices spans more ranks than the LDS bitmap covers, so
+    their positions come from the sampled search of the row."""
+    d = _digests().get(name)
+    if d is None:
+        pytest.skip(f"no stored oracle digest for {name}")
+    n, src, dst = _edges(name)
+    off, idx = fg.build_csr(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    say(f"workload {name}: last tiers only")
+    plan = {"tri_wave_max": 1, "tri_lds_max": 1, "tri_hub_max": -1}
+    f = fg.net(fg.raw(off, idx, plan=plan))
+    torch.cuda.synchronize()
+    assert sha(f.cpu().numpy()) == d["net_sha256"], "net digest mismatch with the last tiers only"
+
+
 def test_batch_workload_through_fglt_batch(fg):
     """The 4096-graph batch that bench.py times, through fglt_batch itself, one
     launch and by HIP-graph replay (three replays with eager work between
