@@ -27,7 +27,7 @@ constexpr int C4_WAVE_MAX = 128;     // wedges handled by one wavefront (256-slo
 constexpr int C4_BLOCK_MAX = 2048;   // wedges handled by one workgroup (4096-slot LDS hash)
 constexpr int C4_HASH_MAX = 16384;   // wedges handled by one large workgroup (32768-slot packed hash)
 constexpr int TRI_MID_D = 4096;      // clique tier above the hub tier: out-degree bound of its first launch (then doubling)
-constexpr int NUM_TRI_SLOTS = 64;    // at most this many workgroups in the global-bitmap clique tier
+constexpr int NUM_TRI_SLOTS = 64;    // clique pass above the hub tier: at most this many slots of the largest bitmaps
 constexpr i64 C4W_SPAN = 65536;      // ranks per window of the 4-cycle window tier with 16-bit counts
 constexpr int C4W_GRID = 256;        // workgroups of the 4-cycle window tier (one per CU)
 constexpr int C4W_GROUP = 16;        // windows per job of a many-middle vertex when runs are searched
@@ -99,7 +99,7 @@ struct RawWs {
     // heavy-tier scratch
     u64* tri_slots;     // tri_nslots * tri_slot_words
     i64 tri_slot_words;
-    int tri_nslots;     // slots (and workgroups) of the global-bitmap tier, 1..NUM_TRI_SLOTS
+    int tri_nslots;     // slots of the largest bitmaps in that memory, 1..NUM_TRI_SLOTS (launches cut it finer)
     i64* tri_jobpre;    // [n+2] job counts, then their prefix, of the split triangle tier
     i64* tri_partials;  // scan partials of the triangle pass (the second stream scans with `partials`)
     i64* c4_segoff;     // [2] one segment over the window-tier list

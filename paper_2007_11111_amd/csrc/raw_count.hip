@@ -267,9 +267,10 @@ __global__ void __launch_bounds__(PT) k_tri_wave(const i64* __restrict__ roff, c
 // N+(u) lies in the ranks above u: when they fit, a bitmap of them in LDS
 // answers with one read, and a hit's position in N+(u) is its rank among the
 // set bits (prefix counts per 8 words, then at most 8 word popcounts);
-// otherwise every TRI_SAMP-th entry of N+(u) in LDS narrows a search to one
-// short stretch of the row.  Counts go straight to C3
-// with global atomics (the entries (u, v_k), (u, y) and (v_k, y)).
+// otherwise a sample of at most TRI_SAMP entries of N+(u) in LDS narrows a
+// search to one short stretch of the row.  Counts go to C3 with global
+// atomics: the entries (u, y) and (v_k, y) one per hit, (u, v_k) one per run
+// of lanes on the same entry.
 static constexpr i64 TRI_SPLIT_CH = 262144;
 static constexpr int TRI_SPLIT_T = 1024;  // threads per workgroup
 static constexpr int TRI_SAMP = 4096;     // LDS sample entries
