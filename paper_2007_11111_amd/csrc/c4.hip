@@ -471,6 +471,19 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
     }
 }
 
+// The job a queue ticket t stands for.  16-bit counters: in order (vertex by
+// vertex, top window first).  32-bit counters: the few vertices of degree >=
+// 65536 have a job per window each, and in order the whole GPU would work on
+// the windows of one or two vertices at a time, all adding to the same N-
+// entries' middle sums; a stride of 7919 (prime, so the order is a
+// permutation unless it divides the job count) spreads the concurrent jobs
+// over the vertices.  Tickets at or past the end stay as they are.
+template <bool PACK16>
+__device__ __forceinline__ i64 c4w_job_order(i64 t, i64 njobs) {
+    if (PACK16 || t >= njobs || njobs % 7919 == 0) return t;
+    return (t * 7919) % njobs;
+}
+
 // Windows per job of a vertex with more than one chunk of middles and nw
 // windows, in a part of nh vertices: `group` when the middles' run words fit
 // (L <= lmax) and the part's windows leave every workgroup several jobs,
@@ -557,6 +570,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         i64 j = 0;
         if (l == 0) j = atomicAdd(job_ctr, 1u);
         j = __shfl(j, 0, WAVE);
+        j = c4w_job_order<PACK16>(j, njobs);
         const i64 h = j < njobs ? wave_last_le(jobpre, nh, j) : 0;
         if (l == 0) {
             sj = j;
@@ -861,7 +875,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             red = 0;
         }
         if (wv == 0) {  // decode the next job
-            const i64 nj = __shfl((i64)nxt, 0, WAVE);
+            const i64 nj = c4w_job_order<PACK16>(__shfl((i64)nxt, 0, WAVE), njobs);
             const i64 nhh = nj < njobs ? wave_last_le(jobpre, nh, nj) : 0;
             if (l == 0) {
                 sj = nj;
