@@ -471,16 +471,16 @@ __device__ __forceinline__ void c4w_stream_c(const u32* __restrict__ sc, i32 cs,
     }
 }
 
-// The job a queue ticket t stands for.  16-bit counters: in order (vertex by
-// vertex, top window first).  32-bit counters: the few vertices of degree >=
-// 65536 have a job per window each, and in order the whole GPU would work on
+// The job a queue ticket t stands for: in order (vertex by vertex, largest
+// first, top window first), except for a part of fewer vertices than
+// workgroups with 32-bit counters: there, in order, the whole GPU would work on
 // the windows of one or two vertices at a time, all adding to the same N-
-// entries' middle sums; a stride of 7919 (prime, so the order is a
-// permutation unless it divides the job count) spreads the concurrent jobs
-// over the vertices.  Tickets at or past the end stay as they are.
+// entries' middle sums, so a stride of 7919 (prime: a permutation unless it
+// divides the job count) spreads the concurrent jobs over the vertices.
+// Tickets at or past the end stay as they are.
 template <bool PACK16>
-__device__ __forceinline__ i64 c4w_job_order(i64 t, i64 njobs) {
-    if (PACK16 || t >= njobs || njobs % 7919 == 0) return t;
+__device__ __forceinline__ i64 c4w_job_order(i64 t, i64 njobs, i64 nh) {
+    if (PACK16 || nh >= C4W_GRID || t >= njobs || njobs % 7919 == 0) return t;
     return (t * 7919) % njobs;
 }
 
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
         i64 j = 0;
         if (l == 0) j = atomicAdd(job_ctr, 1u);
         j = __shfl(j, 0, WAVE);
-        j = c4w_job_order<PACK16>(j, njobs);
+        j = c4w_job_order<PACK16>(j, njobs, nh);
         const i64 h = j < njobs ? wave_last_le(jobpre, nh, j) : 0;
         if (l == 0) {
             sj = j;
@@ -875,7 +875,7 @@ __global__ void __launch_bounds__(CB_THREADS) k_c4_window(const i64* __restrict_
             red = 0;
         }
         if (wv == 0) {  // decode the next job
-            const i64 nj = c4w_job_order<PACK16>(__shfl((i64)nxt, 0, WAVE), njobs);
+            const i64 nj = c4w_job_order<PACK16>(__shfl((i64)nxt, 0, WAVE), njobs, nh);
             const i64 nhh = nj < njobs ? wave_last_le(jobpre, nh, nj) : 0;
             if (l == 0) {
                 sj = nj;
